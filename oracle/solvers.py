@@ -1,0 +1,341 @@
+"""Oracle solvers and the multigrid hierarchy: flexible GCR, the minimal
+residual smoother, the K-cycle, CGNE near-null vectors and the Schur CG
+baseline.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Plain numpy, complex128.
+
+Readings of the paper used here (it leaves these open):
+  * inner solves stop at ||r|| <= 0.25 ||r_in|| or 8 iterations, whichever
+    comes first (Table 1);
+  * the smoother CA-GCR(s) is defined by what it computes, the minimiser of
+    ||r - A v|| over the Krylov space K_s(A, r) from a zero guess; the oracle
+    computes that minimiser with s steps of Arnoldi (MGS) and a small
+    least-squares solve;
+  * the coarsest level (SVD deflation is out of scope) is unpreconditioned
+    GCR to a tolerance / iteration cap, or a dense LU solve;
+  * near-null vectors: CG on A A^dag y = -A phi0, phi = phi0 + A^dag y
+    (CGNE on the homogeneous system, Sec. 2.1 and Table 1), stopping at
+    ||A phi|| <= tol ||A phi0|| or maxiter.  PARITY UNPINNED: a long random
+    iteration; tests only check quality metrics.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import operators as ops
+
+
+def _norm(v):
+    return float(np.sqrt(np.vdot(v, v).real))
+
+
+# --------------------------------------------------------------------------
+# Krylov building blocks
+# --------------------------------------------------------------------------
+
+@dataclass
+class SolveInfo:
+    iters: int = 0
+    converged: bool = False
+    history: list = field(default_factory=list)   # recursive ||r|| / ||b|| per iteration
+    true_rel_residual: float = float("nan")
+    restarts: int = 0
+
+
+def gcr(op, b, precond=None, tol=1e-10, maxiter=1000, nkrylov=16, true_residual=False):
+    """Flexible GCR (Sec. 2.1) with modified Gram-Schmidt, zero initial guess.
+
+    Each iteration: z = K(r), q = A z, orthogonalise q against the stored
+    q_i (applying the same combination to z), normalise, then
+    x += alpha z, r -= alpha q with alpha = <q, r>.  After nkrylov
+    directions the space is discarded and r = b - A x recomputed.
+    With true_residual=True the stop test is the recomputed ||b - A x||.
+    """
+    x = np.zeros_like(b)
+    r = b.copy()
+    bnorm = _norm(b)
+    info = SolveInfo()
+    if bnorm == 0.0:
+        info.converged = True
+        info.true_rel_residual = 0.0
+        return x, info
+    Z, Q = [], []
+    for it in range(maxiter):
+        z = precond(r) if precond is not None else r.copy()
+        q = op(z)
+        for zi, qi in zip(Z, Q):
+            beta = np.vdot(qi, q)
+            q = q - beta * qi
+            z = z - beta * zi
+        g = _norm(q)
+        q = q / g
+        z = z / g
+        alpha = np.vdot(q, r)
+        x = x + alpha * z
+        r = r - alpha * q
+        Z.append(z)
+        Q.append(q)
+        info.iters = it + 1
+        rel = _norm(r) / bnorm
+        info.history.append(rel)
+        if rel <= tol:
+            if not true_residual:
+                info.converged = True
+                break
+            r = b - op(x)
+            Z, Q = [], []
+            info.restarts += 1
+            if _norm(r) / bnorm <= tol:
+                info.converged = True
+                break
+            continue
+        if len(Z) == nkrylov:
+            r = b - op(x)
+            Z, Q = [], []
+            info.restarts += 1
+    if true_residual:
+        info.true_rel_residual = _norm(b - op(x)) / bnorm
+    return x, info
+
+
+def mr_smoother(op, r, s):
+    """v = argmin_{v in K_s(A, r)} ||r - A v||  (the smoother's result).
+
+    Computed with s steps of Arnoldi (MGS) from v_0 = r/||r|| and the
+    (s+1) x s least-squares problem min ||beta e_1 - H y||.
+    """
+    beta = _norm(r)
+    if beta == 0.0:
+        return np.zeros_like(r)
+    V = [r / beta]
+    H = np.zeros((s + 1, s), dtype=np.complex128)
+    k = s
+    for j in range(s):
+        w = op(V[j])
+        for i in range(j + 1):
+            H[i, j] = np.vdot(V[i], w)
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = _norm(w)
+        if H[j + 1, j].real <= 1e-300:
+            k = j + 1
+            break
+        V.append(w / H[j + 1, j])
+    rhs = np.zeros(k + 1, dtype=np.complex128)
+    rhs[0] = beta
+    y = np.linalg.lstsq(H[:k + 1, :k], rhs, rcond=None)[0]
+    return sum(y[i] * V[i] for i in range(k))
+
+
+def cgne_null_vector(op, op_dag, phi0, tol, maxiter):
+    """Near-null vector by CGNE on A phi = 0 from phi0 (Sec. 2.1, Table 1).
+
+    CG on A A^dag y = -A phi0 from y = 0; phi = phi0 + A^dag y.  The CG
+    residual equals -A phi, so the stop test ||r|| <= tol ||A phi0|| is the
+    test on ||A phi||.  Returns (phi, iterations, ||A phi|| / ||A phi0||).
+    """
+    r = -op(phi0)
+    r0 = _norm(r)
+    y = np.zeros_like(phi0)
+    p = r.copy()
+    rr = np.vdot(r, r).real
+    it = 0
+    for it in range(1, maxiter + 1):
+        Ap = op(op_dag(p))
+        alpha = rr / np.vdot(p, Ap).real
+        y = y + alpha * p
+        r = r - alpha * Ap
+        rr_new = np.vdot(r, r).real
+        if np.sqrt(rr_new) <= tol * r0:
+            break
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    phi = phi0 + op_dag(y)
+    return phi, it, _norm(op(phi)) / r0
+
+
+# --------------------------------------------------------------------------
+# Schur CG baseline (Sec. 3.2)
+# --------------------------------------------------------------------------
+
+def cg_schur(W, N, mass, c1, c3, b, tol=1e-10, maxiter=100000):
+    """Single-parity (even) Schur CG for D x = b, D = m + K.
+
+    (m^2 - K_eo K_oe) x_e = m b_e - K_eo b_o, then x_o = (b_o - K_oe x_e)/m.
+    The full residual is the even Schur residual divided by m, so CG runs to
+    ||r_e|| <= m * tol * ||b|| (the m x 1e-10 of Sec. 3.2) and the stop test
+    is confirmed on the true ||b - D x||; a miss restarts CG from the current
+    x_e.  Returns (x, iterations, true relative residual).
+    """
+    T, Z, Y, X = b.shape[:4]
+    epsf = ops.epsilon((X, Y, Z, T))[..., None]
+    Pe = (epsf > 0).astype(np.float64)
+    Po = 1.0 - Pe
+
+    def K(v):
+        return ops.dslash(v, W, N, 0.0, c1, c3)
+
+    def M(v):  # m^2 v_e - K_eo K_oe v_e on even sites
+        return mass * mass * v - Pe * K(Po * K(Pe * v))
+
+    bnorm = _norm(b)
+    rhs = Pe * (mass * b - K(Po * b))
+    xe = np.zeros_like(b)
+    iters = 0
+    while True:
+        r = rhs - M(xe)
+        p = r.copy()
+        rr = np.vdot(r, r).real
+        while np.sqrt(rr) > mass * tol * bnorm and iters < maxiter:
+            Ap = M(p)
+            alpha = rr / np.vdot(p, Ap).real
+            xe = xe + alpha * p
+            r = r - alpha * Ap
+            rr_new = np.vdot(r, r).real
+            p = r + (rr_new / rr) * p
+            rr = rr_new
+            iters += 1
+        x = xe + Po * (b - K(xe)) / mass
+        rel = _norm(b - ops.dslash(x, W, N, mass, c1, c3)) / bnorm
+        if rel <= tol or iters >= maxiter:
+            return x, iters, rel
+
+
+# --------------------------------------------------------------------------
+# Hierarchy and K-cycle (Sec. 2.1, Sec. 2.3, Table 1)
+# --------------------------------------------------------------------------
+
+@dataclass
+class MGParams:
+    dims: tuple
+    c1: float
+    c3: float
+    kd_naik: bool = True
+    blocks: tuple = ((4, 4, 4, 4), (2, 2, 2, 2))   # one entry per aggregation level
+    smoother_s: int = 8
+    inner_tol: float = 0.25
+    inner_maxiter: int = 8
+    coarsest_tol: float = 0.25
+    coarsest_maxiter: int = 16
+    coarsest_direct: bool = False
+    outer_nkrylov: int = 16
+    dense_coarse_limit: int = 6144   # coarse levels up to this many dof are tabulated densely
+
+
+class Hierarchy:
+    """Levels of the KD multigrid (Sec. 2.3, Table 1):
+
+      level 0   D(m)            (full, non-Schur HISQ operator)
+      level 1   A = (B+m)^{-1} D (KD "pseudo-fine": same space, no coarsening;
+                                 Naik dropped inside it when kd_naik is False)
+      level 2   P1^dag A P1     (Galerkin, chirally split block-orthonormal P1)
+      level 3   P2^dag A2 P2    (optional second aggregation)
+
+    Transfers: level 0 -> 1 is r1 = (B+m)^{-1} r0 with identity prolongation
+    (so A e1 = r1 is D e1 = r0); deeper transfers are R = P^dag and P.
+    The coarse operators are applied matrix-free as R A P (their definition).
+    """
+
+    def __init__(self, p: MGParams, W, N, mass, null_vectors):
+        self.p = p
+        self.W, self.N, self.mass = W, N, mass
+        self.c3_kd = p.c3 if p.kd_naik else 0.0
+        self.Kinv = ops.kd_inverse(W, mass, p.c1)
+        self.transfers = []
+        dims = p.dims
+        agg, chi = ops.fine_dof_labels(dims, p.blocks[0])
+        self.transfers.append(ops.Transfer(null_vectors[0], agg, chi))
+        cdims = tuple(d // b for d, b in zip(dims, p.blocks[0]))
+        self.cdims = [cdims]
+        for lvl in range(1, len(p.blocks)):
+            nv = self.transfers[-1].nvec
+            agg, chi = ops.coarse_dof_labels(cdims, nv, p.blocks[lvl])
+            self.transfers.append(ops.Transfer(null_vectors[lvl], agg, chi))
+            cdims = tuple(d // b for d, b in zip(cdims, p.blocks[lvl]))
+            self.cdims.append(cdims)
+        self.nlevels = 2 + len(self.transfers)
+        self._dense_lu = None
+        self._dense = {}
+
+    # --- level operators --------------------------------------------------
+    def op(self, lvl, v):
+        p = self.p
+        if lvl == 0:
+            return ops.dslash(v, self.W, self.N, self.mass, p.c1, p.c3)
+        if lvl == 1:
+            return ops.kd_operator(v, self.W, self.N, self.Kinv, self.mass, p.c1, self.c3_kd)
+        if v.size <= p.dense_coarse_limit:
+            # the same R A P, tabulated column by column once for a small level
+            if lvl not in self._dense:
+                self._dense[lvl] = ops.dense_matrix(lambda u: self._galerkin(lvl, u), v.shape)
+            return (self._dense[lvl] @ v.reshape(-1)).reshape(v.shape)
+        return self._galerkin(lvl, v)
+
+    def _galerkin(self, lvl, v):
+        """R A P v for the operator A of level lvl - 1 (Galerkin, Sec. 2.1)."""
+        t = self.transfers[lvl - 2]
+        fine = t.prolong(v)
+        shape = self.fine_shape(lvl - 1)
+        return t.restrict(self.op(lvl - 1, fine.reshape(shape))).reshape(v.shape)
+
+    def op_dag(self, lvl, v):
+        p = self.p
+        if lvl == 0:
+            return ops.dslash_dagger(v, self.W, self.N, self.mass, p.c1, p.c3)
+        if lvl == 1:
+            return ops.kd_operator_dagger(v, self.W, self.N, self.Kinv, self.mass, p.c1, self.c3_kd)
+        t = self.transfers[lvl - 2]
+        fine = t.prolong(v)
+        shape = self.fine_shape(lvl - 1)
+        return t.restrict(self.op_dag(lvl - 1, fine.reshape(shape))).reshape(v.shape)
+
+    def fine_shape(self, lvl):
+        X, Y, Z, T = self.p.dims
+        if lvl <= 1:
+            return (T, Z, Y, X, 3)
+        Xc, Yc, Zc, Tc = self.cdims[lvl - 2]
+        return (Tc, Zc, Yc, Xc, 2, self.transfers[lvl - 2].nvec)
+
+    def restrict(self, lvl, r):
+        """level lvl -> lvl + 1"""
+        if lvl == 0:
+            return ops.kd_apply(self.Kinv, r)
+        t = self.transfers[lvl - 1]
+        return t.restrict(r).reshape(self.fine_shape(lvl + 1))
+
+    def prolong(self, lvl, e):
+        """level lvl + 1 -> lvl"""
+        if lvl == 0:
+            return e
+        t = self.transfers[lvl - 1]
+        return t.prolong(e).reshape(self.fine_shape(lvl))
+
+    # --- cycle -------------------------------------------------------------
+    def kcycle(self, lvl, r):
+        """K_l(r): no pre-smoothing; restrict; solve on level l+1; prolong;
+        post-smooth with the minimal-residual smoother (Sec. 2.1, Table 1)."""
+        rc = self.restrict(lvl, r)
+        ec = self.solve_level(lvl + 1, rc)
+        e = self.prolong(lvl, ec)
+        return e + mr_smoother(lambda v: self.op(lvl, v), r - self.op(lvl, e), self.p.smoother_s)
+
+    def solve_level(self, lvl, b):
+        p = self.p
+        if lvl == self.nlevels - 1:
+            if p.coarsest_direct:
+                if self._dense_lu is None:
+                    self._dense_lu = ops.dense_matrix(lambda v: self.op(lvl, v), b.shape)
+                return np.linalg.solve(self._dense_lu, b.reshape(-1)).reshape(b.shape)
+            x, _ = gcr(lambda v: self.op(lvl, v), b, None, p.coarsest_tol,
+                       p.coarsest_maxiter, p.coarsest_maxiter)
+            return x
+        x, _ = gcr(lambda v: self.op(lvl, v), b, lambda r: self.kcycle(lvl, r),
+                   p.inner_tol, p.inner_maxiter, p.inner_maxiter)
+        return x
+
+    def solve(self, b, tol=1e-10, maxiter=200):
+        """Outer flexible GCR on D, preconditioned by K_0, stop on the true
+        residual ||b - D x|| / ||b|| <= tol (Sec. 3.2)."""
+        return gcr(lambda v: self.op(0, v), b, lambda r: self.kcycle(0, r), tol, maxiter,
+                   self.p.outer_nkrylov, true_residual=True)

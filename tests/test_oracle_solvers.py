@@ -1,0 +1,151 @@
+"""Pins of the oracle's solvers and hierarchy: dense solves, brute-force
+least squares, the exact two-level cycle of the 4^4 geometry, the Galerkin
+identity on a dense matrix and coarse-stencil locality.  CPU only."""
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from oracle import solvers as sol
+from paper_2212_12559_amd import latgen
+
+C1H, C3H = 9.0 / 8.0, -1.0 / 24.0
+
+
+def test_gcr_matches_dense_solve():
+    dims = (4, 4, 4, 4)
+    W, N, rng = latgen.hisq_style_links(dims, 0.5, 21)
+    m = 0.1
+    b = latgen.fine_vectors(dims, 1, rng)[0]
+    x, info = sol.gcr(lambda v: ops.dslash(v, W, N, m, C1H, C3H), b, None, 1e-12, 2000, 16,
+                      true_residual=True)
+    D = ops.dense_matrix(lambda v: ops.dslash(v, W, N, m, C1H, C3H), b.shape)
+    xs = np.linalg.solve(D, b.reshape(-1))
+    assert info.converged and info.true_rel_residual <= 1e-12
+    assert np.linalg.norm(x.reshape(-1) - xs) <= 1e-12 * np.linalg.norm(b) / m * 1.01
+
+
+def test_mr_smoother_is_krylov_minimiser():
+    """argmin over K_s(A, r) of ||r - A v|| by brute force: least squares on the
+    explicit power basis of a small well-conditioned matrix."""
+    rng = np.random.default_rng(5)
+    n, s = 60, 6
+    A = np.eye(n) + 0.3 * latgen.complex_normal(rng, (n, n)) / np.sqrt(n)
+    r = latgen.complex_normal(rng, (n,))
+    v = sol.mr_smoother(lambda u: A @ u, r, s)
+    K = np.stack([np.linalg.matrix_power(A, j) @ r for j in range(s)], axis=1)
+    c = np.linalg.lstsq(A @ K, r, rcond=None)[0]
+    assert np.linalg.norm(v - K @ c) < 1e-10 * np.linalg.norm(v)
+
+
+def test_cg_schur_matches_dense():
+    dims = (4, 4, 4, 4)
+    W, N, rng = latgen.hisq_style_links(dims, 0.5, 22)
+    m = 0.02
+    b = latgen.fine_vectors(dims, 1, rng)[0]
+    x, iters, rel = sol.cg_schur(W, N, m, C1H, C3H, b, tol=1e-10)
+    D = ops.dense_matrix(lambda v: ops.dslash(v, W, N, m, C1H, C3H), b.shape)
+    xs = np.linalg.solve(D, b.reshape(-1))
+    assert rel <= 1e-10
+    assert np.linalg.norm(D @ x.reshape(-1) - b.reshape(-1)) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x.reshape(-1) - xs) <= 1e-10 * np.linalg.norm(b) / m
+
+
+def c0_hierarchy(mass=0.1, seed=latgen.SEEDS["c0_4x4_naive"], cgne_iters=50):
+    """4^4 naive staggered, U = exp(0.3 i H); KD level then 2^4 aggregation
+    with Nvec = 24 (square P: 24 rows per aggregate and chirality)."""
+    dims = (4, 4, 4, 4)
+    U, Z0, rng = latgen.naive_links(dims, 0.3, seed)
+    p = sol.MGParams(dims=dims, c1=1.0, c3=0.0, blocks=((2, 2, 2, 2),), coarsest_direct=True)
+    b = latgen.fine_vectors(dims, 1, rng)[0]
+    phi0 = latgen.fine_vectors(dims, 24, rng)
+    Kinv = ops.kd_inverse(U, mass, 1.0)
+    A = lambda v: ops.kd_operator(v, U, Z0, Kinv, mass, 1.0, 0.0)
+    Ad = lambda v: ops.kd_operator_dagger(v, U, Z0, Kinv, mass, 1.0, 0.0)
+    nvs = np.stack([sol.cgne_null_vector(A, Ad, phi0[k], 1e-6, cgne_iters)[0] for k in range(24)])
+    return sol.Hierarchy(p, U, Z0, mass, [nvs]), b
+
+
+def test_c0_square_P_exact_two_level():
+    """4^4 with 2^4 aggregation and Nvec = 24: P is square and unitary, so the
+    Galerkin operator P^dag A P has the spectrum of A, and with an exact coarse
+    solve the K-cycle is A^{-1}: outer GCR converges in one iteration."""
+    H, b = c0_hierarchy()
+    t = H.transfers[0]
+    nc = t.nagg * 2 * t.nvec
+    assert nc == 768
+    Pm = np.stack([t.prolong(np.eye(nc)[j]) for j in range(nc)], axis=1)
+    assert np.max(np.abs(Pm @ Pm.conj().T - np.eye(nc))) < 1e-13
+    shape = H.fine_shape(1)
+    A = ops.dense_matrix(lambda v: H.op(1, v), shape)
+    Ac = ops.dense_matrix(lambda v: H.op(2, v), H.fine_shape(2))
+    assert np.max(np.abs(Ac - Pm.conj().T @ A @ Pm)) < 1e-12
+    la = np.linalg.eigvals(A)
+    lc = np.linalg.eigvals(Ac)
+    dist = np.abs(la[:, None] - lc[None, :])
+    assert np.max(dist.min(axis=1)) < 1e-10 and np.max(dist.min(axis=0)) < 1e-10
+    x, info = H.solve(b, tol=1e-10)
+    assert info.converged and info.iters == 1
+    assert info.true_rel_residual < 1e-10
+
+
+def test_coarse_stencil_is_nine_point():
+    """Hops of length <= 3 plus hypercube-local KD couple an aggregate of side
+    >= 3 only to itself and its 8 axis neighbours: a unit vector on coarse site
+    b maps to a vector supported on b and b +- mu."""
+    dims = (8, 8, 8, 8)
+    W, N, rng = latgen.hisq_style_links(dims, 0.5, 23)
+    p = sol.MGParams(dims=dims, c1=C1H, c3=C3H, blocks=((4, 4, 4, 4),))
+    nv = latgen.fine_vectors(dims, 6, rng)
+    H = sol.Hierarchy(p, W, N, 0.05, [nv])
+    shape = H.fine_shape(2)          # (2,2,2,2, 2, 6)
+    e = np.zeros(shape, dtype=np.complex128)
+    e[0, 0, 0, 0, 1, 3] = 1.0        # coarse site 0
+    y = H.op(2, e)
+    nz = np.abs(y).reshape(16, -1).max(axis=1) > 1e-14
+    support = set(np.nonzero(nz)[0])
+    neighbours = {0, 1, 2, 4, 8}      # self and the +-mu neighbours (extent 2 aliases +- mu)
+    assert support <= neighbours and 0 in support and len(support) == 5
+
+
+def test_three_level_solve_small():
+    """Three-level K-cycle (KD, 4^4 then 2^4 aggregation) reaches the true
+    residual 1e-10 on an 8^4 HISQ-style lattice; compared with the dense-free
+    Schur CG solution within ||x - x*|| <= 2e-10 ||b|| / m."""
+    dims = (8, 8, 8, 8)
+    W, N, rng = latgen.hisq_style_links(dims, 0.5, latgen.SEEDS["small_8x4_hisq"])
+    m = 0.05
+    p = sol.MGParams(dims=dims, c1=C1H, c3=C3H, blocks=((4, 4, 4, 4), (2, 2, 2, 2)))
+    nv1 = latgen.fine_vectors(dims, 8, rng)
+    b = latgen.fine_vectors(dims, 1, rng)[0]
+    # level-1 null vectors by a short CGNE, level-2 by CGNE on the level-2 operator
+    Kinv = ops.kd_inverse(W, m, C1H)
+    A = lambda v: ops.kd_operator(v, W, N, Kinv, m, C1H, C3H)
+    Ad = lambda v: ops.kd_operator_dagger(v, W, N, Kinv, m, C1H, C3H)
+    nv1 = np.stack([sol.cgne_null_vector(A, Ad, nv1[k], 1e-6, 30)[0] for k in range(8)])
+    H1 = sol.Hierarchy(sol.MGParams(dims=dims, c1=C1H, c3=C3H, blocks=((4, 4, 4, 4),)), W, N, m, [nv1])
+    nv2 = latgen.coarse_vectors((2, 2, 2, 2), 8, 8, rng)
+    nv2 = np.stack([sol.cgne_null_vector(lambda v: H1.op(2, v), lambda v: H1.op_dag(2, v),
+                                         nv2[k], 1e-6, 20)[0] for k in range(8)])
+    H = sol.Hierarchy(p, W, N, m, [nv1, nv2])
+    x, info = H.solve(b, tol=1e-10)
+    assert info.converged and info.true_rel_residual <= 1e-10
+    xc, iters, rel = sol.cg_schur(W, N, m, C1H, C3H, b, tol=1e-11)
+    assert np.linalg.norm(x - xc) <= 2e-10 * np.linalg.norm(b) / m
+    assert info.iters < iters  # MG needs fewer outer iterations than CG iterations
+
+
+def test_cgne_null_vectors_reduce_A():
+    """Quality metric only (null vectors are parity unpinned): ||A phi|| / ||phi||
+    falls well below its value on the random start."""
+    dims = (4, 4, 4, 4)
+    W, N, rng = latgen.hisq_style_links(dims, 0.5, 24)
+    m = 0.01
+    Kinv = ops.kd_inverse(W, m, C1H)
+    A = lambda v: ops.kd_operator(v, W, N, Kinv, m, C1H, C3H)
+    Ad = lambda v: ops.kd_operator_dagger(v, W, N, Kinv, m, C1H, C3H)
+    phi0 = latgen.fine_vectors(dims, 1, rng)[0]
+    phi, it, rel = sol.cgne_null_vector(A, Ad, phi0, 1e-6, 200)
+    q0 = np.linalg.norm(A(phi0)) / np.linalg.norm(phi0)
+    q1 = np.linalg.norm(A(phi)) / np.linalg.norm(phi)
+    assert q1 < 0.25 * q0
+    assert rel == pytest.approx(np.linalg.norm(A(phi)) / np.linalg.norm(A(phi0)), rel=1e-12)
