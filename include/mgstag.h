@@ -1,0 +1,196 @@
+/*
+ * mgstag: 4D staggered / HISQ Kahler-Dirac multigrid on one AMD MI355X (gfx950).
+ *
+ * The method is that of Ayyar, Brower, Clark, Wagner and Weinberg,
+ * "Optimizing Staggered Multigrid for Exascale performance" (Lattice 2022,
+ * arXiv:2212.12559): an outer flexible GCR on the full HISQ operator,
+ * preconditioned by a K-cycle whose first level is the Kahler-Dirac (KD)
+ * block-preconditioned operator (Sec. 2.2-2.3), followed by Galerkin
+ * coarsenings with chirally split, block-orthonormal near-null vectors
+ * (Sec. 2.1), CA-GCR post-smoothers and inner solves to 0.25 or 8 iterations
+ * (Table 1).
+ *
+ * Conventions (all calls):
+ *   - lattice extents dims = {X, Y, Z, T}, even, periodic in every direction
+ *     (an antiperiodic time boundary is a sign the caller puts on the links);
+ *   - complex numbers are interleaved (re, im);
+ *   - fine vector:   [nrhs][T][Z][Y][X][3]
+ *   - link field:    [4][T][Z][Y][X][3][3] complex128, mu = 0..3 is x,y,z,t,
+ *                    row-major 3x3
+ *   - coarse vector: [nrhs][Tc][Zc][Yc][Xc][2][Nvec], spin index 0 is the
+ *                    chirality eps = +1 projection, Tc = T / block etc.
+ *   - staggered phases eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y),
+ *     eta_3 = (-1)^(x+y+z); eps(x) = (-1)^(x+y+z+t).
+ *   - every pointer argument named "device" points to GPU memory of the
+ *     current HIP device; the library reads inputs, writes outputs and keeps
+ *     no reference to them after the call, except the two workspaces passed to
+ *     mg_setup, which must stay allocated until mg_destroy.
+ *   - stream: a hipStream_t passed as void* (NULL = the null stream).  All
+ *     work is enqueued on it.  mg_apply_*, mg_restrict and mg_prolong return
+ *     without waiting; mg_setup, mg_solve and mg_cg_solve synchronise the
+ *     stream before returning (they fill host-side results).
+ *   - the library never allocates device memory; it carves everything it
+ *     needs from the caller's workspaces (sizes from mg_workspace_bytes).
+ *   - errors: every function returns an mg_status; MG_OK is 0.  Arguments are
+ *     validated before any launch.  mg_last_error() gives a thread-local
+ *     message for the last failure.  No C++ exception crosses this boundary.
+ *   - one context is single-threaded; distinct contexts are independent.
+ */
+#ifndef MGSTAG_H
+#define MGSTAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_ctx_s* mg_ctx;
+
+typedef enum {
+  MG_OK = 0,
+  MG_E_ARG = 1,        /* bad pointer, size or enum value */
+  MG_E_CONFIG = 2,     /* inconsistent parameters (odd extents, block not dividing, ...) */
+  MG_E_ALIGN = 3,      /* pointer not 16-byte aligned */
+  MG_E_RANK = 4,       /* near-null vectors numerically rank deficient on some block */
+  MG_E_NOCONV = 5,     /* solver hit its iteration cap; x holds the last iterate */
+  MG_E_NONFINITE = 6,  /* NaN or Inf in a right-hand side or a residual */
+  MG_E_HIP = 7,        /* a HIP runtime call failed */
+  MG_E_STATE = 8,      /* call not valid in the context's current state */
+  MG_E_WORKSPACE = 9   /* workspace smaller than mg_workspace_bytes asked for */
+} mg_status;
+
+/* element types of vectors and stored operators */
+typedef enum { MG_C128 = 0, MG_C64 = 1, MG_CBF16 = 2, MG_CF16 = 3 } mg_dtype;
+
+/* Multigrid parameters; defaults follow Table 1 of the paper where it gives
+ * one (smoother CA-GCR(8), inner solves 0.25 or 8 iterations, setup CGNE to
+ * 1e-6 or 2000 iterations).  mg_default_params fills every field. */
+typedef struct {
+  int32_t dims[4];           /* X, Y, Z, T: even, >= 4 */
+  double c1, c3;             /* one-hop and three-hop coefficients: naive (1, 0), HISQ-style (9/8, -1/24) */
+  int32_t kd_naik;           /* 1: keep the Naik term inside the KD level; 0: truncated KD operator (Sec. 3.1) */
+  double mass0;              /* mass the hierarchy (KD inverse, null vectors, coarse operators) is built at */
+  int32_t nagg;              /* aggregation levels after the KD level: 1 or 2 */
+  int32_t block[2][4];       /* aggregation blocks per level (level 1: even extents) */
+  int32_t nvec[2];           /* near-null vectors per level (<= 128) */
+  int32_t setup_maxiter[2];  /* CGNE iteration cap per level */
+  double setup_tol[2];       /* CGNE tolerance ||A phi|| / ||A phi0|| per level */
+  int32_t smoother_s;        /* CA-GCR basis size (<= 8) */
+  double inner_tol;          /* inner-level GCR: stop at ||r|| <= inner_tol ||r_in|| ... */
+  int32_t inner_maxiter;     /* ... or after this many iterations (<= 16) */
+  double coarsest_tol;       /* coarsest level GCR tolerance */
+  int32_t coarsest_maxiter;  /* coarsest level GCR iteration cap (<= 16 per restart cycle) */
+  int32_t coarsest_restarts; /* restart cycles on the coarsest level (>= 1) */
+  int32_t outer_nkrylov;     /* outer GCR restart length (<= 16) */
+  int32_t outer_maxiter;     /* outer GCR iteration cap */
+  double reliable_delta;     /* outer GCR recomputes r = b - D x when ||r|| < delta * ||r at last recompute|| */
+  int32_t fine_prec;         /* MG_C128 or MG_C64: precision of the K-cycle on levels 0 and 1 */
+  int32_t coarse_prec;       /* MG_C128 or MG_C64: precision of the coarse levels */
+  int32_t max_nrhs;          /* largest nrhs * nmass a solve or apply will be given */
+  int32_t max_nmass;         /* masses with their own KD inverse (>= 1; slot 0 is mass0) */
+  uint64_t seed;             /* seed of the GPU-generated null-vector starts */
+} mg_params;
+
+typedef struct {
+  int32_t outer_iters;       /* outer GCR iterations (CG: iterations) */
+  int32_t reliable_updates;  /* recomputations of the true residual */
+  int32_t level_iters[4];    /* total inner iterations per level 1..3 (index 0: level 1) */
+  double true_rel_residual;  /* ||b - D(m) x|| / ||b|| recomputed in FP64 at exit */
+  double seconds;            /* wall time of this system's solve (shared by a batch) */
+  int32_t status;            /* mg_status of this system */
+} mg_solve_info;
+
+/* Fill *p with defaults for the given extents: HISQ-style coefficients,
+ * KD with Naik, two aggregations (4^4, Nvec 64 then 2^4, Nvec 96), FP32
+ * fine and coarse levels, Table 1 solver settings. */
+void mg_default_params(mg_params* p, const int32_t dims[4]);
+
+/* Device bytes the library needs: `persistent` must outlive the context
+ * (links, KD inverses, P, coarse operators, null vectors), `scratch` is
+ * solver workspace.  Validates *p (MG_E_CONFIG on inconsistency). */
+mg_status mg_workspace_bytes(const mg_params* p, size_t* persistent, size_t* scratch);
+
+/* Build the hierarchy (Sec. 2.1, Sec. 2.3; setup is excluded from the
+ * paper's time-to-solution, Sec. 3.2).
+ *   fat, naik: device, complex128 link fields (naik ignored when c3 == 0)
+ *   null_vectors: device array of nagg pointers (host array) to complex128
+ *     near-null vectors, level 1 as [nvec[0]][T][Z][Y][X][3], level 2 as
+ *     [nvec[1]][Tc][Zc][Yc][Xc][2][nvec[0]]; pass NULL (or a NULL entry) to
+ *     generate that level on the GPU by CGNE on the level's operator
+ *     (Sec. 2.1, Table 1).
+ *   persistent_ws / scratch_ws: device, caller-owned, at least the sizes
+ *     reported by mg_workspace_bytes (MG_E_WORKSPACE otherwise), 256-byte
+ *     aligned.
+ * Returns MG_E_RANK when block orthonormalisation finds a dependent set. */
+mg_status mg_setup(const mg_params* p, const void* fat, const void* naik, const void* const* null_vectors,
+                   void* persistent_ws, size_t persistent_bytes, void* scratch_ws, size_t scratch_bytes,
+                   void* stream, mg_ctx* out);
+
+/* Fine-level operator applications on a fine vector (device in/out,
+ * distinct buffers), dtype MG_C128 or MG_C64:
+ *   op 0: D(m) x                        (Sec. 2.2; HISQ stencil)
+ *   op 1: A x = (B + m)^{-1} D x        (Sec. 2.2 Eq. 2, Sec. 3.1; Naik per kd_naik)
+ *   op 2: (B + m)^{-1} x                (the KD block inverse alone, Sec. 3.1)
+ *   op 3: D(m)^dag x
+ * For ops 1 and 2, mass must have a KD inverse (mass0 or a mass of an
+ * earlier mg_solve); MG_E_ARG otherwise. */
+mg_status mg_apply_dslash(mg_ctx ctx, int32_t op, double mass, int32_t dtype, const void* in, void* out,
+                          int32_t nrhs, void* stream);
+
+/* Coarse operator of level 2 (P1^dag A P1) or 3 (P2^dag A2 P2) on a coarse
+ * vector of that level (Sec. 2.1; 9-point stencil of dense blocks, Sec. 3.1).
+ * dtype MG_C128 uses the FP64 operator; MG_C64 the coarse_prec operator. */
+mg_status mg_apply_coarse(mg_ctx ctx, int32_t level, int32_t dtype, const void* in, void* out, int32_t nrhs,
+                          void* stream);
+
+/* Restriction R = P^dag from level `level` (1: fine, 2: first coarse) to the
+ * next level (Sec. 2.1).  dtype MG_C128 or MG_C64. */
+mg_status mg_restrict(mg_ctx ctx, int32_t level, int32_t dtype, const void* fine, void* coarse, int32_t nrhs,
+                      void* stream);
+
+/* Prolongation P from level `level` + 1 to `level`; accumulate = 1 adds into
+ * the fine vector instead of overwriting it. */
+mg_status mg_prolong(mg_ctx ctx, int32_t level, int32_t dtype, const void* coarse, void* fine,
+                     int32_t accumulate, int32_t nrhs, void* stream);
+
+/* Solve D(m_j) x = b for every mass m_j and right-hand side by the
+ * MG-preconditioned GCR of Sec. 2.1 (K-cycle, Table 1), FP64 outer solver,
+ * to ||b - D x|| / ||b|| <= tol (Sec. 3.2).  The hierarchy built at mass0 is
+ * reused for every mass (Sec. 3.2-3.3); each mass gets its own exact KD
+ * inverse.
+ *   b: device complex128 [nrhs][T][Z][Y][X][3]
+ *   x: device complex128 [nmass][nrhs][T][Z][Y][X][3] (overwritten)
+ *   info: host array of nmass * nrhs entries (mass-major)
+ * nmass * nrhs <= max_nrhs; distinct masses <= max_nmass.  Returns MG_OK
+ * when every system converged, MG_E_NOCONV otherwise. */
+mg_status mg_solve(mg_ctx ctx, const double* masses, int32_t nmass, const void* b, void* x, int32_t nrhs,
+                   double tol, mg_solve_info* info, void* stream);
+
+/* Baseline: single-parity (even) Schur CG in FP64 on the same stencil kernel
+ * (Sec. 3.2): (m^2 - K_eo K_oe) x_e = m b_e - K_eo b_o, x_o = (b_o - K_oe x_e)/m,
+ * iterated to ||r_e|| <= m tol ||b|| and confirmed on the true residual.
+ * Same layouts and semantics as mg_solve; maxiter caps the CG iterations. */
+mg_status mg_cg_solve(mg_ctx ctx, const double* masses, int32_t nmass, const void* b, void* x, int32_t nrhs,
+                      double tol, int32_t maxiter, mg_solve_info* info, void* stream);
+
+/* Copy internal data to a caller buffer (device dst of at least `bytes`):
+ *   what 0: fine index tables, int32 [V][22] (neighbours x+-mu, x+-3mu, eta
+ *           bits, eps, hypercube, hypercube-local index, aggregate, chirality)
+ *   what 1: near-null vectors of `level` (1 or 2), complex128, layout as the
+ *           null_vectors argument of mg_setup
+ *   what 2: coarse links of `level` (2 or 3), complex128 [site][9][n][n]
+ *           row-major blocks, n = 2 Nvec, d = 0 self, 1 + 2 mu: +mu, 2 + 2 mu: -mu
+ * Returns the needed size in *bytes_needed when dst is NULL. */
+mg_status mg_export(mg_ctx ctx, int32_t what, int32_t level, void* dst, size_t bytes, size_t* bytes_needed,
+                    void* stream);
+
+mg_status mg_destroy(mg_ctx ctx);
+
+const char* mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGSTAG_H */

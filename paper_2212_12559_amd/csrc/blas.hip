@@ -1,0 +1,278 @@
+// Krylov BLAS for the GCR / CA-GCR / CG drivers.  Vectors are batches of
+// nrhs independent systems, [nrhs][n] complex; every scalar lives on the
+// device as one double2 per (slot, rhs), so the drivers never wait on the host
+// except for their convergence tests.  All reductions accumulate in FP64 and
+// combine their per-block partial sums in a fixed order (bit-reproducible).
+#include "kernels.hpp"
+
+namespace mg {
+
+__device__ __forceinline__ double wsum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// partial sums of <x_p, y_p> (conjugate on x) for p < np
+template <typename T, int MAXP>
+__global__ void __launch_bounds__(256) pairdot_kernel(const PairDotArgs<T> a, double2* __restrict__ part,
+                                                      int nblk) {
+  __shared__ double2 red[4][MAXP];
+  const int r = blockIdx.y;
+  const int64_t off = (int64_t)r * a.stride;
+  double2 acc[MAXP];
+#pragma unroll
+  for (int p = 0; p < MAXP; ++p) acc[p] = make_double2(0.0, 0.0);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.n; e += (int64_t)nblk * 256) {
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p) {
+      if (p < a.np) {
+        const double2 x = to_d2(a.x[p][off + e]);
+        const double2 y = to_d2(a.y[p][off + e]);
+        cfmac(acc[p], x, y);
+      }
+    }
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int p = 0; p < MAXP; ++p) {
+    if (p < a.np) {
+      const double sx = wsum(acc[p].x), sy = wsum(acc[p].y);
+      if (lane == 0) red[wave][p] = make_double2(sx, sy);
+    }
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < a.np; p += 256) {
+    double2 s = red[0][p];
+    for (int w = 1; w < 4; ++w) { s.x += red[w][p].x; s.y += red[w][p].y; }
+    part[((int64_t)p * a.nrhs + r) * nblk + blockIdx.x] = s;
+  }
+}
+
+// res[p][r] = (sum of partials) (+ scale)
+__global__ void finalize_kernel(const double2* __restrict__ part, int nblk, int np, int nrhs,
+                                double2* __restrict__ res, int ldr) {
+  const int r = blockIdx.x;
+  for (int p = threadIdx.x; p < np; p += blockDim.x) {
+    const double2* s = part + ((int64_t)p * nrhs + r) * nblk;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int b = 0; b < nblk; ++b) { acc.x += s[b].x; acc.y += s[b].y; }
+    res[(int64_t)p * ldr + r] = acc;
+  }
+}
+
+int reduce_blocks(int64_t n) {
+  int64_t b = (n + 2047) / 2048;
+  if (b < 1) b = 1;
+  if (b > 480) b = 480;
+  return (int)b;
+}
+
+template <typename T>
+void launch_pairdot(const PairDotArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
+  const int nblk = reduce_blocks(a.n);
+  dim3 grid(nblk, a.nrhs);
+  if (a.np <= 4) pairdot_kernel<T, 4><<<grid, 256, 0, st>>>(a, part, nblk);
+  else if (a.np <= 18) pairdot_kernel<T, 18><<<grid, 256, 0, st>>>(a, part, nblk);
+  else pairdot_kernel<T, kMaxPairs><<<grid, 256, 0, st>>>(a, part, nblk);
+  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, a.np, a.nrhs, res, ldr);
+}
+template void launch_pairdot<float2>(const PairDotArgs<float2>&, double2*, double2*, int, hipStream_t);
+template void launch_pairdot<double2>(const PairDotArgs<double2>&, double2*, double2*, int, hipStream_t);
+
+// out = sum_t coef_t(r) v_t  (out may alias one of the v_t)
+template <typename T>
+__global__ void __launch_bounds__(256) lincomb_kernel(const LinCombArgs<T> a) {
+  const int r = blockIdx.y;
+  const int64_t off = (int64_t)r * a.stride;
+  double2 cf[kMaxTerms];
+#pragma unroll
+  for (int t = 0; t < kMaxTerms; ++t) {
+    if (t < a.nt) {
+      double2 c = a.c[t] ? a.c[t][r] : a.cconst[t];
+      if (a.conj[t]) c.y = -c.y;
+      if (a.neg[t]) { c.x = -c.x; c.y = -c.y; }
+      if (a.mask && a.mask[r] == 0 && a.masked[t]) { c.x = 0.0; c.y = 0.0; }
+      cf[t] = c;
+    }
+  }
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.n; e += (int64_t)gridDim.x * 256) {
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < kMaxTerms; ++t) {
+      if (t < a.nt) {
+        const double2 v = to_d2(a.v[t][off + e]);
+        cfma(acc, cf[t], v);
+      }
+    }
+    a.out[off + e] = from_d2<T>(acc);
+  }
+}
+
+template <typename T>
+void launch_lincomb(const LinCombArgs<T>& a, hipStream_t st) {
+  int64_t b = (a.n + 255) / 256;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  dim3 grid((unsigned)b, a.nrhs);
+  lincomb_kernel<T><<<grid, 256, 0, st>>>(a);
+}
+template void launch_lincomb<float2>(const LinCombArgs<float2>&, hipStream_t);
+template void launch_lincomb<double2>(const LinCombArgs<double2>&, hipStream_t);
+
+template <typename TI, typename TO>
+__global__ void convert_kernel(TO* __restrict__ out, const TI* __restrict__ in, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = from_d2<TO>(to_d2(in[i]));
+}
+template <typename TI, typename TO>
+void launch_convert(TO* out, const TI* in, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  convert_kernel<TI, TO><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(out, in, n);
+}
+template void launch_convert<double2, float2>(float2*, const double2*, int64_t, hipStream_t);
+template void launch_convert<float2, double2>(double2*, const float2*, int64_t, hipStream_t);
+template void launch_convert<double2, double2>(double2*, const double2*, int64_t, hipStream_t);
+template void launch_convert<float2, float2>(float2*, const float2*, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------- scalars
+// GCR: after orthogonalisation, qq = <q, q>, qr = <q, r>.
+//   alpha = qr / qq (0 for masked systems), inv = 1 / sqrt(qq)
+// out slots: alpha, -alpha, inv
+__global__ void gcr_scalars_kernel(const double2* qq, const double2* qr, const int* mask, int nrhs,
+                                   double2* alpha, double2* nalpha, double2* inv) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const double q = qq[r].x;
+  const bool on = (mask == nullptr || mask[r] != 0) && q > 0.0;
+  double2 al = on ? make_double2(qr[r].x / q, qr[r].y / q) : make_double2(0.0, 0.0);
+  alpha[r] = al;
+  nalpha[r] = make_double2(-al.x, -al.y);
+  inv[r] = make_double2(q > 0.0 ? 1.0 / sqrt(q) : 0.0, 0.0);
+}
+void launch_gcr_scalars(const double2* qq, const double2* qr, const int* mask, int nrhs, double2* alpha,
+                        double2* nalpha, double2* inv, hipStream_t st) {
+  gcr_scalars_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(qq, qr, mask, nrhs, alpha, nalpha, inv);
+}
+
+// CA-GCR: solve the s x s normal equations G a = c per system by Cholesky
+// (FP64).  G[i][j] = <q_i, q_j> given for i <= j in slot order
+// (0,0),(0,1)..(0,s-1),(1,1),...; c_i = <q_i, r> in slots after them.
+// A pivot below 1e-13 of the largest diagonal truncates the basis there.
+__global__ void cagcr_solve_kernel(const double2* gram, int s, int nrhs, int ldr, const int* mask,
+                                   double2* coef) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double2 G[kMaxS][kMaxS];
+  double2 c[kMaxS];
+  int p = 0;
+  for (int i = 0; i < s; ++i)
+    for (int j = i; j < s; ++j) {
+      const double2 g = gram[(int64_t)(p++) * ldr + r];
+      G[i][j] = g;
+      G[j][i] = make_double2(g.x, -g.y);
+    }
+  for (int i = 0; i < s; ++i) c[i] = gram[(int64_t)(p++) * ldr + r];
+  double dmax = 0.0;
+  for (int i = 0; i < s; ++i) dmax = fmax(dmax, G[i][i].x);
+  int k = s;
+  // Cholesky G = L L^dag, L stored in G's lower triangle
+  for (int j = 0; j < s && k == s; ++j) {
+    double d = G[j][j].x;
+    for (int q = 0; q < j; ++q) d -= G[j][q].x * G[j][q].x + G[j][q].y * G[j][q].y;
+    if (!(d > 1e-13 * dmax)) { k = j; break; }
+    const double ljj = sqrt(d);
+    G[j][j] = make_double2(ljj, 0.0);
+    for (int i = j + 1; i < s; ++i) {
+      double2 v = G[i][j];
+      for (int q = 0; q < j; ++q) {   // v -= L[i][q] conj(L[j][q])
+        const double2 a = G[i][q], b = G[j][q];
+        v.x -= a.x * b.x + a.y * b.y;
+        v.y -= a.y * b.x - a.x * b.y;
+      }
+      G[i][j] = make_double2(v.x / ljj, v.y / ljj);
+    }
+  }
+  double2 y[kMaxS];
+  for (int i = 0; i < k; ++i) {   // L y = c
+    double2 v = c[i];
+    for (int q = 0; q < i; ++q) {
+      const double2 a = G[i][q], b = y[q];
+      v.x -= a.x * b.x - a.y * b.y;
+      v.y -= a.x * b.y + a.y * b.x;
+    }
+    y[i] = make_double2(v.x / G[i][i].x, v.y / G[i][i].x);
+  }
+  for (int i = k - 1; i >= 0; --i) {   // L^dag a = y
+    double2 v = y[i];
+    for (int q = i + 1; q < k; ++q) {  // v -= conj(L[q][i]) a[q]
+      const double2 a = G[q][i], b = y[q];
+      v.x -= a.x * b.x + a.y * b.y;
+      v.y -= a.x * b.y - a.y * b.x;
+    }
+    y[i] = make_double2(v.x / G[i][i].x, v.y / G[i][i].x);
+  }
+  const bool on = mask == nullptr || mask[r] != 0;
+  for (int i = 0; i < s; ++i) coef[(int64_t)i * ldr + r] = (on && i < k) ? y[i] : make_double2(0.0, 0.0);
+}
+void launch_cagcr_solve(const double2* gram, int s, int nrhs, int ldr, const int* mask, double2* coef,
+                        hipStream_t st) {
+  cagcr_solve_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(gram, s, nrhs, ldr, mask, coef);
+}
+
+// CG scalars: alpha = rr / pAp, -alpha; beta = rr_new / rr (rr updated in place)
+__global__ void cg_alpha_kernel(const double2* rr, const double2* pap, const int* mask, int nrhs, double2* alpha,
+                                double2* nalpha) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const bool on = (mask == nullptr || mask[r] != 0) && pap[r].x > 0.0;
+  const double a = on ? rr[r].x / pap[r].x : 0.0;
+  alpha[r] = make_double2(a, 0.0);
+  nalpha[r] = make_double2(-a, 0.0);
+}
+__global__ void cg_beta_kernel(double2* rr, const double2* rrnew, const int* mask, int nrhs, double2* beta) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const bool on = (mask == nullptr || mask[r] != 0) && rr[r].x > 0.0;
+  beta[r] = make_double2(on ? rrnew[r].x / rr[r].x : 0.0, 0.0);
+  if (on) rr[r] = rrnew[r];
+}
+void launch_cg_alpha(const double2* rr, const double2* pap, const int* mask, int nrhs, double2* alpha,
+                     double2* nalpha, hipStream_t st) {
+  cg_alpha_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(rr, pap, mask, nrhs, alpha, nalpha);
+}
+void launch_cg_beta(double2* rr, const double2* rrnew, const int* mask, int nrhs, double2* beta, hipStream_t st) {
+  cg_beta_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(rr, rrnew, mask, nrhs, beta);
+}
+
+}  // namespace mg
+
+namespace mg {
+
+// Seeded standard complex normal numbers (E|z|^2 = 1): a splitmix64 hash of
+// (seed, index) gives two uniforms, Box-Muller gives the pair.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+template <typename T>
+__global__ void random_normal_kernel(T* out, int64_t n, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t h1 = splitmix64(seed ^ splitmix64((uint64_t)i * 2 + 1));
+  const uint64_t h2 = splitmix64(h1 + 0x632BE59BD9B4E019ull);
+  const double u1 = ((h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double u2 = ((h2 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double rad = sqrt(-log(u1));          // sqrt(-2 log u1) / sqrt(2)
+  const double ang = 6.283185307179586 * u2;
+  out[i] = from_d2<T>(make_double2(rad * cos(ang), rad * sin(ang)));
+}
+template <typename T>
+void launch_random_normal(T* out, int64_t n, uint64_t seed, hipStream_t st) {
+  random_normal_kernel<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(out, n, seed);
+}
+template void launch_random_normal<float2>(float2*, int64_t, uint64_t, hipStream_t);
+template void launch_random_normal<double2>(double2*, int64_t, uint64_t, hipStream_t);
+
+}  // namespace mg

@@ -1,0 +1,293 @@
+// Fine staggered / HISQ operator (Sec. 2.2, Sec. 3.1):
+//   (D x)(x) = m x(x) + sum_mu [ W'_mu(x) x(x+mu) - W'_mu(x-mu)^dag x(x-mu)
+//                              + N'_mu(x) x(x+3mu) - N'_mu(x-3mu)^dag x(x-3mu) ]
+// with W' = (c1/2) eta_mu W and N' = (c3/2) eta_mu N folded in at set-up.
+//
+// One thread per output site; the links of a direction are stored as nine
+// site-contiguous arrays so every load of a wavefront is one contiguous
+// 512 B (FP32) or 1 KiB (FP64) segment; the backward links W'(x-mu) are the
+// same arrays read at the neighbour, served from L2 / Infinity Cache.  A tile
+// of NR right-hand sides shares every link load.
+#include "kernels.hpp"
+
+namespace mg {
+
+template <typename R, int NR, bool NAIK, bool CB, bool PIECE>
+__global__ void __launch_bounds__(256) dslash_kernel(const DslashArgs<R> a) {
+  using T = cplx<R>;
+  const int64_t V = a.g.V;
+  const int64_t nout = CB ? V / 2 : V;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nout) return;
+  const int r0 = blockIdx.y * NR;
+  const int nr = (a.nrhs - r0) < NR ? (a.nrhs - r0) : NR;
+  int c[4];
+  int64_t s;
+  if (CB) {
+    const int hx = a.g.L[0] / 2;
+    int64_t rest = tid / hx;
+    c[1] = (int)(rest % a.g.L[1]); rest /= a.g.L[1];
+    c[2] = (int)(rest % a.g.L[2]);
+    c[3] = (int)(rest / a.g.L[2]);
+    c[0] = 2 * (int)(tid % hx) + ((c[1] + c[2] + c[3] + a.parity) & 1);
+    s = site_index(c, a.g);
+  } else {
+    s = tid;
+    site_coords(s, a.g, c);
+  }
+  T acc[NR][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { acc[r][i].x = 0; acc[r][i].y = 0; }
+
+  const T* in = a.in + (int64_t)r0 * a.in_stride;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+    for (int h = 0; h < (NAIK ? 2 : 1); ++h) {
+      const int hop = h ? 3 : 1;
+      const T* L = (h ? a.lng : a.fat) + (int64_t)mu * 9 * V;
+      bool use_f = true, use_b = true;
+      if (PIECE) {
+        const int u = c[mu] % a.blk[mu];
+        const int pf = (u + hop >= a.blk[mu]) ? 1 + 2 * mu : 0;
+        const int pb = (u - hop < 0) ? 2 + 2 * mu : 0;
+        use_f = (pf == a.piece);
+        use_b = (pb == a.piece);
+      }
+      if (use_f) {
+        const int64_t sf = site_shift(c, mu, hop, a.g);
+        const int64_t vi = CB ? (sf >> 1) * 3 : sf * 3;
+        T U[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) U[k] = L[k * V + s];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r < nr) {
+            const T* v = in + r * a.in_stride + vi;
+            const T v0 = v[0], v1 = v[1], v2 = v[2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              cfma(acc[r][i], U[3 * i + 0], v0);
+              cfma(acc[r][i], U[3 * i + 1], v1);
+              cfma(acc[r][i], U[3 * i + 2], v2);
+            }
+          }
+        }
+      }
+      if (use_b) {
+        const int64_t sb = site_shift(c, mu, -hop, a.g);
+        const int64_t vi = CB ? (sb >> 1) * 3 : sb * 3;
+        T U[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) U[k] = L[k * V + sb];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r < nr) {
+            const T* v = in + r * a.in_stride + vi;
+            const T v0 = v[0], v1 = v[1], v2 = v[2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              T t; t.x = 0; t.y = 0;
+              cfmac(t, U[0 + i], v0);
+              cfmac(t, U[3 + i], v1);
+              cfmac(t, U[6 + i], v2);
+              acc[r][i].x -= t.x;
+              acc[r][i].y -= t.y;
+            }
+          }
+        }
+      }
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nr) continue;
+    if (CB) {
+      const int64_t o = (int64_t)(r0 + r) * a.out_stride + (s >> 1) * 3;
+      const R bc = a.b_coef;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        T res;
+        res.x = bc * acc[r][i].x;
+        res.y = bc * acc[r][i].y;
+        if (a.xs) {
+          const T xv = a.xs[(int64_t)(r0 + r) * a.xs_stride + (s >> 1) * 3 + i];
+          res.x = fma(a.a_coef, xv.x, res.x);
+          res.y = fma(a.a_coef, xv.y, res.y);
+        }
+        a.out[o + i] = res;
+      }
+    } else {
+      const R m = a.mass_rhs ? a.mass_rhs[r0 + r] : a.mass;
+      const bool with_mass = !PIECE || a.piece == 0;
+      const R sg = (a.eps_out && site_parity(c)) ? R(-1) : R(1);
+      const T* xin = in + r * a.in_stride + s * 3;
+      const int64_t o = (int64_t)(r0 + r) * a.out_stride + s * 3;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        T res = acc[r][i];
+        if (with_mass) {
+          const T xv = xin[i];
+          res.x = fma(m, xv.x, res.x);
+          res.y = fma(m, xv.y, res.y);
+        }
+        res.x *= sg;
+        res.y *= sg;
+        a.out[o + i] = res;
+      }
+    }
+  }
+}
+
+template <typename R, int NR>
+static void launch_nr(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st) {
+  const int64_t nout = cb ? a.g.V / 2 : a.g.V;
+  dim3 grid((unsigned)((nout + 255) / 256), (unsigned)((a.nrhs + NR - 1) / NR));
+  dim3 block(256);
+  if (piece) {
+    if (naik) dslash_kernel<R, NR, true, false, true><<<grid, block, 0, st>>>(a);
+    else dslash_kernel<R, NR, false, false, true><<<grid, block, 0, st>>>(a);
+  } else if (cb) {
+    if (naik) dslash_kernel<R, NR, true, true, false><<<grid, block, 0, st>>>(a);
+    else dslash_kernel<R, NR, false, true, false><<<grid, block, 0, st>>>(a);
+  } else {
+    if (naik) dslash_kernel<R, NR, true, false, false><<<grid, block, 0, st>>>(a);
+    else dslash_kernel<R, NR, false, false, false><<<grid, block, 0, st>>>(a);
+  }
+}
+
+template <typename R>
+void launch_dslash(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st) {
+  if (a.nrhs <= 0 || a.g.V <= 0) return;
+  if (a.nrhs == 1) launch_nr<R, 1>(a, naik, cb, piece, st);
+  else launch_nr<R, 4>(a, naik, cb, piece, st);
+}
+template void launch_dslash<float>(const DslashArgs<float>&, bool, bool, bool, hipStream_t);
+template void launch_dslash<double>(const DslashArgs<double>&, bool, bool, bool, hipStream_t);
+
+// Canonical links [4][T][Z][Y][X][3][3] (complex128) -> internal structure of
+// arrays with (c/2) eta_mu(x) folded in; FP64 and FP32 copies.
+__global__ void pack_links_kernel(const double2* __restrict__ src, double2* __restrict__ d64,
+                                  float2* __restrict__ d32, Geom g, double coef) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= 4 * g.V) return;
+  const int mu = (int)(tid / g.V);
+  const int64_t s = tid - (int64_t)mu * g.V;
+  int c[4];
+  site_coords(s, g, c);
+  const double f = coef * stag_eta(c, mu);
+  for (int k = 0; k < 9; ++k) {
+    const double2 v = src[tid * 9 + k];
+    const double2 w = make_double2(f * v.x, f * v.y);
+    d64[((int64_t)mu * 9 + k) * g.V + s] = w;
+    if (d32) d32[((int64_t)mu * 9 + k) * g.V + s] = make_float2((float)w.x, (float)w.y);
+  }
+}
+
+void launch_pack_links(const double2* src, double2* d64, float2* d32, const Geom& g, double coef,
+                       hipStream_t st) {
+  const int64_t n = 4 * g.V;
+  pack_links_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, d64, d32, g, coef);
+}
+
+// Index tables of the fine lattice exactly as the kernels compute them, for
+// the bit-exact comparison with the oracle's definitions.  Per site, int32:
+//   [0..3] x+mu  [4..7] x-mu  [8..11] x+3mu  [12..15] x-3mu
+//   [16] eta bits (bit mu set when eta_mu = -1)  [17] epsilon (+1/-1)
+//   [18] hypercube  [19] hypercube-local index  [20] aggregate  [21] chirality
+__global__ void export_fine_index_kernel(int32_t* __restrict__ out, Geom g, Agg A) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  int c[4];
+  site_coords(s, g, c);
+  int32_t* o = out + s * 22;
+  for (int mu = 0; mu < 4; ++mu) {
+    o[mu] = (int32_t)site_shift(c, mu, 1, g);
+    o[4 + mu] = (int32_t)site_shift(c, mu, -1, g);
+    o[8 + mu] = (int32_t)site_shift(c, mu, 3, g);
+    o[12 + mu] = (int32_t)site_shift(c, mu, -3, g);
+  }
+  int bits = 0;
+  for (int mu = 0; mu < 4; ++mu) bits |= (stag_eta(c, mu) < 0 ? 1 : 0) << mu;
+  o[16] = bits;
+  o[17] = site_parity(c) ? -1 : 1;
+  int64_t hc;
+  int sl;
+  hc_of_site(c, g, &hc, &sl);
+  o[18] = (int32_t)hc;
+  o[19] = sl;
+  int ac[4];
+  for (int mu = 0; mu < 4; ++mu) ac[mu] = c[mu] / A.b[mu];
+  o[20] = (int32_t)(ac[0] + A.cd[0] * (ac[1] + A.cd[1] * (ac[2] + A.cd[2] * ac[3])));
+  o[21] = site_parity(c);
+}
+
+void launch_export_fine_index(int32_t* out, const Geom& g, const Agg& A, hipStream_t st) {
+  export_fine_index_kernel<<<(unsigned)((g.V + 255) / 256), 256, 0, st>>>(out, g, A);
+}
+
+// Multiply by epsilon(x) (per site sign), in place or out of place.
+template <typename T>
+__global__ void eps_kernel(T* out, const T* in, Geom g, int64_t nrhs) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= g.V * 3 * nrhs) return;
+  const int64_t s = (tid / 3) % g.V;
+  int c[4];
+  site_coords(s, g, c);
+  T v = in[tid];
+  if (site_parity(c)) { v.x = -v.x; v.y = -v.y; }
+  out[tid] = v;
+}
+template <typename T>
+void launch_eps(T* out, const T* in, const Geom& g, int nrhs, hipStream_t st) {
+  const int64_t n = g.V * 3 * nrhs;
+  eps_kernel<T><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(out, in, g, nrhs);
+}
+template void launch_eps<float2>(float2*, const float2*, const Geom&, int, hipStream_t);
+template void launch_eps<double2>(double2*, const double2*, const Geom&, int, hipStream_t);
+
+}  // namespace mg
+
+namespace mg {
+
+// Full-lattice batch [nrhs][V][3] <-> checkerboard halves [nrhs][V/2][3]
+// (index site >> 1 within each parity).
+__global__ void cb_split_kernel(const double2* __restrict__ full, double2* __restrict__ ev,
+                                double2* __restrict__ od, Geom g, int nrhs) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= g.V * 3 * nrhs) return;
+  const int64_t r = tid / (g.V * 3);
+  const int64_t e = tid - r * g.V * 3;
+  const int64_t s = e / 3;
+  const int col = (int)(e - s * 3);
+  int c[4];
+  site_coords(s, g, c);
+  double2* dst = site_parity(c) ? od : ev;
+  dst[r * (g.V / 2) * 3 + (s >> 1) * 3 + col] = full[tid];
+}
+__global__ void cb_merge_kernel(double2* __restrict__ full, const double2* __restrict__ ev,
+                                const double2* __restrict__ od, Geom g, int nrhs) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= g.V * 3 * nrhs) return;
+  const int64_t r = tid / (g.V * 3);
+  const int64_t e = tid - r * g.V * 3;
+  const int64_t s = e / 3;
+  const int col = (int)(e - s * 3);
+  int c[4];
+  site_coords(s, g, c);
+  const double2* src = site_parity(c) ? od : ev;
+  full[tid] = src[r * (g.V / 2) * 3 + (s >> 1) * 3 + col];
+}
+void launch_cb_split(const double2* full, double2* ev, double2* od, const Geom& g, int nrhs, hipStream_t st) {
+  const int64_t n = g.V * 3 * nrhs;
+  cb_split_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(full, ev, od, g, nrhs);
+}
+void launch_cb_merge(double2* full, const double2* ev, const double2* od, const Geom& g, int nrhs, hipStream_t st) {
+  const int64_t n = g.V * 3 * nrhs;
+  cb_merge_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(full, ev, od, g, nrhs);
+}
+
+}  // namespace mg

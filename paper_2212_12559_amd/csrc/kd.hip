@@ -1,0 +1,186 @@
+// Kahler-Dirac block preconditioner (Sec. 2.2 Eq. 1-2, Sec. 3.1).
+//
+// B holds the one-hop terms of D inside each 2^4 hypercube; the paper stores
+// the explicit (B + m)^{-1}, one 48 x 48 complex matrix per hypercube, and
+// applies it in a kernel of its own after the stencil.
+//
+// Set-up (FP64): B is anti-Hermitian, so (B + m)(m - B) = m^2 + B^dag B = M,
+// a Hermitian positive definite matrix; (B + m)^{-1} = (m - B) M^{-1}.
+// M is inverted by Gauss-Jordan without pivoting (safe for HPD), all in LDS,
+// one workgroup per hypercube.  This avoids pivoting; the oracle uses plain LU.
+//
+// Apply: one wavefront per hypercube, lane = row (48 of 64 lanes), the
+// matrix stored column-major so each column is one coalesced segment; the
+// hypercube's 48 input components are exchanged between lanes with
+// cross-lane shuffles.
+#include "kernels.hpp"
+
+namespace mg {
+
+__global__ void __launch_bounds__(256) kd_inverse_kernel(const double2* __restrict__ fat, Geom g,
+                                                         double mass, double2* __restrict__ out64,
+                                                         float2* __restrict__ out32) {
+  // Bs[u][mu][3 i + j]: the 3x3 block of B at block row u, block column u ^ (1 << mu)
+  __shared__ double2 Bs[16][4][9];
+  __shared__ double2 M[48][48];
+  const int64_t hc = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t V = g.V;
+  for (int e = tid; e < 16 * 4 * 9; e += 256) {
+    const int u = e / 36, mu = (e / 9) % 4, k = e % 9;
+    const int i = k / 3, j = k % 3;
+    double2 v;
+    if (((u >> mu) & 1) == 0) {
+      // forward hop x -> x + mu inside the cube: W'_mu(x)[i][j]
+      const int64_t x = hc_site(hc, u, g);
+      v = fat[((int64_t)mu * 9 + 3 * i + j) * V + x];
+    } else {
+      // backward hop x -> x - mu: -(W'_mu(x - mu)^dag)[i][j] = -conj(W'_mu(x - mu)[j][i])
+      const int64_t xm = hc_site(hc, u ^ (1 << mu), g);
+      const double2 w = fat[((int64_t)mu * 9 + 3 * j + i) * V + xm];
+      v = make_double2(-w.x, w.y);
+    }
+    Bs[u][mu][k] = v;
+  }
+  __syncthreads();
+  // M = m^2 + B^dag B; (B^dag B)[(s,i),(t,j)] = sum over block rows u adjacent to both s and t
+  for (int e = tid; e < 48 * 48; e += 256) {
+    const int a = e / 48, b = e % 48;
+    const int sa = a / 3, ia = a % 3, sb = b / 3, ib = b % 3;
+    double2 acc = make_double2(a == b ? mass * mass : 0.0, 0.0);
+    for (int mu = 0; mu < 4; ++mu) {
+      const int u = sa ^ (1 << mu);
+      const int d = u ^ sb;
+      if (__popc(d) != 1) continue;
+      const int nu = __ffs(d) - 1;
+      for (int k = 0; k < 3; ++k) cfmac(acc, Bs[u][mu][3 * k + ia], Bs[u][nu][3 * k + ib]);
+    }
+    M[a][b] = acc;
+  }
+  __syncthreads();
+  // Gauss-Jordan inversion in place, no pivoting
+  for (int k = 0; k < 48; ++k) {
+    const double2 p = M[k][k];
+    const double pn = p.x * p.x + p.y * p.y;
+    const double2 pinv = make_double2(p.x / pn, -p.y / pn);
+    __syncthreads();
+    if (tid < 48 && tid != k) M[k][tid] = cmul(M[k][tid], pinv);
+    __syncthreads();
+    for (int e = tid; e < 48 * 48; e += 256) {
+      const int i = e / 48, j = e % 48;
+      if (i != k && j != k) {
+        const double2 f = M[i][k];
+        const double2 t = M[k][j];
+        double2 v = M[i][j];
+        v.x -= f.x * t.x - f.y * t.y;
+        v.y -= f.x * t.y + f.y * t.x;
+        M[i][j] = v;
+      }
+    }
+    __syncthreads();
+    if (tid < 48 && tid != k) {
+      const double2 q = cmul(M[tid][k], pinv);
+      M[tid][k] = make_double2(-q.x, -q.y);
+    }
+    if (tid == 0) M[k][k] = pinv;
+    __syncthreads();
+  }
+  // (B + m)^{-1} = (m - B) M^{-1}, stored column-major: out[hc][col][row]
+  for (int e = tid; e < 48 * 48; e += 256) {
+    const int j = e / 48, i = e % 48;   // column j, row i
+    const int si = i / 3, ci = i % 3;
+    double2 acc = make_double2(mass * M[i][j].x, mass * M[i][j].y);
+    for (int mu = 0; mu < 4; ++mu) {
+      const int sn = si ^ (1 << mu);
+      for (int k = 0; k < 3; ++k) {
+        const double2 b = Bs[si][mu][3 * ci + k];
+        const double2 m = M[3 * sn + k][j];
+        acc.x -= b.x * m.x - b.y * m.y;
+        acc.y -= b.x * m.y + b.y * m.x;
+      }
+    }
+    const int64_t o = hc * 2304 + (int64_t)j * 48 + i;
+    out64[o] = acc;
+    if (out32) out32[o] = make_float2((float)acc.x, (float)acc.y);
+  }
+}
+
+void launch_kd_inverse(const double2* fat64, const Geom& g, double mass, double2* out64, float2* out32,
+                       hipStream_t st) {
+  const int64_t nhc = g.V / 16;
+  kd_inverse_kernel<<<(unsigned)nhc, 256, 0, st>>>(fat64, g, mass, out64, out32);
+}
+
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) kd_apply_kernel(const KdArgs<R> a) {
+  using T = cplx<R>;
+  const int lane = threadIdx.x & 63;
+  const int64_t hc = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nhc = a.g.V / 16;
+  if (hc >= nhc) return;
+  const int r0 = blockIdx.y * NR;
+  const int nr = (a.nrhs - r0) < NR ? (a.nrhs - r0) : NR;
+  const bool act = lane < 48;
+  const int sl = act ? lane / 3 : 0;
+  const int col = act ? lane - 3 * (lane / 3) : 0;
+  const int64_t site = hc_site(hc, sl, a.g);
+  const int64_t vi = site * 3 + col;
+  const bool odd = (__popc(sl) & 1) != 0;
+  const int slot = a.rhs_per_slot > 0 ? r0 / a.rhs_per_slot : 0;
+  const T* K = a.kinv + (int64_t)slot * a.slot_stride + hc * 2304;
+
+  T xr[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    T v;
+    v.x = 0; v.y = 0;
+    if (act && r < nr) {
+      v = a.in[(int64_t)(r0 + r) * a.in_stride + vi];
+      if (a.eps_in && odd) { v.x = -v.x; v.y = -v.y; }
+    }
+    xr[r] = v;
+  }
+  T acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) { acc[r].x = 0; acc[r].y = 0; }
+#pragma unroll 4
+  for (int j = 0; j < 48; ++j) {
+    T k;
+    if (act) k = K[j * 48 + lane];
+    else { k.x = 0; k.y = 0; }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T xj;
+      xj.x = __shfl(xr[r].x, j, 64);
+      xj.y = __shfl(xr[r].y, j, 64);
+      cfma(acc[r], k, xj);
+    }
+  }
+  if (!act) return;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nr) continue;
+    T v = acc[r];
+    if (a.eps_out && odd) { v.x = -v.x; v.y = -v.y; }
+    a.out[(int64_t)(r0 + r) * a.out_stride + vi] = v;
+  }
+}
+
+template <typename R>
+void launch_kd_apply(const KdArgs<R>& a, hipStream_t st) {
+  if (a.nrhs <= 0) return;
+  const int64_t nhc = a.g.V / 16;
+  const unsigned gx = (unsigned)((nhc + 3) / 4);
+  const bool tile4 = a.nrhs >= 4 && (a.rhs_per_slot <= 0 || a.rhs_per_slot % 4 == 0);
+  if (tile4) {
+    dim3 grid(gx, (unsigned)((a.nrhs + 3) / 4));
+    kd_apply_kernel<R, 4><<<grid, 256, 0, st>>>(a);
+  } else {
+    dim3 grid(gx, (unsigned)a.nrhs);
+    kd_apply_kernel<R, 1><<<grid, 256, 0, st>>>(a);
+  }
+}
+template void launch_kd_apply<float>(const KdArgs<float>&, hipStream_t);
+template void launch_kd_apply<double>(const KdArgs<double>&, hipStream_t);
+
+}  // namespace mg

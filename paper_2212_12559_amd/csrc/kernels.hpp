@@ -1,0 +1,146 @@
+// Kernel argument blocks and host-side launchers of the mgstag HIP library.
+#pragma once
+#include "common.hpp"
+
+namespace mg {
+
+constexpr int kMaxPairs = 48;   // pair dot products per reduction launch
+constexpr int kMaxTerms = 20;   // terms of one linear combination
+
+// ---------------------------------------------------------------- Dslash
+template <typename R>
+struct DslashArgs {
+  cplx<R>* out;
+  const cplx<R>* in;
+  const cplx<R>* xs;        // checkerboard mode: optional same-parity addend
+  const cplx<R>* fat;       // [4][9][V], (c1/2) eta folded in
+  const cplx<R>* lng;       // [4][9][V], (c3/2) eta folded in
+  Geom g;
+  int64_t in_stride, out_stride, xs_stride;   // per rhs, complex elements
+  int nrhs;
+  R mass;                   // full-lattice mode: out = mass * in + hops
+  const R* mass_rhs;        // optional per-rhs mass (device)
+  R a_coef, b_coef;         // checkerboard mode: out = a * xs + b * hops
+  int parity;               // checkerboard mode: output parity
+  int piece;                // Galerkin piece: 0 self, 1 + 2 mu (+mu face), 2 + 2 mu (-mu face)
+  int blk[4];               // aggregation block of the piece decomposition
+  int eps_out;              // multiply the result by epsilon(x)
+};
+template <typename R>
+void launch_dslash(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st);
+void launch_pack_links(const double2* src, double2* d64, float2* d32, const Geom& g, double coef,
+                       hipStream_t st);
+void launch_export_fine_index(int32_t* out, const Geom& g, const Agg& A, hipStream_t st);
+template <typename T>
+void launch_eps(T* out, const T* in, const Geom& g, int nrhs, hipStream_t st);
+void launch_cb_split(const double2* full, double2* ev, double2* od, const Geom& g, int nrhs, hipStream_t st);
+void launch_cb_merge(double2* full, const double2* ev, const double2* od, const Geom& g, int nrhs, hipStream_t st);
+
+// ---------------------------------------------------------------- KD
+template <typename R>
+struct KdArgs {
+  cplx<R>* out;
+  const cplx<R>* in;
+  const cplx<R>* kinv;      // [slot][hc][48][48], column-major blocks
+  Geom g;
+  int64_t in_stride, out_stride;
+  int nrhs;
+  int rhs_per_slot;         // rhs r uses slot r / rhs_per_slot (0: slot 0 for all)
+  int64_t slot_stride;
+  int eps_in, eps_out;      // (B+m)^{-dag} = eps (B+m)^{-1} eps
+};
+void launch_kd_inverse(const double2* fat64, const Geom& g, double mass, double2* out64, float2* out32,
+                       hipStream_t st);
+template <typename R>
+void launch_kd_apply(const KdArgs<R>& a, hipStream_t st);
+
+// ---------------------------------------------------------------- transfer
+template <typename R>
+struct RestrictArgs {
+  cplx<R>* out;
+  const cplx<R>* in;
+  const cplx<R>* pr;        // [agg][2][nrows][nvec]
+  Agg A;
+  int64_t in_stride, out_stride;
+  int64_t out_site_stride;  // complex elements between aggregates in the output (2 nvec normally)
+  int nrhs;
+};
+template <typename R>
+struct ProlongArgs {
+  cplx<R>* out;
+  const cplx<R>* in;        // coarse [nrhs][nagg][2][nvec]
+  const cplx<R>* pp;        // [agg][2][nvec][nrows]
+  Agg A;
+  int64_t in_stride, out_stride;
+  int nrhs;
+  int accumulate;
+  int unit_col;             // >= 0: prolong the unit coarse vector (sigma nvec + k == unit_col) on every aggregate
+};
+void launch_gather_null(const double2* nv, int64_t nflat, double2* pp, const Agg& A, hipStream_t st);
+void launch_block_orth(double2* pp, const Agg& A, int* status, hipStream_t st);
+void launch_p_layouts(const double2* pp64, double2* pr64, float2* pr32, float2* pp32, const Agg& A,
+                      hipStream_t st);
+template <typename R>
+void launch_restrict(const RestrictArgs<R>& a, hipStream_t st);
+template <typename R>
+void launch_prolong(const ProlongArgs<R>& a, hipStream_t st);
+
+// ---------------------------------------------------------------- coarse
+template <typename R, typename LT>
+struct CoarseArgs {
+  cplx<R>* out;
+  const cplx<R>* in;
+  const LT* links;          // [site][9][n][n] (col-major blocks)
+  Geom g;                   // coarse lattice
+  int n;                    // 2 nvec
+  int64_t in_stride, out_stride;
+  int nrhs;
+  int piece;
+  int blk[4];
+};
+template <typename R, typename LT>
+void launch_coarse(const CoarseArgs<R, LT>& a, bool piece, bool dag, hipStream_t st);
+void launch_convert_links(const double2* in, float2* out, int64_t n, hipStream_t st);
+void launch_export_links(const double2* in, double2* out, int64_t nsite, int n, hipStream_t st);
+
+// ---------------------------------------------------------------- BLAS
+template <typename T>
+struct PairDotArgs {
+  const T* x[kMaxPairs];
+  const T* y[kMaxPairs];
+  int np;
+  int64_t n, stride;
+  int nrhs;
+};
+template <typename T>
+struct LinCombArgs {
+  T* out;
+  const T* v[kMaxTerms];
+  const double2* c[kMaxTerms];   // per-rhs device coefficient, or null for cconst
+  double2 cconst[kMaxTerms];
+  int neg[kMaxTerms];
+  int conj[kMaxTerms];
+  int masked[kMaxTerms];
+  const int* mask;
+  int nt;
+  int64_t n, stride;
+  int nrhs;
+};
+int reduce_blocks(int64_t n);
+template <typename T>
+void launch_pairdot(const PairDotArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st);
+template <typename T>
+void launch_lincomb(const LinCombArgs<T>& a, hipStream_t st);
+template <typename TI, typename TO>
+void launch_convert(TO* out, const TI* in, int64_t n, hipStream_t st);
+void launch_gcr_scalars(const double2* qq, const double2* qr, const int* mask, int nrhs, double2* alpha,
+                        double2* nalpha, double2* inv, hipStream_t st);
+void launch_cagcr_solve(const double2* gram, int s, int nrhs, int ldr, const int* mask, double2* coef,
+                        hipStream_t st);
+void launch_cg_alpha(const double2* rr, const double2* pap, const int* mask, int nrhs, double2* alpha,
+                     double2* nalpha, hipStream_t st);
+void launch_cg_beta(double2* rr, const double2* rrnew, const int* mask, int nrhs, double2* beta, hipStream_t st);
+template <typename T>
+void launch_random_normal(T* out, int64_t n, uint64_t seed, hipStream_t st);
+
+}  // namespace mg

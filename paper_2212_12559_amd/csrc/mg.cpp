@@ -1,0 +1,519 @@
+// Host driver of the staggered KD multigrid: workspace plan, hierarchy
+// set-up (Sec. 2.1, Sec. 2.3, Table 1), operator dispatch and the Krylov
+// drivers.  Every vector operation is a kernel on the context's stream; the
+// host only reads one norm per system and iteration for convergence tests.
+#include "mg.hpp"
+
+#include <cmath>
+#include <cstring>
+
+namespace mg {
+
+#define HIPCHK(x)                                                                 \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess) throw Error{MG_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+static void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error{MG_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e)};
+}
+
+// ======================================================================= plan
+bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string* why) {
+  auto fail = [&](const std::string& s) { *why = s; return false; };
+  for (int mu = 0; mu < 4; ++mu)
+    if (p.dims[mu] < 4 || (p.dims[mu] & 1)) return fail("lattice extents must be even and >= 4");
+  if (p.nagg < 1 || p.nagg > 2) return fail("nagg must be 1 or 2");
+  if (p.fine_prec != MG_C128 && p.fine_prec != MG_C64) return fail("fine_prec must be MG_C128 or MG_C64");
+  if (p.coarse_prec != MG_C128 && p.coarse_prec != MG_C64) return fail("coarse_prec must be MG_C128 or MG_C64");
+  if (p.coarse_prec != p.fine_prec) return fail("coarse_prec must equal fine_prec (coarse vectors share the level-1 precision)");
+  if (p.smoother_s < 1 || p.smoother_s > kMaxS) return fail("smoother_s must be in 1..8");
+  if (p.inner_maxiter < 1 || p.inner_maxiter > kMaxNK) return fail("inner_maxiter must be in 1..16");
+  if (p.coarsest_maxiter < 1 || p.coarsest_maxiter > kMaxNK) return fail("coarsest_maxiter must be in 1..16");
+  if (p.coarsest_restarts < 1) return fail("coarsest_restarts must be >= 1");
+  if (p.outer_nkrylov < 1 || p.outer_nkrylov > kMaxNK) return fail("outer_nkrylov must be in 1..16");
+  if (p.outer_maxiter < 1) return fail("outer_maxiter must be >= 1");
+  if (p.max_nrhs < 1 || p.max_nmass < 1) return fail("max_nrhs and max_nmass must be >= 1");
+  if (!(p.mass0 > 0.0)) return fail("mass0 must be positive");
+  const bool naik_kd = p.c3 != 0.0 && p.kd_naik;
+  Geom g0{};
+  g0.V = 1;
+  for (int mu = 0; mu < 4; ++mu) { g0.L[mu] = p.dims[mu]; g0.V *= p.dims[mu]; }
+  Geom gcur = g0;
+  Agg A[2]{};
+  Geom gc[2]{};
+  int nin = 0;
+  for (int l = 0; l < p.nagg; ++l) {
+    Agg& a = A[l];
+    a.fine = gcur;
+    a.kind = l == 0 ? 1 : 2;
+    a.nvec = p.nvec[l];
+    a.nvec_in = nin;
+    int bs = 1;
+    Geom g{};
+    g.V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+      const int b = p.block[l][mu];
+      if (b < 1 || gcur.L[mu] % b) return fail("aggregation block must divide the lattice");
+      if (l == 0 && (b & 1)) return fail("first aggregation block must have even extents");
+      if (l == 0 && naik_kd && b < 3) return fail("Naik term with a first block below 3 reaches beyond neighbouring aggregates");
+      a.b[mu] = b;
+      a.cd[mu] = gcur.L[mu] / b;
+      g.L[mu] = a.cd[mu];
+      g.V *= a.cd[mu];
+      bs *= b;
+    }
+    a.nagg = g.V;
+    a.nrows = l == 0 ? bs / 2 * 3 : bs * nin;
+    if (a.nvec < 1 || a.nvec > 128) return fail("nvec must be in 1..128");
+    if (a.nvec > a.nrows) return fail("nvec exceeds the rows of an aggregate and chirality");
+    gc[l] = g;
+    gcur = g;
+    nin = a.nvec;
+  }
+  if (c) {
+    c->P = p;
+    c->g0 = g0;
+    c->nlev = 2 + p.nagg;
+    for (int l = 0; l < 2; ++l) { c->A[l] = A[l]; c->gc[l] = gc[l]; c->ncoarse[l] = 2 * A[l].nvec; }
+  }
+  const int64_t V = g0.V;
+  auto P = [&](size_t n) { return pers.take(n); };
+  // ---- persistent
+  void* fat64 = P(36 * V * 16);
+  void* fat32 = P(36 * V * 8);
+  void* lng64 = p.c3 != 0.0 ? P(36 * V * 16) : nullptr;
+  void* lng32 = p.c3 != 0.0 ? P(36 * V * 8) : nullptr;
+  const int64_t kslot = V / 16 * 2304;
+  void* kinv64 = P((size_t)p.max_nmass * kslot * 16);
+  void* kinv32 = P((size_t)p.max_nmass * kslot * 8);
+  void *nvp[2]{}, *pp64[2]{}, *pr64[2]{}, *pp32[2]{}, *pr32[2]{}, *cl64[2]{}, *cl32[2]{};
+  for (int l = 0; l < p.nagg; ++l) {
+    const int64_t nflat = A[l].nagg * 2 * A[l].nrows;   // dof of the aggregated level
+    const int64_t pel = nflat * A[l].nvec;
+    nvp[l] = P(pel * 16);
+    pp64[l] = P(pel * 16);
+    pr64[l] = P(pel * 16);
+    pp32[l] = P(pel * 8);
+    pr32[l] = P(pel * 8);
+    const int64_t n = 2 * A[l].nvec;
+    cl64[l] = P(gc[l].V * 9 * n * n * 16);
+    cl32[l] = P(gc[l].V * 9 * n * n * 8);
+  }
+  void* status = P(256);
+  // ---- scratch
+  const int ms = std::max({p.max_nrhs, p.nvec[0], p.nagg > 1 ? p.nvec[1] : 1});
+  auto S = [&](size_t n) { return scr.take(n); };
+  void* part = S((size_t)kMaxPairs * ms * 480 * 16);
+  void* scal = S((size_t)4 * kMaxSlots * ms * 16);
+  void* m64 = S((size_t)ms * 8);
+  void* m32 = S((size_t)ms * 4);
+  void* mask = S((size_t)4 * ms * 4);
+  const size_t solver_base = scr.off;
+  // solver buffers
+  LevelBufs L[4];
+  const int64_t nlv[4] = {V * 3, V * 3, p.nagg >= 1 ? gc[0].V * 2 * A[0].nvec : 0,
+                          p.nagg >= 2 ? gc[1].V * 2 * A[1].nvec : 0};
+  const int fp = p.fine_prec == MG_C128 ? P64 : P32;
+  const int cp = p.coarse_prec == MG_C128 ? P64 : P32;
+  const int precs[4] = {P64, fp, cp, cp};
+  const int nks[4] = {p.outer_nkrylov, p.inner_maxiter, p.inner_maxiter, p.inner_maxiter};
+  const int nlev = 2 + p.nagg;
+  Vec r0s, e0s;
+  for (int l = 0; l < nlev; ++l) {
+    LevelBufs& B = L[l];
+    B.prec = precs[l];
+    B.n = nlv[l];
+    const bool coarsest = l == nlev - 1;
+    B.nk = coarsest ? p.coarsest_maxiter : nks[l];
+    auto mk = [&](Vec& v, int prec) { v.prec = prec; v.n = B.n; v.p = S((size_t)p.max_nrhs * B.n * csize(prec)); };
+    mk(B.b, B.prec);
+    if (l > 0) mk(B.x, B.prec);
+    mk(B.r, B.prec);
+    for (int k = 0; k < B.nk; ++k) { mk(B.z[k], B.prec); mk(B.q[k], B.prec); }
+    if (!coarsest) {
+      // K-cycle / smoother work vectors, in the level's smoothing precision
+      const int sp = l == 0 ? fp : B.prec;
+      mk(B.t, sp);
+      mk(B.tmp, sp);
+      for (int j = 0; j < p.smoother_s; ++j) mk(B.sm[j], sp);
+    } else if (l == 1) {
+      mk(B.tmp, B.prec);
+    }
+    if (l == 0) {
+      r0s.prec = fp; r0s.n = B.n; r0s.p = S((size_t)p.max_nrhs * B.n * csize(fp));
+      e0s.prec = fp; e0s.n = B.n; e0s.p = S((size_t)p.max_nrhs * B.n * csize(fp));
+    }
+  }
+  const size_t solver_end = scr.off;
+  // set-up scratch aliases the solver buffers
+  scr.off = solver_base;
+  for (int l = 0; l < p.nagg; ++l) {
+    const int64_t n = l == 0 ? V * 3 : gc[0].V * 2 * A[0].nvec;
+    const int prec = l == 0 ? fp : cp;
+    for (int v = 0; v < 6; ++v) S((size_t)p.nvec[l] * n * csize(prec));   // CGNE
+    for (int v = 0; v < 3; ++v) S((size_t)n * 16);                          // Galerkin
+    scr.off = solver_base;
+  }
+  size_t setup_end = solver_base;
+  for (int l = 0; l < p.nagg; ++l) {
+    const int64_t n = l == 0 ? V * 3 : gc[0].V * 2 * A[0].nvec;
+    const int prec = l == 0 ? fp : cp;
+    size_t e = solver_base + 6 * (((size_t)p.nvec[l] * n * csize(prec) + 255) & ~(size_t)255) +
+               3 * (((size_t)n * 16 + 255) & ~(size_t)255) + 256;
+    setup_end = std::max(setup_end, e);
+  }
+  scr.off = std::max(solver_end, setup_end);
+  if (c) {
+    c->fat64 = (double2*)fat64; c->fat32 = (float2*)fat32;
+    c->lng64 = (double2*)lng64; c->lng32 = (float2*)lng32;
+    c->kinv64 = (double2*)kinv64; c->kinv32 = (float2*)kinv32;
+    c->kinv_slot = kslot;
+    c->kd_mass.assign(p.max_nmass, NAN);
+    for (int l = 0; l < 2; ++l) {
+      c->nv[l] = (double2*)nvp[l];
+      c->pp64[l] = (double2*)pp64[l]; c->pr64[l] = (double2*)pr64[l];
+      c->pp32[l] = (float2*)pp32[l]; c->pr32[l] = (float2*)pr32[l];
+      c->cl64[l] = (double2*)cl64[l]; c->cl32[l] = (float2*)cl32[l];
+    }
+    c->status_dev = (int*)status;
+    c->max_sys = ms;
+    c->part = (double2*)part;
+    c->scal = (double2*)scal;
+    c->mass64 = (double*)m64;
+    c->mass32 = (float*)m32;
+    c->mask = (int*)mask;
+    for (int l = 0; l < 4; ++l) c->L[l] = L[l];
+    c->r0s = r0s;
+    c->e0s = e0s;
+    c->scratch_base = scr.base ? scr.base + solver_base : nullptr;
+    c->scratch_cap = scr.off - solver_base;
+  }
+  return true;
+}
+
+// ================================================================== operators
+template <typename R>
+static DslashArgs<R> dslash_args(const Ctx& c, void* out, const void* in, int nsys) {
+  DslashArgs<R> a{};
+  a.out = (cplx<R>*)out;
+  a.in = (const cplx<R>*)in;
+  const bool d = sizeof(R) == 8;
+  a.fat = d ? (const cplx<R>*)c.fat64 : (const cplx<R>*)c.fat32;
+  a.lng = d ? (const cplx<R>*)c.lng64 : (const cplx<R>*)c.lng32;
+  a.g = c.g0;
+  a.in_stride = a.out_stride = a.xs_stride = c.g0.V * 3;
+  a.nrhs = nsys;
+  a.b_coef = 1;
+  return a;
+}
+
+void Ctx::apply_D(int prec, void* out, const void* in, int nsys, bool naik, const void* mass_rhs, double mass,
+                  bool eps_out) {
+  naik = naik && P.c3 != 0.0;
+  if (prec == P64) {
+    auto a = dslash_args<double>(*this, out, in, nsys);
+    a.mass = mass;
+    a.mass_rhs = (const double*)mass_rhs;
+    a.eps_out = eps_out;
+    launch_dslash(a, naik, false, false, st);
+  } else {
+    auto a = dslash_args<float>(*this, out, in, nsys);
+    a.mass = (float)mass;
+    a.mass_rhs = (const float*)mass_rhs;
+    a.eps_out = eps_out;
+    launch_dslash(a, naik, false, false, st);
+  }
+  check_launch();
+}
+
+void Ctx::apply_KD(int prec, void* out, const void* in, int nsys, bool eps_in, bool eps_out, int rps) {
+  if (prec == P64) {
+    KdArgs<double> a{};
+    a.out = (double2*)out; a.in = (const double2*)in; a.kinv = kinv64;
+    a.g = g0; a.in_stride = a.out_stride = g0.V * 3; a.nrhs = nsys;
+    a.rhs_per_slot = rps; a.slot_stride = kinv_slot; a.eps_in = eps_in; a.eps_out = eps_out;
+    launch_kd_apply(a, st);
+  } else {
+    KdArgs<float> a{};
+    a.out = (float2*)out; a.in = (const float2*)in; a.kinv = kinv32;
+    a.g = g0; a.in_stride = a.out_stride = g0.V * 3; a.nrhs = nsys;
+    a.rhs_per_slot = rps; a.slot_stride = kinv_slot; a.eps_in = eps_in; a.eps_out = eps_out;
+    launch_kd_apply(a, st);
+  }
+  check_launch();
+}
+
+void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, bool dag) {
+  const int l = lvl - 2;
+  const int n = ncoarse[l];
+  if (prec == P64) {
+    CoarseArgs<double, double2> a{};
+    a.out = (double2*)out; a.in = (const double2*)in; a.links = cl64[l];
+    a.g = gc[l]; a.n = n; a.in_stride = a.out_stride = gc[l].V * n; a.nrhs = nsys;
+    launch_coarse(a, false, dag, st);
+  } else {
+    CoarseArgs<float, float2> a{};
+    a.out = (float2*)out; a.in = (const float2*)in; a.links = cl32[l];
+    a.g = gc[l]; a.n = n; a.in_stride = a.out_stride = gc[l].V * n; a.nrhs = nsys;
+    launch_coarse(a, false, dag, st);
+  }
+  check_launch();
+}
+
+void Ctx::restrict_(int lvl, int prec, void* out, const void* in, int nsys) {
+  const int l = lvl - 1;   // lvl 1: fine -> level 2, lvl 2: level 2 -> level 3
+  const Agg& a = A[l];
+  const int64_t nin = a.nagg * 2 * a.nrows, nout = a.nagg * 2 * a.nvec;
+  if (prec == P64) {
+    RestrictArgs<double> r{};
+    r.out = (double2*)out; r.in = (const double2*)in; r.pr = pr64[l]; r.A = a;
+    r.in_stride = nin; r.out_stride = nout; r.out_site_stride = 2 * a.nvec; r.nrhs = nsys;
+    launch_restrict(r, st);
+  } else {
+    RestrictArgs<float> r{};
+    r.out = (float2*)out; r.in = (const float2*)in; r.pr = pr32[l]; r.A = a;
+    r.in_stride = nin; r.out_stride = nout; r.out_site_stride = 2 * a.nvec; r.nrhs = nsys;
+    launch_restrict(r, st);
+  }
+  check_launch();
+}
+
+void Ctx::prolong_(int lvl, int prec, void* out, const void* in, int nsys, bool acc) {
+  const int l = lvl - 1;
+  const Agg& a = A[l];
+  const int64_t nfine = a.nagg * 2 * a.nrows, ncrs = a.nagg * 2 * a.nvec;
+  if (prec == P64) {
+    ProlongArgs<double> r{};
+    r.out = (double2*)out; r.in = (const double2*)in; r.pp = pp64[l]; r.A = a;
+    r.in_stride = ncrs; r.out_stride = nfine; r.nrhs = nsys; r.accumulate = acc; r.unit_col = -1;
+    launch_prolong(r, st);
+  } else {
+    ProlongArgs<float> r{};
+    r.out = (float2*)out; r.in = (const float2*)in; r.pp = pp32[l]; r.A = a;
+    r.in_stride = ncrs; r.out_stride = nfine; r.nrhs = nsys; r.accumulate = acc; r.unit_col = -1;
+    launch_prolong(r, st);
+  }
+  check_launch();
+}
+
+// A_lvl on a batch: level 0 D(m_s), level 1 (B + m_s)^{-1} D(m_s), coarse levels
+void Ctx::apply_level(int lvl, const Vec& out, const Vec& in, int nsys) {
+  if (lvl == 0) {
+    apply_D(in.prec, out.p, in.p, nsys, true, in.prec == P64 ? (const void*)mass64 : (const void*)mass32, 0.0);
+  } else if (lvl == 1) {
+    apply_D(in.prec, L[1].tmp.p, in.p, nsys, P.kd_naik != 0,
+            in.prec == P64 ? (const void*)mass64 : (const void*)mass32, 0.0);
+    apply_KD(in.prec, out.p, L[1].tmp.p, nsys, false, false, rhs_per_slot);
+  } else {
+    apply_coarse(lvl, in.prec, out.p, in.p, nsys, false);
+  }
+}
+
+// ======================================================================= BLAS
+void Ctx::dots(int prec, int64_t n, int nsys, const std::vector<std::pair<const void*, const void*>>& pairs,
+               double2* res) {
+  if (pairs.empty()) return;
+  if ((int)pairs.size() > kMaxPairs) throw Error{MG_E_ARG, "too many dot products in one reduction"};
+  if (prec == P64) {
+    PairDotArgs<double2> a{};
+    for (size_t i = 0; i < pairs.size(); ++i) { a.x[i] = (const double2*)pairs[i].first; a.y[i] = (const double2*)pairs[i].second; }
+    a.np = (int)pairs.size(); a.n = n; a.stride = n; a.nrhs = nsys;
+    launch_pairdot(a, part, res, max_sys, st);
+  } else {
+    PairDotArgs<float2> a{};
+    for (size_t i = 0; i < pairs.size(); ++i) { a.x[i] = (const float2*)pairs[i].first; a.y[i] = (const float2*)pairs[i].second; }
+    a.np = (int)pairs.size(); a.n = n; a.stride = n; a.nrhs = nsys;
+    launch_pairdot(a, part, res, max_sys, st);
+  }
+  check_launch();
+}
+
+// out = sum_t c_t v_t; c_t from a device per-system array when given, else consts[t]; neg flips sign
+void Ctx::lincomb(int prec, int64_t n, int nsys, void* out,
+                  const std::vector<std::pair<const void*, const double2*>>& terms, const std::vector<int>& neg,
+                  const std::vector<double2>& consts) {
+  if ((int)terms.size() > kMaxTerms) throw Error{MG_E_ARG, "too many terms in a linear combination"};
+  auto fill = [&](auto& a) {
+    for (size_t t = 0; t < terms.size(); ++t) {
+      a.v[t] = (decltype(a.v[0]))terms[t].first;
+      a.c[t] = terms[t].second;
+      a.cconst[t] = t < consts.size() ? consts[t] : make_double2(1.0, 0.0);
+      a.neg[t] = t < neg.size() ? neg[t] : 0;
+    }
+    a.nt = (int)terms.size(); a.n = n; a.stride = n; a.nrhs = nsys;
+  };
+  if (prec == P64) {
+    LinCombArgs<double2> a{};
+    a.out = (double2*)out;
+    fill(a);
+    launch_lincomb(a, st);
+  } else {
+    LinCombArgs<float2> a{};
+    a.out = (float2*)out;
+    fill(a);
+    launch_lincomb(a, st);
+  }
+  check_launch();
+}
+
+void Ctx::copy(const Vec& dst, const Vec& src, int nsys) {
+  const int64_t n = src.n * nsys;
+  if (dst.prec == src.prec) {
+    HIPCHK(hipMemcpyAsync(dst.p, src.p, n * csize(src.prec), hipMemcpyDeviceToDevice, st));
+  } else if (src.prec == P64) {
+    launch_convert<double2, float2>((float2*)dst.p, (const double2*)src.p, n, st);
+  } else {
+    launch_convert<float2, double2>((double2*)dst.p, (const float2*)src.p, n, st);
+  }
+  check_launch();
+}
+
+void Ctx::zero(const Vec& v, int nsys) {
+  HIPCHK(hipMemsetAsync(v.p, 0, (size_t)v.n * nsys * csize(v.prec), st));
+}
+
+void Ctx::norms_host(int prec, int64_t n, int nsys, const void* v, double2* res_dev, std::vector<double>& out) {
+  dots(prec, n, nsys, {{v, v}}, res_dev);
+  std::vector<double2> h(nsys);
+  HIPCHK(hipMemcpyAsync(h.data(), res_dev, nsys * sizeof(double2), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  out.resize(nsys);
+  for (int s = 0; s < nsys; ++s) out[s] = std::sqrt(std::fmax(h[s].x, 0.0));
+}
+
+// ==================================================================== solvers
+// CA-GCR(s) smoother: e += argmin_{v in K_s(A, t)} ||t - A v|| via the power
+// basis p_0 = t, p_j = A p_{j-1}, one Gram reduction and an s x s Cholesky
+// solve in FP64 (the basis-free definition of the smoother's result).
+void Ctx::smoother(int lvl, const Vec& e, const Vec& t, int nsys) {
+  LevelBufs& B = L[lvl];
+  const int s = P.smoother_s;
+  const int prec = t.prec;
+  for (int j = 0; j < s; ++j) {
+    const Vec& src = j == 0 ? t : B.sm[j - 1];
+    apply_level(lvl, B.sm[j], src, nsys);
+  }
+  std::vector<std::pair<const void*, const void*>> pairs;
+  for (int i = 0; i < s; ++i)
+    for (int j = i; j < s; ++j) pairs.push_back({B.sm[i].p, B.sm[j].p});
+  for (int i = 0; i < s; ++i) pairs.push_back({B.sm[i].p, t.p});
+  double2* gram = slot(lvl, 0);
+  dots(prec, t.n, nsys, pairs, gram);
+  double2* a = slot(lvl, kSlotCoef);
+  launch_cagcr_solve(gram, s, nsys, max_sys, lmask(lvl), a, st);
+  check_launch();
+  std::vector<std::pair<const void*, const double2*>> terms;
+  terms.push_back({e.p, nullptr});
+  terms.push_back({t.p, a});
+  for (int j = 1; j < s; ++j) terms.push_back({B.sm[j - 1].p, a + (int64_t)j * max_sys});
+  lincomb(prec, t.n, nsys, e.p, terms, {}, {});
+}
+
+// K_lvl(r) -> e (Sec. 2.1 K-cycle: no pre-smoothing, restrict, solve the next
+// level to its tolerance, prolong, post-smooth)
+void Ctx::kcycle(int lvl, const Vec& r, const Vec& e, int nsys, SolveStats& stats) {
+  if (lvl == 0) {
+    // level 0 -> 1: r1 = (B + m)^{-1} r (in the fine precision), e0 = e1
+    copy(r0s, r, nsys);
+    apply_KD(r0s.prec, L[1].b.p, r0s.p, nsys, false, false, rhs_per_slot);
+    level_solve(1, nsys, stats);
+    copy(e0s, L[1].x, nsys);
+    // t = r - D e0
+    apply_level(0, L[0].t, e0s, nsys);
+    lincomb(r0s.prec, r0s.n, nsys, L[0].t.p, {{r0s.p, nullptr}, {L[0].t.p, nullptr}}, {0, 1}, {});
+    smoother(0, e0s, L[0].t, nsys);
+    copy(e, e0s, nsys);
+    return;
+  }
+  LevelBufs& B = L[lvl];
+  LevelBufs& C = L[lvl + 1];
+  restrict_(lvl, r.prec, C.b.p, r.p, nsys);
+  level_solve(lvl + 1, nsys, stats);
+  prolong_(lvl, r.prec, e.p, C.x.p, nsys, false);
+  apply_level(lvl, B.t, e, nsys);
+  lincomb(r.prec, r.n, nsys, B.t.p, {{r.p, nullptr}, {B.t.p, nullptr}}, {0, 1}, {});
+  smoother(lvl, e, B.t, nsys);
+}
+
+// Flexible GCR on level lvl (>= 1) from x = 0 for L[lvl].b, preconditioned by
+// the K-cycle except on the coarsest level; stops per system at
+// ||r|| <= tol ||b|| or after the iteration cap (Table 1: 0.25 or 8).
+void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
+  LevelBufs& B = L[lvl];
+  const bool coarsest = lvl == nlev - 1;
+  const double tol = coarsest ? P.coarsest_tol : P.inner_tol;
+  const int maxit = coarsest ? P.coarsest_maxiter : P.inner_maxiter;
+  const int cycles = coarsest ? P.coarsest_restarts : 1;
+  const int prec = B.prec;
+  const int64_t n = B.n;
+  zero(B.x, nsys);
+  copy(B.r, B.b, nsys);
+  std::vector<double> r0, rn;
+  norms_host(prec, n, nsys, B.b.p, slot(lvl, kSlotNorm), r0);
+  std::vector<int> act(nsys);
+  int nact = 0;
+  for (int s = 0; s < nsys; ++s) { act[s] = r0[s] > 0.0 && std::isfinite(r0[s]); nact += act[s]; }
+  HIPCHK(hipMemcpyAsync(lmask(lvl), act.data(), nsys * sizeof(int), hipMemcpyHostToDevice, st));
+  for (int cyc = 0; cyc < cycles && nact > 0; ++cyc) {
+    if (cyc > 0) {   // restart: r = b - A x
+      apply_level(lvl, B.r, B.x, nsys);
+      lincomb(prec, n, nsys, B.r.p, {{B.b.p, nullptr}, {B.r.p, nullptr}}, {0, 1}, {});
+    }
+    for (int k = 0; k < maxit && nact > 0; ++k) {
+      stats.level[lvl - 1] += 1;
+      if (coarsest) copy(B.z[k], B.r, nsys);
+      else kcycle(lvl, B.r, B.z[k], nsys, stats);
+      apply_level(lvl, B.q[k], B.z[k], nsys);
+      // classical Gram-Schmidt, twice
+      for (int pass = 0; pass < 2 && k > 0; ++pass) {
+        std::vector<std::pair<const void*, const void*>> pr;
+        for (int i = 0; i < k; ++i) pr.push_back({B.q[i].p, B.q[k].p});
+        double2* beta = slot(lvl, 0);
+        dots(prec, n, nsys, pr, beta);
+        std::vector<std::pair<const void*, const double2*>> tq, tz;
+        std::vector<int> ng(k + 1, 1);
+        ng[0] = 0;
+        tq.push_back({B.q[k].p, nullptr});
+        tz.push_back({B.z[k].p, nullptr});
+        for (int i = 0; i < k; ++i) {
+          tq.push_back({B.q[i].p, beta + (int64_t)i * max_sys});
+          tz.push_back({B.z[i].p, beta + (int64_t)i * max_sys});
+        }
+        lincomb(prec, n, nsys, B.q[k].p, tq, ng, {});
+        lincomb(prec, n, nsys, B.z[k].p, tz, ng, {});
+      }
+      double2* qq = slot(lvl, kSlotQQ);
+      dots(prec, n, nsys, {{B.q[k].p, B.q[k].p}, {B.q[k].p, B.r.p}}, qq);
+      double2 *al = slot(lvl, kSlotQQ + 2), *nal = slot(lvl, kSlotQQ + 3), *inv = slot(lvl, kSlotQQ + 4);
+      launch_gcr_scalars(qq, qq + max_sys, lmask(lvl), nsys, al, nal, inv, st);
+      check_launch();
+      lincomb(prec, n, nsys, B.x.p, {{B.x.p, nullptr}, {B.z[k].p, al}}, {}, {});
+      lincomb(prec, n, nsys, B.r.p, {{B.r.p, nullptr}, {B.q[k].p, nal}}, {}, {});
+      lincomb(prec, n, nsys, B.q[k].p, {{B.q[k].p, inv}}, {}, {});
+      lincomb(prec, n, nsys, B.z[k].p, {{B.z[k].p, inv}}, {}, {});
+      norms_host(prec, n, nsys, B.r.p, slot(lvl, kSlotNorm), rn);
+      bool changed = false;
+      for (int s = 0; s < nsys; ++s) {
+        if (act[s] && (!(rn[s] > tol * r0[s]) || !std::isfinite(rn[s]))) { act[s] = 0; --nact; changed = true; }
+      }
+      if (changed && nact > 0)
+        HIPCHK(hipMemcpyAsync(lmask(lvl), act.data(), nsys * sizeof(int), hipMemcpyHostToDevice, st));
+    }
+  }
+}
+
+// ======================================================================== KD
+void Ctx::ensure_kd(const std::vector<double>& masses) {
+  if ((int)masses.size() > P.max_nmass) throw Error{MG_E_ARG, "more masses than max_nmass"};
+  for (size_t j = 0; j < masses.size(); ++j) {
+    if (kd_mass[j] == masses[j]) continue;
+    launch_kd_inverse(fat64, g0, masses[j], kinv64 + (int64_t)j * kinv_slot, kinv32 + (int64_t)j * kinv_slot, st);
+    check_launch();
+    kd_mass[j] = masses[j];
+  }
+}
+
+}  // namespace mg

@@ -1,0 +1,133 @@
+// Host-side multigrid context: workspace layout, hierarchy set-up and the
+// GCR / CA-GCR / K-cycle / CG drivers.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/mgstag.h"
+#include "kernels.hpp"
+
+namespace mg {
+
+struct Error {
+  mg_status code;
+  std::string msg;
+};
+
+// A batch of nrhs vectors of n complex numbers each, contiguous per rhs.
+struct Vec {
+  void* p = nullptr;
+  int prec = P64;
+  int64_t n = 0;
+};
+
+// Bump allocator over a caller-owned workspace; a dry run (base == nullptr)
+// measures the size.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  void* take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+struct LevelBufs {
+  int prec = P32;
+  int64_t n = 0;            // complex numbers per system
+  Vec b, x, r, t, tmp;
+  Vec z[kMaxNK], q[kMaxNK];
+  Vec sm[kMaxS];
+  int nk = 0;
+};
+
+struct SolveStats {
+  int outer = 0, reliable = 0;
+  int level[4] = {0, 0, 0, 0};
+};
+
+struct Ctx {
+  mg_params P{};
+  hipStream_t st = nullptr;
+  int nlev = 0;             // levels: 0 (D), 1 (A), 2, 3
+  Geom g0{};                // fine lattice
+  Geom gc[2]{};             // coarse lattices of levels 2 and 3
+  Agg A[2]{};               // aggregation 1 -> 2 and 2 -> 3
+  int ncoarse[2]{};         // 2 nvec per level
+
+  // persistent
+  double2 *fat64 = nullptr, *lng64 = nullptr;
+  float2 *fat32 = nullptr, *lng32 = nullptr;
+  double2* kinv64 = nullptr;
+  float2* kinv32 = nullptr;
+  int64_t kinv_slot = 0;    // complex per slot
+  std::vector<double> kd_mass;   // mass of each slot (NaN: empty)
+  double2* nv[2]{};         // null vectors, canonical per-level layout
+  double2 *pp64[2]{}, *pr64[2]{};
+  float2 *pp32[2]{}, *pr32[2]{};
+  double2* cl64[2]{};       // coarse links of levels 2 and 3
+  float2* cl32[2]{};
+  int* status_dev = nullptr;
+
+  // scratch (solver)
+  int max_sys = 0;
+  LevelBufs L[4];
+  Vec x0s, r0s, e0s;        // level-0 K-cycle in fine precision (x0s unused)
+  double2* part = nullptr;  // reduction partials
+  double2* scal = nullptr;  // scalar slots [level][kMaxSlots][max_sys]
+  double* mass64 = nullptr; // per-system masses (device)
+  float* mass32 = nullptr;
+  int* mask = nullptr;      // per-system active flag (device)
+  // scratch (set-up, aliases the solver scratch)
+  char* scratch_base = nullptr;
+  size_t scratch_cap = 0;
+
+  // current batch
+  int nsys = 0;
+  int rhs_per_slot = 0;     // systems per KD slot in the current batch
+
+  std::vector<double> host_buf;
+
+  // ---- layout
+  static bool plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string* why);
+
+  // ---- operators (all on stream st, batch of nsys systems)
+  void apply_level(int lvl, const Vec& out, const Vec& in, int nsys);
+  void apply_D(int prec, void* out, const void* in, int nsys, bool naik, const void* mass_rhs, double mass,
+               bool eps_out = false);
+  void apply_KD(int prec, void* out, const void* in, int nsys, bool eps_in, bool eps_out, int rhs_per_slot);
+  void apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, bool dag);
+  void restrict_(int lvl, int prec, void* out, const void* in, int nsys);
+  void prolong_(int lvl, int prec, void* out, const void* in, int nsys, bool acc);
+
+  // ---- BLAS helpers
+  double2* slot(int lvl, int s) { return scal + ((int64_t)lvl * kMaxSlots + s) * max_sys; }
+  int* lmask(int lvl) { return mask + (int64_t)lvl * max_sys; }
+  void dots(int prec, int64_t n, int nsys, const std::vector<std::pair<const void*, const void*>>& pairs,
+            double2* res);
+  void lincomb(int prec, int64_t n, int nsys, void* out,
+               const std::vector<std::pair<const void*, const double2*>>& terms, const std::vector<int>& neg,
+               const std::vector<double2>& consts);
+  void copy(const Vec& dst, const Vec& src, int nsys);
+  void zero(const Vec& v, int nsys);
+  void norms_host(int prec, int64_t n, int nsys, const void* v, double2* res_dev, std::vector<double>& out);
+
+  // ---- solvers
+  void smoother(int lvl, const Vec& e, const Vec& t, int nsys);
+  void kcycle(int lvl, const Vec& r, const Vec& e, int nsys, SolveStats& stats);
+  void level_solve(int lvl, int nsys, SolveStats& stats);   // L[lvl].b -> L[lvl].x
+  void ensure_kd(const std::vector<double>& masses);
+
+  // ---- set-up
+  void setup(const void* fat, const void* naik, const void* const* nvs);
+  void solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, mg_solve_info* info);
+  void cg_solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, int maxiter,
+                mg_solve_info* info);
+  void build_level(int l, const void* nv_import);
+  void cgne_null(int l);
+  void galerkin(int l);
+};
+
+}  // namespace mg

@@ -1,0 +1,183 @@
+// Hierarchy set-up (Sec. 2.1, Sec. 2.3, Table 1): links to the internal
+// layout, the KD block inverse at mass0, near-null vectors (imported, or CGNE
+// on the level's own operator), chiral doubling + FP64 block
+// orthonormalisation, and the Galerkin coarse operators.
+#include <cmath>
+
+#include "mg.hpp"
+
+namespace mg {
+
+#define HIPCHK(x)                                                                 \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess) throw Error{MG_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+static void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error{MG_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e)};
+}
+
+void Ctx::setup(const void* fat, const void* naik, const void* const* nvs) {
+  launch_pack_links((const double2*)fat, fat64, fat32, g0, 0.5 * P.c1, st);
+  check_launch();
+  if (P.c3 != 0.0) {
+    launch_pack_links((const double2*)naik, lng64, lng32, g0, 0.5 * P.c3, st);
+    check_launch();
+  }
+  ensure_kd({P.mass0});
+  rhs_per_slot = 0;
+  for (int l = 0; l < P.nagg; ++l) build_level(l, nvs ? nvs[l] : nullptr);
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+void Ctx::build_level(int l, const void* imp) {
+  const Agg& a = A[l];
+  const int64_t nflat = a.nagg * 2 * a.nrows;
+  if (imp) {
+    HIPCHK(hipMemcpyAsync(nv[l], imp, (size_t)a.nvec * nflat * 16, hipMemcpyDeviceToDevice, st));
+  } else {
+    cgne_null(l);
+  }
+  launch_gather_null(nv[l], nflat, pp64[l], a, st);
+  check_launch();
+  HIPCHK(hipMemsetAsync(status_dev, 0, sizeof(int), st));
+  launch_block_orth(pp64[l], a, status_dev, st);
+  check_launch();
+  int status = 0;
+  HIPCHK(hipMemcpyAsync(&status, status_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (status) throw Error{MG_E_RANK, "block orthonormalisation: near-null vectors are rank deficient on a block"};
+  launch_p_layouts(pp64[l], pr64[l], pr32[l], pp32[l], a, st);
+  check_launch();
+  galerkin(l);
+}
+
+// Near-null vectors by CGNE on A phi = 0 from seeded random starts, all nvec
+// vectors as one batch (Sec. 2.1, Table 1: CGNE to tol or maxiter):
+//   t = A^dag p, alpha = |r|^2 / |t|^2, phi += alpha t, r -= alpha A t, ...
+// Level 1: A = (B + m0)^{-1} D, A^dag = eps D (B + m0)^{-1} eps.
+// Level 2: the level-2 coarse operator and its adjoint stencil.
+void Ctx::cgne_null(int l) {
+  const Agg& a = A[l];
+  const int nv_ = a.nvec;
+  const int64_t n = a.nagg * 2 * a.nrows;
+  const int prec = L[l + 1].prec;
+  const size_t vb = ((size_t)nv_ * n * csize(prec) + 255) & ~(size_t)255;
+  char* base = scratch_base;
+  void* phi = base;
+  void* r = base + vb;
+  void* p = base + 2 * vb;
+  void* t = base + 3 * vb;
+  void* At = base + 4 * vb;
+  void* tmp = base + 5 * vb;
+  auto A_apply = [&](void* out, const void* in, bool dag) {
+    if (l == 0) {
+      const bool nk = P.kd_naik != 0;
+      if (!dag) {
+        apply_D(prec, tmp, in, nv_, nk, nullptr, P.mass0);
+        apply_KD(prec, out, tmp, nv_, false, false, 0);
+      } else {
+        apply_KD(prec, tmp, in, nv_, true, false, 0);
+        apply_D(prec, out, tmp, nv_, nk, nullptr, P.mass0, true);
+      }
+    } else {
+      apply_coarse(2, prec, out, in, nv_, dag);
+    }
+  };
+  if (prec == P64) launch_random_normal<double2>((double2*)phi, (int64_t)nv_ * n, P.seed + 7919ull * l, st);
+  else launch_random_normal<float2>((float2*)phi, (int64_t)nv_ * n, P.seed + 7919ull * l, st);
+  check_launch();
+  A_apply(r, phi, false);
+  lincomb(prec, n, nv_, r, {{r, nullptr}}, {1}, {});
+  std::vector<double> r0, rn;
+  double2* rr = slot(3, kSlotQQ);
+  double2* rrn = slot(3, kSlotQQ + 1);
+  double2* al = slot(3, kSlotQQ + 2);
+  double2* nal = slot(3, kSlotQQ + 3);
+  double2* be = slot(3, kSlotQQ + 4);
+  double2* tt = slot(3, kSlotQQ + 5);
+  norms_host(prec, n, nv_, r, rr, r0);
+  HIPCHK(hipMemcpyAsync(p, r, (size_t)nv_ * n * csize(prec), hipMemcpyDeviceToDevice, st));
+  std::vector<int> act(nv_, 1);
+  int* mk = lmask(3);
+  HIPCHK(hipMemcpyAsync(mk, act.data(), nv_ * sizeof(int), hipMemcpyHostToDevice, st));
+  int nact = nv_;
+  for (int it = 0; it < P.setup_maxiter[l] && nact > 0; ++it) {
+    A_apply(t, p, true);
+    A_apply(At, t, false);
+    dots(prec, n, nv_, {{t, t}}, tt);
+    launch_cg_alpha(rr, tt, mk, nv_, al, nal, st);
+    check_launch();
+    lincomb(prec, n, nv_, phi, {{phi, nullptr}, {t, al}}, {}, {});
+    lincomb(prec, n, nv_, r, {{r, nullptr}, {At, nal}}, {}, {});
+    norms_host(prec, n, nv_, r, rrn, rn);
+    launch_cg_beta(rr, rrn, mk, nv_, be, st);
+    check_launch();
+    lincomb(prec, n, nv_, p, {{r, nullptr}, {p, be}}, {}, {});
+    bool changed = false;
+    for (int s = 0; s < nv_; ++s)
+      if (act[s] && !(rn[s] > P.setup_tol[l] * r0[s])) { act[s] = 0; --nact; changed = true; }
+    if (changed) HIPCHK(hipMemcpyAsync(mk, act.data(), nv_ * sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  if (prec == P64) launch_convert<double2, double2>(nv[l], (const double2*)phi, (int64_t)nv_ * n, st);
+  else launch_convert<float2, double2>(nv[l], (const float2*)phi, (int64_t)nv_ * n, st);
+  check_launch();
+}
+
+// Galerkin coarse operator (Sec. 2.1: A_c = R A P), built column by column
+// in FP64: for coarse dof j, v = P e_j on every aggregate at once; each of the
+// nine stencil pieces of the level operator (hops staying inside the
+// aggregate, or crossing its +mu / -mu face) is applied to v and restricted,
+// which yields column j of X(a) and of Y_{+-mu}(a) for every aggregate a.
+void Ctx::galerkin(int l) {
+  const Agg& a = A[l];
+  const int n = 2 * a.nvec;
+  const int64_t nflat = a.nagg * 2 * a.nrows;
+  const size_t vb = ((size_t)nflat * 16 + 255) & ~(size_t)255;
+  // past the CGNE buffers of this level
+  const size_t cg = (((size_t)a.nvec * nflat * csize(L[l + 1].prec) + 255) & ~(size_t)255) * 6;
+  double2* v = (double2*)(scratch_base + cg);
+  double2* w = (double2*)(scratch_base + cg + vb);
+  double2* u = (double2*)(scratch_base + cg + 2 * vb);
+  for (int j = 0; j < n; ++j) {
+    ProlongArgs<double> pa{};
+    pa.out = v; pa.in = nullptr; pa.pp = pp64[l]; pa.A = a;
+    pa.in_stride = a.nagg * n; pa.out_stride = nflat; pa.nrhs = 1; pa.accumulate = 0; pa.unit_col = j;
+    launch_prolong(pa, st);
+    check_launch();
+    for (int piece = 0; piece < 9; ++piece) {
+      const double2* src;
+      if (l == 0) {
+        DslashArgs<double> d{};
+        d.out = w; d.in = v; d.fat = fat64; d.lng = lng64; d.g = g0;
+        d.in_stride = d.out_stride = g0.V * 3; d.nrhs = 1; d.mass = P.mass0; d.b_coef = 1;
+        d.piece = piece;
+        for (int mu = 0; mu < 4; ++mu) d.blk[mu] = a.b[mu];
+        launch_dslash(d, P.c3 != 0.0 && P.kd_naik, false, true, st);
+        check_launch();
+        apply_KD(P64, u, w, 1, false, false, 0);
+        src = u;
+      } else {
+        CoarseArgs<double, double2> c{};
+        c.out = w; c.in = v; c.links = cl64[0]; c.g = gc[0]; c.n = ncoarse[0];
+        c.in_stride = c.out_stride = gc[0].V * ncoarse[0]; c.nrhs = 1; c.piece = piece;
+        for (int mu = 0; mu < 4; ++mu) c.blk[mu] = a.b[mu];
+        launch_coarse(c, true, false, st);
+        check_launch();
+        src = w;
+      }
+      RestrictArgs<double> ra{};
+      ra.out = cl64[l] + ((int64_t)piece * n + j) * n;
+      ra.in = src; ra.pr = pr64[l]; ra.A = a;
+      ra.in_stride = nflat; ra.out_stride = 0; ra.out_site_stride = (int64_t)9 * n * n; ra.nrhs = 1;
+      launch_restrict(ra, st);
+      check_launch();
+    }
+  }
+  launch_convert_links(cl64[l], cl32[l], gc[l].V * 9 * (int64_t)n * n, st);
+  check_launch();
+}
+
+}  // namespace mg

@@ -1,0 +1,261 @@
+// Outer solvers: MG-preconditioned flexible GCR in FP64 (Sec. 2.1, Table 1)
+// and the single-parity Schur CG baseline (Sec. 3.2).  Both stop on the true
+// residual ||b - D(m) x|| / ||b|| recomputed in FP64.
+#include <chrono>
+#include <cmath>
+
+#include "mg.hpp"
+
+namespace mg {
+
+#define HIPCHK(x)                                                                 \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess) throw Error{MG_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+static void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error{MG_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e)};
+}
+
+static double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Per-system masses of a [nmass][nrhs] batch on the device (FP64 and FP32)
+static void set_masses(Ctx& c, const double* masses, int nmass, int nrhs) {
+  const int ns = nmass * nrhs;
+  std::vector<double> m64(ns);
+  std::vector<float> m32(ns);
+  for (int j = 0; j < nmass; ++j)
+    for (int r = 0; r < nrhs; ++r) { m64[j * nrhs + r] = masses[j]; m32[j * nrhs + r] = (float)masses[j]; }
+  HIPCHK(hipMemcpyAsync(c.mass64, m64.data(), ns * sizeof(double), hipMemcpyHostToDevice, c.st));
+  HIPCHK(hipMemcpyAsync(c.mass32, m32.data(), ns * sizeof(float), hipMemcpyHostToDevice, c.st));
+  HIPCHK(hipStreamSynchronize(c.st));
+}
+
+void Ctx::solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, mg_solve_info* info) {
+  const int ns = nmass * nrhs;
+  const double t0 = now();
+  std::vector<double> ms(masses, masses + nmass);
+  ensure_kd(ms);
+  rhs_per_slot = nrhs;
+  set_masses(*this, masses, nmass, nrhs);
+  LevelBufs& B = L[0];
+  const int64_t n = B.n;
+  Vec X{x, P64, n};
+  // b replicated per mass
+  for (int j = 0; j < nmass; ++j)
+    HIPCHK(hipMemcpyAsync((char*)B.b.p + (size_t)j * nrhs * n * 16, b, (size_t)nrhs * n * 16,
+                          hipMemcpyDeviceToDevice, st));
+  zero(X, ns);
+  copy(B.r, B.b, ns);
+  std::vector<double> bn, rn;
+  norms_host(P64, n, ns, B.b.p, slot(0, kSlotNorm), bn);
+  std::vector<int> act(ns), stat(ns, MG_OK);
+  std::vector<double> rlast(bn);
+  int nact = 0;
+  for (int s = 0; s < ns; ++s) {
+    if (!std::isfinite(bn[s])) { stat[s] = MG_E_NONFINITE; act[s] = 0; }
+    else act[s] = bn[s] > 0.0;
+    nact += act[s];
+  }
+  int* mk = lmask(0);
+  HIPCHK(hipMemcpyAsync(mk, act.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+  SolveStats stats;
+  std::vector<int> iters(ns, 0), rel_upd(ns, 0);
+  int k = 0;
+  auto true_residual = [&]() {   // r = b - D x for every system (FP64)
+    apply_level(0, B.r, X, ns);
+    lincomb(P64, n, ns, B.r.p, {{B.b.p, nullptr}, {B.r.p, nullptr}}, {0, 1}, {});
+    norms_host(P64, n, ns, B.r.p, slot(0, kSlotNorm), rn);
+  };
+  for (int it = 0; it < P.outer_maxiter && nact > 0; ++it) {
+    kcycle(0, B.r, B.z[k], ns, stats);
+    apply_level(0, B.q[k], B.z[k], ns);
+    for (int pass = 0; pass < 2 && k > 0; ++pass) {
+      std::vector<std::pair<const void*, const void*>> pr;
+      for (int i = 0; i < k; ++i) pr.push_back({B.q[i].p, B.q[k].p});
+      double2* beta = slot(0, 0);
+      dots(P64, n, ns, pr, beta);
+      std::vector<std::pair<const void*, const double2*>> tq, tz;
+      std::vector<int> ng(k + 1, 1);
+      ng[0] = 0;
+      tq.push_back({B.q[k].p, nullptr});
+      tz.push_back({B.z[k].p, nullptr});
+      for (int i = 0; i < k; ++i) {
+        tq.push_back({B.q[i].p, beta + (int64_t)i * max_sys});
+        tz.push_back({B.z[i].p, beta + (int64_t)i * max_sys});
+      }
+      lincomb(P64, n, ns, B.q[k].p, tq, ng, {});
+      lincomb(P64, n, ns, B.z[k].p, tz, ng, {});
+    }
+    double2* qq = slot(0, kSlotQQ);
+    dots(P64, n, ns, {{B.q[k].p, B.q[k].p}, {B.q[k].p, B.r.p}}, qq);
+    double2 *al = slot(0, kSlotQQ + 2), *nal = slot(0, kSlotQQ + 3), *inv = slot(0, kSlotQQ + 4);
+    launch_gcr_scalars(qq, qq + max_sys, mk, ns, al, nal, inv, st);
+    check_launch();
+    lincomb(P64, n, ns, X.p, {{X.p, nullptr}, {B.z[k].p, al}}, {}, {});
+    lincomb(P64, n, ns, B.r.p, {{B.r.p, nullptr}, {B.q[k].p, nal}}, {}, {});
+    lincomb(P64, n, ns, B.q[k].p, {{B.q[k].p, inv}}, {}, {});
+    lincomb(P64, n, ns, B.z[k].p, {{B.z[k].p, inv}}, {}, {});
+    norms_host(P64, n, ns, B.r.p, slot(0, kSlotNorm), rn);
+    bool check = false, reliable = false, nonfinite = false;
+    for (int s = 0; s < ns; ++s) {
+      if (!act[s]) continue;
+      iters[s] += 1;
+      if (!std::isfinite(rn[s])) nonfinite = true;
+      else if (rn[s] <= tol * bn[s]) check = true;
+      else if (rn[s] < P.reliable_delta * rlast[s]) reliable = true;
+    }
+    const bool restart = k + 1 == P.outer_nkrylov;
+    if (check || reliable || restart || nonfinite) {
+      // reliable update: replace the recursive residual by b - D x (FP64)
+      true_residual();
+      bool changed = false;
+      for (int s = 0; s < ns; ++s) {
+        if (!act[s]) continue;
+        rel_upd[s] += 1;
+        rlast[s] = rn[s];
+        if (!std::isfinite(rn[s])) { act[s] = 0; --nact; stat[s] = MG_E_NONFINITE; changed = true; }
+        else if (rn[s] <= tol * bn[s]) { act[s] = 0; --nact; changed = true; }
+      }
+      if (changed && nact > 0) HIPCHK(hipMemcpyAsync(mk, act.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+      k = restart ? 0 : k + 1;
+    } else {
+      k += 1;
+    }
+  }
+  true_residual();
+  HIPCHK(hipStreamSynchronize(st));
+  const double t1 = now();
+  for (int s = 0; s < ns; ++s) {
+    mg_solve_info& I = info[s];
+    I.outer_iters = iters[s];
+    I.reliable_updates = rel_upd[s];
+    for (int l = 0; l < 4; ++l) I.level_iters[l] = stats.level[l];
+    I.true_rel_residual = bn[s] > 0 ? rn[s] / bn[s] : 0.0;
+    I.seconds = t1 - t0;
+    if (stat[s] == MG_OK && !(I.true_rel_residual <= tol)) stat[s] = MG_E_NOCONV;
+    I.status = stat[s];
+  }
+}
+
+// Single-parity Schur CG (Sec. 3.2) for every (mass, rhs) system, one mass
+// at a time with the right-hand sides batched.
+void Ctx::cg_solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, int maxiter,
+                   mg_solve_info* info) {
+  if (P.outer_nkrylov < 2) throw Error{MG_E_CONFIG, "the CG baseline needs outer_nkrylov >= 2 (work vectors)"};
+  const int64_t V = g0.V;
+  const int64_t n = V * 3, nh = V / 2 * 3;
+  LevelBufs& B = L[0];
+  // half-lattice batches carved from the outer GCR work vectors
+  const size_t hb = (size_t)nrhs * nh * 16;
+  double2* be = (double2*)B.z[0].p;
+  double2* bo = (double2*)((char*)B.z[0].p + hb);
+  double2* xe = (double2*)B.q[0].p;
+  double2* r = (double2*)((char*)B.q[0].p + hb);
+  double2* p = (double2*)B.z[1].p;
+  double2* Ap = (double2*)((char*)B.z[1].p + hb);
+  double2* to = (double2*)B.q[1].p;
+  double2* rhs = (double2*)((char*)B.q[1].p + hb);
+  double2* xo = (double2*)B.r.p;     // odd half, then the full residual
+  double2* rfull = (double2*)B.b.p;
+  int* mk = lmask(0);
+  double2 *rr = slot(0, kSlotQQ), *rrn = slot(0, kSlotQQ + 1), *al = slot(0, kSlotQQ + 2),
+          *nal = slot(0, kSlotQQ + 3), *bt = slot(0, kSlotQQ + 4), *pap = slot(0, kSlotQQ + 5);
+  for (int j = 0; j < nmass; ++j) {
+    const double t0 = now();
+    const double m = masses[j];
+    double2* xj = (double2*)x + (size_t)j * nrhs * n;
+    auto cbd = [&](double2* out, const double2* in, const double2* xs, int par, double ac, double bc) {
+      DslashArgs<double> d{};
+      d.out = out; d.in = in; d.xs = xs; d.fat = fat64; d.lng = lng64; d.g = g0;
+      d.in_stride = d.out_stride = d.xs_stride = nh; d.nrhs = nrhs; d.a_coef = ac; d.b_coef = bc; d.parity = par;
+      launch_dslash(d, P.c3 != 0.0, true, false, st);
+      check_launch();
+    };
+    launch_cb_split((const double2*)b, be, bo, g0, nrhs, st);
+    check_launch();
+    cbd(rhs, bo, be, 0, m, -1.0);   // m b_e - K_eo b_o
+    std::vector<double> bn, rn;
+    norms_host(P64, n, nrhs, b, slot(0, kSlotNorm), bn);
+    std::vector<int> act(nrhs), stat(nrhs, MG_OK), its(nrhs, 0);
+    int nact = 0;
+    for (int s = 0; s < nrhs; ++s) {
+      act[s] = bn[s] > 0.0 && std::isfinite(bn[s]);
+      if (!std::isfinite(bn[s])) stat[s] = MG_E_NONFINITE;
+      nact += act[s];
+    }
+    HIPCHK(hipMemsetAsync(xe, 0, hb, st));
+    int total = 0, restarts = 0;
+    std::vector<double> rel(nrhs, 0.0);
+    while (true) {
+      // r = rhs - M xe,  M = m^2 - K_eo K_oe
+      cbd(to, xe, nullptr, 1, 0.0, 1.0);
+      cbd(r, to, xe, 0, m * m, -1.0);
+      lincomb(P64, nh, nrhs, r, {{rhs, nullptr}, {r, nullptr}}, {0, 1}, {});
+      HIPCHK(hipMemcpyAsync(p, r, hb, hipMemcpyDeviceToDevice, st));
+      norms_host(P64, nh, nrhs, r, rr, rn);
+      HIPCHK(hipMemcpyAsync(mk, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+      auto done = [&](int s) { return !(rn[s] > m * tol * bn[s]); };
+      int live = 0;
+      for (int s = 0; s < nrhs; ++s) if (act[s] && !done(s)) ++live;
+      while (live > 0 && total < maxiter) {
+        cbd(to, p, nullptr, 1, 0.0, 1.0);
+        cbd(Ap, to, p, 0, m * m, -1.0);
+        dots(P64, nh, nrhs, {{p, Ap}}, pap);
+        launch_cg_alpha(rr, pap, mk, nrhs, al, nal, st);
+        check_launch();
+        lincomb(P64, nh, nrhs, xe, {{xe, nullptr}, {p, al}}, {}, {});
+        lincomb(P64, nh, nrhs, r, {{r, nullptr}, {Ap, nal}}, {}, {});
+        norms_host(P64, nh, nrhs, r, rrn, rn);
+        launch_cg_beta(rr, rrn, mk, nrhs, bt, st);
+        check_launch();
+        lincomb(P64, nh, nrhs, p, {{r, nullptr}, {p, bt}}, {}, {});
+        ++total;
+        bool changed = false;
+        live = 0;
+        for (int s = 0; s < nrhs; ++s) {
+          if (!act[s]) continue;
+          its[s] += 1;
+          if (done(s) || !std::isfinite(rn[s])) { act[s] = 0; changed = true; }
+          else ++live;
+        }
+        if (changed) HIPCHK(hipMemcpyAsync(mk, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+      }
+      // x_o = (b_o - K_oe x_e) / m, then the true residual of the full system
+      cbd(xo, xe, bo, 1, 1.0 / m, -1.0 / m);
+      launch_cb_merge(xj, xe, xo, g0, nrhs, st);
+      check_launch();
+      apply_D(P64, rfull, xj, nrhs, true, nullptr, m);
+      lincomb(P64, n, nrhs, rfull, {{b, nullptr}, {rfull, nullptr}}, {0, 1}, {});
+      std::vector<double> tr;
+      norms_host(P64, n, nrhs, rfull, slot(0, kSlotNorm), tr);
+      bool again = false;
+      for (int s = 0; s < nrhs; ++s) {
+        rel[s] = bn[s] > 0 ? tr[s] / bn[s] : 0.0;
+        act[s] = stat[s] == MG_OK && bn[s] > 0 && !(rel[s] <= tol) && std::isfinite(rel[s]);
+        if (!std::isfinite(rel[s])) stat[s] = MG_E_NONFINITE;
+        again = again || act[s];
+      }
+      if (!again || total >= maxiter || restarts >= 5) break;
+      ++restarts;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    const double t1 = now();
+    for (int s = 0; s < nrhs; ++s) {
+      mg_solve_info& I = info[j * nrhs + s];
+      I.outer_iters = its[s];
+      I.reliable_updates = restarts;
+      for (int l = 0; l < 4; ++l) I.level_iters[l] = 0;
+      I.true_rel_residual = rel[s];
+      I.seconds = t1 - t0;
+      if (stat[s] == MG_OK && !(rel[s] <= tol)) stat[s] = MG_E_NOCONV;
+      I.status = stat[s];
+    }
+  }
+}
+
+}  // namespace mg

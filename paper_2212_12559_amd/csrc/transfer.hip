@@ -1,0 +1,266 @@
+// Transfer operators (Sec. 2.1, Sec. 2.3): near-null vectors are split by
+// the chiral projectors (1 +- eps)/2, block-orthonormalised per aggregate and
+// chirality (FP64), and define P and R = P^dag.
+//
+//   restrict  r_c[a, sigma, k] = sum_{rows of (a, sigma)} conj(P[row, k]) r[row]
+//             one workgroup per (a, sigma); lanes run over k (Nvec <= 128),
+//             the four wavefronts over interleaved rows, reduced in LDS.
+//   prolong   e[row] = sum_k P[row, k] e_c[a, sigma, k] (optionally += e)
+//             one workgroup per (a, sigma); threads over rows, P read in its
+//             second, row-contiguous copy, e_c staged in LDS.
+#include "kernels.hpp"
+
+namespace mg {
+
+// Null vectors (canonical single-level layout, nv[k][flat]) -> P in the
+// prolong layout PP[a][sigma][k][row], FP64, before orthonormalisation.
+__global__ void gather_null_kernel(const double2* __restrict__ nv, int64_t nflat, double2* __restrict__ pp,
+                                   Agg A) {
+  const int64_t per = (int64_t)A.nvec * A.nrows;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= A.nagg * 2 * per) return;
+  const int64_t as = tid / per;
+  const int rem = (int)(tid - as * per);
+  const int k = rem / A.nrows, row = rem - k * A.nrows;
+  const int64_t a = as >> 1;
+  const int sigma = (int)(as & 1);
+  pp[tid] = nv[(int64_t)k * nflat + agg_row_index(A, a, sigma, row)];
+}
+
+void launch_gather_null(const double2* nv, int64_t nflat, double2* pp, const Agg& A, hipStream_t st) {
+  const int64_t n = A.nagg * 2 * (int64_t)A.nvec * A.nrows;
+  gather_null_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(nv, nflat, pp, A);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block orthonormalisation in place (FP64): for every (a, sigma) the columns
+// of PP become the Q factor of the thin QR with positive real diag(R), by
+// classical Gram-Schmidt applied twice per column.  status[0] is set to 1 when
+// a column loses more than 1 - 1e-12 of its norm (numerically rank deficient).
+__global__ void __launch_bounds__(256) block_orth_kernel(double2* __restrict__ pp, Agg A,
+                                                         int* __restrict__ status) {
+  __shared__ double2 d[128];
+  __shared__ double red[4];
+  const int nrows = A.nrows, nvec = A.nvec;
+  double2* Q = pp + (int64_t)blockIdx.x * nvec * nrows;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int k = 0; k < nvec; ++k) {
+    double2* v = Q + (int64_t)k * nrows;
+    // initial norm
+    double s = 0.0;
+    for (int row = tid; row < nrows; row += 256) s += v[row].x * v[row].x + v[row].y * v[row].y;
+    s = wave_sum(s);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    const double n0 = sqrt(red[0] + red[1] + red[2] + red[3]);
+    __syncthreads();
+    for (int pass = 0; pass < 2 && k > 0; ++pass) {
+      for (int j = wave; j < k; j += 4) {
+        const double2* q = Q + (int64_t)j * nrows;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int row = lane; row < nrows; row += 64) cfmac(acc, q[row], v[row]);
+        acc.x = wave_sum(acc.x);
+        acc.y = wave_sum(acc.y);
+        if (lane == 0) d[j] = acc;
+      }
+      __syncthreads();
+      for (int row = tid; row < nrows; row += 256) {
+        double2 w = v[row];
+        for (int j = 0; j < k; ++j) {
+          const double2 q = Q[(int64_t)j * nrows + row];
+          const double2 dj = d[j];
+          w.x -= q.x * dj.x - q.y * dj.y;
+          w.y -= q.x * dj.y + q.y * dj.x;
+        }
+        v[row] = w;
+      }
+      __syncthreads();
+    }
+    s = 0.0;
+    for (int row = tid; row < nrows; row += 256) s += v[row].x * v[row].x + v[row].y * v[row].y;
+    s = wave_sum(s);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    const double n1 = sqrt(red[0] + red[1] + red[2] + red[3]);
+    __syncthreads();
+    if (!(n1 > 1e-12 * n0) || !(n0 > 0.0)) {
+      if (tid == 0) atomicOr(status, 1);
+    }
+    const double inv = n1 > 0.0 ? 1.0 / n1 : 0.0;
+    for (int row = tid; row < nrows; row += 256) {
+      double2 w = v[row];
+      v[row] = make_double2(w.x * inv, w.y * inv);
+    }
+    __syncthreads();
+  }
+}
+
+void launch_block_orth(double2* pp, const Agg& A, int* status, hipStream_t st) {
+  block_orth_kernel<<<(unsigned)(A.nagg * 2), 256, 0, st>>>(pp, A, status);
+}
+
+// PP64 -> PR64 (restrict layout), PR32, PP32
+__global__ void p_layouts_kernel(const double2* __restrict__ pp64, double2* __restrict__ pr64,
+                                 float2* __restrict__ pr32, float2* __restrict__ pp32, Agg A) {
+  const int64_t per = (int64_t)A.nvec * A.nrows;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= A.nagg * 2 * per) return;
+  const int64_t as = tid / per;
+  const int rem = (int)(tid - as * per);
+  const int row = rem / A.nvec, k = rem - row * A.nvec;   // restrict-layout position
+  const int64_t src = as * per + (int64_t)k * A.nrows + row;
+  const double2 v = pp64[src];
+  pr64[tid] = v;
+  if (pr32) pr32[tid] = make_float2((float)v.x, (float)v.y);
+  if (pp32) pp32[src] = make_float2((float)v.x, (float)v.y);
+}
+
+void launch_p_layouts(const double2* pp64, double2* pr64, float2* pr32, float2* pp32, const Agg& A,
+                      hipStream_t st) {
+  const int64_t n = A.nagg * 2 * (int64_t)A.nvec * A.nrows;
+  p_layouts_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(pp64, pr64, pr32, pp32, A);
+}
+
+template <typename R, int NR, int KPL>
+__global__ void __launch_bounds__(256) restrict_kernel(const RestrictArgs<R> a) {
+  using T = cplx<R>;
+  __shared__ T red[3][NR][KPL * 64];
+  const int64_t as = blockIdx.x;
+  const int64_t agg = as >> 1;
+  const int sigma = (int)(as & 1);
+  const int r0 = blockIdx.y * NR;
+  const int nr = (a.nrhs - r0) < NR ? (a.nrhs - r0) : NR;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nvec = a.A.nvec, nrows = a.A.nrows;
+  const T* P = a.pr + as * (int64_t)nrows * nvec;
+  T acc[NR][KPL];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) { acc[r][q].x = 0; acc[r][q].y = 0; }
+  for (int row = wave; row < nrows; row += 4) {
+    const int64_t fi = agg_row_index(a.A, agg, sigma, row);
+    T x[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r < nr) x[r] = a.in[(int64_t)(r0 + r) * a.in_stride + fi];
+      else { x[r].x = 0; x[r].y = 0; }
+    }
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+      const int k = lane + 64 * q;
+      if (k < nvec) {
+        const T p = P[(int64_t)row * nvec + k];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cfmac(acc[r][q], p, x[r]);
+      }
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int q = 0; q < KPL; ++q) red[wave - 1][r][lane + 64 * q] = acc[r][q];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+      const int k = lane + 64 * q;
+      if (k >= nvec) continue;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r >= nr) continue;
+        T v = acc[r][q];
+        for (int w = 0; w < 3; ++w) { v.x += red[w][r][k].x; v.y += red[w][r][k].y; }
+        a.out[(int64_t)(r0 + r) * a.out_stride + agg * a.out_site_stride + sigma * nvec + k] = v;
+      }
+    }
+  }
+}
+
+template <typename R>
+void launch_restrict(const RestrictArgs<R>& a, hipStream_t st) {
+  if (a.nrhs <= 0) return;
+  const unsigned gx = (unsigned)(a.A.nagg * 2);
+  const bool big = a.A.nvec > 64;
+  if (a.nrhs >= 4) {
+    dim3 grid(gx, (unsigned)((a.nrhs + 3) / 4));
+    if (big) restrict_kernel<R, 4, 2><<<grid, 256, 0, st>>>(a);
+    else restrict_kernel<R, 4, 1><<<grid, 256, 0, st>>>(a);
+  } else {
+    dim3 grid(gx, (unsigned)a.nrhs);
+    if (big) restrict_kernel<R, 1, 2><<<grid, 256, 0, st>>>(a);
+    else restrict_kernel<R, 1, 1><<<grid, 256, 0, st>>>(a);
+  }
+}
+template void launch_restrict<float>(const RestrictArgs<float>&, hipStream_t);
+template void launch_restrict<double>(const RestrictArgs<double>&, hipStream_t);
+
+template <typename R, int NR>
+__global__ void __launch_bounds__(256) prolong_kernel(const ProlongArgs<R> a) {
+  using T = cplx<R>;
+  __shared__ T ec[NR][128];
+  const int64_t as = blockIdx.x;
+  const int64_t agg = as >> 1;
+  const int sigma = (int)(as & 1);
+  const int r0 = blockIdx.y * NR;
+  const int nr = (a.nrhs - r0) < NR ? (a.nrhs - r0) : NR;
+  const int tid = threadIdx.x;
+  const int nvec = a.A.nvec, nrows = a.A.nrows;
+  const T* P = a.pp + as * (int64_t)nrows * nvec;
+  for (int e = tid; e < NR * nvec; e += 256) {
+    const int r = e / nvec, k = e - r * nvec;
+    T v;
+    v.x = 0; v.y = 0;
+    if (r < nr) {
+      if (a.unit_col >= 0) {
+        if (sigma * nvec + k == a.unit_col) v.x = 1;
+      } else {
+        v = a.in[(int64_t)(r0 + r) * a.in_stride + agg * 2 * nvec + sigma * nvec + k];
+      }
+    }
+    ec[r][k] = v;
+  }
+  __syncthreads();
+  for (int row = tid; row < nrows; row += 256) {
+    T acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) { acc[r].x = 0; acc[r].y = 0; }
+    for (int k = 0; k < nvec; ++k) {
+      const T p = P[(int64_t)k * nrows + row];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) cfma(acc[r], p, ec[r][k]);
+    }
+    const int64_t fi = agg_row_index(a.A, agg, sigma, row);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r >= nr) continue;
+      T* o = a.out + (int64_t)(r0 + r) * a.out_stride + fi;
+      T v = acc[r];
+      if (a.accumulate) { const T old = *o; v.x += old.x; v.y += old.y; }
+      *o = v;
+    }
+  }
+}
+
+template <typename R>
+void launch_prolong(const ProlongArgs<R>& a, hipStream_t st) {
+  if (a.nrhs <= 0) return;
+  const unsigned gx = (unsigned)(a.A.nagg * 2);
+  if (a.nrhs >= 4) {
+    dim3 grid(gx, (unsigned)((a.nrhs + 3) / 4));
+    prolong_kernel<R, 4><<<grid, 256, 0, st>>>(a);
+  } else {
+    dim3 grid(gx, (unsigned)a.nrhs);
+    prolong_kernel<R, 1><<<grid, 256, 0, st>>>(a);
+  }
+}
+template void launch_prolong<float>(const ProlongArgs<float>&, hipStream_t);
+template void launch_prolong<double>(const ProlongArgs<double>&, hipStream_t);
+
+}  // namespace mg

@@ -1,0 +1,293 @@
+"""Python binding of the mgstag C ABI (include/mgstag.h).
+
+Argument marshalling only: every operation runs in the HIP library
+libmgstag.so next to this file.  PyTorch provides device memory (the
+workspaces are torch uint8 tensors owned by the Context object) and streams
+(torch's current stream is passed to every call).  Importing this module
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmgstag.so")
+
+MG_OK, MG_E_ARG, MG_E_CONFIG, MG_E_ALIGN, MG_E_RANK, MG_E_NOCONV, MG_E_NONFINITE, MG_E_HIP, MG_E_STATE, \
+    MG_E_WORKSPACE = range(10)
+MG_C128, MG_C64, MG_CBF16, MG_CF16 = range(4)
+STATUS_NAMES = ["MG_OK", "MG_E_ARG", "MG_E_CONFIG", "MG_E_ALIGN", "MG_E_RANK", "MG_E_NOCONV",
+                "MG_E_NONFINITE", "MG_E_HIP", "MG_E_STATE", "MG_E_WORKSPACE"]
+
+
+class MGParams(ctypes.Structure):
+    _fields_ = [
+        ("dims", ctypes.c_int32 * 4),
+        ("c1", ctypes.c_double), ("c3", ctypes.c_double),
+        ("kd_naik", ctypes.c_int32),
+        ("mass0", ctypes.c_double),
+        ("nagg", ctypes.c_int32),
+        ("block", (ctypes.c_int32 * 4) * 2),
+        ("nvec", ctypes.c_int32 * 2),
+        ("setup_maxiter", ctypes.c_int32 * 2),
+        ("setup_tol", ctypes.c_double * 2),
+        ("smoother_s", ctypes.c_int32),
+        ("inner_tol", ctypes.c_double),
+        ("inner_maxiter", ctypes.c_int32),
+        ("coarsest_tol", ctypes.c_double),
+        ("coarsest_maxiter", ctypes.c_int32),
+        ("coarsest_restarts", ctypes.c_int32),
+        ("outer_nkrylov", ctypes.c_int32),
+        ("outer_maxiter", ctypes.c_int32),
+        ("reliable_delta", ctypes.c_double),
+        ("fine_prec", ctypes.c_int32),
+        ("coarse_prec", ctypes.c_int32),
+        ("max_nrhs", ctypes.c_int32),
+        ("max_nmass", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class MGSolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("outer_iters", ctypes.c_int32),
+        ("reliable_updates", ctypes.c_int32),
+        ("level_iters", ctypes.c_int32 * 4),
+        ("true_rel_residual", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("status", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {"outer_iters": self.outer_iters, "reliable_updates": self.reliable_updates,
+                "level_iters": list(self.level_iters), "true_rel_residual": self.true_rel_residual,
+                "seconds": self.seconds, "status": STATUS_NAMES[self.status]}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"mgstag HIP library not built: {LIB_PATH} is missing "
+                          "(run python -m paper_2212_12559_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, vp, sz, i32, f64 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "mg_default_params": (None, [P(MGParams), P(ctypes.c_int32 * 4)]),
+        "mg_workspace_bytes": (i32, [P(MGParams), P(sz), P(sz)]),
+        "mg_setup": (i32, [P(MGParams), vp, vp, P(vp), vp, sz, vp, sz, vp, P(vp)]),
+        "mg_apply_dslash": (i32, [vp, i32, f64, i32, vp, vp, i32, vp]),
+        "mg_apply_coarse": (i32, [vp, i32, i32, vp, vp, i32, vp]),
+        "mg_restrict": (i32, [vp, i32, i32, vp, vp, i32, vp]),
+        "mg_prolong": (i32, [vp, i32, i32, vp, vp, i32, i32, vp]),
+        "mg_solve": (i32, [vp, P(f64), i32, vp, vp, i32, f64, P(MGSolveInfo), vp]),
+        "mg_cg_solve": (i32, [vp, P(f64), i32, vp, vp, i32, f64, i32, P(MGSolveInfo), vp]),
+        "mg_export": (i32, [vp, i32, i32, vp, sz, P(sz), vp]),
+        "mg_destroy": (i32, [vp]),
+        "mg_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+class MGError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = LIB.mg_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES[status] if 0 <= status < 10 else status}: {msg}")
+
+
+def _check(status, where):
+    if status != MG_OK:
+        raise MGError(status, where)
+
+
+def default_params(dims, **overrides) -> MGParams:
+    p = MGParams()
+    d = (ctypes.c_int32 * 4)(*dims)
+    LIB.mg_default_params(ctypes.byref(p), ctypes.byref(d))
+    for k, v in overrides.items():
+        if k == "block":
+            for l in range(2):
+                for mu in range(4):
+                    p.block[l][mu] = v[l][mu] if l < len(v) else 1
+        elif k in ("nvec", "setup_maxiter", "setup_tol", "dims"):
+            arr = getattr(p, k)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def workspace_bytes(p: MGParams):
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(LIB.mg_workspace_bytes(ctypes.byref(p), ctypes.byref(a), ctypes.byref(b)), "mg_workspace_bytes")
+    return a.value, b.value
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return MG_C128
+    if t.dtype == torch.complex64:
+        return MG_C64
+    raise TypeError(f"unsupported dtype {t.dtype} (complex128 or complex64)")
+
+
+def _dev(t, name):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """An mg_ctx with its two caller-owned device workspaces."""
+
+    def __init__(self, params: MGParams, fat, naik=None, null_vectors=None):
+        torch = _torch()
+        self.params = params
+        self.dims = tuple(params.dims)
+        pb, sb = workspace_bytes(params)
+        dev = fat.device
+        # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
+        self.persistent = torch.empty(pb, dtype=torch.uint8, device=dev)
+        self.scratch = torch.empty(sb, dtype=torch.uint8, device=dev)
+        if fat.dtype != torch.complex128:
+            raise TypeError("links must be complex128")
+        nvp = None
+        self._keep = []
+        if null_vectors is not None:
+            arr = (ctypes.c_void_p * 2)()
+            for l in range(params.nagg):
+                v = null_vectors[l] if l < len(null_vectors) else None
+                if v is not None:
+                    if v.dtype != torch.complex128:
+                        raise TypeError("null vectors must be complex128")
+                    self._keep.append(v)
+                    arr[l] = v.data_ptr()
+            nvp = arr
+        ctx = ctypes.c_void_p()
+        st = LIB.mg_setup(ctypes.byref(params), _dev(fat, "fat"),
+                          _dev(naik, "naik") if naik is not None else None,
+                          nvp, ctypes.c_void_p(self.persistent.data_ptr()), pb,
+                          ctypes.c_void_p(self.scratch.data_ptr()), sb, _stream(), ctypes.byref(ctx))
+        _check(st, "mg_setup")
+        self.ctx = ctx
+        X, Y, Z, T = self.dims
+        self.fine_shape = (T, Z, Y, X, 3)
+        self.coarse_shapes = []
+        cd = list(self.dims)
+        nin = None
+        for l in range(params.nagg):
+            cd = [cd[mu] // params.block[l][mu] for mu in range(4)]
+            self.coarse_shapes.append((cd[3], cd[2], cd[1], cd[0], 2, params.nvec[l]))
+
+    # ---------------------------------------------------------------- applies
+    def apply_dslash(self, op, mass, x, out=None):
+        torch = _torch()
+        out = torch.empty_like(x) if out is None else out
+        nrhs = x.numel() // (3 * self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3])
+        _check(LIB.mg_apply_dslash(self.ctx, op, mass, _dtype_code(x), _dev(x, "x"), _dev(out, "out"), nrhs,
+                                   _stream()), "mg_apply_dslash")
+        return out
+
+    def _level_size(self, level):
+        if level == 1:
+            return 3 * self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        s = self.coarse_shapes[level - 2]
+        n = 1
+        for v in s:
+            n *= v
+        return n
+
+    def apply_coarse(self, level, x, out=None):
+        torch = _torch()
+        out = torch.empty_like(x) if out is None else out
+        nrhs = x.numel() // self._level_size(level)
+        _check(LIB.mg_apply_coarse(self.ctx, level, _dtype_code(x), _dev(x, "x"), _dev(out, "out"), nrhs,
+                                   _stream()), "mg_apply_coarse")
+        return out
+
+    def restrict(self, level, x, out=None):
+        torch = _torch()
+        nrhs = x.numel() // self._level_size(level)
+        if out is None:
+            out = torch.empty((nrhs,) + self.coarse_shapes[level - 1], dtype=x.dtype, device=x.device)
+        _check(LIB.mg_restrict(self.ctx, level, _dtype_code(x), _dev(x, "x"), _dev(out, "out"), nrhs, _stream()),
+               "mg_restrict")
+        return out
+
+    def prolong(self, level, xc, out=None, accumulate=False):
+        torch = _torch()
+        nrhs = xc.numel() // self._level_size(level + 1)
+        if out is None:
+            shape = self.fine_shape if level == 1 else self.coarse_shapes[level - 2]
+            out = torch.zeros((nrhs,) + tuple(shape), dtype=xc.dtype, device=xc.device)
+        _check(LIB.mg_prolong(self.ctx, level, _dtype_code(xc), _dev(xc, "xc"), _dev(out, "out"),
+                              1 if accumulate else 0, nrhs, _stream()), "mg_prolong")
+        return out
+
+    # ---------------------------------------------------------------- solves
+    def _solve(self, fn, masses, b, tol, extra=()):
+        torch = _torch()
+        nrhs = b.shape[0]
+        nm = len(masses)
+        x = torch.empty((nm,) + tuple(b.shape), dtype=torch.complex128, device=b.device)
+        infos = (MGSolveInfo * (nm * nrhs))()
+        m = (ctypes.c_double * nm)(*masses)
+        st = fn(self.ctx, m, nm, _dev(b, "b"), _dev(x, "x"), nrhs, tol, *extra, infos, _stream())
+        return st, x, [i.as_dict() for i in infos]
+
+    def solve(self, masses, b, tol=1e-10, check=True):
+        """MG-GCR solve of D(m) x = b for every mass; b [nrhs][T][Z][Y][X][3] complex128."""
+        st, x, info = self._solve(LIB.mg_solve, masses, b, tol)
+        if check:
+            _check(st, "mg_solve")
+        return x, info, st
+
+    def cg_solve(self, masses, b, tol=1e-10, maxiter=100000, check=True):
+        st, x, info = self._solve(LIB.mg_cg_solve, masses, b, tol, (maxiter,))
+        if check:
+            _check(st, "mg_cg_solve")
+        return x, info, st
+
+    def export(self, what, level=1):
+        torch = _torch()
+        need = ctypes.c_size_t()
+        _check(LIB.mg_export(self.ctx, what, level, None, 0, ctypes.byref(need), _stream()), "mg_export")
+        dt = torch.int32 if what == 0 else torch.complex128
+        esz = 4 if what == 0 else 16
+        out = torch.empty(need.value // esz, dtype=dt, device=self.persistent.device)
+        _check(LIB.mg_export(self.ctx, what, level, _dev(out, "dst"), need.value, None, _stream()), "mg_export")
+        return out
+
+    def destroy(self):
+        if getattr(self, "ctx", None):
+            LIB.mg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def setup(params, fat, naik=None, null_vectors=None) -> Context:
+    return Context(params, fat, naik, null_vectors)

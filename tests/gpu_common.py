@@ -1,0 +1,80 @@
+"""Shared helpers of the GPU parity tests: seeded configurations, oracle
+counterparts and error metrics."""
+import sys
+
+import numpy as np
+
+from oracle import operators as ops
+from oracle import solvers as sol
+from paper_2212_12559_amd import latgen
+
+C1H, C3H = 9.0 / 8.0, -1.0 / 24.0
+
+# name: dims, coefficients, kd_naik, blocks, nvec, mass0
+CONFIGS = {
+    # 4^4 naive, KD then 2^4 aggregation, Nvec 24 (square P)
+    "c0": dict(dims=(4, 4, 4, 4), c1=1.0, c3=0.0, kd_naik=1, blocks=[(2, 2, 2, 2)], nvec=(24,), mass0=0.1,
+               eps=0.3, seed=latgen.SEEDS["c0_4x4_naive"]),
+    # 8^4 HISQ-style, two aggregations (coarse 2^4, then 1^4)
+    "cubic": dict(dims=(8, 8, 8, 8), c1=C1H, c3=C3H, kd_naik=1, blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], nvec=(8, 8),
+                  mass0=0.05, eps=0.5, seed=latgen.SEEDS["small_8x4_hisq"]),
+    # ragged: V = 2304 (9 blocks of 256), odd coarse extent 3, extents 1
+    "ragged": dict(dims=(8, 4, 6, 12), c1=C1H, c3=C3H, kd_naik=0, blocks=[(4, 4, 6, 4), (2, 1, 1, 3)],
+                   nvec=(10, 12), mass0=0.07, eps=0.5, seed=424242),
+    # the 16^4 HISQ-style hierarchy shape: KD, 4^4 / Nvec 64, 2^4 / Nvec 96
+    "c1": dict(dims=(16, 16, 16, 16), c1=C1H, c3=C3H, kd_naik=1, blocks=[(4, 4, 4, 4), (2, 2, 2, 2)],
+               nvec=(64, 96), mass0=0.01, eps=0.5, seed=latgen.SEEDS["c1_16x4_hisq"]),
+}
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def links(cfg):
+    if cfg["c3"] == 0.0:
+        W, N, rng = latgen.naive_links(cfg["dims"], cfg["eps"], cfg["seed"])
+    else:
+        W, N, rng = latgen.hisq_style_links(cfg["dims"], cfg["eps"], cfg["seed"])
+    return W, N, rng
+
+
+def coarse_dims(dims, block):
+    return tuple(d // b for d, b in zip(dims, block))
+
+
+def random_null_vectors(cfg, rng):
+    """Full-rank random near-null vectors (inputs only; any full-rank set
+    defines a valid transfer for operator parity)."""
+    nv = [latgen.fine_vectors(cfg["dims"], cfg["nvec"][0], rng)]
+    if len(cfg["blocks"]) > 1:
+        cd = coarse_dims(cfg["dims"], cfg["blocks"][0])
+        nv.append(latgen.coarse_vectors(cd, cfg["nvec"][0], cfg["nvec"][1], rng))
+    return nv
+
+
+def oracle_hierarchy(cfg, W, N, mass, nvs, **kw):
+    p = sol.MGParams(dims=cfg["dims"], c1=cfg["c1"], c3=cfg["c3"], kd_naik=bool(cfg["kd_naik"]),
+                     blocks=tuple(cfg["blocks"]), **kw)
+    return sol.Hierarchy(p, W, N, mass, nvs)
+
+
+def gpu_params(mg, cfg, **kw):
+    p = mg.default_params(cfg["dims"], c1=cfg["c1"], c3=cfg["c3"], kd_naik=cfg["kd_naik"],
+                          nagg=len(cfg["blocks"]), block=cfg["blocks"], nvec=tuple(cfg["nvec"]) + (1,) * (2 - len(cfg["nvec"])),
+                          mass0=cfg["mass0"])
+    for k, v in kw.items():
+        if k in ("setup_maxiter", "setup_tol", "nvec"):
+            arr = getattr(p, k)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def rel_err(got, want):
+    got = np.asarray(got)
+    want = np.asarray(want)
+    return float(np.max(np.abs(got - want)) / max(np.max(np.abs(want)), 1e-300))

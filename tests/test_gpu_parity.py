@@ -1,0 +1,214 @@
+"""GPU parity: every hot-path operator of the HIP library, called through the
+C ABI, against the FP64 oracle on the same seeded inputs.
+
+Tolerances (max |gpu - oracle| / max |oracle| over the output):
+  FP64 paths 1e-12; FP32 paths 1e-5 (the per-apply bars of the method's
+  mixed-precision design); integer index tables bit-exact.
+"""
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from paper_2212_12559_amd import latgen
+
+from gpu_common import CONFIGS, coarse_dims, gpu_params, links, log, oracle_hierarchy, random_null_vectors, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mg(torch):
+    from paper_2212_12559_amd import mgstag
+    return mgstag
+
+
+class Case:
+    """One configuration with random (full-rank) imported null vectors."""
+
+    def __init__(self, name, torch, mg, max_nrhs=5):
+        log(f"[setup] config {name}")
+        self.name = name
+        self.cfg = cfg = CONFIGS[name]
+        self.W, self.N, rng = links(cfg)
+        self.rng = rng
+        self.nvs = random_null_vectors(cfg, rng)
+        self.torch = torch
+        dev = "cuda:0"
+        self.Wt = torch.from_numpy(self.W).to(dev)
+        self.Nt = torch.from_numpy(self.N).to(dev)
+        nvt = [torch.from_numpy(v).to(dev) for v in self.nvs]
+        p = gpu_params(mg, cfg, max_nrhs=max_nrhs, fine_prec=mg.MG_C128, coarse_prec=mg.MG_C128)
+        self.ctx = mg.setup(p, self.Wt, self.Nt if cfg["c3"] != 0.0 else None, nvt)
+        torch.cuda.synchronize()
+        self.H = oracle_hierarchy(cfg, self.W, self.N, cfg["mass0"], self.nvs)
+
+    def to_gpu(self, a, dtype):
+        return self.torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0").to(dtype)
+
+    def back(self, t):
+        self.torch.cuda.synchronize()
+        return t.to(self.torch.complex128).cpu().numpy()
+
+
+_cases = {}
+
+
+@pytest.fixture(scope="module", params=["c0", "cubic", "ragged"])
+def case(request, torch, mg):
+    name = request.param
+    if name not in _cases:
+        _cases[name] = Case(name, torch, mg)
+    return _cases[name]
+
+
+def test_index_tables_bit_exact(case):
+    """Neighbours, eta, eps, hypercube and aggregate maps exactly as the
+    kernels compute them, against the oracle's definitions."""
+    log(f"[index] {case.name}")
+    t = case.ctx.export(0).cpu().numpy().reshape(-1, 22)
+    dims = case.cfg["dims"]
+    X, Y, Z, T = dims
+    x, y, z, tt = [c.reshape(-1) for c in ops.coords(dims)]
+    co = [x, y, z, tt]
+    L = [X, Y, Z, T]
+    idx = lambda c: c[0] + X * (c[1] + Y * (c[2] + Z * c[3]))
+    for mu in range(4):
+        for k, (h, col) in enumerate([(1, 0), (-1, 4), (3, 8), (-3, 12)]):
+            cc = list(co)
+            cc[mu] = (co[mu] + h) % L[mu]
+            assert np.array_equal(t[:, col + mu], idx(cc)), (mu, h)
+    eta = ops.staggered_eta(dims).reshape(4, -1)
+    bits = sum(((eta[mu] < 0).astype(np.int64) << mu) for mu in range(4))
+    assert np.array_equal(t[:, 16], bits)
+    assert np.array_equal(t[:, 17], ops.epsilon(dims).reshape(-1).astype(np.int64))
+    hc, s = ops.hypercube_index(dims)
+    assert np.array_equal(t[:, 18], hc.reshape(-1))
+    assert np.array_equal(t[:, 19], s.reshape(-1))
+    agg, chi = ops.fine_dof_labels(dims, case.cfg["blocks"][0])
+    assert np.array_equal(t[:, 20], agg[::3])
+    assert np.array_equal(t[:, 21], chi[::3])
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("nrhs", [1, 5])
+def test_dslash_parity(case, prec, nrhs):
+    torch = case.torch
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    tol = TOL64 if prec == "c128" else TOL32
+    cfg = case.cfg
+    m = 0.0371
+    x = latgen.fine_vectors(cfg["dims"], nrhs, case.rng)
+    log(f"[dslash] {case.name} {prec} nrhs={nrhs}")
+    y = case.back(case.ctx.apply_dslash(0, m, case.to_gpu(x, dt)))
+    yd = case.back(case.ctx.apply_dslash(3, m, case.to_gpu(x, dt)))
+    for r in range(nrhs):
+        want = ops.dslash(x[r], case.W, case.N, m, cfg["c1"], cfg["c3"])
+        assert rel_err(y[r], want) < tol
+        want_d = ops.dslash_dagger(x[r], case.W, case.N, m, cfg["c1"], cfg["c3"])
+        assert rel_err(yd[r], want_d) < tol
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_kd_parity(case, prec):
+    """(B+m)^{-1} x and A x = (B+m)^{-1} D x (Naik kept or truncated per config)."""
+    torch = case.torch
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    tol = TOL64 if prec == "c128" else TOL32
+    cfg = case.cfg
+    m = cfg["mass0"]
+    x = latgen.fine_vectors(cfg["dims"], 3, case.rng)
+    log(f"[kd] {case.name} {prec}")
+    yk = case.back(case.ctx.apply_dslash(2, m, case.to_gpu(x, dt)))
+    ya = case.back(case.ctx.apply_dslash(1, m, case.to_gpu(x, dt)))
+    c3kd = cfg["c3"] if cfg["kd_naik"] else 0.0
+    for r in range(3):
+        assert rel_err(yk[r], ops.kd_apply(case.H.Kinv, x[r])) < tol
+        want = ops.kd_operator(x[r], case.W, case.N, case.H.Kinv, m, cfg["c1"], c3kd)
+        assert rel_err(ya[r], want) < tol
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_restrict_prolong_parity(case, prec):
+    torch = case.torch
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    tol = TOL64 if prec == "c128" else TOL32
+    cfg = case.cfg
+    nlev = len(cfg["blocks"])
+    for lvl in range(1, nlev + 1):
+        shape = case.H.fine_shape(lvl)
+        cshape = case.H.fine_shape(lvl + 1)
+        r = latgen.complex_normal(case.rng, (3,) + shape)
+        ec = latgen.complex_normal(case.rng, (3,) + cshape)
+        log(f"[transfer] {case.name} {prec} level {lvl}")
+        rc = case.back(case.ctx.restrict(lvl, case.to_gpu(r, dt)))
+        base = latgen.complex_normal(case.rng, (3,) + shape)
+        e = case.back(case.ctx.prolong(lvl, case.to_gpu(ec, dt)))
+        ea = case.back(case.ctx.prolong(lvl, case.to_gpu(ec, dt), out=case.to_gpu(base, dt), accumulate=True))
+        t = case.H.transfers[lvl - 1]
+        for k in range(3):
+            assert rel_err(rc[k].reshape(-1), t.restrict(r[k]).reshape(-1)) < tol
+            pe = t.prolong(ec[k]).reshape(shape)
+            assert rel_err(e[k], pe) < tol
+            assert rel_err(ea[k], base[k] + pe) < tol
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_coarse_parity(case, prec):
+    """Coarse stencil (GPU-built direction-split Galerkin links) against the
+    oracle's definition R A P applied matrix-free."""
+    torch = case.torch
+    dt = torch.complex128 if prec == "c128" else torch.complex64
+    tol = TOL64 if prec == "c128" else TOL32
+    nlev = len(case.cfg["blocks"])
+    for lvl in range(2, nlev + 2):
+        shape = case.H.fine_shape(lvl)
+        x = latgen.complex_normal(case.rng, (2,) + shape)
+        log(f"[coarse] {case.name} {prec} level {lvl}")
+        y = case.back(case.ctx.apply_coarse(lvl, case.to_gpu(x, dt)))
+        for k in range(2):
+            want = case.H._galerkin(lvl, x[k])
+            assert rel_err(y[k], want) < tol
+
+
+def test_export_null_vectors_roundtrip(case):
+    log(f"[export] {case.name}")
+    for lvl in range(1, len(case.cfg["blocks"]) + 1):
+        got = case.ctx.export(1, lvl).cpu().numpy()
+        assert np.array_equal(got, case.nvs[lvl - 1].reshape(-1))
+
+
+def test_coarse_links_export_blocks(case):
+    """Exported level-2 links: applying them densely reproduces R A P, and the
+    +mu/-mu pieces are separately the face-crossing parts (their sum over the
+    aliasing neighbours equals the dense Galerkin block)."""
+    cfg = case.cfg
+    lvl = 2
+    n = 2 * cfg["nvec"][0]
+    cd = coarse_dims(cfg["dims"], cfg["blocks"][0])
+    Vc = int(np.prod(cd))
+    log(f"[links] {case.name}")
+    Lk = case.ctx.export(2, lvl).cpu().numpy().reshape(Vc, 9, n, n)
+    x = latgen.complex_normal(case.rng, case.H.fine_shape(lvl)).reshape(Vc, n)
+    X, Y, Z, T = cd
+    y = np.zeros_like(x)
+    for s in range(Vc):
+        c = [s % X, (s // X) % Y, (s // (X * Y)) % Z, s // (X * Y * Z)]
+        y[s] += Lk[s, 0] @ x[s]
+        for mu in range(4):
+            for d, h in ((1 + 2 * mu, 1), (2 + 2 * mu, -1)):
+                cc = list(c)
+                cc[mu] = (c[mu] + h) % cd[mu]
+                t = cc[0] + X * (cc[1] + Y * (cc[2] + Z * cc[3]))
+                y[s] += Lk[s, d] @ x[t]
+    want = case.H._galerkin(lvl, x.reshape(case.H.fine_shape(lvl))).reshape(Vc, n)
+    assert rel_err(y, want) < TOL64
