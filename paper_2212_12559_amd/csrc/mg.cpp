@@ -381,7 +381,8 @@ void Ctx::norms_host(int prec, int64_t n, int nsys, const void* v, double2* res_
   HIPCHK(hipMemcpyAsync(h.data(), res_dev, nsys * sizeof(double2), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   out.resize(nsys);
-  for (int s = 0; s < nsys; ++s) out[s] = std::sqrt(std::fmax(h[s].x, 0.0));
+  // NaN propagates (a non-finite input must be reported, not read as zero)
+  for (int s = 0; s < nsys; ++s) out[s] = h[s].x >= 0.0 ? std::sqrt(h[s].x) : (h[s].x < 0.0 ? 0.0 : h[s].x);
 }
 
 // ==================================================================== solvers
