@@ -27,11 +27,11 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     # 32^4 HISQ-style, eps 0.5 (as the 16^4 workload), mass 0.005, KD + 4^4/Nvec 64 + 2^4/Nvec 96
-    "c2": dict(dims=(32, 32, 32, 32), mass=0.005, nrhs=1, eps=0.5, seed=20221226,
-               nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(300, 200)),
+    "c2": dict(dims=(32, 32, 32, 32), mass=0.005, nrhs=1, eps=0.5, seed=20221226, kd_naik=0,
+               nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(1000, 300)),
     # 16^4 HISQ-style, mass 0.01
-    "c1": dict(dims=(16, 16, 16, 16), mass=0.01, nrhs=1, eps=0.5, seed=20221225,
-               nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(300, 200)),
+    "c1": dict(dims=(16, 16, 16, 16), mass=0.01, nrhs=1, eps=0.5, seed=20221225, kd_naik=0,
+               nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 2000)),
 }
 
 
@@ -60,10 +60,10 @@ def op_counts(info, s, nlev):
 
 
 # ---------------------------------------------------------------- bytes
-def algorithmic_bytes(dims, nvec, nrhs=1, csz=8):
+def algorithmic_bytes(dims, nvec, nrhs=1, csz=8, naik=True):
     """Per-apply algorithmic HBM bytes (each operand read or written once)."""
     V = int(np.prod(dims))
-    links = 8 * 9 * csz          # fat + Naik, 4 directions each, 3x3 complex
+    links = 8 * 9 * csz          # fat + Naik, 4 directions each, 3x3 complex (op 0 always has Naik)
     vec = 3 * csz
     b = {
         "dslash": V * (links + 2 * vec * nrhs),
@@ -75,6 +75,110 @@ def algorithmic_bytes(dims, nvec, nrhs=1, csz=8):
     n = 2 * nvec[0]
     b["coarse2"] = Vc * (9 * n * n * csz + 2 * n * csz * nrhs)
     return b
+
+
+def kernel_rates(torch, ctx, wl, reps, mg):
+    """Average duration of each hot-path kernel at the workload's shape,
+    timed with HIP events on torch's current stream (the library's stream)."""
+    dims, m = wl["dims"], wl["mass"]
+    dev = "cuda:0"
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    X, Y, Z, T = dims
+    x = torch.randn((1, T, Z, Y, X, 3), dtype=torch.complex64, device=dev, generator=gen)
+    xc = torch.randn((1,) + ctx.coarse_shapes[0], dtype=torch.complex64, device=dev, generator=gen)
+    xc3 = torch.randn((1,) + ctx.coarse_shapes[1], dtype=torch.complex64, device=dev, generator=gen)
+    y = torch.empty_like(x)
+    yc = torch.empty_like(xc)
+    yc3 = torch.empty_like(xc3)
+    b = algorithmic_bytes(dims, wl["nvec"], naik=wl["kd_naik"] != 0)
+    n3 = 2 * wl["nvec"][1]
+    Vc3 = int(np.prod(ctx.coarse_shapes[1][:4]))
+    b["coarse3"] = Vc3 * (9 * n3 * n3 * 8 + 2 * n3 * 8)
+    ops = {
+        "dslash": lambda: ctx.apply_dslash(0, m, x, y),
+        "kd": lambda: ctx.apply_dslash(2, m, x, y),
+        "restrict": lambda: ctx.restrict(1, x, yc),
+        "prolong": lambda: ctx.prolong(1, xc, y),
+        "coarse2": lambda: ctx.apply_coarse(2, xc, yc),
+        "coarse3": lambda: ctx.apply_coarse(3, xc3, yc3),
+    }
+    out = {}
+    for name, f in ops.items():
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out[name] = {"us": us, "bytes": b[name], "GBps": b[name] / (us * 1e-6) / 1e9}
+        log(f"[bench] kernel {name}: {us:.1f} us, {out[name]['GBps']:.0f} GB/s")
+    return out
+
+
+def cpu_baseline(wl, info, s):
+    """The FP64 oracle (numpy, one thread) timed on a bounded sample: one
+    application of each hot-path operator at the workload's lattice (the
+    coarse operator at a 16^4 lattice, scaled by the volume ratio), combined
+    with the operator counts of the measured MG solve into the oracle's time
+    for the same solve."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import operators as ops
+    from oracle import solvers as sol
+    from paper_2212_12559_amd import latgen
+
+    dims, m = wl["dims"], wl["mass"]
+    c1, c3 = 9.0 / 8.0, -1.0 / 24.0
+    c3kd = c3 if wl["kd_naik"] else 0.0
+    t_total = time.perf_counter()
+    with threadpool_limits(1):
+        W, N, rng = latgen.hisq_style_links(dims, wl["eps"], wl["seed"])
+        x = latgen.fine_vectors(dims, 1, rng)[0]
+        t0 = time.perf_counter()
+        ops.dslash(x, W, N, m, c1, c3)
+        t_d = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ops.dslash(x, W, N, m, c1, c3kd)
+        t_d1 = time.perf_counter() - t0
+        Kinv = ops.kd_inverse(W, m, c1)
+        t0 = time.perf_counter()
+        ops.kd_apply(Kinv, x)
+        t_kd = time.perf_counter() - t0
+        del Kinv, W, N
+        # transfer and coarse operators on a 16^4 lattice, scaled by volume
+        sd = (16, 16, 16, 16)
+        scale = float(np.prod(dims)) / float(np.prod(sd))
+        W2, N2, rng2 = latgen.hisq_style_links(sd, wl["eps"], wl["seed"])
+        nv1 = latgen.fine_vectors(sd, wl["nvec"][0], rng2)
+        p = sol.MGParams(dims=sd, c1=c1, c3=c3, kd_naik=bool(wl["kd_naik"]), blocks=tuple(wl["blocks"][:1]))
+        H = sol.Hierarchy(p, W2, N2, m, [nv1])
+        xs = latgen.fine_vectors(sd, 1, rng2)[0]
+        t0 = time.perf_counter()
+        rc = H.restrict(1, xs)
+        t_r = (time.perf_counter() - t0) * scale
+        t0 = time.perf_counter()
+        H.prolong(1, rc)
+        t_p = (time.perf_counter() - t0) * scale
+        t0 = time.perf_counter()
+        H.op(2, rc)
+        t_c2 = (time.perf_counter() - t0) * scale
+    sample_s = time.perf_counter() - t_total
+    cnt = op_counts(info, s, 4)
+    est = (cnt["dslash_fp64"] * t_d + cnt["dslash_fp32_level0"] * t_d + cnt["dslash_fp32_level1"] * t_d1
+           + cnt["kd_fp32"] * t_kd + cnt["restrict1"] * t_r + cnt["prolong1"] * t_p
+           + (cnt["coarse2"] + cnt["coarse3"]) * t_c2)
+    log(f"[bench] cpu oracle: D {t_d:.2f}s KD {t_kd:.2f}s R {t_r:.2f}s P {t_p:.2f}s C2 {t_c2:.2f}s -> {est:.0f} s")
+    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"one oracle application each of D, D_KD, (B+m)^-1 at {'x'.join(map(str, dims))}, and of "
+                       f"R, P, the level-2 operator R A P at 16^4 scaled by the volume ratio; multiplied by the "
+                       f"operator counts of the measured MG solve (level-3 applies priced as level 2, Krylov "
+                       f"BLAS omitted: a lower bound); sample took {sample_s:.1f} s"),
+            "per_op_s": {"dslash": t_d, "dslash_kd": t_d1, "kd": t_kd, "restrict": t_r, "prolong": t_p,
+                         "coarse": t_c2}}
 
 
 def main():
@@ -104,7 +208,7 @@ def main():
     bt = torch.from_numpy(b).to(dev)
     del W, N
     p = mg.default_params(dims, mass0=m, nvec=wl["nvec"], block=wl["blocks"], setup_maxiter=wl["setup_iters"],
-                          max_nrhs=wl["nrhs"], max_nmass=1)
+                          max_nrhs=wl["nrhs"], max_nmass=1, kd_naik=wl["kd_naik"])
     log("[bench] setup")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -137,6 +241,17 @@ def main():
         cg_info = cinfo[0]
         log(f"[bench] CG {cg_s:.3f} s {cg_info}")
 
+    # ---- per-kernel timings (HIP events on the stream the library launches on)
+    kern = kernel_rates(torch, ctx, wl, args.kernel_reps, mg)
+    dom = kern["coarse2"]
+    roof = {"bound": "hbm", "kernel": "coarse_kernel<float,float2,1> (level-2 coarse stencil)",
+            "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": dom["bytes"], "avg_launch_us": dom["us"]}
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, infos[-1][0], p.smoother_s)
+
     out = {
         "metric": "MG-GCR time-to-1e-10 vs plain CG at 32^4 HISQ; Dslash/coarse GB/s, MFMA %",
         "value": mg_s,
@@ -158,6 +273,9 @@ def main():
         "cg_iters": cg_info["outer_iters"] if cg_info else None,
         "speedup_vs_cg": (cg_s / mg_s) if cg_s else None,
         "true_rel_residual": res,
+        "roofline": roof,
+        "kernels": {k: {"us": round(v["us"], 2), "GBps": round(v["GBps"], 1)} for k, v in kern.items()},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

@@ -96,15 +96,16 @@ __global__ void __launch_bounds__(256) lincomb_kernel(const LinCombArgs<T> a) {
     }
   }
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.n; e += (int64_t)gridDim.x * 256) {
-    double2 acc = make_double2(0.0, 0.0);
+    double2 acc = make_double2(0.0, 0.0), acc2 = make_double2(0.0, 0.0);
 #pragma unroll
     for (int t = 0; t < kMaxTerms; ++t) {
       if (t < a.nt) {
-        const double2 v = to_d2(a.v[t][off + e]);
-        cfma(acc, cf[t], v);
+        cfma(acc, cf[t], to_d2(a.v[t][off + e]));
+        if (a.out2) cfma(acc2, cf[t], to_d2(a.v2[t][off + e]));
       }
     }
     a.out[off + e] = from_d2<T>(acc);
+    if (a.out2) a.out2[off + e] = from_d2<T>(acc2);
   }
 }
 
@@ -133,6 +134,64 @@ template void launch_convert<double2, float2>(float2*, const double2*, int64_t, 
 template void launch_convert<float2, double2>(double2*, const float2*, int64_t, hipStream_t);
 template void launch_convert<double2, double2>(double2*, const double2*, int64_t, hipStream_t);
 template void launch_convert<float2, float2>(float2*, const float2*, int64_t, hipStream_t);
+
+// GCR update after orthogonalisation, one pass over the four vectors:
+//   x += alpha z, r -= alpha q, q *= inv, z *= inv, and partial sums of |r|^2
+template <typename T>
+__global__ void __launch_bounds__(256) gcr_update_kernel(T* __restrict__ x, T* __restrict__ r, T* __restrict__ q,
+                                                         T* __restrict__ z, const double2* __restrict__ alpha,
+                                                         const double2* __restrict__ inv, int64_t n,
+                                                         double2* __restrict__ part, int nblk, int nrhs) {
+  __shared__ double red[4];
+  const int rr = blockIdx.y;
+  const int64_t off = (int64_t)rr * n;
+  const double2 al = alpha[rr];
+  const double iv = inv[rr].x;
+  double s = 0.0;
+  for (int64_t e = off + (int64_t)blockIdx.x * 256 + threadIdx.x; e < off + n; e += (int64_t)nblk * 256) {
+    const double2 zv = to_d2(z[e]), qv = to_d2(q[e]);
+    double2 xv = to_d2(x[e]), rv = to_d2(r[e]);
+    cfma(xv, al, zv);
+    cfma(rv, make_double2(-al.x, -al.y), qv);
+    const T rt = from_d2<T>(rv);
+    x[e] = from_d2<T>(xv);
+    r[e] = rt;
+    q[e] = from_d2<T>(make_double2(qv.x * iv, qv.y * iv));
+    z[e] = from_d2<T>(make_double2(zv.x * iv, zv.y * iv));
+    const double2 rs = to_d2(rt);
+    s += rs.x * rs.x + rs.y * rs.y;
+  }
+  s = wsum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(int64_t)rr * nblk + blockIdx.x] = make_double2(red[0] + red[1] + red[2] + red[3], 0.0);
+}
+template <typename T>
+void launch_gcr_update(T* x, T* r, T* q, T* z, const double2* alpha, const double2* inv, int64_t n, int nrhs,
+                       double2* part, double2* res, int ldr, hipStream_t st) {
+  const int nblk = reduce_blocks(n);
+  dim3 grid(nblk, nrhs);
+  gcr_update_kernel<T><<<grid, 256, 0, st>>>(x, r, q, z, alpha, inv, n, part, nblk, nrhs);
+  finalize_kernel<<<nrhs, 64, 0, st>>>(part, nblk, 1, nrhs, res, ldr);
+}
+template void launch_gcr_update<float2>(float2*, float2*, float2*, float2*, const double2*, const double2*, int64_t,
+                                        int, double2*, double2*, int, hipStream_t);
+template void launch_gcr_update<double2>(double2*, double2*, double2*, double2*, const double2*, const double2*,
+                                         int64_t, int, double2*, double2*, int, hipStream_t);
+
+// Convergence on the device: mask[r] stays 1 while |r|^2 > tol^2 |r0|^2
+// (and both are finite); init sets mask from |r0|^2 > 0.
+__global__ void conv_kernel(int* mask, const double2* rn2, const double2* r0sq, double tol2, int nrhs, int init) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const double a = rn2[r].x, b = r0sq[r].x;
+  if (init) mask[r] = (b > 0.0 && b < 1e300) ? 1 : 0;
+  else if (mask[r]) mask[r] = (a > tol2 * b && a < 1e300) ? 1 : 0;
+}
+void launch_conv(int* mask, const double2* rn2, const double2* r0sq, double tol2, int nrhs, int init,
+                 hipStream_t st) {
+  conv_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(mask, rn2, r0sq, tol2, nrhs, init);
+}
 
 // ---------------------------------------------------------------- scalars
 // GCR: after orthogonalisation, qq = <q, q>, qr = <q, r>.

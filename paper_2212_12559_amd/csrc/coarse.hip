@@ -1,10 +1,11 @@
 // Coarse operator (Sec. 2.1 Galerkin A_c = R A P; Sec. 3.1 coarse stencil):
 //   y(a) = X(a) x(a) + sum_mu [ Y_{+mu}(a) x(a+mu) + Y_{-mu}(a) x(a-mu) ]
 // with dense (2 Nvec) x (2 Nvec) complex blocks, stored per site and direction
-// as [d][col][row] so that the rows of one column are contiguous: one thread
-// per output row, a workgroup per coarse site, the nine neighbour vectors
-// staged in LDS.  The +mu and -mu blocks are kept apart, so an extent-2
-// coarse direction (where a+mu = a-mu) is still exact.
+// as [d][col][row] so that the rows of one column are contiguous.  The +mu and
+// -mu blocks are kept apart, so an extent-2 coarse direction (where
+// a+mu = a-mu) is still exact.  The coarse lattices are small, so the
+// matrix-vector product is split over the K dimension as well (the paper's
+// "additional parallelism" for the coarse stencil, Sec. 3.1).
 #include "kernels.hpp"
 
 namespace mg {
@@ -16,101 +17,118 @@ __device__ __forceinline__ double2 load_link<double, double2>(const double2* p) 
 template <>
 __device__ __forceinline__ float2 load_link<float, float2>(const float2* p) { return *p; }
 
+// One workgroup of 16 wavefronts per (coarse site, 64-row tile, rhs tile):
+// the K = 9 n columns of the site's block row are split evenly over the
+// wavefronts (lanes run over rows, so every link load is one coalesced
+// segment), and the 16 partial sums are reduced in LDS.  This exposes
+// 16x more parallelism than one thread per row, which the small coarse
+// lattices need to keep enough loads in flight.
+constexpr int kCoarseWaves = 16;
+
 template <typename R, typename LT, int NR, bool PIECE, bool DAG>
-__global__ void __launch_bounds__(256) coarse_kernel(const CoarseArgs<R, LT> a) {
+__global__ void __launch_bounds__(64 * kCoarseWaves) coarse_kernel(const CoarseArgs<R, LT> a) {
   using T = cplx<R>;
-  extern __shared__ unsigned char smem_raw[];
-  T* xs = reinterpret_cast<T*>(smem_raw);   // [9][NR][n]
+  __shared__ T red[kCoarseWaves - 1][NR][64];
   const int n = a.n;
   const int64_t site = blockIdx.x;
-  const int r0 = blockIdx.y * NR;
+  const int row0 = blockIdx.y * 64;
+  const int r0 = blockIdx.z * NR;
   const int nr = (a.nrhs - r0) < NR ? (a.nrhs - r0) : NR;
-  const int tid = threadIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = row0 + lane;
+  const bool act = row < n;
   int c[4];
   site_coords(site, a.g, c);
   int64_t nb[9];
   int use[9];
   nb[0] = site;
-  use[0] = 1;
+  use[0] = PIECE ? (a.piece == 0) : 1;
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     nb[1 + 2 * mu] = site_shift(c, mu, 1, a.g);
     nb[2 + 2 * mu] = site_shift(c, mu, -1, a.g);
     if (PIECE) {
       const int u = c[mu] % a.blk[mu];
-      const int pf = (u == a.blk[mu] - 1) ? 1 + 2 * mu : 0;
-      const int pb = (u == 0) ? 2 + 2 * mu : 0;
-      use[1 + 2 * mu] = pf == a.piece;
-      use[2 + 2 * mu] = pb == a.piece;
+      use[1 + 2 * mu] = ((u == a.blk[mu] - 1) ? 1 + 2 * mu : 0) == a.piece;
+      use[2 + 2 * mu] = ((u == 0) ? 2 + 2 * mu : 0) == a.piece;
     } else {
       use[1 + 2 * mu] = 1;
       use[2 + 2 * mu] = 1;
     }
   }
-  if (PIECE) use[0] = (a.piece == 0);
-  for (int e = tid; e < 9 * NR * n; e += blockDim.x) {
-    const int d = e / (NR * n);
-    const int rem = e - d * NR * n;
-    const int r = rem / n, col = rem - r * n;
-    T v;
-    v.x = 0; v.y = 0;
-    if (r < nr && use[d]) v = a.in[(int64_t)(r0 + r) * a.in_stride + nb[d] * n + col];
-    xs[e] = v;
-  }
-  __syncthreads();
   const int64_t nn = (int64_t)n * n;
-  for (int row = tid; row < n; row += blockDim.x) {
-    T acc[NR];
+  const int K = 9 * n;
+  const int per = (K + kCoarseWaves - 1) / kCoarseWaves;
+  const int k0 = wave * per;
+  const int k1 = (k0 + per) < K ? (k0 + per) : K;
+  T acc[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) { acc[r].x = 0; acc[r].y = 0; }
-    for (int d = 0; d < 9; ++d) {
-      if (!use[d]) continue;
-      const T* xd = xs + d * NR * n;
-      if (!DAG) {
-        const LT* L = a.links + (site * 9 + d) * nn + row;
+  for (int r = 0; r < NR; ++r) { acc[r].x = 0; acc[r].y = 0; }
+  const T* in = a.in + (int64_t)r0 * a.in_stride;
+  int kk = k0;
+  while (kk < k1) {
+    const int d = kk / n;
+    const int cbeg = kk - d * n;
+    const int cend = (k1 - d * n) < n ? (k1 - d * n) : n;
+    kk = d * n + cend;
+    if (!use[d]) continue;
+    const T* xv = in + nb[d] * n;
+    if (!DAG) {
+      const LT* L = a.links + (site * 9 + d) * nn + (act ? row : 0);
 #pragma unroll 8
-        for (int col = 0; col < n; ++col) {
-          const T l = load_link<R, LT>(L + (int64_t)col * n);
+      for (int col = cbeg; col < cend; ++col) {
+        T l;
+        if (act) l = L[(int64_t)col * n];
+        else { l.x = 0; l.y = 0; }
 #pragma unroll
-          for (int r = 0; r < NR; ++r) cfma(acc[r], l, xd[r * n + col]);
-        }
-      } else {
-        // (A^dag)_{a, nb} = (A_{nb, a})^dag: the opposite direction's block at the neighbour
-        const int dd = d == 0 ? 0 : ((d & 1) ? d + 1 : d - 1);
-        const LT* L = a.links + (nb[d] * 9 + dd) * nn + (int64_t)row * n;
-#pragma unroll 8
-        for (int col = 0; col < n; ++col) {
-          const T l = load_link<R, LT>(L + col);
+        for (int r = 0; r < NR; ++r)
+          if (r < nr) cfma(acc[r], l, xv[(int64_t)r * a.in_stride + col]);
+      }
+    } else {
+      // (A^dag)_{a, nb} = (A_{nb, a})^dag: the opposite direction's block at the neighbour
+      const int dd = d == 0 ? 0 : ((d & 1) ? d + 1 : d - 1);
+      const LT* L = a.links + (nb[d] * 9 + dd) * nn + (int64_t)(act ? row : 0) * n;
+#pragma unroll 4
+      for (int col = cbeg; col < cend; ++col) {
+        T l;
+        if (act) l = L[col];
+        else { l.x = 0; l.y = 0; }
 #pragma unroll
-          for (int r = 0; r < NR; ++r) cfmac(acc[r], l, xd[r * n + col]);
-        }
+        for (int r = 0; r < NR; ++r)
+          if (r < nr) cfmac(acc[r], l, xv[(int64_t)r * a.in_stride + col]);
       }
     }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[wave - 1][r][lane] = acc[r];
+  }
+  __syncthreads();
+  if (wave == 0 && act) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       if (r >= nr) continue;
-      a.out[(int64_t)(r0 + r) * a.out_stride + site * n + row] = acc[r];
+      T v = acc[r];
+      for (int w = 0; w < kCoarseWaves - 1; ++w) { v.x += red[w][r][lane].x; v.y += red[w][r][lane].y; }
+      a.out[(int64_t)(r0 + r) * a.out_stride + site * n + row] = v;
     }
   }
 }
 
 template <typename R, typename LT, int NR>
 static void coarse_launch_nr(const CoarseArgs<R, LT>& a, bool piece, bool dag, hipStream_t st) {
-  const int threads = ((a.n + 63) / 64) * 64 > 256 ? 256 : ((a.n + 63) / 64) * 64;
-  dim3 grid((unsigned)a.g.V, (unsigned)((a.nrhs + NR - 1) / NR));
-  const size_t lds = (size_t)9 * NR * a.n * sizeof(cplx<R>);
-  if (piece) coarse_kernel<R, LT, NR, true, false><<<grid, threads, lds, st>>>(a);
-  else if (dag) coarse_kernel<R, LT, NR, false, true><<<grid, threads, lds, st>>>(a);
-  else coarse_kernel<R, LT, NR, false, false><<<grid, threads, lds, st>>>(a);
+  dim3 grid((unsigned)a.g.V, (unsigned)((a.n + 63) / 64), (unsigned)((a.nrhs + NR - 1) / NR));
+  const int threads = 64 * kCoarseWaves;
+  if (piece) coarse_kernel<R, LT, NR, true, false><<<grid, threads, 0, st>>>(a);
+  else if (dag) coarse_kernel<R, LT, NR, false, true><<<grid, threads, 0, st>>>(a);
+  else coarse_kernel<R, LT, NR, false, false><<<grid, threads, 0, st>>>(a);
 }
 
 template <typename R, typename LT>
 void launch_coarse(const CoarseArgs<R, LT>& a, bool piece, bool dag, hipStream_t st) {
   if (a.nrhs <= 0) return;
-  // keep the staged neighbour vectors within 64 KiB of LDS
-  const size_t per = (size_t)9 * a.n * sizeof(cplx<R>);
-  if (a.nrhs >= 4 && 4 * per <= 65536) coarse_launch_nr<R, LT, 4>(a, piece, dag, st);
-  else if (a.nrhs >= 2 && 2 * per <= 65536) coarse_launch_nr<R, LT, 2>(a, piece, dag, st);
+  if (a.nrhs >= 4) coarse_launch_nr<R, LT, 4>(a, piece, dag, st);
+  else if (a.nrhs >= 2) coarse_launch_nr<R, LT, 2>(a, piece, dag, st);
   else coarse_launch_nr<R, LT, 1>(a, piece, dag, st);
 }
 template void launch_coarse<double, double2>(const CoarseArgs<double, double2>&, bool, bool, hipStream_t);

@@ -149,10 +149,15 @@ __host__ __device__ __forceinline__ int64_t agg_row_index(const Agg& A, int64_t 
 enum Prec { P64 = 0, P32 = 1, PBF16 = 2, PF16 = 3 };
 inline size_t csize(int p) { return p == P64 ? 16 : (p == P32 ? 8 : 4); }
 
-constexpr int kMaxSlots = 64;        // reduction slots per rhs and level
+// Per-level scalar slots (one double2 per system each):
+//   0..47 dot products of one reduction (Gram matrix, projections)
+//   48..53 GCR / CG scalars, 54..61 CA-GCR coefficients, 64.. norms
+constexpr int kMaxSlots = 72;
 constexpr int kSlotQQ = 48;          // GCR: <q,q>, <q,r>, alpha, -alpha, 1/|q|
 constexpr int kSlotCoef = 54;        // CA-GCR coefficients (8)
-constexpr int kSlotNorm = 62;        // norms read by the host
+constexpr int kSlotRN = 64;          // |r|^2 after a GCR step
+constexpr int kSlotR0 = 65;          // |b|^2 of a level solve
+constexpr int kSlotNorm = 66;        // norms read by the host
 constexpr int kMaxNK = 16;           // Krylov directions per GCR
 constexpr int kMaxS = 8;             // CA-GCR basis size
 

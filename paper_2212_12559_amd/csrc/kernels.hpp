@@ -115,6 +115,8 @@ struct PairDotArgs {
 template <typename T>
 struct LinCombArgs {
   T* out;
+  T* out2;                       // optional second output with the same coefficients over v2
+  const T* v2[kMaxTerms];
   const T* v[kMaxTerms];
   const double2* c[kMaxTerms];   // per-rhs device coefficient, or null for cconst
   double2 cconst[kMaxTerms];
@@ -142,5 +144,10 @@ void launch_cg_alpha(const double2* rr, const double2* pap, const int* mask, int
 void launch_cg_beta(double2* rr, const double2* rrnew, const int* mask, int nrhs, double2* beta, hipStream_t st);
 template <typename T>
 void launch_random_normal(T* out, int64_t n, uint64_t seed, hipStream_t st);
+template <typename T>
+void launch_gcr_update(T* x, T* r, T* q, T* z, const double2* alpha, const double2* inv, int64_t n, int nrhs,
+                       double2* part, double2* res, int ldr, hipStream_t st);
+void launch_conv(int* mask, const double2* rn2, const double2* r0sq, double tol2, int nrhs, int init,
+                 hipStream_t st);
 
 }  // namespace mg

@@ -439,69 +439,120 @@ void Ctx::kcycle(int lvl, const Vec& r, const Vec& e, int nsys, SolveStats& stat
   smoother(lvl, e, B.t, nsys);
 }
 
+// One flexible-GCR direction on level lvl: z_k already holds K(r).
+// q_k = A z_k; classical Gram-Schmidt twice against q_0..q_{k-1} (the same
+// combination applied to z_k); then x += alpha z_k, r -= alpha q_k with
+// alpha = <q_k, r> / |q_k|^2 and q_k, z_k normalised, in one fused pass that
+// also leaves |r|^2 per system in slot(lvl, kSlotRN).
+void Ctx::gcr_step(int lvl, LevelBufs& B, const Vec& X, int k, int nsys) {
+  const int prec = B.prec;
+  const int64_t n = B.n;
+  apply_level(lvl, B.q[k], B.z[k], nsys);
+  for (int pass = 0; pass < 2 && k > 0; ++pass) {
+    std::vector<std::pair<const void*, const void*>> pr;
+    for (int i = 0; i < k; ++i) pr.push_back({B.q[i].p, B.q[k].p});
+    double2* beta = slot(lvl, 0);
+    dots(prec, n, nsys, pr, beta);
+    project(prec, n, nsys, B, k, beta);
+  }
+  double2* qq = slot(lvl, kSlotQQ);
+  dots(prec, n, nsys, {{B.q[k].p, B.q[k].p}, {B.q[k].p, B.r.p}}, qq);
+  double2 *al = slot(lvl, kSlotQQ + 2), *nal = slot(lvl, kSlotQQ + 3), *inv = slot(lvl, kSlotQQ + 4);
+  launch_gcr_scalars(qq, qq + max_sys, lmask(lvl), nsys, al, nal, inv, st);
+  check_launch();
+  if (prec == P64)
+    launch_gcr_update<double2>((double2*)X.p, (double2*)B.r.p, (double2*)B.q[k].p, (double2*)B.z[k].p, al, inv, n,
+                               nsys, part, slot(lvl, kSlotRN), max_sys, st);
+  else
+    launch_gcr_update<float2>((float2*)X.p, (float2*)B.r.p, (float2*)B.q[k].p, (float2*)B.z[k].p, al, inv, n, nsys,
+                              part, slot(lvl, kSlotRN), max_sys, st);
+  check_launch();
+}
+
+// q_k -= sum_i beta_i q_i and z_k -= sum_i beta_i z_i in one pass
+void Ctx::project(int prec, int64_t n, int nsys, LevelBufs& B, int k, const double2* beta) {
+  auto fill = [&](auto& a) {
+    using TP = decltype(a.out);
+    a.out = (TP)B.q[k].p;
+    a.out2 = (TP)B.z[k].p;
+    a.v[0] = (TP)B.q[k].p;
+    a.v2[0] = (TP)B.z[k].p;
+    a.cconst[0] = make_double2(1.0, 0.0);
+    for (int i = 0; i < k; ++i) {
+      a.v[i + 1] = (TP)B.q[i].p;
+      a.v2[i + 1] = (TP)B.z[i].p;
+      a.c[i + 1] = beta + (int64_t)i * max_sys;
+      a.neg[i + 1] = 1;
+    }
+    a.nt = k + 1; a.n = n; a.stride = n; a.nrhs = nsys;
+  };
+  if (prec == P64) {
+    LinCombArgs<double2> a{};
+    fill(a);
+    launch_lincomb(a, st);
+  } else {
+    LinCombArgs<float2> a{};
+    fill(a);
+    launch_lincomb(a, st);
+  }
+  check_launch();
+}
+
+std::vector<double> Ctx::read_norms(const double2* dev, int nsys) {
+  std::vector<double2> h(nsys);
+  HIPCHK(hipMemcpyAsync(h.data(), dev, nsys * sizeof(double2), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<double> out(nsys);
+  for (int s = 0; s < nsys; ++s) out[s] = h[s].x >= 0.0 ? std::sqrt(h[s].x) : (h[s].x < 0.0 ? 0.0 : h[s].x);
+  return out;
+}
+
+bool Ctx::any_active(int lvl, int nsys) {
+  std::vector<int> h(nsys);
+  HIPCHK(hipMemcpyAsync(h.data(), lmask(lvl), nsys * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int s = 0; s < nsys; ++s)
+    if (h[s]) return true;
+  return false;
+}
+
 // Flexible GCR on level lvl (>= 1) from x = 0 for L[lvl].b, preconditioned by
 // the K-cycle except on the coarsest level; stops per system at
 // ||r|| <= tol ||b|| or after the iteration cap (Table 1: 0.25 or 8).
+// Convergence is tracked on the device (a converged system's updates become
+// no-ops); the host reads the flags after every iteration, or every fourth
+// on the coarsest level, whose iterations are short.
 void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   LevelBufs& B = L[lvl];
   const bool coarsest = lvl == nlev - 1;
   const double tol = coarsest ? P.coarsest_tol : P.inner_tol;
   const int maxit = coarsest ? P.coarsest_maxiter : P.inner_maxiter;
   const int cycles = coarsest ? P.coarsest_restarts : 1;
+  const int every = coarsest ? 4 : 1;
   const int prec = B.prec;
   const int64_t n = B.n;
   zero(B.x, nsys);
   copy(B.r, B.b, nsys);
-  std::vector<double> r0, rn;
-  norms_host(prec, n, nsys, B.b.p, slot(lvl, kSlotNorm), r0);
-  std::vector<int> act(nsys);
-  int nact = 0;
-  for (int s = 0; s < nsys; ++s) { act[s] = r0[s] > 0.0 && std::isfinite(r0[s]); nact += act[s]; }
-  HIPCHK(hipMemcpyAsync(lmask(lvl), act.data(), nsys * sizeof(int), hipMemcpyHostToDevice, st));
-  for (int cyc = 0; cyc < cycles && nact > 0; ++cyc) {
+  double2* r0 = slot(lvl, kSlotR0);
+  dots(prec, n, nsys, {{B.b.p, B.b.p}}, r0);
+  launch_conv(lmask(lvl), nullptr, r0, tol * tol, nsys, 1, st);
+  check_launch();
+  bool live = true;
+  for (int cyc = 0; cyc < cycles && live; ++cyc) {
     if (cyc > 0) {   // restart: r = b - A x
       apply_level(lvl, B.r, B.x, nsys);
       lincomb(prec, n, nsys, B.r.p, {{B.b.p, nullptr}, {B.r.p, nullptr}}, {0, 1}, {});
     }
-    for (int k = 0; k < maxit && nact > 0; ++k) {
+    for (int k = 0; k < maxit; ++k) {
       stats.level[lvl - 1] += 1;
       if (coarsest) copy(B.z[k], B.r, nsys);
       else kcycle(lvl, B.r, B.z[k], nsys, stats);
-      apply_level(lvl, B.q[k], B.z[k], nsys);
-      // classical Gram-Schmidt, twice
-      for (int pass = 0; pass < 2 && k > 0; ++pass) {
-        std::vector<std::pair<const void*, const void*>> pr;
-        for (int i = 0; i < k; ++i) pr.push_back({B.q[i].p, B.q[k].p});
-        double2* beta = slot(lvl, 0);
-        dots(prec, n, nsys, pr, beta);
-        std::vector<std::pair<const void*, const double2*>> tq, tz;
-        std::vector<int> ng(k + 1, 1);
-        ng[0] = 0;
-        tq.push_back({B.q[k].p, nullptr});
-        tz.push_back({B.z[k].p, nullptr});
-        for (int i = 0; i < k; ++i) {
-          tq.push_back({B.q[i].p, beta + (int64_t)i * max_sys});
-          tz.push_back({B.z[i].p, beta + (int64_t)i * max_sys});
-        }
-        lincomb(prec, n, nsys, B.q[k].p, tq, ng, {});
-        lincomb(prec, n, nsys, B.z[k].p, tz, ng, {});
-      }
-      double2* qq = slot(lvl, kSlotQQ);
-      dots(prec, n, nsys, {{B.q[k].p, B.q[k].p}, {B.q[k].p, B.r.p}}, qq);
-      double2 *al = slot(lvl, kSlotQQ + 2), *nal = slot(lvl, kSlotQQ + 3), *inv = slot(lvl, kSlotQQ + 4);
-      launch_gcr_scalars(qq, qq + max_sys, lmask(lvl), nsys, al, nal, inv, st);
+      gcr_step(lvl, B, B.x, k, nsys);
+      launch_conv(lmask(lvl), slot(lvl, kSlotRN), r0, tol * tol, nsys, 0, st);
       check_launch();
-      lincomb(prec, n, nsys, B.x.p, {{B.x.p, nullptr}, {B.z[k].p, al}}, {}, {});
-      lincomb(prec, n, nsys, B.r.p, {{B.r.p, nullptr}, {B.q[k].p, nal}}, {}, {});
-      lincomb(prec, n, nsys, B.q[k].p, {{B.q[k].p, inv}}, {}, {});
-      lincomb(prec, n, nsys, B.z[k].p, {{B.z[k].p, inv}}, {}, {});
-      norms_host(prec, n, nsys, B.r.p, slot(lvl, kSlotNorm), rn);
-      bool changed = false;
-      for (int s = 0; s < nsys; ++s) {
-        if (act[s] && (!(rn[s] > tol * r0[s]) || !std::isfinite(rn[s]))) { act[s] = 0; --nact; changed = true; }
+      if ((k + 1) % every == 0 || k + 1 == maxit) {
+        if (!any_active(lvl, nsys)) { live = false; break; }
       }
-      if (changed && nact > 0)
-        HIPCHK(hipMemcpyAsync(lmask(lvl), act.data(), nsys * sizeof(int), hipMemcpyHostToDevice, st));
     }
   }
 }

@@ -118,6 +118,10 @@ struct Ctx {
   void smoother(int lvl, const Vec& e, const Vec& t, int nsys);
   void kcycle(int lvl, const Vec& r, const Vec& e, int nsys, SolveStats& stats);
   void level_solve(int lvl, int nsys, SolveStats& stats);   // L[lvl].b -> L[lvl].x
+  void gcr_step(int lvl, LevelBufs& B, const Vec& X, int k, int nsys);
+  void project(int prec, int64_t n, int nsys, LevelBufs& B, int k, const double2* beta);
+  std::vector<double> read_norms(const double2* dev, int nsys);
+  bool any_active(int lvl, int nsys);
   void ensure_kd(const std::vector<double>& masses);
 
   // ---- set-up

@@ -73,34 +73,8 @@ void Ctx::solve(const double* masses, int nmass, const void* b, void* x, int nrh
   };
   for (int it = 0; it < P.outer_maxiter && nact > 0; ++it) {
     kcycle(0, B.r, B.z[k], ns, stats);
-    apply_level(0, B.q[k], B.z[k], ns);
-    for (int pass = 0; pass < 2 && k > 0; ++pass) {
-      std::vector<std::pair<const void*, const void*>> pr;
-      for (int i = 0; i < k; ++i) pr.push_back({B.q[i].p, B.q[k].p});
-      double2* beta = slot(0, 0);
-      dots(P64, n, ns, pr, beta);
-      std::vector<std::pair<const void*, const double2*>> tq, tz;
-      std::vector<int> ng(k + 1, 1);
-      ng[0] = 0;
-      tq.push_back({B.q[k].p, nullptr});
-      tz.push_back({B.z[k].p, nullptr});
-      for (int i = 0; i < k; ++i) {
-        tq.push_back({B.q[i].p, beta + (int64_t)i * max_sys});
-        tz.push_back({B.z[i].p, beta + (int64_t)i * max_sys});
-      }
-      lincomb(P64, n, ns, B.q[k].p, tq, ng, {});
-      lincomb(P64, n, ns, B.z[k].p, tz, ng, {});
-    }
-    double2* qq = slot(0, kSlotQQ);
-    dots(P64, n, ns, {{B.q[k].p, B.q[k].p}, {B.q[k].p, B.r.p}}, qq);
-    double2 *al = slot(0, kSlotQQ + 2), *nal = slot(0, kSlotQQ + 3), *inv = slot(0, kSlotQQ + 4);
-    launch_gcr_scalars(qq, qq + max_sys, mk, ns, al, nal, inv, st);
-    check_launch();
-    lincomb(P64, n, ns, X.p, {{X.p, nullptr}, {B.z[k].p, al}}, {}, {});
-    lincomb(P64, n, ns, B.r.p, {{B.r.p, nullptr}, {B.q[k].p, nal}}, {}, {});
-    lincomb(P64, n, ns, B.q[k].p, {{B.q[k].p, inv}}, {}, {});
-    lincomb(P64, n, ns, B.z[k].p, {{B.z[k].p, inv}}, {}, {});
-    norms_host(P64, n, ns, B.r.p, slot(0, kSlotNorm), rn);
+    gcr_step(0, B, X, k, ns);
+    rn = read_norms(slot(0, kSlotRN), ns);
     bool check = false, reliable = false, nonfinite = false;
     for (int s = 0; s < ns; ++s) {
       if (!act[s]) continue;

@@ -4,7 +4,7 @@
 //
 //   restrict  r_c[a, sigma, k] = sum_{rows of (a, sigma)} conj(P[row, k]) r[row]
 //             one workgroup per (a, sigma); lanes run over k (Nvec <= 128),
-//             the four wavefronts over interleaved rows, reduced in LDS.
+//             eight wavefronts over interleaved rows, reduced in LDS.
 //   prolong   e[row] = sum_k P[row, k] e_c[a, sigma, k] (optionally += e)
 //             one workgroup per (a, sigma); threads over rows, P read in its
 //             second, row-contiguous copy, e_c staged in LDS.
@@ -125,10 +125,12 @@ void launch_p_layouts(const double2* pp64, double2* pr64, float2* pr32, float2* 
   p_layouts_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(pp64, pr64, pr32, pp32, A);
 }
 
+constexpr int kRestrictWaves = 8;
+
 template <typename R, int NR, int KPL>
-__global__ void __launch_bounds__(256) restrict_kernel(const RestrictArgs<R> a) {
+__global__ void __launch_bounds__(64 * kRestrictWaves) restrict_kernel(const RestrictArgs<R> a) {
   using T = cplx<R>;
-  __shared__ T red[3][NR][KPL * 64];
+  __shared__ T red[kRestrictWaves - 1][NR][KPL * 64];
   const int64_t as = blockIdx.x;
   const int64_t agg = as >> 1;
   const int sigma = (int)(as & 1);
@@ -142,7 +144,7 @@ __global__ void __launch_bounds__(256) restrict_kernel(const RestrictArgs<R> a) 
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int q = 0; q < KPL; ++q) { acc[r][q].x = 0; acc[r][q].y = 0; }
-  for (int row = wave; row < nrows; row += 4) {
+  for (int row = wave; row < nrows; row += kRestrictWaves) {
     const int64_t fi = agg_row_index(a.A, agg, sigma, row);
     T x[NR];
 #pragma unroll
@@ -176,7 +178,7 @@ __global__ void __launch_bounds__(256) restrict_kernel(const RestrictArgs<R> a) 
       for (int r = 0; r < NR; ++r) {
         if (r >= nr) continue;
         T v = acc[r][q];
-        for (int w = 0; w < 3; ++w) { v.x += red[w][r][k].x; v.y += red[w][r][k].y; }
+        for (int w = 0; w < kRestrictWaves - 1; ++w) { v.x += red[w][r][k].x; v.y += red[w][r][k].y; }
         a.out[(int64_t)(r0 + r) * a.out_stride + agg * a.out_site_stride + sigma * nvec + k] = v;
       }
     }
@@ -190,19 +192,19 @@ void launch_restrict(const RestrictArgs<R>& a, hipStream_t st) {
   const bool big = a.A.nvec > 64;
   if (a.nrhs >= 4) {
     dim3 grid(gx, (unsigned)((a.nrhs + 3) / 4));
-    if (big) restrict_kernel<R, 4, 2><<<grid, 256, 0, st>>>(a);
-    else restrict_kernel<R, 4, 1><<<grid, 256, 0, st>>>(a);
+    if (big) restrict_kernel<R, 4, 2><<<grid, 64 * kRestrictWaves, 0, st>>>(a);
+    else restrict_kernel<R, 4, 1><<<grid, 64 * kRestrictWaves, 0, st>>>(a);
   } else {
     dim3 grid(gx, (unsigned)a.nrhs);
-    if (big) restrict_kernel<R, 1, 2><<<grid, 256, 0, st>>>(a);
-    else restrict_kernel<R, 1, 1><<<grid, 256, 0, st>>>(a);
+    if (big) restrict_kernel<R, 1, 2><<<grid, 64 * kRestrictWaves, 0, st>>>(a);
+    else restrict_kernel<R, 1, 1><<<grid, 64 * kRestrictWaves, 0, st>>>(a);
   }
 }
 template void launch_restrict<float>(const RestrictArgs<float>&, hipStream_t);
 template void launch_restrict<double>(const RestrictArgs<double>&, hipStream_t);
 
 template <typename R, int NR>
-__global__ void __launch_bounds__(256) prolong_kernel(const ProlongArgs<R> a) {
+__global__ void __launch_bounds__(512) prolong_kernel(const ProlongArgs<R> a) {
   using T = cplx<R>;
   __shared__ T ec[NR][128];
   const int64_t as = blockIdx.x;
@@ -213,7 +215,7 @@ __global__ void __launch_bounds__(256) prolong_kernel(const ProlongArgs<R> a) {
   const int tid = threadIdx.x;
   const int nvec = a.A.nvec, nrows = a.A.nrows;
   const T* P = a.pp + as * (int64_t)nrows * nvec;
-  for (int e = tid; e < NR * nvec; e += 256) {
+  for (int e = tid; e < NR * nvec; e += 512) {
     const int r = e / nvec, k = e - r * nvec;
     T v;
     v.x = 0; v.y = 0;
@@ -227,7 +229,7 @@ __global__ void __launch_bounds__(256) prolong_kernel(const ProlongArgs<R> a) {
     ec[r][k] = v;
   }
   __syncthreads();
-  for (int row = tid; row < nrows; row += 256) {
+  for (int row = tid; row < nrows; row += 512) {
     T acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) { acc[r].x = 0; acc[r].y = 0; }
@@ -254,10 +256,10 @@ void launch_prolong(const ProlongArgs<R>& a, hipStream_t st) {
   const unsigned gx = (unsigned)(a.A.nagg * 2);
   if (a.nrhs >= 4) {
     dim3 grid(gx, (unsigned)((a.nrhs + 3) / 4));
-    prolong_kernel<R, 4><<<grid, 256, 0, st>>>(a);
+    prolong_kernel<R, 4><<<grid, 512, 0, st>>>(a);
   } else {
     dim3 grid(gx, (unsigned)a.nrhs);
-    prolong_kernel<R, 1><<<grid, 256, 0, st>>>(a);
+    prolong_kernel<R, 1><<<grid, 512, 0, st>>>(a);
   }
 }
 template void launch_prolong<float>(const ProlongArgs<float>&, hipStream_t);
