@@ -275,3 +275,104 @@ class Transfer:
         e = np.zeros(self.nflat, dtype=np.complex128)
         e[self.rows] = np.einsum("asrk,ask->asr", self.Q, np.asarray(ec).reshape(self.nagg, 2, self.nvec))
         return e
+
+
+# --------------------------------------------------------------------------
+# Explicit direction-split coarse links (Sec. 2.1 Galerkin; 9-point stencil)
+# --------------------------------------------------------------------------
+
+def dslash_pieces(x, W, N, mass, c1, c3, block):
+    """D x split by where each hop goes relative to the aggregate of the
+    output site: piece 0 keeps hops that stay inside the aggregate (and the
+    mass), piece 1 + 2 mu the hops that leave through its +mu face, piece
+    2 + 2 mu through its -mu face.  The nine pieces sum to D x."""
+    dims = (int(x.shape[3]), int(x.shape[2]), int(x.shape[1]), int(x.shape[0]))
+    eta = staggered_eta(dims)
+    co = coords(dims)
+    out = [np.zeros_like(x) for _ in range(9)]
+    out[0] = out[0] + mass * x
+    for mu in range(4):
+        ax = axis_of(mu)
+        u = (co[mu] % block[mu])[..., None]
+        for h, coef, F in ((1, c1, W), (3, c3, N)):
+            if coef == 0.0:
+                continue
+            fwd = 0.5 * coef * eta[mu][..., None] * _mv(F[mu], np.roll(x, -h, axis=ax))
+            bwd = -0.5 * coef * eta[mu][..., None] * _mv(_dag(np.roll(F[mu], h, axis=ax)), np.roll(x, h, axis=ax))
+            leave_f = (u + h) >= block[mu]
+            leave_b = (u - h) < 0
+            out[1 + 2 * mu] = out[1 + 2 * mu] + np.where(leave_f, fwd, 0)
+            out[0] = out[0] + np.where(leave_f, 0, fwd)
+            out[2 + 2 * mu] = out[2 + 2 * mu] + np.where(leave_b, bwd, 0)
+            out[0] = out[0] + np.where(leave_b, 0, bwd)
+    return out
+
+
+def coarse_neighbours(cdims):
+    """[Vc][9] site index of the self / +mu / -mu neighbours (periodic)."""
+    X, Y, Z, T = cdims
+    V = X * Y * Z * T
+    s = np.arange(V)
+    c = [s % X, (s // X) % Y, (s // (X * Y)) % Z, s // (X * Y * Z)]
+    nb = np.empty((V, 9), dtype=np.int64)
+    nb[:, 0] = s
+    for mu in range(4):
+        for d, h in ((1 + 2 * mu, 1), (2 + 2 * mu, -1)):
+            cc = list(c)
+            cc[mu] = (c[mu] + h) % cdims[mu]
+            nb[:, d] = cc[0] + X * (cc[1] + Y * (cc[2] + Z * cc[3]))
+    return nb, c
+
+
+def coarse_apply_links(L, cdims, x):
+    """y(a) = sum_d L[a, d] x(nb_d(a)) for links L [Vc][9][n][n] (row-major)."""
+    nb, _ = coarse_neighbours(cdims)
+    xv = x.reshape(L.shape[0], -1)
+    y = np.einsum("adij,adj->ai", L, xv[nb])
+    return y.reshape(x.shape)
+
+
+def coarse_pieces(L, cdims, x, block):
+    """The coarse stencil split like dslash_pieces, relative to the aggregates
+    (blocks `block`) of the next coarsening."""
+    nb, c = coarse_neighbours(cdims)
+    xv = x.reshape(L.shape[0], -1)
+    out = [np.zeros_like(xv) for _ in range(9)]
+    out[0] = out[0] + np.einsum("aij,aj->ai", L[:, 0], xv)
+    for mu in range(4):
+        u = c[mu] % block[mu]
+        for d, leave in ((1 + 2 * mu, u == block[mu] - 1), (2 + 2 * mu, u == 0)):
+            y = np.einsum("aij,aj->ai", L[:, d], xv[nb[:, d]])
+            out[d] = out[d] + np.where(leave[:, None], y, 0)
+            out[0] = out[0] + np.where(leave[:, None], 0, y)
+    return [o.reshape(x.shape) for o in out]
+
+
+def galerkin_links(transfer, pieces_of, fine_shape, ncoarse_sites):
+    """Coarse links [Vc][9][n][n] (row-major blocks) of R A P: column j of
+    every block is R applied to piece d of A acting on P e_j (e_j on every
+    aggregate at once)."""
+    n = 2 * transfer.nvec
+    L = np.zeros((ncoarse_sites, 9, n, n), dtype=np.complex128)
+    for j in range(n):
+        e = np.zeros((ncoarse_sites, n), dtype=np.complex128)
+        e[:, j] = 1.0
+        v = transfer.prolong(e).reshape(fine_shape)
+        for d, p in enumerate(pieces_of(v)):
+            L[:, d, :, j] = transfer.restrict(p).reshape(ncoarse_sites, n)
+    return L
+
+
+def round_bf16(a):
+    """Round to bfloat16 (round to nearest, ties to even), returned as float64;
+    the input is first taken to float32."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def round_fp16(a):
+    """Round to IEEE binary16 (numpy's float16 conversion is round to nearest
+    even), returned as float64."""
+    return np.asarray(a, dtype=np.float32).astype(np.float16).astype(np.float64)

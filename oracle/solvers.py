@@ -339,3 +339,27 @@ class Hierarchy:
         residual ||b - D x|| / ||b|| <= tol (Sec. 3.2)."""
         return gcr(lambda v: self.op(0, v), b, lambda r: self.kcycle(0, r), tol, maxiter,
                    self.p.outer_nkrylov, true_residual=True)
+
+
+def hierarchy_links(H):
+    """Explicit direction-split coarse links of every coarse level of the
+    hierarchy H ([Vc][9][n][n] row-major), built from the pieces of the level
+    operators (the Galerkin definition written out block by block)."""
+    p = H.p
+    links = []
+    t0 = H.transfers[0]
+    nc0 = int(np.prod(H.cdims[0]))
+
+    def pieces1(v):
+        ps = ops.dslash_pieces(v, H.W, H.N, H.mass, p.c1, H.c3_kd, p.blocks[0])
+        return [ops.kd_apply(H.Kinv, q) for q in ps]
+
+    L2 = ops.galerkin_links(t0, pieces1, H.fine_shape(1), nc0)
+    links.append(L2)
+    if len(H.transfers) > 1:
+        t1 = H.transfers[1]
+        nc1 = int(np.prod(H.cdims[1]))
+        L3 = ops.galerkin_links(t1, lambda v: ops.coarse_pieces(L2, H.cdims[0], v, p.blocks[1]),
+                                H.fine_shape(2), nc1)
+        links.append(L3)
+    return links

@@ -17,17 +17,19 @@ __device__ __forceinline__ double2 load_link<double, double2>(const double2* p) 
 template <>
 __device__ __forceinline__ float2 load_link<float, float2>(const float2* p) { return *p; }
 
-// One workgroup of 16 wavefronts per (coarse site, 64-row tile, rhs tile):
-// the K = 9 n columns of the site's block row are split evenly over the
-// wavefronts (lanes run over rows, so every link load is one coalesced
-// segment), and the 16 partial sums are reduced in LDS.  This exposes
-// 16x more parallelism than one thread per row, which the small coarse
-// lattices need to keep enough loads in flight.
-constexpr int kCoarseWaves = 16;
+// One workgroup per (coarse site, 64-row tile, rhs tile) whose wavefronts
+// (16 for one or two right-hand sides, fewer for wider rhs tiles) split the
+// K = 9 n columns of the site's block row evenly (lanes run over rows, so
+// every link load is one coalesced segment); the partial sums are reduced in
+// LDS.  This exposes far more parallelism than one thread per row, which the
+// small coarse lattices need to keep enough loads in flight.
+template <int NR>
+struct CoarseWaves { static constexpr int value = NR <= 2 ? 16 : (NR <= 4 ? 8 : 4); };
 
 template <typename R, typename LT, int NR, bool PIECE, bool DAG>
-__global__ void __launch_bounds__(64 * kCoarseWaves) coarse_kernel(const CoarseArgs<R, LT> a) {
+__global__ void __launch_bounds__(64 * CoarseWaves<NR>::value) coarse_kernel(const CoarseArgs<R, LT> a) {
   using T = cplx<R>;
+  constexpr int kCoarseWaves = CoarseWaves<NR>::value;
   __shared__ T red[kCoarseWaves - 1][NR][64];
   const int n = a.n;
   const int64_t site = blockIdx.x;
@@ -118,7 +120,7 @@ __global__ void __launch_bounds__(64 * kCoarseWaves) coarse_kernel(const CoarseA
 template <typename R, typename LT, int NR>
 static void coarse_launch_nr(const CoarseArgs<R, LT>& a, bool piece, bool dag, hipStream_t st) {
   dim3 grid((unsigned)a.g.V, (unsigned)((a.n + 63) / 64), (unsigned)((a.nrhs + NR - 1) / NR));
-  const int threads = 64 * kCoarseWaves;
+  const int threads = 64 * CoarseWaves<NR>::value;
   if (piece) coarse_kernel<R, LT, NR, true, false><<<grid, threads, 0, st>>>(a);
   else if (dag) coarse_kernel<R, LT, NR, false, true><<<grid, threads, 0, st>>>(a);
   else coarse_kernel<R, LT, NR, false, false><<<grid, threads, 0, st>>>(a);
@@ -127,7 +129,9 @@ static void coarse_launch_nr(const CoarseArgs<R, LT>& a, bool piece, bool dag, h
 template <typename R, typename LT>
 void launch_coarse(const CoarseArgs<R, LT>& a, bool piece, bool dag, hipStream_t st) {
   if (a.nrhs <= 0) return;
-  if (a.nrhs >= 4) coarse_launch_nr<R, LT, 4>(a, piece, dag, st);
+  if (a.nrhs >= 16 && sizeof(R) == 4 && !dag) coarse_launch_nr<R, LT, 16>(a, piece, dag, st);
+  else if (a.nrhs >= 8 && !dag) coarse_launch_nr<R, LT, 8>(a, piece, dag, st);
+  else if (a.nrhs >= 4) coarse_launch_nr<R, LT, 4>(a, piece, dag, st);
   else if (a.nrhs >= 2) coarse_launch_nr<R, LT, 2>(a, piece, dag, st);
   else coarse_launch_nr<R, LT, 1>(a, piece, dag, st);
 }

@@ -100,6 +100,21 @@ struct CoarseArgs {
 };
 template <typename R, typename LT>
 void launch_coarse(const CoarseArgs<R, LT>& a, bool piece, bool dag, hipStream_t st);
+struct CoarseMfmaArgs {
+  float2* out;
+  const float2* in;
+  const uint16_t* links;    // swizzled 16-bit fragments
+  Geom g;
+  int n;
+  int64_t in_stride, out_stride;
+  int nrhs;
+  float inv_scale;
+};
+void launch_coarse_mfma(const CoarseMfmaArgs& a, int fmt, hipStream_t st);   // fmt 0 bf16, 1 fp16
+void launch_swizzle_links(const double2* cl, uint16_t* out, int64_t nsite, int n, int fmt, double scale,
+                          hipStream_t st);
+void launch_absmax(const double2* v, int64_t n, unsigned long long* out, hipStream_t st);
+int64_t swizzled_link_elems(int64_t nsite, int n);
 void launch_convert_links(const double2* in, float2* out, int64_t n, hipStream_t st);
 void launch_export_links(const double2* in, double2* out, int64_t nsite, int n, hipStream_t st);
 

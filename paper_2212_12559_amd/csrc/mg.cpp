@@ -27,8 +27,11 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     if (p.dims[mu] < 4 || (p.dims[mu] & 1)) return fail("lattice extents must be even and >= 4");
   if (p.nagg < 1 || p.nagg > 2) return fail("nagg must be 1 or 2");
   if (p.fine_prec != MG_C128 && p.fine_prec != MG_C64) return fail("fine_prec must be MG_C128 or MG_C64");
-  if (p.coarse_prec != MG_C128 && p.coarse_prec != MG_C64) return fail("coarse_prec must be MG_C128 or MG_C64");
-  if (p.coarse_prec != p.fine_prec) return fail("coarse_prec must equal fine_prec (coarse vectors share the level-1 precision)");
+  if (p.coarse_prec < MG_C128 || p.coarse_prec > MG_CF16) return fail("coarse_prec must be an mg_dtype");
+  if (p.fine_prec == MG_C128 && p.coarse_prec != MG_C128)
+    return fail("coarse_prec must be MG_C128 when fine_prec is MG_C128");
+  if (p.fine_prec == MG_C64 && p.coarse_prec == MG_C128)
+    return fail("coarse_prec MG_C128 needs fine_prec MG_C128 (coarse vectors share the level-1 precision)");
   if (p.smoother_s < 1 || p.smoother_s > kMaxS) return fail("smoother_s must be in 1..8");
   if (p.inner_maxiter < 1 || p.inner_maxiter > kMaxNK) return fail("inner_maxiter must be in 1..16");
   if (p.coarsest_maxiter < 1 || p.coarsest_maxiter > kMaxNK) return fail("coarsest_maxiter must be in 1..16");
@@ -68,6 +71,8 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     a.nagg = g.V;
     a.nrows = l == 0 ? bs / 2 * 3 : bs * nin;
     if (a.nvec < 1 || a.nvec > 128) return fail("nvec must be in 1..128");
+    if ((p.coarse_prec == MG_CBF16 || p.coarse_prec == MG_CF16) && (a.nvec % 8))
+      return fail("nvec must be a multiple of 8 for 16-bit coarse links (16-row MFMA tiles)");
     if (a.nvec > a.nrows) return fail("nvec exceeds the rows of an aggregate and chirality");
     gc[l] = g;
     gcur = g;
@@ -89,7 +94,8 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   const int64_t kslot = V / 16 * 2304;
   void* kinv64 = P((size_t)p.max_nmass * kslot * 16);
   void* kinv32 = P((size_t)p.max_nmass * kslot * 8);
-  void *nvp[2]{}, *pp64[2]{}, *pr64[2]{}, *pp32[2]{}, *pr32[2]{}, *cl64[2]{}, *cl32[2]{};
+  void *nvp[2]{}, *pp64[2]{}, *pr64[2]{}, *pp32[2]{}, *pr32[2]{}, *cl64[2]{}, *cl32[2]{}, *cl16[2]{};
+  const bool c16 = p.coarse_prec == MG_CBF16 || p.coarse_prec == MG_CF16;
   for (int l = 0; l < p.nagg; ++l) {
     const int64_t nflat = A[l].nagg * 2 * A[l].nrows;   // dof of the aggregated level
     const int64_t pel = nflat * A[l].nvec;
@@ -101,6 +107,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     const int64_t n = 2 * A[l].nvec;
     cl64[l] = P(gc[l].V * 9 * n * n * 16);
     cl32[l] = P(gc[l].V * 9 * n * n * 8);
+    if (c16) cl16[l] = P(swizzled_link_elems(gc[l].V, (int)n) * 2);
   }
   void* status = P(256);
   // ---- scratch
@@ -177,7 +184,9 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
       c->pp64[l] = (double2*)pp64[l]; c->pr64[l] = (double2*)pr64[l];
       c->pp32[l] = (float2*)pp32[l]; c->pr32[l] = (float2*)pr32[l];
       c->cl64[l] = (double2*)cl64[l]; c->cl32[l] = (float2*)cl32[l];
+      c->cl16[l] = (uint16_t*)cl16[l];
     }
+    c->fmt16 = p.coarse_prec == MG_CBF16 ? 0 : (p.coarse_prec == MG_CF16 ? 1 : -1);
     c->status_dev = (int*)status;
     c->max_sys = ms;
     c->part = (double2*)part;
@@ -254,6 +263,12 @@ void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, b
     a.out = (double2*)out; a.in = (const double2*)in; a.links = cl64[l];
     a.g = gc[l]; a.n = n; a.in_stride = a.out_stride = gc[l].V * n; a.nrhs = nsys;
     launch_coarse(a, false, dag, st);
+  } else if (fmt16 >= 0 && !dag && !setup_phase) {
+    CoarseMfmaArgs a{};
+    a.out = (float2*)out; a.in = (const float2*)in; a.links = cl16[l];
+    a.g = gc[l]; a.n = n; a.in_stride = a.out_stride = gc[l].V * n; a.nrhs = nsys;
+    a.inv_scale = cl16_inv_scale[l];
+    launch_coarse_mfma(a, fmt16, st);
   } else {
     CoarseArgs<float, float2> a{};
     a.out = (float2*)out; a.in = (const float2*)in; a.links = cl32[l];

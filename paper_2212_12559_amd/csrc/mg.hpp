@@ -69,6 +69,10 @@ struct Ctx {
   float2 *pp32[2]{}, *pr32[2]{};
   double2* cl64[2]{};       // coarse links of levels 2 and 3
   float2* cl32[2]{};
+  uint16_t* cl16[2]{};      // 16-bit MFMA fragments (coarse_prec BF16 / FP16)
+  float cl16_inv_scale[2]{1.0f, 1.0f};
+  int fmt16 = -1;           // -1: none, 0: bf16, 1: fp16
+  bool setup_phase = false;
   int* status_dev = nullptr;
 
   // scratch (solver)

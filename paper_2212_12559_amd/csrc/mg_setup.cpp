@@ -3,6 +3,7 @@
 // on the level's own operator), chiral doubling + FP64 block
 // orthonormalisation, and the Galerkin coarse operators.
 #include <cmath>
+#include <cstring>
 
 #include "mg.hpp"
 
@@ -28,7 +29,9 @@ void Ctx::setup(const void* fat, const void* naik, const void* const* nvs) {
   }
   ensure_kd({P.mass0});
   rhs_per_slot = 0;
+  setup_phase = true;
   for (int l = 0; l < P.nagg; ++l) build_level(l, nvs ? nvs[l] : nullptr);
+  setup_phase = false;
   HIPCHK(hipStreamSynchronize(st));
 }
 
@@ -178,6 +181,25 @@ void Ctx::galerkin(int l) {
   }
   launch_convert_links(cl64[l], cl32[l], gc[l].V * 9 * (int64_t)n * n, st);
   check_launch();
+  if (fmt16 >= 0) {
+    // 16-bit fragments; FP16 gets a power-of-two scale with max |L| <= 1
+    double scale = 1.0;
+    if (fmt16 == 1) {
+      unsigned long long* mx = (unsigned long long*)(status_dev + 16);
+      HIPCHK(hipMemsetAsync(mx, 0, sizeof(unsigned long long), st));
+      launch_absmax(cl64[l], gc[l].V * 9 * (int64_t)n * n, mx, st);
+      check_launch();
+      unsigned long long bits = 0;
+      HIPCHK(hipMemcpyAsync(&bits, mx, sizeof(bits), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      double amax;
+      memcpy(&amax, &bits, sizeof(amax));
+      if (amax > 0.0) scale = std::ldexp(1.0, -(int)std::ceil(std::log2(amax)));
+    }
+    cl16_inv_scale[l] = (float)(1.0 / scale);
+    launch_swizzle_links(cl64[l], cl16[l], gc[l].V, n, fmt16, scale, st);
+    check_launch();
+  }
 }
 
 }  // namespace mg

@@ -11,7 +11,7 @@ import pytest
 from oracle import operators as ops
 from paper_2212_12559_amd import latgen
 
-from gpu_common import CONFIGS, coarse_dims, gpu_params, links, log, oracle_hierarchy, random_null_vectors, rel_err
+from gpu_common import CONFIGS, coarse_dims, gpu_params, links, log, oracle_hierarchy, random_null_vectors, rel_err  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -212,3 +212,61 @@ def test_coarse_links_export_blocks(case):
                 y[s] += Lk[s, d] @ x[t]
     want = case.H._galerkin(lvl, x.reshape(case.H.fine_shape(lvl))).reshape(Vc, n)
     assert rel_err(y, want) < TOL64
+
+
+def test_galerkin_links_match_oracle(case):
+    """Every exported FP64 coarse link block equals the oracle's explicit
+    direction-split Galerkin block (block by block, 1e-12)."""
+    from oracle import solvers as sol
+    log(f"[galerkin links] {case.name}")
+    links = sol.hierarchy_links(case.H)
+    for lvl in range(2, len(case.cfg["blocks"]) + 2):
+        got = case.ctx.export(2, lvl).cpu().numpy().reshape(links[lvl - 2].shape)
+        assert rel_err(got, links[lvl - 2]) < TOL64
+
+
+_cases16 = {}
+
+
+@pytest.mark.parametrize("name", ["c0", "cubic"])
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_coarse_mfma_16bit(torch, mg, name, fmt):
+    """Coarse stencil with 16-bit links on the matrix cores: against the oracle
+    applying the same links and inputs rounded to bf16 / fp16 (round to
+    nearest even; fp16 links scaled by a power of two so max |L| <= 1) and
+    accumulating in FP64; tolerance 1e-5 (FP32 accumulation).  The error
+    against the unrounded FP64 operator is reported."""
+    from oracle import solvers as sol
+    key = (name, fmt)
+    if key not in _cases16:
+        log(f"[setup] {name} {fmt}")
+        cfg = CONFIGS[name]
+        W, N, rng = links(cfg)
+        nvs = random_null_vectors(cfg, rng)
+        dev = "cuda:0"
+        cp = mg.MG_CBF16 if fmt == "bf16" else mg.MG_CF16
+        p = gpu_params(mg, cfg, max_nrhs=17, fine_prec=mg.MG_C64, coarse_prec=cp)
+        ctx = mg.setup(p, torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev) if cfg["c3"] else None,
+                       [torch.from_numpy(v).to(dev) for v in nvs])
+        H = oracle_hierarchy(cfg, W, N, cfg["mass0"], nvs)
+        _cases16[key] = (cfg, ctx, H, sol.hierarchy_links(H), rng)
+    cfg, ctx, H, Ls, rng = _cases16[key]
+    rnd = ops.round_bf16 if fmt == "bf16" else ops.round_fp16
+    for lvl in range(2, len(cfg["blocks"]) + 2):
+        L = Ls[lvl - 2]
+        scale = 1.0
+        if fmt == "fp16":
+            amax = max(np.max(np.abs(L.real)), np.max(np.abs(L.imag)))
+            scale = 2.0 ** (-np.ceil(np.log2(amax)))
+        Lr = (rnd(L.real * scale) + 1j * rnd(L.imag * scale)) / scale
+        cd = H.cdims[lvl - 2]
+        for nrhs in (1, 5, 17):
+            x = latgen.complex_normal(rng, (nrhs,) + H.fine_shape(lvl)).astype(np.complex64)
+            log(f"[mfma] {name} {fmt} level {lvl} nrhs {nrhs}")
+            y = ctx.apply_coarse(lvl, torch.from_numpy(x).to("cuda:0")).cpu().numpy().astype(np.complex128)
+            for r in range(nrhs):
+                xr = rnd(x[r].real) + 1j * rnd(x[r].imag)
+                want = ops.coarse_apply_links(Lr, cd, xr)
+                assert rel_err(y[r], want) < TOL32, (lvl, nrhs, r)
+                exact = ops.coarse_apply_links(L, cd, x[r].astype(np.complex128))
+                log(f"    rel err vs unrounded FP64 operator: {rel_err(y[r], exact):.2e}")

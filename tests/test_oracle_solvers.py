@@ -149,3 +149,38 @@ def test_cgne_null_vectors_reduce_A():
     q1 = np.linalg.norm(A(phi)) / np.linalg.norm(phi)
     assert q1 < 0.25 * q0
     assert rel == pytest.approx(np.linalg.norm(A(phi)) / np.linalg.norm(A(phi0)), rel=1e-12)
+
+
+def test_explicit_links_equal_rap():
+    """The explicit direction-split links (pieces summed over the aliasing
+    neighbours) reproduce R A P on every coarse level, including coarse
+    extents 2 and 1 where +mu and -mu meet the same neighbour."""
+    dims = (8, 8, 8, 8)
+    W, N, rng = latgen.hisq_style_links(dims, 0.5, 31)
+    p = sol.MGParams(dims=dims, c1=C1H, c3=C3H, kd_naik=False, blocks=((4, 4, 4, 4), (2, 2, 2, 2)))
+    nv1 = latgen.fine_vectors(dims, 6, rng)
+    nv2 = latgen.coarse_vectors((2, 2, 2, 2), 6, 5, rng)
+    H = sol.Hierarchy(p, W, N, 0.05, [nv1, nv2])
+    L2, L3 = sol.hierarchy_links(H)
+    for lvl, L, cd in ((2, L2, H.cdims[0]), (3, L3, H.cdims[1])):
+        x = latgen.complex_normal(rng, H.fine_shape(lvl))
+        y = ops.coarse_apply_links(L, cd, x)
+        want = H._galerkin(lvl, x)
+        assert np.max(np.abs(y - want)) < 1e-12 * np.max(np.abs(want))
+    # pieces of D sum to D
+    x = latgen.fine_vectors(dims, 1, rng)[0]
+    ps = ops.dslash_pieces(x, W, N, 0.05, C1H, C3H, (4, 4, 4, 4))
+    assert np.max(np.abs(sum(ps) - ops.dslash(x, W, N, 0.05, C1H, C3H))) < 1e-13
+
+
+def test_round_to_nearest_even():
+    """bf16 / fp16 rounding: exact values, halfway cases to even, relative error bound."""
+    # 1 + 2^-8 is halfway between bf16 neighbours 1 and 1 + 2^-7: ties to even (1)
+    assert ops.round_bf16(1.0 + 2.0 ** -8) == 1.0
+    assert ops.round_bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6   # tie -> even mantissa
+    assert ops.round_bf16(-2.5) == -2.5
+    rng = np.random.default_rng(9)
+    v = rng.standard_normal(10000)
+    assert np.max(np.abs(ops.round_bf16(v) - v) / np.abs(v)) <= 2.0 ** -8
+    assert np.max(np.abs(ops.round_fp16(v) - v) / np.maximum(np.abs(v), 2.0 ** -14)) <= 2.0 ** -11
+    assert ops.round_fp16(1.0 + 2.0 ** -11) == 1.0
