@@ -87,9 +87,12 @@ typedef struct {
   int32_t outer_maxiter;     /* outer GCR iteration cap */
   double reliable_delta;     /* outer GCR recomputes r = b - D x when ||r|| < delta * ||r at last recompute|| */
   int32_t fine_prec;         /* MG_C128 or MG_C64: precision of the K-cycle on levels 0 and 1 */
-  int32_t coarse_prec;       /* MG_C128 or MG_C64: precision of the coarse levels */
-  int32_t max_nrhs;          /* largest nrhs * nmass a solve or apply will be given */
-  int32_t max_nmass;         /* masses with their own KD inverse (>= 1; slot 0 is mass0) */
+  int32_t coarse_prec;       /* stored coarse links: MG_C128 (needs fine_prec MG_C128), MG_C64, or 16-bit
+                                MG_CBF16 / MG_CF16 applied on the matrix cores with FP32 accumulation
+                                (nvec multiples of 8; FP16 links carry a power-of-two scale); coarse vectors
+                                are kept in fine_prec */
+  int32_t max_nrhs;          /* systems solved in lockstep (mass x rhs pairs) and largest nrhs of an apply */
+  int32_t max_nmass;         /* KD inverse slots: masses in one lockstep batch (>= 1) */
   uint64_t seed;             /* seed of the GPU-generated null-vector starts */
 } mg_params;
 
@@ -141,7 +144,8 @@ mg_status mg_apply_dslash(mg_ctx ctx, int32_t op, double mass, int32_t dtype, co
 
 /* Coarse operator of level 2 (P1^dag A P1) or 3 (P2^dag A2 P2) on a coarse
  * vector of that level (Sec. 2.1; 9-point stencil of dense blocks, Sec. 3.1).
- * dtype MG_C128 uses the FP64 operator; MG_C64 the coarse_prec operator. */
+ * dtype MG_C128 uses the FP64 operator; MG_C64 the coarse_prec operator
+ * (FP32 links, or 16-bit links on the matrix cores). */
 mg_status mg_apply_coarse(mg_ctx ctx, int32_t level, int32_t dtype, const void* in, void* out, int32_t nrhs,
                           void* stream);
 
@@ -163,8 +167,10 @@ mg_status mg_prolong(mg_ctx ctx, int32_t level, int32_t dtype, const void* coars
  *   b: device complex128 [nrhs][T][Z][Y][X][3]
  *   x: device complex128 [nmass][nrhs][T][Z][Y][X][3] (overwritten)
  *   info: host array of nmass * nrhs entries (mass-major)
- * nmass * nrhs <= max_nrhs; distinct masses <= max_nmass.  Returns MG_OK
- * when every system converged, MG_E_NOCONV otherwise. */
+ * Systems are solved in lockstep batches of whole masses with at most
+ * max_nrhs (mass, rhs) pairs each (nrhs <= max_nrhs; the masses of one batch
+ * <= max_nmass).  Returns MG_OK when every system converged, MG_E_NOCONV
+ * otherwise. */
 mg_status mg_solve(mg_ctx ctx, const double* masses, int32_t nmass, const void* b, void* x, int32_t nrhs,
                    double tol, mg_solve_info* info, void* stream);
 

@@ -1,6 +1,7 @@
 // C ABI of the mgstag library (declared in include/mgstag.h).  Every entry
 // point validates its arguments, runs the work inside a try block and maps
 // failures to an mg_status with a thread-local message.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -222,8 +223,9 @@ static mg_status check_solve(Ctx& c, const double* masses, int32_t nmass, const 
                              double tol, mg_solve_info* info) {
   if (!masses || !b || !x || !info) return fail(MG_E_ARG, "null argument");
   if (nmass < 1 || nrhs < 1) return fail(MG_E_ARG, "nmass and nrhs must be >= 1");
-  if ((int64_t)nmass * nrhs > c.P.max_nrhs) return fail(MG_E_ARG, "nmass * nrhs exceeds max_nrhs");
-  if (nmass > c.P.max_nmass) return fail(MG_E_ARG, "nmass exceeds max_nmass");
+  if (nrhs > c.P.max_nrhs) return fail(MG_E_ARG, "nrhs exceeds max_nrhs");
+  if (std::min(nmass, std::max(1, c.P.max_nrhs / nrhs)) > c.P.max_nmass)
+    return fail(MG_E_ARG, "a batch would hold more masses than max_nmass");
   for (int j = 0; j < nmass; ++j)
     if (!(masses[j] > 0.0) || !std::isfinite(masses[j])) return fail(MG_E_ARG, "masses must be positive and finite");
   if (!(tol > 0.0)) return fail(MG_E_ARG, "tol must be positive");

@@ -138,6 +138,41 @@ void launch_coarse(const CoarseArgs<R, LT>& a, bool piece, bool dag, hipStream_t
 template void launch_coarse<double, double2>(const CoarseArgs<double, double2>&, bool, bool, hipStream_t);
 template void launch_coarse<float, float2>(const CoarseArgs<float, float2>&, bool, bool, hipStream_t);
 
+// Adjoint stencil as explicit links: (A^dag)_{a, a+d} = (A_{a+d, a})^dag, i.e.
+// out[a][d] = (in[nb_d(a)][opposite d])^dag, in the same [site][d][col][row]
+// layout, so the adjoint apply is an ordinary coalesced apply.
+template <typename T>
+__global__ void dagger_links_kernel(const T* __restrict__ in, T* __restrict__ out, Geom g, int n) {
+  const int64_t nn = (int64_t)n * n;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= g.V * 9 * nn) return;
+  const int64_t sd = tid / nn;
+  const int64_t e = tid - sd * nn;
+  const int col = (int)(e / n), row = (int)(e - (int64_t)col * n);
+  const int64_t site = sd / 9;
+  const int d = (int)(sd - site * 9);
+  int c[4];
+  site_coords(site, g, c);
+  int64_t nb = site;
+  int dd = 0;
+  if (d > 0) {
+    const int mu = (d - 1) >> 1;
+    nb = site_shift(c, mu, (d & 1) ? 1 : -1, g);
+    dd = (d & 1) ? d + 1 : d - 1;
+  }
+  // element (row, col) of the adjoint block = conj(element (col, row) of the neighbour's block)
+  T v = in[(nb * 9 + dd) * nn + (int64_t)row * n + col];
+  v.y = -v.y;
+  out[tid] = v;
+}
+template <typename T>
+void launch_dagger_links(const T* in, T* out, const Geom& g, int n, hipStream_t st) {
+  const int64_t tot = g.V * 9 * (int64_t)n * n;
+  dagger_links_kernel<T><<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(in, out, g, n);
+}
+template void launch_dagger_links<float2>(const float2*, float2*, const Geom&, int, hipStream_t);
+template void launch_dagger_links<double2>(const double2*, double2*, const Geom&, int, hipStream_t);
+
 __global__ void convert_c128_c64_kernel(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);

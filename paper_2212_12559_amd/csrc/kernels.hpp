@@ -116,6 +116,8 @@ void launch_swizzle_links(const double2* cl, uint16_t* out, int64_t nsite, int n
 void launch_absmax(const double2* v, int64_t n, unsigned long long* out, hipStream_t st);
 int64_t swizzled_link_elems(int64_t nsite, int n);
 void launch_convert_links(const double2* in, float2* out, int64_t n, hipStream_t st);
+template <typename T>
+void launch_dagger_links(const T* in, T* out, const Geom& g, int n, hipStream_t st);
 void launch_export_links(const double2* in, double2* out, int64_t nsite, int n, hipStream_t st);
 
 // ---------------------------------------------------------------- BLAS

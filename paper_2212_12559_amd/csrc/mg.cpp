@@ -170,6 +170,10 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     const int prec = l == 0 ? fp : cp;
     size_t e = solver_base + 6 * (((size_t)p.nvec[l] * n * csize(prec) + 255) & ~(size_t)255) +
                3 * (((size_t)n * 16 + 255) & ~(size_t)255) + 256;
+    if (l == 1) {   // explicit adjoint links of the level-2 stencil
+      const int64_t nc = 2 * A[0].nvec;
+      e += (size_t)gc[0].V * 9 * nc * nc * csize(prec) + 256;
+    }
     setup_end = std::max(setup_end, e);
   }
   scr.off = std::max(solver_end, setup_end);

@@ -131,6 +131,8 @@ struct Ctx {
   // ---- set-up
   void setup(const void* fat, const void* naik, const void* const* nvs);
   void solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, mg_solve_info* info);
+  void solve_batch(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol,
+                   mg_solve_info* info);
   void cg_solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, int maxiter,
                 mg_solve_info* info);
   void build_level(int l, const void* nv_import);

@@ -75,6 +75,16 @@ void Ctx::cgne_null(int l) {
   void* t = base + 3 * vb;
   void* At = base + 4 * vb;
   void* tmp = base + 5 * vb;
+  // past the six CGNE vectors and the three Galerkin vectors
+  void* dagl = nullptr;
+  if (l == 1) {
+    const size_t gb = ((size_t)n * 16 + 255) & ~(size_t)255;
+    dagl = base + 6 * vb + 3 * gb;
+    const int nc = ncoarse[0];
+    if (prec == P64) launch_dagger_links<double2>(cl64[0], (double2*)dagl, gc[0], nc, st);
+    else launch_dagger_links<float2>(cl32[0], (float2*)dagl, gc[0], nc, st);
+    check_launch();
+  }
   auto A_apply = [&](void* out, const void* in, bool dag) {
     if (l == 0) {
       const bool nk = P.kd_naik != 0;
@@ -85,8 +95,23 @@ void Ctx::cgne_null(int l) {
         apply_KD(prec, tmp, in, nv_, true, false, 0);
         apply_D(prec, out, tmp, nv_, nk, nullptr, P.mass0, true);
       }
+    } else if (!dag) {
+      apply_coarse(2, prec, out, in, nv_, false);
     } else {
-      apply_coarse(2, prec, out, in, nv_, dag);
+      // the adjoint stencil through its explicit links (coalesced)
+      const int nc = ncoarse[0];
+      if (prec == P64) {
+        CoarseArgs<double, double2> c{};
+        c.out = (double2*)out; c.in = (const double2*)in; c.links = (const double2*)dagl;
+        c.g = gc[0]; c.n = nc; c.in_stride = c.out_stride = gc[0].V * nc; c.nrhs = nv_;
+        launch_coarse(c, false, false, st);
+      } else {
+        CoarseArgs<float, float2> c{};
+        c.out = (float2*)out; c.in = (const float2*)in; c.links = (const float2*)dagl;
+        c.g = gc[0]; c.n = nc; c.in_stride = c.out_stride = gc[0].V * nc; c.nrhs = nv_;
+        launch_coarse(c, false, false, st);
+      }
+      check_launch();
     }
   };
   if (prec == P64) launch_random_normal<double2>((double2*)phi, (int64_t)nv_ * n, P.seed + 7919ull * l, st);

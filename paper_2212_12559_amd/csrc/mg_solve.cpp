@@ -35,7 +35,19 @@ static void set_masses(Ctx& c, const double* masses, int nmass, int nrhs) {
   HIPCHK(hipStreamSynchronize(c.st));
 }
 
+// Systems are solved in lockstep batches of at most max_nrhs (mass, rhs)
+// pairs: whole masses per batch, all right-hand sides of a mass together.
 void Ctx::solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, mg_solve_info* info) {
+  if (nrhs > P.max_nrhs) throw Error{MG_E_ARG, "nrhs exceeds max_nrhs"};
+  const int per = std::max(1, P.max_nrhs / nrhs);
+  for (int j0 = 0; j0 < nmass; j0 += per) {
+    const int nm = std::min(per, nmass - j0);
+    solve_batch(masses + j0, nm, b, (char*)x + (size_t)j0 * nrhs * g0.V * 3 * 16, nrhs, tol, info + j0 * nrhs);
+  }
+}
+
+void Ctx::solve_batch(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol,
+                      mg_solve_info* info) {
   const int ns = nmass * nrhs;
   const double t0 = now();
   std::vector<double> ms(masses, masses + nmass);
