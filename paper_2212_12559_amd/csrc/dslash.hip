@@ -163,7 +163,8 @@ template <typename R>
 void launch_dslash(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st) {
   if (a.nrhs <= 0 || a.g.V <= 0) return;
   if (a.nrhs == 1) launch_nr<R, 1>(a, naik, cb, piece, st);
-  else launch_nr<R, 4>(a, naik, cb, piece, st);
+  else if (a.nrhs < 8) launch_nr<R, 4>(a, naik, cb, piece, st);
+  else launch_nr<R, 8>(a, naik, cb, piece, st);
 }
 template void launch_dslash<float>(const DslashArgs<float>&, bool, bool, bool, hipStream_t);
 template void launch_dslash<double>(const DslashArgs<double>&, bool, bool, bool, hipStream_t);

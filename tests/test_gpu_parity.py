@@ -35,7 +35,7 @@ def mg(torch):
 class Case:
     """One configuration with random (full-rank) imported null vectors."""
 
-    def __init__(self, name, torch, mg, max_nrhs=5):
+    def __init__(self, name, torch, mg, max_nrhs=9):
         log(f"[setup] config {name}")
         self.name = name
         self.cfg = cfg = CONFIGS[name]
@@ -100,7 +100,7 @@ def test_index_tables_bit_exact(case):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-@pytest.mark.parametrize("nrhs", [1, 5])
+@pytest.mark.parametrize("nrhs", [1, 5, 9])
 def test_dslash_parity(case, prec, nrhs):
     torch = case.torch
     dt = torch.complex128 if prec == "c128" else torch.complex64
@@ -126,12 +126,12 @@ def test_kd_parity(case, prec):
     tol = TOL64 if prec == "c128" else TOL32
     cfg = case.cfg
     m = cfg["mass0"]
-    x = latgen.fine_vectors(cfg["dims"], 3, case.rng)
+    x = latgen.fine_vectors(cfg["dims"], 9, case.rng)
     log(f"[kd] {case.name} {prec}")
     yk = case.back(case.ctx.apply_dslash(2, m, case.to_gpu(x, dt)))
     ya = case.back(case.ctx.apply_dslash(1, m, case.to_gpu(x, dt)))
     c3kd = cfg["c3"] if cfg["kd_naik"] else 0.0
-    for r in range(3):
+    for r in range(9):
         assert rel_err(yk[r], ops.kd_apply(case.H.Kinv, x[r])) < tol
         want = ops.kd_operator(x[r], case.W, case.N, case.H.Kinv, m, cfg["c1"], c3kd)
         assert rel_err(ya[r], want) < tol
