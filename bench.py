@@ -29,6 +29,11 @@ WORKLOADS = {
     # 32^4 HISQ-style, eps 0.5 (as the 16^4 workload), mass 0.005, KD + 4^4/Nvec 64 + 2^4/Nvec 96
     "c2": dict(dims=(32, 32, 32, 32), mass=0.005, nrhs=1, eps=0.5, seed=20221226, kd_naik=0,
                nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(1000, 300)),
+    # the multi-mass batch: 32^4, 16 rhs x 8 masses (log-spaced 0.005..0.2), 16-bit coarse links
+    "c2batch": dict(dims=(32, 32, 32, 32), mass=0.005, nrhs=16, eps=0.5, seed=20221226, kd_naik=0,
+                    nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(1000, 300),
+                    masses=(0.005, 0.0084691, 0.014345, 0.024298, 0.041156, 0.069711, 0.11808, 0.2),
+                    coarse_prec="bf16"),
     # 16^4 HISQ-style, mass 0.01
     "c1": dict(dims=(16, 16, 16, 16), mass=0.01, nrhs=1, eps=0.5, seed=20221225, kd_naik=0,
                nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 2000)),
@@ -190,6 +195,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG comparator")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="set up, time the hot kernels and copy a known-size buffer (for counter runs)")
+    ap.add_argument("--coarse-prec", default=None, choices=["fp32", "bf16", "fp16"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus 1)", file=sys.stderr)
@@ -206,9 +214,13 @@ def main():
     b = latgen.fine_vectors(dims, wl["nrhs"], rng)
     Wt, Nt = torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev)
     bt = torch.from_numpy(b).to(dev)
-    del W, N
+    del W, N, b
+    masses = list(wl.get("masses", (m,)))
+    cprec = args.coarse_prec or wl.get("coarse_prec", "fp32")
+    cp = {"fp32": mg.MG_C64, "bf16": mg.MG_CBF16, "fp16": mg.MG_CF16}[cprec]
     p = mg.default_params(dims, mass0=m, nvec=wl["nvec"], block=wl["blocks"], setup_maxiter=wl["setup_iters"],
-                          max_nrhs=wl["nrhs"], max_nmass=1, kd_naik=wl["kd_naik"])
+                          max_nrhs=wl["nrhs"], max_nmass=len(masses), kd_naik=wl["kd_naik"], coarse_prec=cp,
+                          outer_nkrylov=8 if wl["nrhs"] > 1 else 16)
     log("[bench] setup")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -217,28 +229,39 @@ def main():
     setup_s = time.perf_counter() - t0
     log(f"[bench] setup {setup_s:.2f} s")
 
+    if args.kernels_only:
+        kern = kernel_rates(torch, ctx, wl, args.kernel_reps, mg)
+        src = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)   # known-size copy (512 MiB read + 512 MiB write) to calibrate byte counters
+        torch.cuda.synchronize()
+        print(json.dumps({k: {"us": v["us"], "bytes": v["bytes"]} for k, v in kern.items()}), flush=True)
+        return
+
     for i in range(args.warmup):
-        x, info, st = ctx.solve([m], bt, tol=1e-10)
+        x, info, st = ctx.solve(masses, bt, tol=1e-10)
         log(f"[bench] warmup {i}: {info[0]}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
     for i in range(args.steps):
-        x, info, st = ctx.solve([m], bt, tol=1e-10)
+        x, info, st = ctx.solve(masses, bt, tol=1e-10)
         infos.append(info)
-        log(f"[bench] step {i}: {info[0]}")
+        log(f"[bench] step {i}: {info[0]} ... {info[-1]['outer_iters']} outer at the heaviest mass")
     torch.cuda.synchronize()
     mg_s = (time.perf_counter() - t0) / args.steps
-    res = max(i[0]["true_rel_residual"] for i in infos)
+    res = max(s["true_rel_residual"] for i in infos for s in i)
 
     cg_s, cg_info = None, None
     if not args.no_cg:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        xc, cinfo, st = ctx.cg_solve([m], bt, tol=1e-10, maxiter=200000)
+        xc, cinfo, st = ctx.cg_solve(masses, bt, tol=1e-10, maxiter=200000)
         torch.cuda.synchronize()
         cg_s = time.perf_counter() - t0
         cg_info = cinfo[0]
+        del xc
         log(f"[bench] CG {cg_s:.3f} s {cg_info}")
 
     # ---- per-kernel timings (HIP events on the stream the library launches on)
@@ -265,8 +288,10 @@ def main():
         "vs_baseline": None,
         "dtype": "c128 outer / c64 K-cycle",
         "data": "synthetic",
-        "config": {"workload": f"{'x'.join(map(str, dims))} HISQ-style, mass {m}, {wl['nrhs']} rhs, "
-                               f"KD + {wl['blocks'][0]}/Nvec {wl['nvec'][0]} + {wl['blocks'][1]}/Nvec {wl['nvec'][1]}"},
+        "config": {"workload": f"{'x'.join(map(str, dims))} HISQ-style eps 0.5, masses {masses}, "
+                               f"{wl['nrhs']} rhs per mass, truncated-KD={not wl['kd_naik']}, "
+                               f"KD + {wl['blocks'][0]}/Nvec {wl['nvec'][0]} + {wl['blocks'][1]}/Nvec {wl['nvec'][1]}, "
+                               f"coarse links {cprec}"},
         "mg_info": infos[-1][0],
         "setup_s": setup_s,
         "cg_s": cg_s,

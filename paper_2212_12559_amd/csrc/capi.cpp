@@ -147,13 +147,9 @@ mg_status mg_apply_dslash(mg_ctx ctx, int32_t op, double mass, int32_t dtype, co
       else launch_eps<float2>((float2*)tmp, (const float2*)in, c.g0, nrhs, c.st);
       c.apply_D(prec, out, tmp, nrhs, true, nullptr, mass, true);
     } else {
-      std::vector<double> m{mass};
-      int slot = -1;
-      for (size_t j = 0; j < c.kd_mass.size(); ++j)
-        if (c.kd_mass[j] == mass) { slot = (int)j; break; }
-      if (slot < 0) { c.ensure_kd(m); slot = 0; }
+      c.ensure_kd(std::vector<double>{mass});
       c.rhs_per_slot = 0;
-      const int64_t off = (int64_t)slot * c.kinv_slot;
+      const int64_t off = (int64_t)c.kd_base * c.kinv_slot;
       if (op == 2) {
         if (prec == P64) {
           KdArgs<double> a{};

@@ -245,13 +245,13 @@ void Ctx::apply_D(int prec, void* out, const void* in, int nsys, bool naik, cons
 void Ctx::apply_KD(int prec, void* out, const void* in, int nsys, bool eps_in, bool eps_out, int rps) {
   if (prec == P64) {
     KdArgs<double> a{};
-    a.out = (double2*)out; a.in = (const double2*)in; a.kinv = kinv64;
+    a.out = (double2*)out; a.in = (const double2*)in; a.kinv = kinv64 + (int64_t)kd_base * kinv_slot;
     a.g = g0; a.in_stride = a.out_stride = g0.V * 3; a.nrhs = nsys;
     a.rhs_per_slot = rps; a.slot_stride = kinv_slot; a.eps_in = eps_in; a.eps_out = eps_out;
     launch_kd_apply(a, st);
   } else {
     KdArgs<float> a{};
-    a.out = (float2*)out; a.in = (const float2*)in; a.kinv = kinv32;
+    a.out = (float2*)out; a.in = (const float2*)in; a.kinv = kinv32 + (int64_t)kd_base * kinv_slot;
     a.g = g0; a.in_stride = a.out_stride = g0.V * 3; a.nrhs = nsys;
     a.rhs_per_slot = rps; a.slot_stride = kinv_slot; a.eps_in = eps_in; a.eps_out = eps_out;
     launch_kd_apply(a, st);
@@ -577,14 +577,30 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
 }
 
 // ======================================================================== KD
+// KD inverses live in max_nmass slots.  A batch needs its masses in
+// consecutive slots kd_base, kd_base + 1, ...: an existing run is reused,
+// otherwise a free run (or slot 0 onwards) is rebuilt.
 void Ctx::ensure_kd(const std::vector<double>& masses) {
-  if ((int)masses.size() > P.max_nmass) throw Error{MG_E_ARG, "more masses than max_nmass"};
-  for (size_t j = 0; j < masses.size(); ++j) {
-    if (kd_mass[j] == masses[j]) continue;
-    launch_kd_inverse(fat64, g0, masses[j], kinv64 + (int64_t)j * kinv_slot, kinv32 + (int64_t)j * kinv_slot, st);
-    check_launch();
-    kd_mass[j] = masses[j];
+  const int nm = (int)masses.size();
+  if (nm > P.max_nmass) throw Error{MG_E_ARG, "more masses than max_nmass"};
+  for (int base = 0; base + nm <= P.max_nmass; ++base) {
+    bool ok = true;
+    for (int j = 0; j < nm && ok; ++j) ok = kd_mass[base + j] == masses[j];
+    if (ok) { kd_base = base; return; }
   }
+  int base = 0;
+  for (int b = 0; b + nm <= P.max_nmass; ++b) {
+    bool free_run = true;
+    for (int j = 0; j < nm && free_run; ++j) free_run = std::isnan(kd_mass[b + j]);
+    if (free_run) { base = b; break; }
+  }
+  for (int j = 0; j < nm; ++j) {
+    const int sl = base + j;
+    launch_kd_inverse(fat64, g0, masses[j], kinv64 + (int64_t)sl * kinv_slot, kinv32 + (int64_t)sl * kinv_slot, st);
+    check_launch();
+    kd_mass[sl] = masses[j];
+  }
+  kd_base = base;
 }
 
 }  // namespace mg

@@ -91,6 +91,7 @@ struct Ctx {
   // current batch
   int nsys = 0;
   int rhs_per_slot = 0;     // systems per KD slot in the current batch
+  int kd_base = 0;          // first KD slot of the current batch
 
   std::vector<double> host_buf;
 
