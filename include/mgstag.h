@@ -89,7 +89,8 @@ typedef struct {
   int32_t fine_prec;         /* MG_C128 or MG_C64: precision of the K-cycle on levels 0 and 1 */
   int32_t coarse_prec;       /* stored coarse links: MG_C128 (needs fine_prec MG_C128), MG_C64, or 16-bit
                                 MG_CBF16 / MG_CF16 applied on the matrix cores with FP32 accumulation
-                                (nvec multiples of 8; FP16 links carry a power-of-two scale); coarse vectors
+                                (nvec multiples of 8; FP16 links carry the power-of-two scale
+                                2^-round(log2 max|L|)); coarse vectors
                                 are kept in fine_prec */
   int32_t max_nrhs;          /* systems solved in lockstep (mass x rhs pairs) and largest nrhs of an apply */
   int32_t max_nmass;         /* KD inverse slots: masses in one lockstep batch (>= 1) */

@@ -12,7 +12,7 @@
 // (the site's 16 right-hand-side columns, converted to 16 bits with
 // round-to-nearest-even) is staged once per workgroup in LDS as [rhs][k]
 // planes, read with the same k mapping.  FP16 links carry a power-of-two scale
-// (max |L| <= 1) undone on the FP32 result.
+// (2^-round(log2 max|L|)) undone on the FP32 result.
 #include "kernels.hpp"
 
 namespace mg {
@@ -34,7 +34,6 @@ __device__ __forceinline__ uint16_t f32_to_f16_rne(float f) {
 template <int FMT>
 __device__ __forceinline__ uint16_t to16(float f) { return FMT == 0 ? f32_to_bf16_rne(f) : f32_to_f16_rne(f); }
 
-struct Frag { uint4 v; };
 
 template <int FMT>
 __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {

@@ -207,7 +207,9 @@ void Ctx::galerkin(int l) {
   launch_convert_links(cl64[l], cl32[l], gc[l].V * 9 * (int64_t)n * n, st);
   check_launch();
   if (fmt16 >= 0) {
-    // 16-bit fragments; FP16 gets a power-of-two scale with max |L| <= 1
+    // 16-bit fragments; FP16 links get the power-of-two scale 2^-round(log2 max|L|),
+    // which puts max |L| in [2^-1/2, 2^1/2] (far from the FP16 range limits, and
+    // with no tie at the exact powers of two a Galerkin identity block produces)
     double scale = 1.0;
     if (fmt16 == 1) {
       unsigned long long* mx = (unsigned long long*)(status_dev + 16);
@@ -219,7 +221,7 @@ void Ctx::galerkin(int l) {
       HIPCHK(hipStreamSynchronize(st));
       double amax;
       memcpy(&amax, &bits, sizeof(amax));
-      if (amax > 0.0) scale = std::ldexp(1.0, -(int)std::ceil(std::log2(amax)));
+      if (amax > 0.0) scale = std::ldexp(1.0, -(int)std::lround(std::log2(amax)));
     }
     cl16_inv_scale[l] = (float)(1.0 / scale);
     launch_swizzle_links(cl64[l], cl16[l], gc[l].V, n, fmt16, scale, st);

@@ -233,7 +233,7 @@ _cases16 = {}
 def test_coarse_mfma_16bit(torch, mg, name, fmt):
     """Coarse stencil with 16-bit links on the matrix cores: against the oracle
     applying the same links and inputs rounded to bf16 / fp16 (round to
-    nearest even; fp16 links scaled by a power of two so max |L| <= 1) and
+    nearest even; fp16 links scaled by 2^-round(log2 max|L|)) and
     accumulating in FP64; tolerance 1e-5 (FP32 accumulation).  The error
     against the unrounded FP64 operator is reported."""
     from oracle import solvers as sol
@@ -257,7 +257,7 @@ def test_coarse_mfma_16bit(torch, mg, name, fmt):
         scale = 1.0
         if fmt == "fp16":
             amax = max(np.max(np.abs(L.real)), np.max(np.abs(L.imag)))
-            scale = 2.0 ** (-np.ceil(np.log2(amax)))
+            scale = 2.0 ** (-np.round(np.log2(amax)))
         Lr = (rnd(L.real * scale) + 1j * rnd(L.imag * scale)) / scale
         cd = H.cdims[lvl - 2]
         for nrhs in (1, 5, 17):
