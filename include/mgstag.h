@@ -182,6 +182,24 @@ mg_status mg_solve(mg_ctx ctx, const double* masses, int32_t nmass, const void* 
 mg_status mg_cg_solve(mg_ctx ctx, const double* masses, int32_t nmass, const void* b, void* x, int32_t nrhs,
                       double tol, int32_t maxiter, mg_solve_info* info, void* stream);
 
+/* Fermion force for HMC (the solver inside gauge generation, Sec. 4.2):
+ * for S = sum_r phi_r^dag (D(m)^dag D(m))^{-1} phi_r computes
+ *   X = (D^dag D)^{-1} phi and Y = D X  by two MG solves (D^dag = eps D eps),
+ *   grad_fat[mu][x]  = -c1 eta_mu(x) sum_r [Y(x) X(x+mu)^dag  - X(x) Y(x+mu)^dag ]
+ *   grad_naik[mu][x] = -c3 eta_mu(x) sum_r [Y(x) X(x+3mu)^dag - X(x) Y(x+3mu)^dag]
+ * the gradients in PyTorch's convention (dS/dRe U + i dS/dIm U), canonical
+ * link layout, complex128, overwritten.  S = sum_r Re <phi_r, X_r>.
+ *   phi, X, Y: device complex128 [nrhs][T][Z][Y][X][3] (X, Y overwritten)
+ *   info: host, 2 * nrhs entries (the D^dag solves, then the D solves). */
+mg_status mg_solve_backward(mg_ctx ctx, double mass, const void* phi, void* X, void* Y, void* grad_fat,
+                            void* grad_naik, int32_t nrhs, double tol, mg_solve_info* info, void* stream);
+
+/* Replace the gauge links of an existing context (device, complex128): the
+ * fine operator and the KD inverses follow the new links, the near-null
+ * vectors, transfers and coarse operators stay those of the set-up (the
+ * hierarchy then preconditions a nearby operator; solves stay exact). */
+mg_status mg_update_links(mg_ctx ctx, const void* fat, const void* naik, void* stream);
+
 /* Copy internal data to a caller buffer (device dst of at least `bytes`):
  *   what 0: fine index tables, int32 [V][22] (neighbours x+-mu, x+-3mu, eta
  *           bits, eps, hypercube, hypercube-local index, aggregate, chirality)

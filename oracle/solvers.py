@@ -363,3 +363,50 @@ def hierarchy_links(H):
                                 H.fine_shape(2), nc1)
         links.append(L3)
     return links
+
+
+# --------------------------------------------------------------------------
+# Fermion force: gradient of S = phi^dag (D^dag D)^{-1} phi (HMC use, Sec. 4.2)
+# --------------------------------------------------------------------------
+
+def force(W, N, mass, c1, c3, phi, tol=1e-12):
+    """S = phi^dag (D^dag D)^{-1} phi and its gradients with respect to the
+    fat and Naik links in PyTorch's convention (dS/dRe U + i dS/dIm U):
+
+      X = (D^dag D)^{-1} phi,  Y = D X  (so D^dag Y = phi),
+      G^W_mu(x) = -c1 eta_mu(x) [ Y(x) X(x+mu)^dag  - X(x) Y(x+mu)^dag  ]
+      G^N_mu(x) = -c3 eta_mu(x) [ Y(x) X(x+3mu)^dag - X(x) Y(x+3mu)^dag ]
+
+    from dS = -2 Re(Y^dag dD X).  The two solves are D^dag Y = phi and D X = Y
+    (Schur CG, FP64).  Pinned by central finite differences."""
+    T, Z, Yd, X = phi.shape[:4]
+    dims = (X, Yd, Z, T)
+    eta = ops.staggered_eta(dims)
+    # D^dag = eps D eps: Y = eps D^{-1} (eps phi)
+    e = ops.epsilon(dims)[..., None]
+    y1, _, _ = cg_schur(W, N, mass, c1, c3, e * phi, tol=tol)
+    Yv = e * y1
+    Xv, _, _ = cg_schur(W, N, mass, c1, c3, Yv, tol=tol)
+    S = float(np.vdot(phi, Xv).real)
+
+    def outer(a, b):
+        return np.einsum("...i,...j->...ij", a, b.conj())
+
+    gW = np.empty_like(W)
+    gN = np.empty_like(N)
+    for mu in range(4):
+        ax = ops.axis_of(mu)
+        et = eta[mu][..., None, None]
+        X1, Y1 = np.roll(Xv, -1, axis=ax), np.roll(Yv, -1, axis=ax)
+        gW[mu] = -c1 * et * (outer(Yv, X1) - outer(Xv, Y1))
+        X3, Y3 = np.roll(Xv, -3, axis=ax), np.roll(Yv, -3, axis=ax)
+        gN[mu] = -c3 * et * (outer(Yv, X3) - outer(Xv, Y3))
+    return S, gW, gN, Xv, Yv
+
+
+def action(W, N, mass, c1, c3, phi, tol=1e-13):
+    """S = phi^dag (D^dag D)^{-1} phi = |D^{-dag} phi|^2 (one Schur CG solve)."""
+    T, Z, Yd, X = phi.shape[:4]
+    e = ops.epsilon((X, Yd, Z, T))[..., None]
+    y1, _, _ = cg_schur(W, N, mass, c1, c3, e * phi, tol=tol)
+    return float(np.vdot(y1, y1).real)

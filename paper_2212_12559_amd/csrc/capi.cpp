@@ -260,6 +260,35 @@ mg_status mg_cg_solve(mg_ctx ctx, const double* masses, int32_t nmass, const voi
   return MG_OK;
 }
 
+mg_status mg_solve_backward(mg_ctx ctx, double mass, const void* phi, void* X, void* Y, void* grad_fat,
+                            void* grad_naik, int32_t nrhs, double tol, mg_solve_info* info, void* stream) {
+  if (!ctx) return fail(MG_E_ARG, "null context");
+  Ctx& c = ctx->c;
+  if (!phi || !X || !Y || !grad_fat || !info) return fail(MG_E_ARG, "null argument");
+  if (c.P.c3 != 0.0 && !grad_naik) return fail(MG_E_ARG, "grad_naik required when c3 != 0");
+  if (nrhs < 1 || nrhs > c.P.max_nrhs) return fail(MG_E_ARG, "nrhs out of range (1..max_nrhs)");
+  if (!(mass > 0.0) || !std::isfinite(mass)) return fail(MG_E_ARG, "mass must be positive and finite");
+  if (!(tol > 0.0)) return fail(MG_E_ARG, "tol must be positive");
+  if (phi == X || phi == Y || X == Y) return fail(MG_E_ARG, "phi, X and Y must be distinct");
+  if (!aligned(phi) || !aligned(X) || !aligned(Y) || !aligned(grad_fat) || (grad_naik && !aligned(grad_naik)))
+    return fail(MG_E_ALIGN, "buffers must be 16-byte aligned");
+  c.st = (hipStream_t)stream;
+  mg_status s = guarded([&] { c.solve_backward(mass, phi, X, Y, grad_fat, grad_naik, nrhs, tol, info); });
+  if (s != MG_OK) return s;
+  for (int i = 0; i < 2 * nrhs; ++i)
+    if (info[i].status != MG_OK) return fail((mg_status)info[i].status, "a solve did not converge");
+  return MG_OK;
+}
+
+mg_status mg_update_links(mg_ctx ctx, const void* fat, const void* naik, void* stream) {
+  if (!ctx) return fail(MG_E_ARG, "null context");
+  Ctx& c = ctx->c;
+  if (!fat || (c.P.c3 != 0.0 && !naik)) return fail(MG_E_ARG, "null links");
+  if (!aligned(fat) || (naik && !aligned(naik))) return fail(MG_E_ALIGN, "links must be 16-byte aligned");
+  c.st = (hipStream_t)stream;
+  return guarded([&] { c.update_links(fat, naik); });
+}
+
 mg_status mg_export(mg_ctx ctx, int32_t what, int32_t level, void* dst, size_t bytes, size_t* bytes_needed,
                     void* stream) {
   if (!ctx) return fail(MG_E_ARG, "null context");

@@ -292,3 +292,65 @@ void launch_cb_merge(double2* full, const double2* ev, const double2* od, const 
 }
 
 }  // namespace mg
+
+namespace mg {
+
+// Fermion force outer products, summed over right-hand sides (HMC use of the
+// solver, Sec. 4.2): for S = sum_r phi_r^dag (D^dag D)^{-1} phi_r with
+// X = (D^dag D)^{-1} phi, Y = D X,
+//   G^W_mu(x) = -c1 eta_mu(x) sum_r [ Y(x) X(x+mu)^dag  - X(x) Y(x+mu)^dag  ]
+//   G^N_mu(x) = -c3 eta_mu(x) sum_r [ Y(x) X(x+3mu)^dag - X(x) Y(x+3mu)^dag ]
+// in PyTorch's gradient convention, written in the canonical link layout
+// [mu][site][3][3]; accumulate adds into the output.
+__global__ void __launch_bounds__(256) force_kernel(const double2* __restrict__ X, const double2* __restrict__ Y,
+                                                    double2* __restrict__ gw, double2* __restrict__ gn, Geom g,
+                                                    int nrhs, double c1, double c3, int accumulate) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= 4 * g.V) return;
+  const int mu = (int)(tid / g.V);
+  const int64_t s = tid - (int64_t)mu * g.V;
+  int c[4];
+  site_coords(s, g, c);
+  const double eta = (double)stag_eta(c, mu);
+  for (int h = 0; h < 2; ++h) {
+    double2* out = h ? gn : gw;
+    if (!out) continue;
+    const double coef = -(h ? c3 : c1) * eta;
+    const int64_t sn = site_shift(c, mu, h ? 3 : 1, g);
+    double2 acc[9];
+    for (int k = 0; k < 9; ++k) acc[k] = make_double2(0.0, 0.0);
+    for (int r = 0; r < nrhs; ++r) {
+      const double2* xr = X + (int64_t)r * g.V * 3;
+      const double2* yr = Y + (int64_t)r * g.V * 3;
+      double2 xa[3], ya[3], xb[3], yb[3];
+      for (int i = 0; i < 3; ++i) {
+        xa[i] = xr[s * 3 + i]; ya[i] = yr[s * 3 + i];
+        xb[i] = xr[sn * 3 + i]; yb[i] = yr[sn * 3 + i];
+      }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          // Y_i(x) conj(X_j(x+h)) - X_i(x) conj(Y_j(x+h))
+          double2 t = make_double2(0.0, 0.0);
+          cfmac(t, xb[j], ya[i]);
+          double2 u = make_double2(0.0, 0.0);
+          cfmac(u, yb[j], xa[i]);
+          acc[3 * i + j].x += t.x - u.x;
+          acc[3 * i + j].y += t.y - u.y;
+        }
+    }
+    double2* o = out + tid * 9;
+    for (int k = 0; k < 9; ++k) {
+      double2 v = make_double2(coef * acc[k].x, coef * acc[k].y);
+      if (accumulate) { v.x += o[k].x; v.y += o[k].y; }
+      o[k] = v;
+    }
+  }
+}
+
+void launch_force(const double2* X, const double2* Y, double2* gw, double2* gn, const Geom& g, int nrhs, double c1,
+                  double c3, int accumulate, hipStream_t st) {
+  const int64_t n = 4 * g.V;
+  force_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(X, Y, gw, gn, g, nrhs, c1, c3, accumulate);
+}
+
+}  // namespace mg

@@ -35,6 +35,8 @@ template <typename T>
 void launch_eps(T* out, const T* in, const Geom& g, int nrhs, hipStream_t st);
 void launch_cb_split(const double2* full, double2* ev, double2* od, const Geom& g, int nrhs, hipStream_t st);
 void launch_cb_merge(double2* full, const double2* ev, const double2* od, const Geom& g, int nrhs, hipStream_t st);
+void launch_force(const double2* X, const double2* Y, double2* gw, double2* gn, const Geom& g, int nrhs, double c1,
+                  double c3, int accumulate, hipStream_t st);
 
 // ---------------------------------------------------------------- KD
 template <typename R>

@@ -128,6 +128,38 @@ void Ctx::solve_batch(const double* masses, int nmass, const void* b, void* x, i
   }
 }
 
+// Fermion force (HMC use of the solver, Sec. 4.2): X = (D^dag D)^{-1} phi and
+// Y = D X from two MG solves, D^dag = eps D eps giving Y = eps D^{-1} (eps phi)
+// and then X = D^{-1} Y, followed by the outer-product kernel.
+void Ctx::solve_backward(double mass, const void* phi, void* X, void* Y, void* gw, void* gn, int nrhs, double tol,
+                         mg_solve_info* info) {
+  launch_eps<double2>((double2*)X, (const double2*)phi, g0, nrhs, st);
+  check_launch();
+  solve(&mass, 1, X, Y, nrhs, tol, info);
+  launch_eps<double2>((double2*)Y, (const double2*)Y, g0, nrhs, st);
+  check_launch();
+  solve(&mass, 1, Y, X, nrhs, tol, info + nrhs);
+  launch_force((const double2*)X, (const double2*)Y, (double2*)gw, P.c3 != 0.0 ? (double2*)gn : nullptr, g0, nrhs,
+               P.c1, P.c3, 0, st);
+  check_launch();
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// New gauge links for an existing hierarchy: the fine operator and the KD
+// inverses follow the new links, the near-null vectors, transfers and coarse
+// operators stay those built at set-up (the hierarchy is then a
+// preconditioner for a nearby operator; the outer solve is exact).
+void Ctx::update_links(const void* fat, const void* naik) {
+  launch_pack_links((const double2*)fat, fat64, fat32, g0, 0.5 * P.c1, st);
+  check_launch();
+  if (P.c3 != 0.0) {
+    launch_pack_links((const double2*)naik, lng64, lng32, g0, 0.5 * P.c3, st);
+    check_launch();
+  }
+  for (auto& m : kd_mass) m = NAN;
+  HIPCHK(hipStreamSynchronize(st));
+}
+
 // Single-parity Schur CG (Sec. 3.2) for every (mass, rhs) system, one mass
 // at a time with the right-hand sides batched.
 void Ctx::cg_solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, int maxiter,

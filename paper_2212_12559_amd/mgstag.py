@@ -82,6 +82,8 @@ def _load():
         "mg_solve": (i32, [vp, P(f64), i32, vp, vp, i32, f64, P(MGSolveInfo), vp]),
         "mg_cg_solve": (i32, [vp, P(f64), i32, vp, vp, i32, f64, i32, P(MGSolveInfo), vp]),
         "mg_export": (i32, [vp, i32, i32, vp, sz, P(sz), vp]),
+        "mg_solve_backward": (i32, [vp, f64, vp, vp, vp, vp, vp, i32, f64, P(MGSolveInfo), vp]),
+        "mg_update_links": (i32, [vp, vp, vp, vp]),
         "mg_destroy": (i32, [vp]),
         "mg_last_error": (ctypes.c_char_p, []),
     }
@@ -267,6 +269,27 @@ class Context:
             _check(st, "mg_cg_solve")
         return x, info, st
 
+    def solve_backward(self, mass, phi, tol=1e-10):
+        """X = (D^dag D)^{-1} phi, Y = D X and the fermion-force gradients of
+        S = sum_r phi_r^dag (D^dag D)^{-1} phi_r with respect to the fat and
+        Naik links (PyTorch convention).  phi [nrhs][T][Z][Y][X][3] complex128."""
+        torch = _torch()
+        nrhs = phi.shape[0]
+        X = torch.empty_like(phi)
+        Y = torch.empty_like(phi)
+        T_, Z_, Y_, X_ = self.fine_shape[:4]
+        gw = torch.empty((4, T_, Z_, Y_, X_, 3, 3), dtype=torch.complex128, device=phi.device)
+        gn = torch.empty_like(gw) if self.params.c3 != 0.0 else None
+        infos = (MGSolveInfo * (2 * nrhs))()
+        st = LIB.mg_solve_backward(self.ctx, mass, _dev(phi, "phi"), _dev(X, "X"), _dev(Y, "Y"), _dev(gw, "grad_fat"),
+                                   _dev(gn, "grad_naik") if gn is not None else None, nrhs, tol, infos, _stream())
+        _check(st, "mg_solve_backward")
+        return X, Y, gw, gn, [i.as_dict() for i in infos]
+
+    def update_links(self, fat, naik=None):
+        _check(LIB.mg_update_links(self.ctx, _dev(fat, "fat"), _dev(naik, "naik") if naik is not None else None,
+                                   _stream()), "mg_update_links")
+
     def export(self, what, level=1):
         torch = _torch()
         need = ctypes.c_size_t()
@@ -291,3 +314,33 @@ class Context:
 
 def setup(params, fat, naik=None, null_vectors=None) -> Context:
     return Context(params, fat, naik, null_vectors)
+
+
+def _fermion_action_class():
+    torch = _torch()
+
+    class FermionAction(torch.autograd.Function):
+        """S = sum_r phi_r^dag (D^dag D)^{-1} phi_r as a differentiable function
+        of the fat and Naik links; the forward pass runs the two MG solves and
+        the force kernel of the library, the backward pass scales the stored
+        gradients.  `ctx_mg` is a Context whose links are replaced by (W, N)."""
+
+        @staticmethod
+        def forward(ctx, W, N, phi, ctx_mg, mass, tol):
+            ctx_mg.update_links(W.detach().contiguous(), N.detach().contiguous() if N is not None else None)
+            X, Y, gw, gn, info = ctx_mg.solve_backward(mass, phi.detach().contiguous(), tol)
+            ctx.save_for_backward(gw, gn if gn is not None else gw)
+            ctx.has_naik = gn is not None
+            return torch.sum(torch.conj(phi.detach()) * X).real
+
+        @staticmethod
+        def backward(ctx, g):
+            gw, gn = ctx.saved_tensors
+            return g * gw, (g * gn if ctx.has_naik else None), None, None, None, None
+
+    return FermionAction
+
+
+def fermion_action(W, N, phi, ctx_mg, mass, tol=1e-10):
+    """Differentiable S(W, N) = sum_r phi_r^dag (D^dag D)^{-1} phi_r (see FermionAction)."""
+    return _fermion_action_class().apply(W, N, phi, ctx_mg, mass, tol)

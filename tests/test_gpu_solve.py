@@ -9,7 +9,7 @@ from oracle import operators as ops
 from oracle import solvers as sol
 from paper_2212_12559_amd import latgen
 
-from gpu_common import CONFIGS, gpu_params, links, log, oracle_hierarchy, rel_err
+from gpu_common import CONFIGS, gpu_params, links, log, oracle_hierarchy, rel_err  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -195,3 +195,33 @@ def test_error_paths(torch, mg, cubic):
     with pytest.raises(mg.MGError) as e:
         make_ctx(torch, mg, cfg, W, N, bad, max_nrhs=1)
     assert e.value.status == mg.MG_E_RANK
+
+
+def test_force_matches_oracle(torch, mg, cubic):
+    """Fermion-force gradients from the MG solves and the outer-product kernel
+    against the oracle's (FD-pinned) force on the same links and source;
+    through torch.autograd as well."""
+    cfg, W, N, nvs, b = cubic
+    m = 0.1
+    log("[force] cubic")
+    ctx = make_ctx(torch, mg, cfg, W, N, nvs, max_nrhs=2, fine_prec=mg.MG_C128, coarse_prec=mg.MG_C128)
+    phi = b
+    X, Y, gw, gn, info = ctx.solve_backward(m, torch.from_numpy(phi).to("cuda:0"), tol=1e-13)
+    gw, gn = gw.cpu().numpy(), gn.cpu().numpy()
+    Sw = np.zeros_like(W)
+    Sn = np.zeros_like(N)
+    S = 0.0
+    for r in range(phi.shape[0]):
+        s_, gW, gN, Xo, Yo = sol.force(W, N, m, cfg["c1"], cfg["c3"], phi[r], tol=1e-13)
+        S += s_
+        Sw += gW
+        Sn += gN
+    assert rel_err(gw, Sw) < 1e-9
+    assert rel_err(gn, Sn) < 1e-9
+    Wt = torch.from_numpy(W).to("cuda:0").requires_grad_(True)
+    Nt = torch.from_numpy(N).to("cuda:0").requires_grad_(True)
+    St = mg.fermion_action(Wt, Nt, torch.from_numpy(phi).to("cuda:0"), ctx, m, 1e-13)
+    St.backward()
+    assert abs(St.item() - S) < 1e-9 * abs(S)
+    assert rel_err(Wt.grad.cpu().numpy(), Sw) < 1e-9
+    assert rel_err(Nt.grad.cpu().numpy(), Sn) < 1e-9

@@ -184,3 +184,28 @@ def test_round_to_nearest_even():
     assert np.max(np.abs(ops.round_bf16(v) - v) / np.abs(v)) <= 2.0 ** -8
     assert np.max(np.abs(ops.round_fp16(v) - v) / np.maximum(np.abs(v), 2.0 ** -14)) <= 2.0 ** -11
     assert ops.round_fp16(1.0 + 2.0 ** -11) == 1.0
+
+
+def test_force_matches_central_differences():
+    """Gradient of S = phi^dag (D^dag D)^{-1} phi with respect to fat and Naik
+    link entries (real and imaginary parts) against central finite differences
+    on a 4^4 lattice."""
+    dims = (4, 4, 4, 4)
+    W, N, rng = latgen.hisq_style_links(dims, 0.5, 41)
+    m = 0.2
+    phi = latgen.fine_vectors(dims, 1, rng)[0]
+    S, gW, gN, X, Y = sol.force(W, N, m, C1H, C3H, phi)
+    assert abs(S - sol.action(W, N, m, C1H, C3H, phi)) < 1e-9 * abs(S)
+    h = 1e-5
+    picks = [(0, 1, 2, 3, 0, 1, 2), (3, 0, 0, 1, 2, 2, 0), (2, 3, 1, 0, 1, 0, 0)]
+    for F, G in ((W, gW), (N, gN)):
+        for idx in picks:
+            for unit in (1.0, 1j):
+                Fp, Fm = F.copy(), F.copy()
+                Fp[idx] += h * unit
+                Fm[idx] -= h * unit
+                Wp, Np_ = (Fp, N) if F is W else (W, Fp)
+                Wm, Nm = (Fm, N) if F is W else (W, Fm)
+                fd = (sol.action(Wp, Np_, m, C1H, C3H, phi) - sol.action(Wm, Nm, m, C1H, C3H, phi)) / (2 * h)
+                want = G[idx].real if unit == 1.0 else G[idx].imag
+                assert abs(fd - want) < 1e-5 * max(1.0, abs(want)), (idx, unit, fd, want)
