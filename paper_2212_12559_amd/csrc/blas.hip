@@ -179,6 +179,40 @@ template void launch_gcr_update<float2>(float2*, float2*, float2*, float2*, cons
 template void launch_gcr_update<double2>(double2*, double2*, double2*, double2*, const double2*, const double2*,
                                          int64_t, int, double2*, double2*, int, hipStream_t);
 
+// CG update in one pass: x += alpha p, r -= alpha Ap, partial sums of |r|^2
+__global__ void __launch_bounds__(256) cg_update_kernel(double2* __restrict__ x, double2* __restrict__ r,
+                                                       const double2* __restrict__ p, const double2* __restrict__ ap,
+                                                       const double2* __restrict__ alpha, int64_t n,
+                                                       double2* __restrict__ part, int nblk) {
+  __shared__ double red[4];
+  const int rr = blockIdx.y;
+  const int64_t off = (int64_t)rr * n;
+  const double al = alpha[rr].x;
+  double s = 0.0;
+  for (int64_t e = off + (int64_t)blockIdx.x * 256 + threadIdx.x; e < off + n; e += (int64_t)nblk * 256) {
+    const double2 pv = p[e], av = ap[e];
+    double2 xv = x[e], rv = r[e];
+    xv.x = fma(al, pv.x, xv.x);
+    xv.y = fma(al, pv.y, xv.y);
+    rv.x = fma(-al, av.x, rv.x);
+    rv.y = fma(-al, av.y, rv.y);
+    x[e] = xv;
+    r[e] = rv;
+    s += rv.x * rv.x + rv.y * rv.y;
+  }
+  s = wsum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(int64_t)rr * nblk + blockIdx.x] = make_double2(red[0] + red[1] + red[2] + red[3], 0.0);
+}
+void launch_cg_update(double2* x, double2* r, const double2* p, const double2* ap, const double2* alpha, int64_t n,
+                      int nrhs, double2* part, double2* res, int ldr, hipStream_t st) {
+  const int nblk = reduce_blocks(n);
+  dim3 grid(nblk, nrhs);
+  cg_update_kernel<<<grid, 256, 0, st>>>(x, r, p, ap, alpha, n, part, nblk);
+  finalize_kernel<<<nrhs, 64, 0, st>>>(part, nblk, 1, nrhs, res, ldr);
+}
+
 // Convergence on the device: mask[r] stays 1 while |r|^2 > tol^2 |r0|^2
 // (and both are finite); init sets mask from |r0|^2 > 0.
 __global__ void conv_kernel(int* mask, const double2* rn2, const double2* r0sq, double tol2, int nrhs, int init) {

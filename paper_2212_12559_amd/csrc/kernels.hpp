@@ -166,6 +166,8 @@ void launch_random_normal(T* out, int64_t n, uint64_t seed, hipStream_t st);
 template <typename T>
 void launch_gcr_update(T* x, T* r, T* q, T* z, const double2* alpha, const double2* inv, int64_t n, int nrhs,
                        double2* part, double2* res, int ldr, hipStream_t st);
+void launch_cg_update(double2* x, double2* r, const double2* p, const double2* ap, const double2* alpha, int64_t n,
+                      int nrhs, double2* part, double2* res, int ldr, hipStream_t st);
 void launch_conv(int* mask, const double2* rn2, const double2* r0sq, double tol2, int nrhs, int init,
                  hipStream_t st);
 

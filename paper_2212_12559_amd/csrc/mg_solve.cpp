@@ -220,28 +220,41 @@ void Ctx::cg_solve(const double* masses, int nmass, const void* b, void* x, int 
       auto done = [&](int s) { return !(rn[s] > m * tol * bn[s]); };
       int live = 0;
       for (int s = 0; s < nrhs; ++s) if (act[s] && !done(s)) ++live;
+      for (int s = 0; s < nrhs; ++s) if (act[s] && done(s)) act[s] = 0;
+      HIPCHK(hipMemcpyAsync(mk, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+      // device-side convergence: a system stops updating once |r| <= m tol |b|
+      // (its alpha becomes 0); the host looks at the flags every few iterations
+      std::vector<double2> tgt(nrhs);
+      for (int s = 0; s < nrhs; ++s) tgt[s] = make_double2(bn[s] * bn[s], 0.0);
+      double2* b2 = slot(0, kSlotR0);
+      HIPCHK(hipMemcpyAsync(b2, tgt.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, st));
+      const double tol2 = (m * tol) * (m * tol);
+      int since = 0;
       while (live > 0 && total < maxiter) {
         cbd(to, p, nullptr, 1, 0.0, 1.0);
         cbd(Ap, to, p, 0, m * m, -1.0);
         dots(P64, nh, nrhs, {{p, Ap}}, pap);
         launch_cg_alpha(rr, pap, mk, nrhs, al, nal, st);
         check_launch();
-        lincomb(P64, nh, nrhs, xe, {{xe, nullptr}, {p, al}}, {}, {});
-        lincomb(P64, nh, nrhs, r, {{r, nullptr}, {Ap, nal}}, {}, {});
-        norms_host(P64, nh, nrhs, r, rrn, rn);
+        launch_cg_update(xe, r, p, Ap, al, nh, nrhs, part, rrn, max_sys, st);
+        check_launch();
+        launch_conv(mk, rrn, b2, tol2, nrhs, 0, st);
         launch_cg_beta(rr, rrn, mk, nrhs, bt, st);
         check_launch();
         lincomb(P64, nh, nrhs, p, {{r, nullptr}, {p, bt}}, {}, {});
         ++total;
-        bool changed = false;
-        live = 0;
-        for (int s = 0; s < nrhs; ++s) {
-          if (!act[s]) continue;
-          its[s] += 1;
-          if (done(s) || !std::isfinite(rn[s])) { act[s] = 0; changed = true; }
-          else ++live;
+        for (int s = 0; s < nrhs; ++s) if (act[s]) its[s] += 1;
+        if (++since == 4 || total >= maxiter) {
+          since = 0;
+          std::vector<int> h(nrhs);
+          HIPCHK(hipMemcpyAsync(h.data(), mk, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          live = 0;
+          for (int s = 0; s < nrhs; ++s) {
+            if (act[s] && !h[s]) act[s] = 0;
+            live += act[s];
+          }
         }
-        if (changed) HIPCHK(hipMemcpyAsync(mk, act.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
       }
       // x_o = (b_o - K_oe x_e) / m, then the true residual of the full system
       cbd(xo, xe, bo, 1, 1.0 / m, -1.0 / m);
