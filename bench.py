@@ -198,6 +198,7 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up, time the hot kernels and copy a known-size buffer (for counter runs)")
     ap.add_argument("--coarse-prec", default=None, choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--setup-iters", default=None, help="CGNE iterations per level, e.g. 10,10 (kernel timing runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus 1)", file=sys.stderr)
@@ -218,7 +219,8 @@ def main():
     masses = list(wl.get("masses", (m,)))
     cprec = args.coarse_prec or wl.get("coarse_prec", "fp32")
     cp = {"fp32": mg.MG_C64, "bf16": mg.MG_CBF16, "fp16": mg.MG_CF16}[cprec]
-    p = mg.default_params(dims, mass0=m, nvec=wl["nvec"], block=wl["blocks"], setup_maxiter=wl["setup_iters"],
+    setup_iters = tuple(int(v) for v in args.setup_iters.split(",")) if args.setup_iters else wl["setup_iters"]
+    p = mg.default_params(dims, mass0=m, nvec=wl["nvec"], block=wl["blocks"], setup_maxiter=setup_iters,
                           max_nrhs=wl["nrhs"], max_nmass=len(masses), kd_naik=wl["kd_naik"], coarse_prec=cp,
                           outer_nkrylov=8 if wl["nrhs"] > 1 else 16)
     log("[bench] setup")
