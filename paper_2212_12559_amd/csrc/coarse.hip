@@ -129,9 +129,10 @@ static void coarse_launch_nr(const CoarseArgs<R, LT>& a, bool piece, bool dag, h
 template <typename R, typename LT>
 void launch_coarse(const CoarseArgs<R, LT>& a, bool piece, bool dag, hipStream_t st) {
   if (a.nrhs <= 0) return;
-  if (a.nrhs >= 16 && sizeof(R) == 4 && !dag) coarse_launch_nr<R, LT, 16>(a, piece, dag, st);
-  else if (a.nrhs >= 8 && !dag) coarse_launch_nr<R, LT, 8>(a, piece, dag, st);
-  else if (a.nrhs >= 4) coarse_launch_nr<R, LT, 4>(a, piece, dag, st);
+  // wider rhs tiles issue one broadcast load per rhs and link element and
+  // become issue-bound (measured: 16 rhs per tile ran at a tenth of the
+  // bandwidth of 4); many right-hand sides belong on the matrix cores
+  if (a.nrhs >= 4) coarse_launch_nr<R, LT, 4>(a, piece, dag, st);
   else if (a.nrhs >= 2) coarse_launch_nr<R, LT, 2>(a, piece, dag, st);
   else coarse_launch_nr<R, LT, 1>(a, piece, dag, st);
 }

@@ -46,9 +46,9 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
   }
 }
 
-// FP64 links [site][d][col][row] -> swizzled 16-bit fragments (scaled)
-template <int FMT>
-__global__ void swizzle_links_kernel(const double2* __restrict__ cl, uint16_t* __restrict__ out, int64_t nsite,
+// links [site][d][col][row] (FP64 or FP32) -> swizzled 16-bit fragments (scaled)
+template <int FMT, typename TI>
+__global__ void swizzle_links_kernel(const TI* __restrict__ cl, uint16_t* __restrict__ out, int64_t nsite,
                                      int n, int kc_n, double scale) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int mt_n = n / 16;
@@ -66,20 +66,23 @@ __global__ void swizzle_links_kernel(const double2* __restrict__ cl, uint16_t* _
   float v = 0.0f;
   if (k < 9 * n) {
     const int d = k / n, col = k - d * n;
-    const double2 l = cl[((site * 9 + d) * n + col) * (int64_t)n + row];
-    v = (float)((plane ? l.y : l.x) * scale);
+    const TI l = cl[((site * 9 + d) * n + col) * (int64_t)n + row];
+    v = (float)((double)(plane ? l.y : l.x) * scale);
   }
   out[tid] = to16<FMT>(v);
 }
 
-void launch_swizzle_links(const double2* cl, uint16_t* out, int64_t nsite, int n, int fmt, double scale,
+template <typename TI>
+void launch_swizzle_links(const TI* cl, uint16_t* out, int64_t nsite, int n, int fmt, double scale,
                           hipStream_t st) {
   const int kc_n = (9 * n + 31) / 32;
   const int64_t tot = nsite * (n / 16) * kc_n * 2 * 64 * 8;
   const unsigned g = (unsigned)((tot + 255) / 256);
-  if (fmt == 0) swizzle_links_kernel<0><<<g, 256, 0, st>>>(cl, out, nsite, n, kc_n, scale);
-  else swizzle_links_kernel<1><<<g, 256, 0, st>>>(cl, out, nsite, n, kc_n, scale);
+  if (fmt == 0) swizzle_links_kernel<0, TI><<<g, 256, 0, st>>>(cl, out, nsite, n, kc_n, scale);
+  else swizzle_links_kernel<1, TI><<<g, 256, 0, st>>>(cl, out, nsite, n, kc_n, scale);
 }
+template void launch_swizzle_links<double2>(const double2*, uint16_t*, int64_t, int, int, double, hipStream_t);
+template void launch_swizzle_links<float2>(const float2*, uint16_t*, int64_t, int, int, double, hipStream_t);
 
 __global__ void absmax_kernel(const double2* __restrict__ v, int64_t n, unsigned long long* out) {
   double m = 0.0;

@@ -113,7 +113,8 @@ struct CoarseMfmaArgs {
   float inv_scale;
 };
 void launch_coarse_mfma(const CoarseMfmaArgs& a, int fmt, hipStream_t st);   // fmt 0 bf16, 1 fp16
-void launch_swizzle_links(const double2* cl, uint16_t* out, int64_t nsite, int n, int fmt, double scale,
+template <typename TI>
+void launch_swizzle_links(const TI* cl, uint16_t* out, int64_t nsite, int n, int fmt, double scale,
                           hipStream_t st);
 void launch_absmax(const double2* v, int64_t n, unsigned long long* out, hipStream_t st);
 int64_t swizzled_link_elems(int64_t nsite, int n);

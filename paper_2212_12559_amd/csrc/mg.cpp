@@ -74,6 +74,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     if ((p.coarse_prec == MG_CBF16 || p.coarse_prec == MG_CF16) && (a.nvec % 8))
       return fail("nvec must be a multiple of 8 for 16-bit coarse links (16-row MFMA tiles)");
     if (a.nvec > a.nrows) return fail("nvec exceeds the rows of an aggregate and chirality");
+    if (a.nrows > 4096) return fail("more than 4096 rows per aggregate and chirality");
     gc[l] = g;
     gcur = g;
     nin = a.nvec;
@@ -170,9 +171,10 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     const int prec = l == 0 ? fp : cp;
     size_t e = solver_base + 6 * (((size_t)p.nvec[l] * n * csize(prec) + 255) & ~(size_t)255) +
                3 * (((size_t)n * 16 + 255) & ~(size_t)255) + 256;
-    if (l == 1) {   // explicit adjoint links of the level-2 stencil
+    if (l == 1) {   // explicit adjoint links of the level-2 stencil (+ their 16-bit fragments)
       const int64_t nc = 2 * A[0].nvec;
       e += (size_t)gc[0].V * 9 * nc * nc * csize(prec) + 256;
+      if (c16) e += (size_t)swizzled_link_elems(gc[0].V, (int)nc) * 2 + 256;
     }
     setup_end = std::max(setup_end, e);
   }

@@ -77,6 +77,7 @@ void Ctx::cgne_null(int l) {
   void* tmp = base + 5 * vb;
   // past the six CGNE vectors and the three Galerkin vectors
   void* dagl = nullptr;
+  uint16_t* dag16 = nullptr;
   if (l == 1) {
     const size_t gb = ((size_t)n * 16 + 255) & ~(size_t)255;
     dagl = base + 6 * vb + 3 * gb;
@@ -84,6 +85,12 @@ void Ctx::cgne_null(int l) {
     if (prec == P64) launch_dagger_links<double2>(cl64[0], (double2*)dagl, gc[0], nc, st);
     else launch_dagger_links<float2>(cl32[0], (float2*)dagl, gc[0], nc, st);
     check_launch();
+    if (fmt16 >= 0) {
+      // 16-bit operator: the set-up iterates with the links the solver applies
+      dag16 = (uint16_t*)((char*)dagl + (((size_t)gc[0].V * 9 * nc * nc * csize(prec) + 255) & ~(size_t)255));
+      launch_swizzle_links<float2>((const float2*)dagl, dag16, gc[0].V, nc, fmt16, 1.0 / cl16_inv_scale[0], st);
+      check_launch();
+    }
   }
   auto A_apply = [&](void* out, const void* in, bool dag) {
     if (l == 0) {
@@ -95,6 +102,19 @@ void Ctx::cgne_null(int l) {
         apply_KD(prec, tmp, in, nv_, true, false, 0);
         apply_D(prec, out, tmp, nv_, nk, nullptr, P.mass0, true);
       }
+    } else if (fmt16 >= 0 && prec == P32) {
+      setup_phase = false;   // the 16-bit matrix-core stencil, forward or adjoint links
+      if (!dag) {
+        apply_coarse(2, prec, out, in, nv_, false);
+      } else {
+        CoarseMfmaArgs c{};
+        c.out = (float2*)out; c.in = (const float2*)in; c.links = dag16;
+        c.g = gc[0]; c.n = ncoarse[0]; c.in_stride = c.out_stride = gc[0].V * ncoarse[0]; c.nrhs = nv_;
+        c.inv_scale = cl16_inv_scale[0];
+        launch_coarse_mfma(c, fmt16, st);
+        check_launch();
+      }
+      setup_phase = true;
     } else if (!dag) {
       apply_coarse(2, prec, out, in, nv_, false);
     } else {
@@ -224,7 +244,7 @@ void Ctx::galerkin(int l) {
       if (amax > 0.0) scale = std::ldexp(1.0, -(int)std::lround(std::log2(amax)));
     }
     cl16_inv_scale[l] = (float)(1.0 / scale);
-    launch_swizzle_links(cl64[l], cl16[l], gc[l].V, n, fmt16, scale, st);
+    launch_swizzle_links<double2>(cl64[l], cl16[l], gc[l].V, n, fmt16, scale, st);
     check_launch();
   }
 }

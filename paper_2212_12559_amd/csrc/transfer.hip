@@ -126,11 +126,13 @@ void launch_p_layouts(const double2* pp64, double2* pr64, float2* pr32, float2* 
 }
 
 constexpr int kRestrictWaves = 8;
+constexpr int kMaxRestrictRows = 4096;   // rows per (aggregate, chirality)
 
 template <typename R, int NR, int KPL>
 __global__ void __launch_bounds__(64 * kRestrictWaves) restrict_kernel(const RestrictArgs<R> a) {
   using T = cplx<R>;
   __shared__ T red[kRestrictWaves - 1][NR][KPL * 64];
+  __shared__ int fidx[kMaxRestrictRows];   // fine index of every row of this (a, sigma)
   const int64_t as = blockIdx.x;
   const int64_t agg = as >> 1;
   const int sigma = (int)(as & 1);
@@ -139,13 +141,17 @@ __global__ void __launch_bounds__(64 * kRestrictWaves) restrict_kernel(const Res
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nvec = a.A.nvec, nrows = a.A.nrows;
   const T* P = a.pr + as * (int64_t)nrows * nvec;
+  // row -> fine index once per workgroup; the per-vector offsets fit 32 bits
+  for (int row = tid; row < nrows; row += 64 * kRestrictWaves) fidx[row] = (int)agg_row_index(a.A, agg, sigma, row);
+  __syncthreads();
   T acc[NR][KPL];
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int q = 0; q < KPL; ++q) { acc[r][q].x = 0; acc[r][q].y = 0; }
+#pragma unroll 4
   for (int row = wave; row < nrows; row += kRestrictWaves) {
-    const int64_t fi = agg_row_index(a.A, agg, sigma, row);
+    const int64_t fi = fidx[row];
     T x[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
