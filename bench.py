@@ -28,10 +28,10 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     # 32^4 HISQ-style, eps 0.5 (as the 16^4 workload), mass 0.005, KD + 4^4/Nvec 64 + 2^4/Nvec 96
     "c2": dict(dims=(32, 32, 32, 32), mass=0.005, nrhs=1, eps=0.5, seed=20221226, kd_naik=0,
-               nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(1000, 300)),
+               nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 300)),
     # the multi-mass batch: 32^4, 16 rhs x 8 masses (log-spaced 0.005..0.2), 16-bit coarse links
     "c2batch": dict(dims=(32, 32, 32, 32), mass=0.005, nrhs=16, eps=0.5, seed=20221226, kd_naik=0,
-                    nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(1000, 300),
+                    nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 300),
                     masses=(0.005, 0.0084691, 0.014345, 0.024298, 0.041156, 0.069711, 0.11808, 0.2),
                     coarse_prec="bf16"),
     # 16^4 HISQ-style, mass 0.01
@@ -65,8 +65,9 @@ def op_counts(info, s, nlev):
 
 
 # ---------------------------------------------------------------- bytes
-def algorithmic_bytes(dims, nvec, nrhs=1, csz=8, naik=True):
-    """Per-apply algorithmic HBM bytes (each operand read or written once)."""
+def algorithmic_bytes(dims, nvec, nrhs=1, csz=8, naik=True, link_csz=8):
+    """Per-apply algorithmic HBM bytes (each operand read or written once);
+    link_csz is the size of one stored complex coarse-link entry."""
     V = int(np.prod(dims))
     links = 8 * 9 * csz          # fat + Naik, 4 directions each, 3x3 complex (op 0 always has Naik)
     vec = 3 * csz
@@ -78,11 +79,11 @@ def algorithmic_bytes(dims, nvec, nrhs=1, csz=8, naik=True):
     }
     Vc = V // 256
     n = 2 * nvec[0]
-    b["coarse2"] = Vc * (9 * n * n * csz + 2 * n * csz * nrhs)
+    b["coarse2"] = Vc * (9 * n * n * link_csz + 2 * n * csz * nrhs)
     return b
 
 
-def kernel_rates(torch, ctx, wl, reps, mg):
+def kernel_rates(torch, ctx, wl, reps, mg, link_csz=8):
     """Average duration of each hot-path kernel at the workload's shape,
     timed with HIP events on torch's current stream (the library's stream)."""
     dims, m = wl["dims"], wl["mass"]
@@ -90,16 +91,20 @@ def kernel_rates(torch, ctx, wl, reps, mg):
     gen = torch.Generator(device=dev)
     gen.manual_seed(7)
     X, Y, Z, T = dims
-    x = torch.randn((1, T, Z, Y, X, 3), dtype=torch.complex64, device=dev, generator=gen)
-    xc = torch.randn((1,) + ctx.coarse_shapes[0], dtype=torch.complex64, device=dev, generator=gen)
-    xc3 = torch.randn((1,) + ctx.coarse_shapes[1], dtype=torch.complex64, device=dev, generator=gen)
+    nr = wl["nrhs"]
+    x = torch.randn((nr, T, Z, Y, X, 3), dtype=torch.complex64, device=dev, generator=gen)
+    xc = torch.randn((nr,) + ctx.coarse_shapes[0], dtype=torch.complex64, device=dev, generator=gen)
+    xc3 = torch.randn((nr,) + ctx.coarse_shapes[1], dtype=torch.complex64, device=dev, generator=gen)
     y = torch.empty_like(x)
     yc = torch.empty_like(xc)
     yc3 = torch.empty_like(xc3)
-    b = algorithmic_bytes(dims, wl["nvec"], naik=wl["kd_naik"] != 0)
+    b = algorithmic_bytes(dims, wl["nvec"], nrhs=nr, naik=wl["kd_naik"] != 0, link_csz=link_csz)
     n3 = 2 * wl["nvec"][1]
     Vc3 = int(np.prod(ctx.coarse_shapes[1][:4]))
-    b["coarse3"] = Vc3 * (9 * n3 * n3 * 8 + 2 * n3 * 8)
+    b["coarse3"] = Vc3 * (9 * n3 * n3 * link_csz + 2 * n3 * 8 * nr)
+    n2 = 2 * wl["nvec"][0]
+    Vc2 = int(np.prod(ctx.coarse_shapes[0][:4]))
+    flops = {"coarse2": 8.0 * Vc2 * n2 * 9 * n2 * nr, "coarse3": 8.0 * Vc3 * n3 * 9 * n3 * nr}
     ops = {
         "dslash": lambda: ctx.apply_dslash(0, m, x, y),
         "kd": lambda: ctx.apply_dslash(2, m, x, y),
@@ -120,11 +125,14 @@ def kernel_rates(torch, ctx, wl, reps, mg):
         e1.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / reps
         out[name] = {"us": us, "bytes": b[name], "GBps": b[name] / (us * 1e-6) / 1e9}
-        log(f"[bench] kernel {name}: {us:.1f} us, {out[name]['GBps']:.0f} GB/s")
+        if name in flops:
+            out[name]["TFLOPs"] = flops[name] / (us * 1e-6) / 1e12
+        log(f"[bench] kernel {name}: {us:.1f} us, {out[name]['GBps']:.0f} GB/s"
+            + (f", {out[name]['TFLOPs']:.1f} TFLOP/s" if name in flops else ""))
     return out
 
 
-def cpu_baseline(wl, info, s):
+def cpu_baseline(wl, batch_infos, s):
     """The FP64 oracle (numpy, one thread) timed on a bounded sample: one
     application of each hot-path operator at the workload's lattice (the
     coarse operator at a 16^4 lattice, scaled by the volume ratio), combined
@@ -172,16 +180,18 @@ def cpu_baseline(wl, info, s):
         H.op(2, rc)
         t_c2 = (time.perf_counter() - t0) * scale
     sample_s = time.perf_counter() - t_total
-    cnt = op_counts(info, s, 4)
-    est = (cnt["dslash_fp64"] * t_d + cnt["dslash_fp32_level0"] * t_d + cnt["dslash_fp32_level1"] * t_d1
-           + cnt["kd_fp32"] * t_kd + cnt["restrict1"] * t_r + cnt["prolong1"] * t_p
-           + (cnt["coarse2"] + cnt["coarse3"]) * t_c2)
+    est = 0.0
+    for info in batch_infos:
+        cnt = op_counts(info, s, 4)
+        est += wl["nrhs"] * (cnt["dslash_fp64"] * t_d + cnt["dslash_fp32_level0"] * t_d
+                             + cnt["dslash_fp32_level1"] * t_d1 + cnt["kd_fp32"] * t_kd + cnt["restrict1"] * t_r
+                             + cnt["prolong1"] * t_p + (cnt["coarse2"] + cnt["coarse3"]) * t_c2)
     log(f"[bench] cpu oracle: D {t_d:.2f}s KD {t_kd:.2f}s R {t_r:.2f}s P {t_p:.2f}s C2 {t_c2:.2f}s -> {est:.0f} s")
     return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
             "sample": (f"one oracle application each of D, D_KD, (B+m)^-1 at {'x'.join(map(str, dims))}, and of "
                        f"R, P, the level-2 operator R A P at 16^4 scaled by the volume ratio; multiplied by the "
-                       f"operator counts of the measured MG solve (level-3 applies priced as level 2, Krylov "
-                       f"BLAS omitted: a lower bound); sample took {sample_s:.1f} s"),
+                       f"operator counts of the measured MG solves, per system (level-3 applies priced as "
+                       f"level 2, Krylov BLAS omitted: a lower bound); sample took {sample_s:.1f} s"),
             "per_op_s": {"dslash": t_d, "dslash_kd": t_d1, "kd": t_kd, "restrict": t_r, "prolong": t_p,
                          "coarse": t_c2}}
 
@@ -189,9 +199,9 @@ def cpu_baseline(wl, info, s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="c2batch", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG comparator")
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -232,7 +242,7 @@ def main():
     log(f"[bench] setup {setup_s:.2f} s")
 
     if args.kernels_only:
-        kern = kernel_rates(torch, ctx, wl, args.kernel_reps, mg)
+        kern = kernel_rates(torch, ctx, wl, args.kernel_reps, mg, 8 if cprec == "fp32" else 4)
         src = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
@@ -241,16 +251,30 @@ def main():
         print(json.dumps({k: {"us": v["us"], "bytes": v["bytes"]} for k, v in kern.items()}), flush=True)
         return
 
+    # per-mass set-up (the exact KD inverse of every mass, Sec. 3.1) outside the timed region
+    xk = torch.zeros((1,) + ctx.fine_shape, dtype=torch.complex64, device=dev)
+    for mj in masses:
+        ctx.apply_dslash(2, mj, xk)
+    torch.cuda.synchronize()
+    del xk
+    def mg_step(tag):
+        # one lockstep batch per mass (the library batches per mass anyway); a line per mass
+        info_all = []
+        for mj in masses:
+            x, info, st = ctx.solve([mj], bt, tol=1e-10)
+            info_all += info
+            log(f"[bench] {tag} mass {mj}: {info[0]['outer_iters']} outer, level iters {info[0]['level_iters']}, "
+                f"{info[0]['seconds']:.2f} s, max residual {max(i['true_rel_residual'] for i in info):.2e}")
+            del x
+        return info_all
+
     for i in range(args.warmup):
-        x, info, st = ctx.solve(masses, bt, tol=1e-10)
-        log(f"[bench] warmup {i}: {info[0]}")
+        mg_step(f"warmup {i}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
     for i in range(args.steps):
-        x, info, st = ctx.solve(masses, bt, tol=1e-10)
-        infos.append(info)
-        log(f"[bench] step {i}: {info[0]} ... {info[-1]['outer_iters']} outer at the heaviest mass")
+        infos.append(mg_step(f"step {i}"))
     torch.cuda.synchronize()
     mg_s = (time.perf_counter() - t0) / args.steps
     res = max(s["true_rel_residual"] for i in infos for s in i)
@@ -259,23 +283,30 @@ def main():
     if not args.no_cg:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        xc, cinfo, st = ctx.cg_solve(masses, bt, tol=1e-10, maxiter=200000)
+        cg_iters = []
+        for mj in masses:
+            xc, cinfo, st = ctx.cg_solve([mj], bt, tol=1e-10, maxiter=200000)
+            cg_iters.append(max(i["outer_iters"] for i in cinfo))
+            log(f"[bench] CG mass {mj}: {cg_iters[-1]} iterations, {cinfo[0]['seconds']:.2f} s")
+            del xc
         torch.cuda.synchronize()
         cg_s = time.perf_counter() - t0
-        cg_info = cinfo[0]
-        del xc
+        cg_info = {"outer_iters": cg_iters}
         log(f"[bench] CG {cg_s:.3f} s {cg_info}")
 
     # ---- per-kernel timings (HIP events on the stream the library launches on)
-    kern = kernel_rates(torch, ctx, wl, args.kernel_reps, mg)
+    kern = kernel_rates(torch, ctx, wl, args.kernel_reps, mg, 8 if cprec == "fp32" else 4)
     dom = kern["coarse2"]
-    roof = {"bound": "hbm", "kernel": "coarse_kernel<float,float2,1> (level-2 coarse stencil)",
+    kname = ("coarse_kernel<float,float2>" if cprec == "fp32" else f"coarse_mfma_kernel<{cprec}>")
+    roof = {"bound": "hbm", "kernel": f"{kname} (level-2 coarse stencil, {wl['nrhs']} rhs per launch)",
             "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": None,
             "bytes_per_launch": dom["bytes"], "avg_launch_us": dom["us"]}
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(wl, infos[-1][0], p.smoother_s)
+        # one info per lockstep batch (one mass, nrhs systems): counts x nrhs single applications
+        batch_infos = [infos[-1][j * wl["nrhs"]] for j in range(len(masses))]
+        cpu = cpu_baseline(wl, batch_infos, p.smoother_s)
 
     out = {
         "metric": "MG-GCR time-to-1e-10 vs plain CG at 32^4 HISQ; Dslash/coarse GB/s, MFMA %",
@@ -295,13 +326,15 @@ def main():
                                f"KD + {wl['blocks'][0]}/Nvec {wl['nvec'][0]} + {wl['blocks'][1]}/Nvec {wl['nvec'][1]}, "
                                f"coarse links {cprec}"},
         "mg_info": infos[-1][0],
+        "mg_outer_iters_per_mass": [infos[-1][j * wl["nrhs"]]["outer_iters"] for j in range(len(masses))],
         "setup_s": setup_s,
         "cg_s": cg_s,
-        "cg_iters": cg_info["outer_iters"] if cg_info else None,
+        "cg_iters_per_mass": cg_info["outer_iters"] if cg_info else None,
         "speedup_vs_cg": (cg_s / mg_s) if cg_s else None,
         "true_rel_residual": res,
         "roofline": roof,
-        "kernels": {k: {"us": round(v["us"], 2), "GBps": round(v["GBps"], 1)} for k, v in kern.items()},
+        "kernels": {k: {kk: round(vv, 2) for kk, vv in v.items() if kk != "bytes"} for k, v in kern.items()},
+        "mfma_frac_coarse2": (kern["coarse2"].get("TFLOPs", 0.0) / 2500.0) if cprec != "fp32" else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
