@@ -96,7 +96,7 @@ void launch_absmax(const double2* v, int64_t n, unsigned long long* out, hipStre
   absmax_kernel<<<480, 256, 0, st>>>(v, n, out);
 }
 
-constexpr int kMfmaWaves = 4;
+constexpr int kMfmaWaves = 8;
 
 template <int FMT>
 __global__ void __launch_bounds__(64 * kMfmaWaves) coarse_mfma_kernel(const CoarseMfmaArgs a) {
@@ -119,19 +119,28 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) coarse_mfma_kernel(const Coar
     nb[1 + 2 * mu] = site_shift(c, mu, 1, a.g);
     nb[2 + 2 * mu] = site_shift(c, mu, -1, a.g);
   }
-  // stage B: column j = rhs r0 + j, row k = d n + col
-  for (int e = tid; e < 16 * kc_n * 32; e += 64 * kMfmaWaves) {
-    const int j = e / (kc_n * 32);
-    const int k = e - j * (kc_n * 32);
-    float re = 0.0f, im = 0.0f;
-    if (k < K && r0 + j < a.nrhs) {
-      const int d = k / n, col = k - d * n;
-      const float2 v = a.in[(int64_t)(r0 + j) * a.in_stride + nb[d] * n + col];
-      re = v.x;
-      im = v.y;
+  // stage B: column j = rhs r0 + j, row k = d n + col; each thread converts two
+  // consecutive k (same direction, n is even) per step: one 16-byte load, two
+  // 4-byte LDS stores; the direction / column walk is incremental
+  const int KC = kc_n * 32;
+  constexpr int NT = 64 * kMfmaWaves;
+  for (int j = 0; j < 16; ++j) {
+    const bool live = r0 + j < a.nrhs;
+    const float2* xj = a.in + (int64_t)(live ? r0 + j : 0) * a.in_stride;
+    int k = 2 * tid;
+    int d = k / n, col = k - (k / n) * n;
+    for (; k < KC; k += 2 * NT) {
+      uint32_t pre = 0, pim = 0;
+      if (live && k < K) {
+        const float4 v = *reinterpret_cast<const float4*>(xj + nb[d] * n + col);
+        pre = (uint32_t)to16<FMT>(v.x) | ((uint32_t)to16<FMT>(v.z) << 16);
+        pim = (uint32_t)to16<FMT>(v.y) | ((uint32_t)to16<FMT>(v.w) << 16);
+      }
+      *reinterpret_cast<uint32_t*>(Bre + j * KP + k) = pre;
+      *reinterpret_cast<uint32_t*>(Bim + j * KP + k) = pim;
+      col += 2 * NT;
+      while (col >= n) { col -= n; ++d; }
     }
-    Bre[j * KP + k] = to16<FMT>(re);
-    Bim[j * KP + k] = to16<FMT>(im);
   }
   __syncthreads();
   const int mt_n = n / 16;

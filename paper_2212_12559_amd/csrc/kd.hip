@@ -171,9 +171,13 @@ void launch_kd_apply(const KdArgs<R>& a, hipStream_t st) {
   if (a.nrhs <= 0) return;
   const int64_t nhc = a.g.V / 16;
   const unsigned gx = (unsigned)((nhc + 3) / 4);
+  const bool tile16 = sizeof(R) == 4 && a.nrhs >= 16 && (a.rhs_per_slot <= 0 || a.rhs_per_slot % 16 == 0);
   const bool tile8 = a.nrhs >= 8 && (a.rhs_per_slot <= 0 || a.rhs_per_slot % 8 == 0);
   const bool tile4 = a.nrhs >= 4 && (a.rhs_per_slot <= 0 || a.rhs_per_slot % 4 == 0);
-  if (tile8) {
+  if (tile16) {
+    dim3 grid(gx, (unsigned)((a.nrhs + 15) / 16));
+    kd_apply_kernel<R, 16><<<grid, 256, 0, st>>>(a);
+  } else if (tile8) {
     dim3 grid(gx, (unsigned)((a.nrhs + 7) / 8));
     kd_apply_kernel<R, 8><<<grid, 256, 0, st>>>(a);
   } else if (tile4) {

@@ -126,13 +126,13 @@ void launch_p_layouts(const double2* pp64, double2* pr64, float2* pr32, float2* 
 }
 
 constexpr int kRestrictWaves = 8;
-constexpr int kMaxRestrictRows = 4096;   // rows per (aggregate, chirality)
 
 template <typename R, int NR, int KPL>
 __global__ void __launch_bounds__(64 * kRestrictWaves) restrict_kernel(const RestrictArgs<R> a) {
   using T = cplx<R>;
   __shared__ T red[kRestrictWaves - 1][NR][KPL * 64];
-  __shared__ int fidx[kMaxRestrictRows];   // fine index of every row of this (a, sigma)
+  extern __shared__ unsigned char xs_raw[];   // [NR][nrows] input values of this (a, sigma)
+  T* xs = reinterpret_cast<T*>(xs_raw);
   const int64_t as = blockIdx.x;
   const int64_t agg = as >> 1;
   const int sigma = (int)(as & 1);
@@ -141,30 +141,32 @@ __global__ void __launch_bounds__(64 * kRestrictWaves) restrict_kernel(const Res
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nvec = a.A.nvec, nrows = a.A.nrows;
   const T* P = a.pr + as * (int64_t)nrows * nvec;
-  // row -> fine index once per workgroup; the per-vector offsets fit 32 bits
-  for (int row = tid; row < nrows; row += 64 * kRestrictWaves) fidx[row] = (int)agg_row_index(a.A, agg, sigma, row);
+  // gather the tile's inputs once (rows are spread over the fine lattice)
+  for (int row = tid; row < nrows; row += 64 * kRestrictWaves) {
+    const int64_t fi = agg_row_index(a.A, agg, sigma, row);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T v;
+      v.x = 0; v.y = 0;
+      if (r < nr) v = a.in[(int64_t)(r0 + r) * a.in_stride + fi];
+      xs[r * nrows + row] = v;
+    }
+  }
   __syncthreads();
   T acc[NR][KPL];
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int q = 0; q < KPL; ++q) { acc[r][q].x = 0; acc[r][q].y = 0; }
-#pragma unroll 4
+#pragma unroll 2
   for (int row = wave; row < nrows; row += kRestrictWaves) {
-    const int64_t fi = fidx[row];
-    T x[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      if (r < nr) x[r] = a.in[(int64_t)(r0 + r) * a.in_stride + fi];
-      else { x[r].x = 0; x[r].y = 0; }
-    }
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
       const int k = lane + 64 * q;
       if (k < nvec) {
         const T p = P[(int64_t)row * nvec + k];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) cfmac(acc[r][q], p, x[r]);
+        for (int r = 0; r < NR; ++r) cfmac(acc[r][q], p, xs[r * nrows + row]);
       }
     }
   }
@@ -191,19 +193,28 @@ __global__ void __launch_bounds__(64 * kRestrictWaves) restrict_kernel(const Res
   }
 }
 
+template <typename R, int NR, int KPL>
+static void restrict_launch(const RestrictArgs<R>& a, hipStream_t st) {
+  dim3 grid((unsigned)(a.A.nagg * 2), (unsigned)((a.nrhs + NR - 1) / NR));
+  const size_t lds = (size_t)NR * a.A.nrows * sizeof(cplx<R>);
+  restrict_kernel<R, NR, KPL><<<grid, 64 * kRestrictWaves, lds, st>>>(a);
+}
+
 template <typename R>
 void launch_restrict(const RestrictArgs<R>& a, hipStream_t st) {
   if (a.nrhs <= 0) return;
-  const unsigned gx = (unsigned)(a.A.nagg * 2);
   const bool big = a.A.nvec > 64;
-  if (a.nrhs >= 4) {
-    dim3 grid(gx, (unsigned)((a.nrhs + 3) / 4));
-    if (big) restrict_kernel<R, 4, 2><<<grid, 64 * kRestrictWaves, 0, st>>>(a);
-    else restrict_kernel<R, 4, 1><<<grid, 64 * kRestrictWaves, 0, st>>>(a);
+  // the staged inputs must fit next to the reduction buffer (64 KiB budget)
+  const size_t row_bytes = (size_t)a.A.nrows * sizeof(cplx<R>);
+  if (a.nrhs >= 8 && sizeof(R) == 4 && 8 * row_bytes <= 65536) {
+    if (big) restrict_launch<R, 8, 2>(a, st);
+    else restrict_launch<R, 8, 1>(a, st);
+  } else if (a.nrhs >= 4 && 4 * row_bytes <= 65536) {
+    if (big) restrict_launch<R, 4, 2>(a, st);
+    else restrict_launch<R, 4, 1>(a, st);
   } else {
-    dim3 grid(gx, (unsigned)a.nrhs);
-    if (big) restrict_kernel<R, 1, 2><<<grid, 64 * kRestrictWaves, 0, st>>>(a);
-    else restrict_kernel<R, 1, 1><<<grid, 64 * kRestrictWaves, 0, st>>>(a);
+    if (big) restrict_launch<R, 1, 2>(a, st);
+    else restrict_launch<R, 1, 1>(a, st);
   }
 }
 template void launch_restrict<float>(const RestrictArgs<float>&, hipStream_t);
@@ -260,7 +271,10 @@ template <typename R>
 void launch_prolong(const ProlongArgs<R>& a, hipStream_t st) {
   if (a.nrhs <= 0) return;
   const unsigned gx = (unsigned)(a.A.nagg * 2);
-  if (a.nrhs >= 4) {
+  if (a.nrhs >= 8 && sizeof(R) == 4) {
+    dim3 grid(gx, (unsigned)((a.nrhs + 7) / 8));
+    prolong_kernel<R, 8><<<grid, 512, 0, st>>>(a);
+  } else if (a.nrhs >= 4) {
     dim3 grid(gx, (unsigned)((a.nrhs + 3) / 4));
     prolong_kernel<R, 4><<<grid, 512, 0, st>>>(a);
   } else {
