@@ -29,11 +29,12 @@ WORKLOADS = {
     # 32^4 HISQ-style, eps 0.5 (as the 16^4 workload), mass 0.005, KD + 4^4/Nvec 64 + 2^4/Nvec 96
     "c2": dict(dims=(32, 32, 32, 32), mass=0.005, nrhs=1, eps=0.5, seed=20221226, kd_naik=0,
                nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 300)),
-    # the multi-mass batch: 32^4, 16 rhs x 8 masses (log-spaced 0.005..0.2), 16-bit coarse links
+    # the multi-mass batch: 32^4, 16 rhs x 8 masses (log-spaced 0.005..0.2), 16-bit coarse links;
+    # 4 masses (64 systems) per lockstep solve
     "c2batch": dict(dims=(32, 32, 32, 32), mass=0.005, nrhs=16, eps=0.5, seed=20221226, kd_naik=0,
                     nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 300),
                     masses=(0.005, 0.0084691, 0.014345, 0.024298, 0.041156, 0.069711, 0.11808, 0.2),
-                    coarse_prec="bf16"),
+                    coarse_prec="bf16", mass_batch=4),
     # 16^4 HISQ-style, mass 0.01
     "c1": dict(dims=(16, 16, 16, 16), mass=0.01, nrhs=1, eps=0.5, seed=20221225, kd_naik=0,
                nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 2000)),
@@ -91,7 +92,7 @@ def kernel_rates(torch, ctx, wl, reps, mg, link_csz=8):
     gen = torch.Generator(device=dev)
     gen.manual_seed(7)
     X, Y, Z, T = dims
-    nr = wl["nrhs"]
+    nr = wl["nrhs"] * wl.get("mass_batch", 1)
     x = torch.randn((nr, T, Z, Y, X, 3), dtype=torch.complex64, device=dev, generator=gen)
     xc = torch.randn((nr,) + ctx.coarse_shapes[0], dtype=torch.complex64, device=dev, generator=gen)
     xc3 = torch.randn((nr,) + ctx.coarse_shapes[1], dtype=torch.complex64, device=dev, generator=gen)
@@ -208,6 +209,7 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up, time the hot kernels and copy a known-size buffer (for counter runs)")
     ap.add_argument("--coarse-prec", default=None, choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--nmass", type=int, default=None, help="solve only the first NMASS masses (profiling runs)")
     ap.add_argument("--setup-iters", default=None, help="CGNE iterations per level, e.g. 10,10 (kernel timing runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -226,12 +228,13 @@ def main():
     Wt, Nt = torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev)
     bt = torch.from_numpy(b).to(dev)
     del W, N, b
-    masses = list(wl.get("masses", (m,)))
+    masses = list(wl.get("masses", (m,)))[:args.nmass]
     cprec = args.coarse_prec or wl.get("coarse_prec", "fp32")
     cp = {"fp32": mg.MG_C64, "bf16": mg.MG_CBF16, "fp16": mg.MG_CF16}[cprec]
     setup_iters = tuple(int(v) for v in args.setup_iters.split(",")) if args.setup_iters else wl["setup_iters"]
+    mb = wl.get("mass_batch", 1)
     p = mg.default_params(dims, mass0=m, nvec=wl["nvec"], block=wl["blocks"], setup_maxiter=setup_iters,
-                          max_nrhs=wl["nrhs"], max_nmass=len(masses), kd_naik=wl["kd_naik"], coarse_prec=cp,
+                          max_nrhs=wl["nrhs"] * mb, max_nmass=len(masses), kd_naik=wl["kd_naik"], coarse_prec=cp,
                           outer_nkrylov=8 if wl["nrhs"] > 1 else 16)
     log("[bench] setup")
     torch.cuda.synchronize()
@@ -257,14 +260,20 @@ def main():
         ctx.apply_dslash(2, mj, xk)
     torch.cuda.synchronize()
     del xk
+    nr = wl["nrhs"]
+
     def mg_step(tag):
-        # one lockstep batch per mass (the library batches per mass anyway); a line per mass
+        # lockstep batches of mb masses x nrhs systems; a line per batch and mass
         info_all = []
-        for mj in masses:
-            x, info, st = ctx.solve([mj], bt, tol=1e-10)
+        for j0 in range(0, len(masses), mb):
+            chunk = masses[j0:j0 + mb]
+            x, info, st = ctx.solve(chunk, bt, tol=1e-10)
             info_all += info
-            log(f"[bench] {tag} mass {mj}: {info[0]['outer_iters']} outer, level iters {info[0]['level_iters']}, "
-                f"{info[0]['seconds']:.2f} s, max residual {max(i['true_rel_residual'] for i in info):.2e}")
+            for j, mj in enumerate(chunk):
+                ij = info[j * nr:(j + 1) * nr]
+                log(f"[bench] {tag} mass {mj}: {max(i['outer_iters'] for i in ij)} outer, batch level iters "
+                    f"{ij[0]['level_iters']}, batch {ij[0]['seconds']:.2f} s, "
+                    f"max residual {max(i['true_rel_residual'] for i in ij):.2e}")
             del x
         return info_all
 
@@ -298,7 +307,7 @@ def main():
     kern = kernel_rates(torch, ctx, wl, args.kernel_reps, mg, 8 if cprec == "fp32" else 4)
     dom = kern["coarse2"]
     kname = ("coarse_kernel<float,float2>" if cprec == "fp32" else f"coarse_mfma_kernel<{cprec}>")
-    roof = {"bound": "hbm", "kernel": f"{kname} (level-2 coarse stencil, {wl['nrhs']} rhs per launch)",
+    roof = {"bound": "hbm", "kernel": f"{kname} (level-2 coarse stencil, {wl['nrhs'] * mb} rhs per launch)",
             "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": None,
             "bytes_per_launch": dom["bytes"], "avg_launch_us": dom["us"]}
@@ -322,11 +331,12 @@ def main():
         "dtype": "c128 outer / c64 K-cycle",
         "data": "synthetic",
         "config": {"workload": f"{'x'.join(map(str, dims))} HISQ-style eps 0.5, masses {masses}, "
-                               f"{wl['nrhs']} rhs per mass, truncated-KD={not wl['kd_naik']}, "
+                               f"{wl['nrhs']} rhs per mass, {mb} masses per lockstep solve, truncated-KD={not wl['kd_naik']}, "
                                f"KD + {wl['blocks'][0]}/Nvec {wl['nvec'][0]} + {wl['blocks'][1]}/Nvec {wl['nvec'][1]}, "
                                f"coarse links {cprec}"},
         "mg_info": infos[-1][0],
-        "mg_outer_iters_per_mass": [infos[-1][j * wl["nrhs"]]["outer_iters"] for j in range(len(masses))],
+        "mg_outer_iters_per_mass": [max(i["outer_iters"] for i in infos[-1][j * nr:(j + 1) * nr])
+                                    for j in range(len(masses))],
         "setup_s": setup_s,
         "cg_s": cg_s,
         "cg_iters_per_mass": cg_info["outer_iters"] if cg_info else None,

@@ -213,6 +213,249 @@ void launch_cg_update(double2* x, double2* r, const double2* p, const double2* a
   finalize_kernel<<<nrhs, 64, 0, st>>>(part, nblk, 1, nrhs, res, ldr);
 }
 
+// ------------------------------------------------------------ CA-GCR Gram
+// The smoother's Gram data in one pass over its s + 1 vectors (u_i = A p_i
+// for i < s, u_s = t): G(i, j) = <u_i, u_j> for i <= j < s, then
+// c_i = <u_i, t>, in the slot order of the Cholesky solve.  The four
+// wavefronts of a block walk the same 64 elements and take the pairs of the
+// largest basis round-robin, so each holds at most 11 FP64 accumulators and
+// every vector element is fetched from HBM once.
+template <typename T>
+__global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2* __restrict__ part, int nblk) {
+  constexpr int S = kMaxS;
+  constexpr int NPF = S * (S + 1) / 2 + S;
+  constexpr int PW = (NPF + 3) / 4;
+  const int r = blockIdx.y;
+  const int64_t off = (int64_t)r * a.stride;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int s = a.s;
+  double2 acc[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int64_t e = (int64_t)blockIdx.x * 64 + lane; e < a.n; e += (int64_t)nblk * 64) {
+    double2 v[S + 1];
+#pragma unroll
+    for (int i = 0; i <= S; ++i) {
+      if (i < S) v[i] = i < s ? to_d2(a.u[i][off + e]) : make_double2(0.0, 0.0);
+      else v[i] = to_d2(a.u[s][off + e]);
+    }
+    int f = 0;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+#pragma unroll
+      for (int j = i; j <= S; ++j) {
+        if ((f & 3) == wave && i < s && (j < s || j == S)) cfmac(acc[f >> 2], v[i], v[j]);
+        ++f;
+      }
+    }
+  }
+  int f = 0;
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+#pragma unroll
+    for (int j = i; j <= S; ++j) {
+      if ((f & 3) == wave && i < s && (j < s || j == S)) {
+        const double sx = wsum(acc[f >> 2].x), sy = wsum(acc[f >> 2].y);
+        const int p = j < S ? i * s - i * (i - 1) / 2 + (j - i) : s * (s + 1) / 2 + i;
+        if (lane == 0) part[((int64_t)p * a.nrhs + r) * nblk + blockIdx.x] = make_double2(sx, sy);
+      }
+      ++f;
+    }
+  }
+}
+
+template <typename T>
+void launch_gram(const GramArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
+  int64_t b = (a.n + 1023) / 1024;
+  if (b < 1) b = 1;
+  if (b > 480) b = 480;
+  const int nblk = (int)b;
+  gram_kernel<T><<<dim3(nblk, a.nrhs), 256, 0, st>>>(a, part, nblk);
+  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, a.s * (a.s + 1) / 2 + a.s, a.nrhs, res, ldr);
+}
+template void launch_gram<float2>(const GramArgs<float2>&, double2*, double2*, int, hipStream_t);
+template void launch_gram<double2>(const GramArgs<double2>&, double2*, double2*, int, hipStream_t);
+
+// ---------------------------------------------- deferred-update GCR passes
+// <x_i, y> for i < nv, y fetched once per element
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(256) multidot_kernel(const MultiDotArgs<T> a, double2* __restrict__ part,
+                                                       int nblk) {
+  __shared__ double2 red[4][MAXV];
+  const int r = blockIdx.y;
+  const int64_t off = (int64_t)r * a.stride;
+  double2 acc[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) acc[i] = make_double2(0.0, 0.0);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.n; e += (int64_t)nblk * 256) {
+    const double2 y = to_d2(a.y[off + e]);
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < a.nv) cfmac(acc[i], to_d2(a.x[i][off + e]), y);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    if (i < a.nv) {
+      const double sx = wsum(acc[i].x), sy = wsum(acc[i].y);
+      if (lane == 0) red[wave][i] = make_double2(sx, sy);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.nv; i += 256) {
+    double2 t = red[0][i];
+    for (int w = 1; w < 4; ++w) { t.x += red[w][i].x; t.y += red[w][i].y; }
+    part[((int64_t)i * a.nrhs + r) * nblk + blockIdx.x] = t;
+  }
+}
+
+template <typename T>
+void launch_multidot(const MultiDotArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
+  if (a.nv <= 0) return;
+  const int nblk = reduce_blocks(a.n);
+  dim3 grid(nblk, a.nrhs);
+  if (a.nv <= 4) multidot_kernel<T, 4><<<grid, 256, 0, st>>>(a, part, nblk);
+  else multidot_kernel<T, kMaxNK><<<grid, 256, 0, st>>>(a, part, nblk);
+  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, a.nv, a.nrhs, res, ldr);
+}
+template void launch_multidot<float2>(const MultiDotArgs<float2>&, double2*, double2*, int, hipStream_t);
+template void launch_multidot<double2>(const MultiDotArgs<double2>&, double2*, double2*, int, hipStream_t);
+
+// q <- q - sum_i beta_i x_i (written only when nv > 0), then partial sums of
+// |q|^2 and <q, r> over the stored (rounded) q
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(256) project_dots_kernel(const ProjArgs<T> a, double2* __restrict__ part,
+                                                           int nblk) {
+  __shared__ double2 red[4][2];
+  const int r = blockIdx.y;
+  const int64_t off = (int64_t)r * a.stride;
+  double2 b[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) b[i] = i < a.nv ? a.beta[i][r] : make_double2(0.0, 0.0);
+  double2 qq = make_double2(0.0, 0.0), qr = make_double2(0.0, 0.0);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.n; e += (int64_t)nblk * 256) {
+    double2 qv = to_d2(a.q[off + e]);
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < a.nv) cfma(qv, make_double2(-b[i].x, -b[i].y), to_d2(a.x[i][off + e]));
+    const T qt = from_d2<T>(qv);
+    if (a.nv > 0) a.q[off + e] = qt;
+    const double2 qs = to_d2(qt);
+    qq.x += qs.x * qs.x + qs.y * qs.y;
+    cfmac(qr, qs, to_d2(a.r[off + e]));
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double s0 = wsum(qq.x), s1 = wsum(qr.x), s2 = wsum(qr.y);
+  if (lane == 0) {
+    red[wave][0] = make_double2(s0, 0.0);
+    red[wave][1] = make_double2(s1, s2);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int i = threadIdx.x;
+    double2 t = red[0][i];
+    for (int w = 1; w < 4; ++w) { t.x += red[w][i].x; t.y += red[w][i].y; }
+    part[((int64_t)i * a.nrhs + r) * nblk + blockIdx.x] = t;
+  }
+}
+
+template <typename T>
+void launch_project_dots(const ProjArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
+  const int nblk = reduce_blocks(a.n);
+  dim3 grid(nblk, a.nrhs);
+  if (a.nv <= 4) project_dots_kernel<T, 4><<<grid, 256, 0, st>>>(a, part, nblk);
+  else project_dots_kernel<T, kMaxNK><<<grid, 256, 0, st>>>(a, part, nblk);
+  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, 2, a.nrhs, res, ldr);
+}
+template void launch_project_dots<float2>(const ProjArgs<float2>&, double2*, double2*, int, hipStream_t);
+template void launch_project_dots<double2>(const ProjArgs<double2>&, double2*, double2*, int, hipStream_t);
+
+// Scalars of direction k from qq = |q'|^2, qr = <q', r> (q' orthogonalised):
+// g_k = |q'|, alpha'_k = <q'/g_k, r> (the coefficient of the normalised
+// direction, kept for the deferred solution update), alpha = qr / qq for the
+// residual update and inv = 1 / g_k.  A masked (converged) system or a zero
+// direction gets g_k = 1, alpha'_k = alpha = 0, inv = 0.
+__global__ void gcr_scalars_tri_kernel(const double2* qq, const double2* qr, const int* mask, int nrhs, int k,
+                                       double2* tri, int ld, double2* alpha, double2* inv) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const double q = qq[r].x;
+  const bool on = (mask == nullptr || mask[r] != 0) && q > 0.0 && q < 1e300;
+  const double g = on ? sqrt(q) : 1.0;
+  tri[(int64_t)(kTriG + k) * ld + r] = make_double2(g, 0.0);
+  tri[(int64_t)(kTriA + k) * ld + r] = on ? make_double2(qr[r].x / g, qr[r].y / g) : make_double2(0.0, 0.0);
+  alpha[r] = on ? make_double2(qr[r].x / q, qr[r].y / q) : make_double2(0.0, 0.0);
+  inv[r] = make_double2(on ? 1.0 / g : 0.0, 0.0);
+}
+void launch_gcr_scalars_tri(const double2* qq, const double2* qr, const int* mask, int nrhs, int k, double2* tri,
+                            int ld, double2* alpha, double2* inv, hipStream_t st) {
+  gcr_scalars_tri_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(qq, qr, mask, nrhs, k, tri, ld, alpha, inv);
+}
+
+// r -= alpha q, q *= inv, and partial sums of |r|^2
+template <typename T>
+__global__ void __launch_bounds__(256) gcr_update_r_kernel(T* __restrict__ r, T* __restrict__ q,
+                                                           const double2* __restrict__ alpha,
+                                                           const double2* __restrict__ inv, int64_t n,
+                                                           double2* __restrict__ part, int nblk) {
+  __shared__ double red[4];
+  const int rr = blockIdx.y;
+  const int64_t off = (int64_t)rr * n;
+  const double2 al = alpha[rr];
+  const double iv = inv[rr].x;
+  double s = 0.0;
+  for (int64_t e = off + (int64_t)blockIdx.x * 256 + threadIdx.x; e < off + n; e += (int64_t)nblk * 256) {
+    const double2 qv = to_d2(q[e]);
+    double2 rv = to_d2(r[e]);
+    cfma(rv, make_double2(-al.x, -al.y), qv);
+    const T rt = from_d2<T>(rv);
+    r[e] = rt;
+    q[e] = from_d2<T>(make_double2(qv.x * iv, qv.y * iv));
+    const double2 rs = to_d2(rt);
+    s += rs.x * rs.x + rs.y * rs.y;
+  }
+  s = wsum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(int64_t)rr * nblk + blockIdx.x] = make_double2(red[0] + red[1] + red[2] + red[3], 0.0);
+}
+template <typename T>
+void launch_gcr_update_r(T* r, T* q, const double2* alpha, const double2* inv, int64_t n, int nrhs, double2* part,
+                         double2* res, int ldr, hipStream_t st) {
+  const int nblk = reduce_blocks(n);
+  gcr_update_r_kernel<T><<<dim3(nblk, nrhs), 256, 0, st>>>(r, q, alpha, inv, n, part, nblk);
+  finalize_kernel<<<nrhs, 64, 0, st>>>(part, nblk, 1, nrhs, res, ldr);
+}
+template void launch_gcr_update_r<float2>(float2*, float2*, const double2*, const double2*, int64_t, int, double2*,
+                                          double2*, int, hipStream_t);
+template void launch_gcr_update_r<double2>(double2*, double2*, const double2*, const double2*, int64_t, int,
+                                           double2*, double2*, int, hipStream_t);
+
+// Coefficients of the deferred solution update x += sum_k gamma_k z_k: the
+// raw directions satisfy z_k = g_k zt_k + sum_{i<k} beta(i, k) zt_i with
+// A zt_k the normalised q_k, so gamma solves the upper-triangular system
+// U gamma = alpha' (U(i, k) = beta(i, k), U(k, k) = g_k) by back substitution.
+__global__ void gcr_backsub_kernel(double2* tri, int nk, int nrhs, int ld) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double2 gm[kMaxNK];
+  for (int i = nk - 1; i >= 0; --i) {
+    double2 v = tri[(int64_t)(kTriA + i) * ld + r];
+    for (int k = i + 1; k < nk; ++k) {   // v -= beta(i, k) gamma_k
+      const double2 b = tri[(int64_t)(i * kMaxNK + k) * ld + r];
+      v.x -= b.x * gm[k].x - b.y * gm[k].y;
+      v.y -= b.x * gm[k].y + b.y * gm[k].x;
+    }
+    const double g = tri[(int64_t)(kTriG + i) * ld + r].x;
+    gm[i] = make_double2(v.x / g, v.y / g);
+    tri[(int64_t)(kTriC + i) * ld + r] = gm[i];
+  }
+}
+void launch_gcr_backsub(double2* tri, int nk, int nrhs, int ld, hipStream_t st) {
+  if (nk <= 0) return;
+  gcr_backsub_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(tri, nk, nrhs, ld);
+}
+
 // Convergence on the device: mask[r] stays 1 while |r|^2 > tol^2 |r0|^2
 // (and both are finite); init sets mask from |r0|^2 > 0.
 __global__ void conv_kernel(int* mask, const double2* rn2, const double2* r0sq, double tol2, int nrhs, int init) {

@@ -9,10 +9,12 @@
 //   [site][m-tile (16 rows)][k-chunk (32)][re/im][lane 0..63][8 x 16-bit]
 // lane l holds row 16 mt + (l % 16), k = 32 kc + 8 (l / 16) + t, t = 0..7, so
 // every fragment is one contiguous 1 KiB load of a wavefront.  The B operand
-// (the site's 16 right-hand-side columns, converted to 16 bits with
-// round-to-nearest-even) is staged once per workgroup in LDS as [rhs][k]
-// planes, read with the same k mapping.  FP16 links carry a power-of-two scale
+// (the site's right-hand-side columns, converted to 16 bits with
+// round-to-nearest-even) is staged in LDS as [rhs][k] planes, read with the
+// same k mapping.  FP16 links carry a power-of-two scale
 // (2^-round(log2 max|L|)) undone on the FP32 result.
+#include <stdexcept>
+
 #include "kernels.hpp"
 
 namespace mg {
@@ -96,90 +98,121 @@ void launch_absmax(const double2* v, int64_t n, unsigned long long* out, hipStre
   absmax_kernel<<<480, 256, 0, st>>>(v, n, out);
 }
 
-constexpr int kMfmaWaves = 8;
+// One workgroup per (coarse site, group of 16 RT right-hand sides), one
+// wavefront per m-tile (n <= 256: at most 16 wavefronts).  The B operand is
+// staged through LDS in passes of kMfmaCK k-chunks, so the RT rhs tiles share
+// every A fragment a wavefront streams from HBM: the links, which dominate the
+// traffic, are read once per 16 RT right-hand sides.
+constexpr int kMfmaCK = 4;
+constexpr int kMfmaMaxWaves = 16;
 
-template <int FMT>
-__global__ void __launch_bounds__(64 * kMfmaWaves) coarse_mfma_kernel(const CoarseMfmaArgs a) {
-  extern __shared__ uint16_t bsm[];              // [2 planes][16 rhs][KP]
+template <int FMT, int RT>
+__global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const CoarseMfmaArgs a) {
+  constexpr int NR = 16 * RT;          // right-hand sides per workgroup
+  constexpr int KCH = kMfmaCK * 32;    // k per staging pass
+  constexpr int KPC = KCH + 8;         // padded LDS row: staggers banks between rhs rows
+  extern __shared__ uint16_t bsm[];    // [2 planes][NR][KPC]
+  __shared__ int64_t nbs[9];
+  uint16_t* Bre = bsm;
+  uint16_t* Bim = bsm + NR * KPC;
   const int n = a.n;
   const int K = 9 * n;
   const int kc_n = (K + 31) / 32;
-  const int KP = kc_n * 32 + 8;                  // padded row: staggers LDS banks between rhs rows
-  uint16_t* Bre = bsm;
-  uint16_t* Bim = bsm + 16 * KP;
-  const int64_t site = blockIdx.x;
-  const int r0 = blockIdx.y * 16;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  int c[4];
-  site_coords(site, a.g, c);
-  int64_t nb[9];
-  nb[0] = site;
-#pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-    nb[1 + 2 * mu] = site_shift(c, mu, 1, a.g);
-    nb[2 + 2 * mu] = site_shift(c, mu, -1, a.g);
-  }
-  // stage B: column j = rhs r0 + j, row k = d n + col; each thread converts two
-  // consecutive k (same direction, n is even) per step: one 16-byte load, two
-  // 4-byte LDS stores; the direction / column walk is incremental
-  const int KC = kc_n * 32;
-  constexpr int NT = 64 * kMfmaWaves;
-  for (int j = 0; j < 16; ++j) {
-    const bool live = r0 + j < a.nrhs;
-    const float2* xj = a.in + (int64_t)(live ? r0 + j : 0) * a.in_stride;
-    int k = 2 * tid;
-    int d = k / n, col = k - (k / n) * n;
-    for (; k < KC; k += 2 * NT) {
-      uint32_t pre = 0, pim = 0;
-      if (live && k < K) {
-        const float4 v = *reinterpret_cast<const float4*>(xj + nb[d] * n + col);
-        pre = (uint32_t)to16<FMT>(v.x) | ((uint32_t)to16<FMT>(v.z) << 16);
-        pim = (uint32_t)to16<FMT>(v.y) | ((uint32_t)to16<FMT>(v.w) << 16);
-      }
-      *reinterpret_cast<uint32_t*>(Bre + j * KP + k) = pre;
-      *reinterpret_cast<uint32_t*>(Bim + j * KP + k) = pim;
-      col += 2 * NT;
-      while (col >= n) { col -= n; ++d; }
-    }
-  }
-  __syncthreads();
   const int mt_n = n / 16;
-  const uint4* L = reinterpret_cast<const uint4*>(a.links) + site * (int64_t)mt_n * kc_n * 2 * 64;
-  const int j = lane & 15, g = lane >> 4;
-  for (int mt = wave; mt < mt_n; mt += kMfmaWaves) {
-    f32x4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
-    const uint4* Lm = L + (int64_t)mt * kc_n * 2 * 64;
-#pragma unroll 4
-    for (int kc = 0; kc < kc_n; ++kc) {
-      const uint4 are = Lm[(kc * 2 + 0) * 64 + lane];
-      const uint4 aim = Lm[(kc * 2 + 1) * 64 + lane];
-      const int kb = kc * 32 + 8 * g;
-      const uint4 bre = *reinterpret_cast<const uint4*>(Bre + j * KP + kb);
-      const uint4 bim = *reinterpret_cast<const uint4*>(Bim + j * KP + kb);
-      const uint4 bimn = make_uint4(bim.x ^ 0x80008000u, bim.y ^ 0x80008000u, bim.z ^ 0x80008000u,
-                                    bim.w ^ 0x80008000u);
-      yr = mfma16<FMT>(are, bre, yr);
-      yr = mfma16<FMT>(aim, bimn, yr);
-      yi = mfma16<FMT>(are, bim, yi);
-      yi = mfma16<FMT>(aim, bre, yi);
-    }
-    // D fragment: column j (rhs), rows 4 g + t
-    if (r0 + j < a.nrhs) {
-      float2* o = a.out + (int64_t)(r0 + j) * a.out_stride + site * n + mt * 16 + 4 * g;
+  const int64_t site = blockIdx.x;
+  const int r0 = blockIdx.y * NR;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nthreads = blockDim.x;
+  const int mt = wave;
+  if (tid < 9) {
+    int c[4];
+    site_coords(site, a.g, c);
+    nbs[tid] = tid == 0 ? site : site_shift(c, (tid - 1) >> 1, (tid & 1) ? 1 : -1, a.g);
+  }
+  f32x4 yr[RT], yi[RT];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) o[t] = make_float2(yr[t] * a.inv_scale, yi[t] * a.inv_scale);
+  for (int rt = 0; rt < RT; ++rt) {
+    yr[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    yi[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  const uint4* Lm = reinterpret_cast<const uint4*>(a.links) +
+                    (site * mt_n + mt) * (int64_t)kc_n * 2 * 64;
+  const int j = lane & 15, g = lane >> 4;
+  for (int kc0 = 0; kc0 < kc_n; kc0 += kMfmaCK) {
+    __syncthreads();   // neighbour table ready / previous pass consumed
+    // stage k in [32 kc0, 32 kc0 + KCH): element pairs (k, k + 1) lie in one
+    // direction (n is even); a wavefront covers one rhs row of the pass
+    for (int e = tid; e < NR * (KCH / 2); e += nthreads) {
+      const int jj = e / (KCH / 2);
+      const int kl = 2 * (e - jj * (KCH / 2));
+      const int k = kc0 * 32 + kl;
+      uint32_t pre = 0, pim = 0;
+      if (r0 + jj < a.nrhs && k < K) {
+        const int d = k / n, col = k - d * n;
+        const float2* src = a.in + (int64_t)(r0 + jj) * a.in_stride + nbs[d] * n + col;
+        const float2 v0 = src[0], v1 = src[1];
+        pre = (uint32_t)to16<FMT>(v0.x) | ((uint32_t)to16<FMT>(v1.x) << 16);
+        pim = (uint32_t)to16<FMT>(v0.y) | ((uint32_t)to16<FMT>(v1.y) << 16);
+      }
+      *reinterpret_cast<uint32_t*>(Bre + jj * KPC + kl) = pre;
+      *reinterpret_cast<uint32_t*>(Bim + jj * KPC + kl) = pim;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kcl = 0; kcl < kMfmaCK; ++kcl) {
+      const int kc = kc0 + kcl;
+      if (kc < kc_n) {
+        const uint4 are = Lm[(kc * 2 + 0) * 64 + lane];
+        const uint4 aim = Lm[(kc * 2 + 1) * 64 + lane];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const int off = (rt * 16 + j) * KPC + kcl * 32 + 8 * g;
+          const uint4 bre = *reinterpret_cast<const uint4*>(Bre + off);
+          const uint4 bim = *reinterpret_cast<const uint4*>(Bim + off);
+          const uint4 bimn = make_uint4(bim.x ^ 0x80008000u, bim.y ^ 0x80008000u, bim.z ^ 0x80008000u,
+                                        bim.w ^ 0x80008000u);
+          yr[rt] = mfma16<FMT>(are, bre, yr[rt]);
+          yr[rt] = mfma16<FMT>(aim, bimn, yr[rt]);
+          yi[rt] = mfma16<FMT>(are, bim, yi[rt]);
+          yi[rt] = mfma16<FMT>(aim, bre, yi[rt]);
+        }
+      }
+    }
+  }
+  // D fragment: column j (rhs), rows 4 g + t of m-tile mt
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int r = r0 + rt * 16 + j;
+    if (r < a.nrhs) {
+      float2* o = a.out + (int64_t)r * a.out_stride + site * n + mt * 16 + 4 * g;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) o[t] = make_float2(yr[rt][t] * a.inv_scale, yi[rt][t] * a.inv_scale);
     }
   }
 }
 
+template <int FMT, int RT>
+static void coarse_mfma_launch(const CoarseMfmaArgs& a, hipStream_t st) {
+  const int mt_n = a.n / 16;
+  const size_t lds = (size_t)2 * 16 * RT * (kMfmaCK * 32 + 8) * sizeof(uint16_t);
+  dim3 grid((unsigned)a.g.V, (unsigned)((a.nrhs + 16 * RT - 1) / (16 * RT)));
+  coarse_mfma_kernel<FMT, RT><<<grid, 64 * mt_n, lds, st>>>(a);
+}
+
 void launch_coarse_mfma(const CoarseMfmaArgs& a, int fmt, hipStream_t st) {
   if (a.nrhs <= 0) return;
-  const int kc_n = (9 * a.n + 31) / 32;
-  const int KP = kc_n * 32 + 8;
-  const size_t lds = (size_t)2 * 16 * KP * sizeof(uint16_t);
-  dim3 grid((unsigned)a.g.V, (unsigned)((a.nrhs + 15) / 16));
-  if (fmt == 0) coarse_mfma_kernel<0><<<grid, 64 * kMfmaWaves, lds, st>>>(a);
-  else coarse_mfma_kernel<1><<<grid, 64 * kMfmaWaves, lds, st>>>(a);
+  if (a.n % 16 || a.n < 16 || a.n > 16 * kMfmaMaxWaves)
+    throw std::runtime_error("coarse_mfma: n must be a multiple of 16 in 16..256");
+  const int rt = a.nrhs <= 16 ? 1 : (a.nrhs <= 32 ? 2 : 4);
+  if (fmt == 0) {
+    if (rt == 1) coarse_mfma_launch<0, 1>(a, st);
+    else if (rt == 2) coarse_mfma_launch<0, 2>(a, st);
+    else coarse_mfma_launch<0, 4>(a, st);
+  } else {
+    if (rt == 1) coarse_mfma_launch<1, 1>(a, st);
+    else if (rt == 2) coarse_mfma_launch<1, 2>(a, st);
+    else coarse_mfma_launch<1, 4>(a, st);
+  }
 }
 
 int64_t swizzled_link_elems(int64_t nsite, int n) {

@@ -148,6 +148,41 @@ struct LinCombArgs {
   int64_t n, stride;
   int nrhs;
 };
+// CA-GCR smoother Gram data: u[0..s-1] = A p_0..A p_{s-1}, u[s] = t
+template <typename T>
+struct GramArgs {
+  const T* u[kMaxS + 1];
+  int s;
+  int64_t n, stride;
+  int nrhs;
+};
+// <x_i, y> for i < nv
+template <typename T>
+struct MultiDotArgs {
+  const T* x[kMaxNK];
+  const T* y;
+  int nv;
+  int64_t n, stride;
+  int nrhs;
+};
+// q <- q - sum_i beta_i x_i, then |q|^2 and <q, r>
+template <typename T>
+struct ProjArgs {
+  T* q;
+  const T* x[kMaxNK];
+  const double2* beta[kMaxNK];   // per-rhs device coefficients
+  const T* r;
+  int nv;
+  int64_t n, stride;
+  int nrhs;
+};
+// Deferred-update GCR scalars of one level, per system (ld = max systems):
+// beta(i, k) at [i * kMaxNK + k], g_k at [kTriG + k], alpha'_k at [kTriA + k],
+// gamma_k at [kTriC + k]
+constexpr int kTriG = kMaxNK * kMaxNK;
+constexpr int kTriA = kTriG + kMaxNK;
+constexpr int kTriC = kTriA + kMaxNK;
+constexpr int kTriSlots = kTriC + kMaxNK;
 int reduce_blocks(int64_t n);
 template <typename T>
 void launch_pairdot(const PairDotArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st);
@@ -169,6 +204,18 @@ void launch_gcr_update(T* x, T* r, T* q, T* z, const double2* alpha, const doubl
                        double2* part, double2* res, int ldr, hipStream_t st);
 void launch_cg_update(double2* x, double2* r, const double2* p, const double2* ap, const double2* alpha, int64_t n,
                       int nrhs, double2* part, double2* res, int ldr, hipStream_t st);
+template <typename T>
+void launch_gram(const GramArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st);
+template <typename T>
+void launch_multidot(const MultiDotArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st);
+template <typename T>
+void launch_project_dots(const ProjArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st);
+void launch_gcr_scalars_tri(const double2* qq, const double2* qr, const int* mask, int nrhs, int k, double2* tri,
+                            int ld, double2* alpha, double2* inv, hipStream_t st);
+template <typename T>
+void launch_gcr_update_r(T* r, T* q, const double2* alpha, const double2* inv, int64_t n, int nrhs, double2* part,
+                         double2* res, int ldr, hipStream_t st);
+void launch_gcr_backsub(double2* tri, int nk, int nrhs, int ld, hipStream_t st);
 void launch_conv(int* mask, const double2* rn2, const double2* r0sq, double tol2, int nrhs, int init,
                  hipStream_t st);
 

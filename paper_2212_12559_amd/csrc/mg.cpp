@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 namespace mg {
 
@@ -116,6 +117,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   auto S = [&](size_t n) { return scr.take(n); };
   void* part = S((size_t)kMaxPairs * ms * 480 * 16);
   void* scal = S((size_t)4 * kMaxSlots * ms * 16);
+  void* tri = S((size_t)4 * kTriSlots * ms * 16);
   void* m64 = S((size_t)ms * 8);
   void* m32 = S((size_t)ms * 4);
   void* mask = S((size_t)4 * ms * 4);
@@ -197,6 +199,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     c->max_sys = ms;
     c->part = (double2*)part;
     c->scal = (double2*)scal;
+    c->tri = (double2*)tri;
     c->mass64 = (double*)m64;
     c->mass32 = (float*)m32;
     c->mask = (int*)mask;
@@ -418,12 +421,24 @@ void Ctx::smoother(int lvl, const Vec& e, const Vec& t, int nsys) {
     const Vec& src = j == 0 ? t : B.sm[j - 1];
     apply_level(lvl, B.sm[j], src, nsys);
   }
-  std::vector<std::pair<const void*, const void*>> pairs;
-  for (int i = 0; i < s; ++i)
-    for (int j = i; j < s; ++j) pairs.push_back({B.sm[i].p, B.sm[j].p});
-  for (int i = 0; i < s; ++i) pairs.push_back({B.sm[i].p, t.p});
+  // Gram data <A p_i, A p_j> (i <= j) and <A p_i, t> in one pass over the basis
   double2* gram = slot(lvl, 0);
-  dots(prec, t.n, nsys, pairs, gram);
+  auto fill = [&](auto& a) {
+    using TP = decltype(a.u[0]);
+    for (int j = 0; j < s; ++j) a.u[j] = (TP)B.sm[j].p;
+    a.u[s] = (TP)t.p;
+    a.s = s; a.n = t.n; a.stride = t.n; a.nrhs = nsys;
+  };
+  if (prec == P64) {
+    GramArgs<double2> a{};
+    fill(a);
+    launch_gram(a, part, gram, max_sys, st);
+  } else {
+    GramArgs<float2> a{};
+    fill(a);
+    launch_gram(a, part, gram, max_sys, st);
+  }
+  check_launch();
   double2* a = slot(lvl, kSlotCoef);
   launch_cagcr_solve(gram, s, nsys, max_sys, lmask(lvl), a, st);
   check_launch();
@@ -543,6 +558,15 @@ bool Ctx::any_active(int lvl, int nsys) {
 // Convergence is tracked on the device (a converged system's updates become
 // no-ops); the host reads the flags after every iteration, or every fourth
 // on the coarsest level, whose iterations are short.
+//
+// The iterates are those of the flexible GCR with an orthonormal q basis, but
+// the directions z_k are never orthogonalised: each step stores the
+// projection coefficients beta(i, k) = <q_i, A z_k>, the norm g_k and
+// alpha'_k = <q_k, r>, and the solution x = sum_k gamma_k z_k is formed once
+// at the end of a cycle from the triangular system they define.  Per step the
+// vector passes are: q_k = A z_k; the k coefficients (one pass reading q_k
+// once); the projection of q_k fused with |q_k|^2 and <q_k, r>; the update
+// of r and the normalisation of q_k.
 void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   LevelBufs& B = L[lvl];
   const bool coarsest = lvl == nlev - 1;
@@ -552,7 +576,6 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   const int every = coarsest ? 4 : 1;
   const int prec = B.prec;
   const int64_t n = B.n;
-  zero(B.x, nsys);
   copy(B.r, B.b, nsys);
   double2* r0 = slot(lvl, kSlotR0);
   dots(prec, n, nsys, {{B.b.p, B.b.p}}, r0);
@@ -564,18 +587,67 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
       apply_level(lvl, B.r, B.x, nsys);
       lincomb(prec, n, nsys, B.r.p, {{B.b.p, nullptr}, {B.r.p, nullptr}}, {0, 1}, {});
     }
+    int nk = 0;
     for (int k = 0; k < maxit; ++k) {
       stats.level[lvl - 1] += 1;
       if (coarsest) copy(B.z[k], B.r, nsys);
       else kcycle(lvl, B.r, B.z[k], nsys, stats);
-      gcr_step(lvl, B, B.x, k, nsys);
+      gcr_direction(lvl, B, k, nsys);
+      nk = k + 1;
       launch_conv(lmask(lvl), slot(lvl, kSlotRN), r0, tol * tol, nsys, 0, st);
       check_launch();
       if ((k + 1) % every == 0 || k + 1 == maxit) {
         if (!any_active(lvl, nsys)) { live = false; break; }
       }
     }
+    gcr_flush(lvl, B, nk, nsys, cyc > 0);
   }
+}
+
+// Direction k of the deferred-update GCR (z_k already holds K(r)).
+void Ctx::gcr_direction(int lvl, LevelBufs& B, int k, int nsys) {
+  const int prec = B.prec;
+  const int64_t n = B.n;
+  double2* T = tslot(lvl, 0);
+  apply_level(lvl, B.q[k], B.z[k], nsys);
+  auto run = [&](auto* tag) {
+    using TP = std::remove_pointer_t<decltype(tag)>;
+    if (k > 0) {
+      MultiDotArgs<TP> md{};
+      for (int i = 0; i < k; ++i) md.x[i] = (const TP*)B.q[i].p;
+      md.y = (const TP*)B.q[k].p;
+      md.nv = k; md.n = n; md.stride = n; md.nrhs = nsys;
+      launch_multidot(md, part, T + (int64_t)k * max_sys, kMaxNK * max_sys, st);   // beta(i, k)
+    }
+    ProjArgs<TP> pa{};
+    pa.q = (TP*)B.q[k].p;
+    for (int i = 0; i < k; ++i) {
+      pa.x[i] = (const TP*)B.q[i].p;
+      pa.beta[i] = T + (int64_t)(i * kMaxNK + k) * max_sys;
+    }
+    pa.r = (const TP*)B.r.p;
+    pa.nv = k; pa.n = n; pa.stride = n; pa.nrhs = nsys;
+    launch_project_dots(pa, part, slot(lvl, kSlotQQ), max_sys, st);
+    launch_gcr_scalars_tri(slot(lvl, kSlotQQ), slot(lvl, kSlotQQ + 1), lmask(lvl), nsys, k, T, max_sys,
+                           slot(lvl, kSlotQQ + 2), slot(lvl, kSlotQQ + 4), st);
+    launch_gcr_update_r<TP>((TP*)B.r.p, (TP*)B.q[k].p, slot(lvl, kSlotQQ + 2), slot(lvl, kSlotQQ + 4), n, nsys,
+                            part, slot(lvl, kSlotRN), max_sys, st);
+  };
+  if (prec == P64) run((double2*)nullptr);
+  else run((float2*)nullptr);
+  check_launch();
+}
+
+// x (+)= sum_{k < nk} gamma_k z_k with U gamma = alpha' (back substitution)
+void Ctx::gcr_flush(int lvl, LevelBufs& B, int nk, int nsys, bool accumulate) {
+  if (nk <= 0) return;
+  double2* T = tslot(lvl, 0);
+  launch_gcr_backsub(T, nk, nsys, max_sys, st);
+  check_launch();
+  std::vector<std::pair<const void*, const double2*>> terms;
+  if (accumulate) terms.push_back({B.x.p, nullptr});
+  for (int k = 0; k < nk; ++k) terms.push_back({B.z[k].p, T + (int64_t)(kTriC + k) * max_sys});
+  lincomb(B.prec, B.n, nsys, B.x.p, terms, {}, {});
 }
 
 // ======================================================================== KD

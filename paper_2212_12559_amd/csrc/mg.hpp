@@ -81,6 +81,7 @@ struct Ctx {
   Vec x0s, r0s, e0s;        // level-0 K-cycle in fine precision (x0s unused)
   double2* part = nullptr;  // reduction partials
   double2* scal = nullptr;  // scalar slots [level][kMaxSlots][max_sys]
+  double2* tri = nullptr;   // deferred-update GCR scalars [level][kTriSlots][max_sys]
   double* mass64 = nullptr; // per-system masses (device)
   float* mass32 = nullptr;
   int* mask = nullptr;      // per-system active flag (device)
@@ -109,6 +110,7 @@ struct Ctx {
 
   // ---- BLAS helpers
   double2* slot(int lvl, int s) { return scal + ((int64_t)lvl * kMaxSlots + s) * max_sys; }
+  double2* tslot(int lvl, int s) { return tri + ((int64_t)lvl * kTriSlots + s) * max_sys; }
   int* lmask(int lvl) { return mask + (int64_t)lvl * max_sys; }
   void dots(int prec, int64_t n, int nsys, const std::vector<std::pair<const void*, const void*>>& pairs,
             double2* res);
@@ -124,6 +126,8 @@ struct Ctx {
   void kcycle(int lvl, const Vec& r, const Vec& e, int nsys, SolveStats& stats);
   void level_solve(int lvl, int nsys, SolveStats& stats);   // L[lvl].b -> L[lvl].x
   void gcr_step(int lvl, LevelBufs& B, const Vec& X, int k, int nsys);
+  void gcr_direction(int lvl, LevelBufs& B, int k, int nsys);
+  void gcr_flush(int lvl, LevelBufs& B, int nk, int nsys, bool accumulate);
   void project(int prec, int64_t n, int nsys, LevelBufs& B, int k, const double2* beta);
   std::vector<double> read_norms(const double2* dev, int nsys);
   bool any_active(int lvl, int nsys);

@@ -21,6 +21,10 @@ CONFIGS = {
     # ragged: V = 2304 (9 blocks of 256), odd coarse extent 3, extents 1
     "ragged": dict(dims=(8, 4, 6, 12), c1=C1H, c3=C3H, kd_naik=0, blocks=[(4, 4, 6, 4), (2, 1, 1, 3)],
                    nvec=(10, 12), mass0=0.07, eps=0.5, seed=424242),
+    # widest 16-bit coarse stencil: Nvec 128 (n = 256, sixteen MFMA row tiles),
+    # coarse lattice 2x1x1x1
+    "wide": dict(dims=(8, 4, 4, 4), c1=C1H, c3=C3H, kd_naik=1, blocks=[(4, 4, 4, 4)], nvec=(128,), mass0=0.05,
+                 eps=0.5, seed=515151),
     # the 16^4 HISQ-style hierarchy shape: KD, 4^4 / Nvec 64, 2^4 / Nvec 96
     "c1": dict(dims=(16, 16, 16, 16), c1=C1H, c3=C3H, kd_naik=1, blocks=[(4, 4, 4, 4), (2, 2, 2, 2)],
                nvec=(64, 96), mass0=0.01, eps=0.5, seed=latgen.SEEDS["c1_16x4_hisq"]),

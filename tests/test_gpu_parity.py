@@ -228,7 +228,7 @@ def test_galerkin_links_match_oracle(case):
 _cases16 = {}
 
 
-@pytest.mark.parametrize("name", ["c0", "cubic"])
+@pytest.mark.parametrize("name", ["c0", "cubic", "wide"])
 @pytest.mark.parametrize("fmt", ["bf16", "fp16"])
 def test_coarse_mfma_16bit(torch, mg, name, fmt):
     """Coarse stencil with 16-bit links on the matrix cores, against the oracle
@@ -251,7 +251,7 @@ def test_coarse_mfma_16bit(torch, mg, name, fmt):
         nvs = random_null_vectors(cfg, rng)
         dev = "cuda:0"
         cp = mg.MG_CBF16 if fmt == "bf16" else mg.MG_CF16
-        p = gpu_params(mg, cfg, max_nrhs=17, fine_prec=mg.MG_C64, coarse_prec=cp)
+        p = gpu_params(mg, cfg, max_nrhs=70, fine_prec=mg.MG_C64, coarse_prec=cp)
         ctx = mg.setup(p, torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev) if cfg["c3"] else None,
                        [torch.from_numpy(v).to(dev) for v in nvs])
         H = oracle_hierarchy(cfg, W, N, cfg["mass0"], nvs)
@@ -271,7 +271,8 @@ def test_coarse_mfma_16bit(torch, mg, name, fmt):
         k2 = 2 * 9 * n
         g = k2 * u / (1 - k2 * u)
         cd = H.cdims[lvl - 2]
-        for nrhs in (1, 5, 17):
+        # 1, 2 and 4 rhs tiles per workgroup, ragged, and two workgroups along rhs
+        for nrhs in (1, 5, 17, 37, 70):
             x = latgen.complex_normal(rng, (nrhs,) + H.fine_shape(lvl)).astype(np.complex64)
             log(f"[mfma] {name} {fmt} level {lvl} nrhs {nrhs}")
             y = ctx.apply_coarse(lvl, torch.from_numpy(x).to("cuda:0")).cpu().numpy().astype(np.complex128)
