@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const C
   const int K = 9 * n;
   const int kc_n = (K + 31) / 32;
   const int mt_n = n / 16;
-  const int64_t site = blockIdx.x;
+  const int64_t site = xcd_block(blockIdx.x, gridDim.x);
   const int r0 = blockIdx.y * NR;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nthreads = blockDim.x;

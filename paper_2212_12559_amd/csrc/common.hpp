@@ -71,6 +71,16 @@ __host__ __device__ __forceinline__ int site_parity(const int c[4]) { return (c[
 
 // Kahler-Dirac hypercubes: origin at even coordinates, local index
 // s = sum_mu (x_mu mod 2) 2^mu, 48 x 48 block row 3 s + colour.
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Renumbering block b of nb so that XCD x runs one contiguous range of
+// blocks keeps lattice neighbours, which share input data, in one L2 (blocks
+// past the last multiple of 8 keep their number; the map is a bijection).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t per = nb >> 3;
+  if (b >= per * 8) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
 __host__ __device__ __forceinline__ int64_t hc_site(int64_t hc, int sl, const Geom& g) {
   const int h0 = g.L[0] / 2, h1 = g.L[1] / 2, h2 = g.L[2] / 2;
   int c[4];

@@ -17,7 +17,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(const DslashArgs<R> a) {
   using T = cplx<R>;
   const int64_t V = a.g.V;
   const int64_t nout = CB ? V / 2 : V;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (tid >= nout) return;
   const int r0 = blockIdx.y * NR;
   const int nr = (a.nrhs - r0) < NR ? (a.nrhs - r0) : NR;

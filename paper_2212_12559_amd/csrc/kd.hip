@@ -166,6 +166,65 @@ __global__ void __launch_bounds__(256) kd_apply_kernel(const KdArgs<R> a) {
   }
 }
 
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+// (B + m)^{-1} on 16 right-hand sides per wavefront on the FP32 matrix cores:
+// per hypercube Y[48 x 16] = K[48 x 48] X[48 x 16] as four real products per
+// 16x16x4 step (Re Y = Re K Re X - Im K Im X, Im Y = Re K Im X + Im K Re X).
+// A fragments come straight from the column-major inverse (lane l: row
+// 16 mt + l % 16, column 4 ks + l / 16); B fragments are the inputs of rhs
+// l % 16 at row 4 ks + l / 16; lane l ends with rows 16 mt + 4 (l / 16) + t of
+// rhs l % 16.
+__global__ void __launch_bounds__(256) kd_apply_mfma_kernel(const KdArgs<float> a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t hc = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  const int64_t nhc = a.g.V / 16;
+  if (hc >= nhc) return;
+  const int r0 = blockIdx.y * 16;
+  const int rl = lane & 15, kq = lane >> 4;
+  const int r = r0 + rl;
+  const bool live = r < a.nrhs;
+  const int slot = a.rhs_per_slot > 0 ? r0 / a.rhs_per_slot : 0;
+  const float2* K = a.kinv + (int64_t)slot * a.slot_stride + hc * 2304;
+  const float2* xin = a.in + (int64_t)(live ? r : 0) * a.in_stride;
+  float bre[12], bim[12];
+#pragma unroll
+  for (int ks = 0; ks < 12; ++ks) {
+    const int j = 4 * ks + kq;
+    const int sl = j / 3, col = j - 3 * (j / 3);
+    float2 v = make_float2(0.f, 0.f);
+    if (live) {
+      v = xin[hc_site(hc, sl, a.g) * 3 + col];
+      if (a.eps_in && (__popc(sl) & 1)) { v.x = -v.x; v.y = -v.y; }
+    }
+    bre[ks] = v.x;
+    bim[ks] = v.y;
+  }
+  float2* yout = a.out + (int64_t)(live ? r : 0) * a.out_stride;
+#pragma unroll
+  for (int mt = 0; mt < 3; ++mt) {
+    f32x4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 12; ++ks) {
+      const float2 k = K[(4 * ks + kq) * 48 + 16 * mt + rl];
+      yr = __builtin_amdgcn_mfma_f32_16x16x4f32(k.x, bre[ks], yr, 0, 0, 0);
+      yr = __builtin_amdgcn_mfma_f32_16x16x4f32(-k.y, bim[ks], yr, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_16x16x4f32(k.x, bim[ks], yi, 0, 0, 0);
+      yi = __builtin_amdgcn_mfma_f32_16x16x4f32(k.y, bre[ks], yi, 0, 0, 0);
+    }
+    if (live) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = 16 * mt + 4 * kq + t;
+        const int sl = i / 3, col = i - 3 * (i / 3);
+        float2 v = make_float2(yr[t], yi[t]);
+        if (a.eps_out && (__popc(sl) & 1)) { v.x = -v.x; v.y = -v.y; }
+        yout[hc_site(hc, sl, a.g) * 3 + col] = v;
+      }
+    }
+  }
+}
+
 template <typename R>
 void launch_kd_apply(const KdArgs<R>& a, hipStream_t st) {
   if (a.nrhs <= 0) return;
@@ -176,7 +235,8 @@ void launch_kd_apply(const KdArgs<R>& a, hipStream_t st) {
   const bool tile4 = a.nrhs >= 4 && (a.rhs_per_slot <= 0 || a.rhs_per_slot % 4 == 0);
   if (tile16) {
     dim3 grid(gx, (unsigned)((a.nrhs + 15) / 16));
-    kd_apply_kernel<R, 16><<<grid, 256, 0, st>>>(a);
+    if constexpr (sizeof(R) == 4) kd_apply_mfma_kernel<<<grid, 256, 0, st>>>(a);
+    else kd_apply_kernel<R, 16><<<grid, 256, 0, st>>>(a);
   } else if (tile8) {
     dim3 grid(gx, (unsigned)((a.nrhs + 7) / 8));
     kd_apply_kernel<R, 8><<<grid, 256, 0, st>>>(a);

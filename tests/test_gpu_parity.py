@@ -35,7 +35,7 @@ def mg(torch):
 class Case:
     """One configuration with random (full-rank) imported null vectors."""
 
-    def __init__(self, name, torch, mg, max_nrhs=9):
+    def __init__(self, name, torch, mg, max_nrhs=21):
         log(f"[setup] config {name}")
         self.name = name
         self.cfg = cfg = CONFIGS[name]
@@ -126,12 +126,13 @@ def test_kd_parity(case, prec):
     tol = TOL64 if prec == "c128" else TOL32
     cfg = case.cfg
     m = cfg["mass0"]
-    x = latgen.fine_vectors(cfg["dims"], 9, case.rng)
+    # 21 rhs: one full 16-rhs tile (the FP32 matrix-core path) and a ragged one
+    x = latgen.fine_vectors(cfg["dims"], 21, case.rng)
     log(f"[kd] {case.name} {prec}")
     yk = case.back(case.ctx.apply_dslash(2, m, case.to_gpu(x, dt)))
     ya = case.back(case.ctx.apply_dslash(1, m, case.to_gpu(x, dt)))
     c3kd = cfg["c3"] if cfg["kd_naik"] else 0.0
-    for r in range(9):
+    for r in range(21):
         assert rel_err(yk[r], ops.kd_apply(case.H.Kinv, x[r])) < tol
         want = ops.kd_operator(x[r], case.W, case.N, case.H.Kinv, m, cfg["c1"], c3kd)
         assert rel_err(ya[r], want) < tol

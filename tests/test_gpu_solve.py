@@ -122,6 +122,25 @@ def test_multi_mass_batch(torch, mg, cubic):
             assert true_rel(cfg, W, N, m, x[j, r], b[r]) <= 1e-10, (m, r)
 
 
+def test_lockstep_16rhs_two_masses_bf16(torch, mg, cubic):
+    """The production batch shape: 16 right-hand sides for each of two masses
+    in one lockstep solve (KD on the matrix cores with one inverse slot per
+    mass, 16-bit coarse links); every system reaches 1e-10 on the oracle's
+    true residual."""
+    cfg, W, N, nvs, _ = cubic
+    masses = [0.05, 0.11]
+    rng = np.random.default_rng(4321)
+    b = latgen.fine_vectors(cfg["dims"], 16, rng)
+    log("[solve] cubic 16 rhs x 2 masses bf16")
+    ctx = make_ctx(torch, mg, cfg, W, N, nvs, max_nrhs=32, max_nmass=2, coarse_prec=mg.MG_CBF16)
+    x, info, st = ctx.solve(masses, torch.from_numpy(b).to("cuda:0"), tol=1e-10)
+    x = x.cpu().numpy()
+    for j, m in enumerate(masses):
+        for r in range(16):
+            assert info[j * 16 + r]["status"] == "MG_OK"
+            assert true_rel(cfg, W, N, m, x[j, r], b[r]) <= 1e-10, (m, r)
+
+
 def test_c0_exact_two_level(torch, mg):
     """4^4 naive, KD + 2^4 aggregation with Nvec = 24 (square, unitary P): with
     the coarsest level solved to 1e-14 the K-cycle is the exact inverse and the
