@@ -200,9 +200,153 @@ static void restrict_launch(const RestrictArgs<R>& a, hipStream_t st) {
   restrict_kernel<R, NR, KPL><<<grid, 64 * kRestrictWaves, lds, st>>>(a);
 }
 
+// ------------------------------------------------- FP32 matrix-core transfer
+// Per (aggregate, chirality) block the transfers are small complex GEMMs:
+// restriction C[nvec x N] = P^dag X[nrows x N], prolongation
+// Y[nrows x N] = P C[nvec x N], with N right-hand sides.  They run on
+// v_mfma_f32_16x16x4f32 as four real products per step; a workgroup takes one
+// block and 16 RT right-hand sides (RT = 4, or 1 for 16 or fewer), so P is
+// read once per 16 RT of them.
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+constexpr int kXferChunk = 32;    // fine rows staged per pass (restriction)
+
+__device__ __forceinline__ void cmfma(f32x4& yr, f32x4& yi, float ar, float ai, float br, float bi) {
+  yr = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, yr, 0, 0, 0);
+  yr = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, yr, 0, 0, 0);
+  yi = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, yi, 0, 0, 0);
+  yi = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, yi, 0, 0, 0);
+}
+
+// one wavefront per 16 coarse rows k; lane l: A = conj P(row 4 s + l / 16,
+// k 16 kt + l % 16), B = X(row 4 s + l / 16, rhs l % 16), D rows k = 16 kt +
+// 4 (l / 16) + t of rhs l % 16
+template <int RT>
+__global__ void __launch_bounds__(512) restrict_mfma_kernel(const RestrictArgs<float> a) {
+  __shared__ float2 xs[kXferChunk][16 * RT + 1];
+  const int64_t as = blockIdx.x;
+  const int64_t agg = as >> 1;
+  const int sigma = (int)(as & 1);
+  const int r0 = blockIdx.y * 16 * RT;
+  const int tid = threadIdx.x, kt = tid >> 6, lane = tid & 63;
+  const int nthreads = blockDim.x;
+  const int nvec = a.A.nvec, nrows = a.A.nrows;
+  const float2* P = a.pr + as * (int64_t)nrows * nvec;
+  const int kk = lane >> 4, jl = lane & 15;
+  const int kcol = 16 * kt + jl;
+  f32x4 yr[RT], yi[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    yr[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    yi[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  for (int row0 = 0; row0 < nrows; row0 += kXferChunk) {
+    __syncthreads();
+    for (int e = tid; e < kXferChunk * 16 * RT; e += nthreads) {
+      const int rr = e / kXferChunk, q = e - rr * kXferChunk;   // consecutive threads: consecutive rows
+      float2 v = make_float2(0.f, 0.f);
+      if (row0 + q < nrows && r0 + rr < a.nrhs)
+        v = a.in[(int64_t)(r0 + rr) * a.in_stride + agg_row_index(a.A, agg, sigma, row0 + q)];
+      xs[q][rr] = v;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int s = 0; s < kXferChunk / 4; ++s) {
+      const int row = row0 + 4 * s + kk;
+      float2 p = make_float2(0.f, 0.f);
+      if (row < nrows && kcol < nvec) p = P[(int64_t)row * nvec + kcol];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const float2 x = xs[4 * s + kk][16 * rt + jl];
+        cmfma(yr[rt], yi[rt], p.x, -p.y, x.x, x.y);
+      }
+    }
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int r = r0 + 16 * rt + jl;
+    if (r >= a.nrhs) continue;
+    float2* o = a.out + (int64_t)r * a.out_stride + agg * a.out_site_stride + sigma * nvec;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = 16 * kt + 4 * kk + t;
+      if (k < nvec) o[k] = make_float2(yr[rt][t], yi[rt][t]);
+    }
+  }
+}
+
+// eight wavefronts walk the 16-row tiles of the block; the coarse block
+// C[nvec x 16 RT] sits in LDS.  The product is formed transposed,
+// Y^T = C^T P^T, so that a lane's results are one fine row for four
+// right-hand sides and the 16 lanes of a group store 16 consecutive rows:
+// lane l: A = C(k 4 s + l / 16, rhs l % 16), B = P(row 16 mt + l % 16,
+// k 4 s + l / 16), D = Y(row 16 mt + l % 16, rhs 4 (l / 16) + t).
+template <int RT>
+__global__ void __launch_bounds__(512) prolong_mfma_kernel(const ProlongArgs<float> a) {
+  __shared__ float2 cs[128][16 * RT + 1];
+  const int64_t as = blockIdx.x;
+  const int64_t agg = as >> 1;
+  const int sigma = (int)(as & 1);
+  const int r0 = blockIdx.y * 16 * RT;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nvec = a.A.nvec, nrows = a.A.nrows;
+  const float2* P = a.pp + as * (int64_t)nrows * nvec;
+  const int ksteps = (nvec + 3) / 4;
+  for (int e = tid; e < 4 * ksteps * 16 * RT; e += 512) {
+    const int k = e / (16 * RT), rr = e - k * (16 * RT);
+    float2 v = make_float2(0.f, 0.f);
+    if (k < nvec && r0 + rr < a.nrhs) v = a.in[(int64_t)(r0 + rr) * a.in_stride + agg * 2 * nvec + sigma * nvec + k];
+    cs[k][rr] = v;
+  }
+  __syncthreads();
+  const int kk = lane >> 4, il = lane & 15;
+  const int mt_n = (nrows + 15) / 16;
+  for (int mt = wave; mt < mt_n; mt += 8) {
+    const int row = 16 * mt + il;
+    f32x4 yr[RT], yi[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      yr[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      yi[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll 2
+    for (int s = 0; s < ksteps; ++s) {
+      const int k = 4 * s + kk;
+      float2 p = make_float2(0.f, 0.f);
+      if (row < nrows && k < nvec) p = P[(int64_t)k * nrows + row];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const float2 c = cs[k][16 * rt + il];
+        cmfma(yr[rt], yi[rt], c.x, c.y, p.x, p.y);
+      }
+    }
+    if (row >= nrows) continue;
+    const int64_t fi = agg_row_index(a.A, agg, sigma, row);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = r0 + 16 * rt + 4 * kk + t;
+        if (r >= a.nrhs) continue;
+        float2* o = a.out + (int64_t)r * a.out_stride + fi;
+        float2 v = make_float2(yr[rt][t], yi[rt][t]);
+        if (a.accumulate) { const float2 old = *o; v.x += old.x; v.y += old.y; }
+        *o = v;
+      }
+    }
+  }
+}
+
 template <typename R>
 void launch_restrict(const RestrictArgs<R>& a, hipStream_t st) {
   if (a.nrhs <= 0) return;
+  if constexpr (sizeof(R) == 4) {
+    if (a.nrhs >= 4) {
+      const unsigned gx = (unsigned)(a.A.nagg * 2), nt = 64 * ((a.A.nvec + 15) / 16);
+      if (a.nrhs <= 16) restrict_mfma_kernel<1><<<dim3(gx, 1), nt, 0, st>>>(a);
+      else restrict_mfma_kernel<4><<<dim3(gx, (unsigned)((a.nrhs + 63) / 64)), nt, 0, st>>>(a);
+      return;
+    }
+  }
   const bool big = a.A.nvec > 64;
   // the staged inputs must fit next to the reduction buffer (64 KiB budget)
   const size_t row_bytes = (size_t)a.A.nrows * sizeof(cplx<R>);
@@ -271,6 +415,13 @@ template <typename R>
 void launch_prolong(const ProlongArgs<R>& a, hipStream_t st) {
   if (a.nrhs <= 0) return;
   const unsigned gx = (unsigned)(a.A.nagg * 2);
+  if constexpr (sizeof(R) == 4) {
+    if (a.nrhs >= 4 && a.unit_col < 0) {
+      if (a.nrhs <= 16) prolong_mfma_kernel<1><<<dim3(gx, 1), 512, 0, st>>>(a);
+      else prolong_mfma_kernel<4><<<dim3(gx, (unsigned)((a.nrhs + 63) / 64)), 512, 0, st>>>(a);
+      return;
+    }
+  }
   if (a.nrhs >= 8 && sizeof(R) == 4) {
     dim3 grid(gx, (unsigned)((a.nrhs + 7) / 8));
     prolong_kernel<R, 8><<<grid, 512, 0, st>>>(a);
