@@ -61,7 +61,7 @@ __global__ void finalize_kernel(const double2* __restrict__ part, int nblk, int 
 }
 
 int reduce_blocks(int64_t n) {
-  int64_t b = (n + 2047) / 2048;
+  int64_t b = (n + 511) / 512;
   if (b < 1) b = 1;
   if (b > 480) b = 480;
   return (int)b;
@@ -79,14 +79,18 @@ void launch_pairdot(const PairDotArgs<T>& a, double2* part, double2* res, int ld
 template void launch_pairdot<float2>(const PairDotArgs<float2>&, double2*, double2*, int, hipStream_t);
 template void launch_pairdot<double2>(const PairDotArgs<double2>&, double2*, double2*, int, hipStream_t);
 
-// out = sum_t coef_t(r) v_t  (out may alias one of the v_t)
-template <typename T>
+// out = sum_t coef_t(r) v_t  (out may alias one of the v_t); MAXT bounds the
+// term count (registers), TWO adds the second output over v2; each thread
+// keeps U elements in flight (two for short single-output combinations)
+template <typename T, int MAXT, bool TWO>
 __global__ void __launch_bounds__(256) lincomb_kernel(const LinCombArgs<T> a) {
+  constexpr int U = (MAXT <= 4 && !TWO) ? 2 : 1;
   const int r = blockIdx.y;
   const int64_t off = (int64_t)r * a.stride;
-  double2 cf[kMaxTerms];
+  double2 cf[MAXT];
 #pragma unroll
-  for (int t = 0; t < kMaxTerms; ++t) {
+  for (int t = 0; t < MAXT; ++t) {
+    cf[t] = make_double2(0.0, 0.0);
     if (t < a.nt) {
       double2 c = a.c[t] ? a.c[t][r] : a.cconst[t];
       if (a.conj[t]) c.y = -c.y;
@@ -95,27 +99,50 @@ __global__ void __launch_bounds__(256) lincomb_kernel(const LinCombArgs<T> a) {
       cf[t] = c;
     }
   }
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.n; e += (int64_t)gridDim.x * 256) {
-    double2 acc = make_double2(0.0, 0.0), acc2 = make_double2(0.0, 0.0);
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e0 = (int64_t)blockIdx.x * 256 + threadIdx.x; e0 < a.n; e0 += stride * U) {
+    double2 acc[U], acc2[U];
 #pragma unroll
-    for (int t = 0; t < kMaxTerms; ++t) {
+    for (int u = 0; u < U; ++u) { acc[u] = make_double2(0.0, 0.0); acc2[u] = make_double2(0.0, 0.0); }
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
       if (t < a.nt) {
-        cfma(acc, cf[t], to_d2(a.v[t][off + e]));
-        if (a.out2) cfma(acc2, cf[t], to_d2(a.v2[t][off + e]));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t e = e0 + u * stride;
+          if (e < a.n) {
+            cfma(acc[u], cf[t], to_d2(a.v[t][off + e]));
+            if (TWO) cfma(acc2[u], cf[t], to_d2(a.v2[t][off + e]));
+          }
+        }
       }
     }
-    a.out[off + e] = from_d2<T>(acc);
-    if (a.out2) a.out2[off + e] = from_d2<T>(acc2);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + u * stride;
+      if (e < a.n) {
+        a.out[off + e] = from_d2<T>(acc[u]);
+        if (TWO) a.out2[off + e] = from_d2<T>(acc2[u]);
+      }
+    }
   }
+}
+
+template <typename T, int MAXT>
+static void lincomb_launch(const LinCombArgs<T>& a, dim3 grid, hipStream_t st) {
+  if (a.out2) lincomb_kernel<T, MAXT, true><<<grid, 256, 0, st>>>(a);
+  else lincomb_kernel<T, MAXT, false><<<grid, 256, 0, st>>>(a);
 }
 
 template <typename T>
 void launch_lincomb(const LinCombArgs<T>& a, hipStream_t st) {
-  int64_t b = (a.n + 255) / 256;
-  if (b > 2048) b = 2048;
+  int64_t b = (a.n + 511) / 512;
+  if (b > 1024) b = 1024;
   if (b < 1) b = 1;
   dim3 grid((unsigned)b, a.nrhs);
-  lincomb_kernel<T><<<grid, 256, 0, st>>>(a);
+  if (a.nt <= 4) lincomb_launch<T, 4>(a, grid, st);
+  else if (a.nt <= 10) lincomb_launch<T, 10>(a, grid, st);
+  else lincomb_launch<T, kMaxTerms>(a, grid, st);
 }
 template void launch_lincomb<float2>(const LinCombArgs<float2>&, hipStream_t);
 template void launch_lincomb<double2>(const LinCombArgs<double2>&, hipStream_t);
@@ -216,15 +243,16 @@ void launch_cg_update(double2* x, double2* r, const double2* p, const double2* a
 // ------------------------------------------------------------ CA-GCR Gram
 // The smoother's Gram data in one pass over its s + 1 vectors (u_i = A p_i
 // for i < s, u_s = t): G(i, j) = <u_i, u_j> for i <= j < s, then
-// c_i = <u_i, t>, in the slot order of the Cholesky solve.  The four
-// wavefronts of a block walk the same 64 elements and take the pairs of the
-// largest basis round-robin, so each holds at most 11 FP64 accumulators and
-// every vector element is fetched from HBM once.
+// c_i = <u_i, t>, in the slot order of the Cholesky solve.  A block stages
+// 256 elements of every vector in LDS (each element fetched once); its four
+// wavefronts then take the pairs of the largest basis round-robin, so each
+// holds at most 11 FP64 accumulators.
 template <typename T>
 __global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2* __restrict__ part, int nblk) {
   constexpr int S = kMaxS;
   constexpr int NPF = S * (S + 1) / 2 + S;
   constexpr int PW = (NPF + 3) / 4;
+  __shared__ T us[S + 1][256];
   const int r = blockIdx.y;
   const int64_t off = (int64_t)r * a.stride;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -232,20 +260,31 @@ __global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2*
   double2 acc[PW];
 #pragma unroll
   for (int q = 0; q < PW; ++q) acc[q] = make_double2(0.0, 0.0);
-  for (int64_t e = (int64_t)blockIdx.x * 64 + lane; e < a.n; e += (int64_t)nblk * 64) {
-    double2 v[S + 1];
+  for (int64_t e0 = (int64_t)blockIdx.x * 256; e0 < a.n; e0 += (int64_t)nblk * 256) {
+    const int64_t e = e0 + threadIdx.x;
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i <= S; ++i) {
-      if (i < S) v[i] = i < s ? to_d2(a.u[i][off + e]) : make_double2(0.0, 0.0);
-      else v[i] = to_d2(a.u[s][off + e]);
+      T v{};
+      const int src = i < S ? i : s;
+      if ((i < s || i == S) && e < a.n) v = a.u[src][off + e];
+      us[i][threadIdx.x] = v;
     }
-    int f = 0;
+    __syncthreads();
+#pragma unroll 1
+    for (int q4 = 0; q4 < 4; ++q4) {
+      const int el = lane + 64 * q4;
+      double2 v[S + 1];
 #pragma unroll
-    for (int i = 0; i < S; ++i) {
+      for (int i = 0; i <= S; ++i) v[i] = (i < s || i == S) ? to_d2(us[i][el]) : make_double2(0.0, 0.0);
+      int f = 0;
 #pragma unroll
-      for (int j = i; j <= S; ++j) {
-        if ((f & 3) == wave && i < s && (j < s || j == S)) cfmac(acc[f >> 2], v[i], v[j]);
-        ++f;
+      for (int i = 0; i < S; ++i) {
+#pragma unroll
+        for (int j = i; j <= S; ++j) {
+          if ((f & 3) == wave && i < s && (j < s || j == S)) cfmac(acc[f >> 2], v[i], v[j]);
+          ++f;
+        }
       }
     }
   }
@@ -266,10 +305,7 @@ __global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2*
 
 template <typename T>
 void launch_gram(const GramArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
-  int64_t b = (a.n + 1023) / 1024;
-  if (b < 1) b = 1;
-  if (b > 480) b = 480;
-  const int nblk = (int)b;
+  const int nblk = reduce_blocks(a.n);
   gram_kernel<T><<<dim3(nblk, a.nrhs), 256, 0, st>>>(a, part, nblk);
   finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, a.s * (a.s + 1) / 2 + a.s, a.nrhs, res, ldr);
 }
