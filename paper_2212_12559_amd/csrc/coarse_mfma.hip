@@ -98,15 +98,16 @@ void launch_absmax(const double2* v, int64_t n, unsigned long long* out, hipStre
   absmax_kernel<<<480, 256, 0, st>>>(v, n, out);
 }
 
-// One workgroup per (coarse site, group of 16 RT right-hand sides), one
-// wavefront per m-tile (n <= 256: at most 16 wavefronts).  The B operand is
-// staged through LDS in passes of kMfmaCK k-chunks, so the RT rhs tiles share
-// every A fragment a wavefront streams from HBM: the links, which dominate the
-// traffic, are read once per 16 RT right-hand sides.
+// One workgroup per (coarse site, group of 16 RT right-hand sides); each
+// wavefront takes MT m-tiles (n <= 256: at most 16 m-tiles).  The B operand is
+// staged through LDS in passes of kMfmaCK k-chunks; a B fragment read from LDS
+// feeds 4 MT products and an A fragment streamed from HBM feeds 4 RT, so the
+// links, which dominate the traffic, are read once per 16 RT right-hand sides
+// and the LDS reads per product fall as 1 / MT.
 constexpr int kMfmaCK = 4;
 constexpr int kMfmaMaxWaves = 16;
 
-template <int FMT, int RT>
+template <int FMT, int RT, int MT>
 __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const CoarseMfmaArgs a) {
   constexpr int NR = 16 * RT;          // right-hand sides per workgroup
   constexpr int KCH = kMfmaCK * 32;    // k per staging pass
@@ -123,20 +124,24 @@ __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const C
   const int r0 = blockIdx.y * NR;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nthreads = blockDim.x;
-  const int mt = wave;
+  const int nw = mt_n / MT;            // wavefronts; this one owns m-tiles wave + nw m
   if (tid < 9) {
     int c[4];
     site_coords(site, a.g, c);
     nbs[tid] = tid == 0 ? site : site_shift(c, (tid - 1) >> 1, (tid & 1) ? 1 : -1, a.g);
   }
-  f32x4 yr[RT], yi[RT];
+  f32x4 yr[MT][RT], yi[MT][RT];
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    yr[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    yi[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  }
-  const uint4* Lm = reinterpret_cast<const uint4*>(a.links) +
-                    (site * mt_n + mt) * (int64_t)kc_n * 2 * 64;
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      yr[m][rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+      yi[m][rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  const uint4* Lm[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+    Lm[m] = reinterpret_cast<const uint4*>(a.links) + (site * mt_n + wave + nw * m) * (int64_t)kc_n * 2 * 64;
   const int j = lane & 15, g = lane >> 4;
   for (int kc0 = 0; kc0 < kc_n; kc0 += kMfmaCK) {
     __syncthreads();   // neighbour table ready / previous pass consumed
@@ -162,57 +167,74 @@ __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const C
     for (int kcl = 0; kcl < kMfmaCK; ++kcl) {
       const int kc = kc0 + kcl;
       if (kc < kc_n) {
-        const uint4 are = Lm[(kc * 2 + 0) * 64 + lane];
-        const uint4 aim = Lm[(kc * 2 + 1) * 64 + lane];
+        uint4 are[MT], aim[MT], aimn[MT];   // Re A, Im A and -Im A (sign bits flipped)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          are[m] = Lm[m][(kc * 2 + 0) * 64 + lane];
+          aim[m] = Lm[m][(kc * 2 + 1) * 64 + lane];
+          aimn[m] = make_uint4(aim[m].x ^ 0x80008000u, aim[m].y ^ 0x80008000u, aim[m].z ^ 0x80008000u,
+                               aim[m].w ^ 0x80008000u);
+        }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
           const int off = (rt * 16 + j) * KPC + kcl * 32 + 8 * g;
           const uint4 bre = *reinterpret_cast<const uint4*>(Bre + off);
           const uint4 bim = *reinterpret_cast<const uint4*>(Bim + off);
-          const uint4 bimn = make_uint4(bim.x ^ 0x80008000u, bim.y ^ 0x80008000u, bim.z ^ 0x80008000u,
-                                        bim.w ^ 0x80008000u);
-          yr[rt] = mfma16<FMT>(are, bre, yr[rt]);
-          yr[rt] = mfma16<FMT>(aim, bimn, yr[rt]);
-          yi[rt] = mfma16<FMT>(are, bim, yi[rt]);
-          yi[rt] = mfma16<FMT>(aim, bre, yi[rt]);
+#pragma unroll
+          for (int m = 0; m < MT; ++m) {
+            yr[m][rt] = mfma16<FMT>(are[m], bre, yr[m][rt]);
+            yr[m][rt] = mfma16<FMT>(aimn[m], bim, yr[m][rt]);
+            yi[m][rt] = mfma16<FMT>(are[m], bim, yi[m][rt]);
+            yi[m][rt] = mfma16<FMT>(aim[m], bre, yi[m][rt]);
+          }
         }
       }
     }
   }
-  // D fragment: column j (rhs), rows 4 g + t of m-tile mt
+  // D fragment: column j (rhs), rows 4 g + t of each m-tile
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt) {
-    const int r = r0 + rt * 16 + j;
-    if (r < a.nrhs) {
-      float2* o = a.out + (int64_t)r * a.out_stride + site * n + mt * 16 + 4 * g;
+  for (int m = 0; m < MT; ++m) {
+    const int mt = wave + nw * m;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) o[t] = make_float2(yr[rt][t] * a.inv_scale, yi[rt][t] * a.inv_scale);
+    for (int rt = 0; rt < RT; ++rt) {
+      const int r = r0 + rt * 16 + j;
+      if (r < a.nrhs) {
+        float2* o = a.out + (int64_t)r * a.out_stride + site * n + mt * 16 + 4 * g;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) o[t] = make_float2(yr[m][rt][t] * a.inv_scale, yi[m][rt][t] * a.inv_scale);
+      }
     }
   }
 }
 
-template <int FMT, int RT>
+template <int FMT, int RT, int MT>
 static void coarse_mfma_launch(const CoarseMfmaArgs& a, hipStream_t st) {
   const int mt_n = a.n / 16;
   const size_t lds = (size_t)2 * 16 * RT * (kMfmaCK * 32 + 8) * sizeof(uint16_t);
   dim3 grid((unsigned)a.g.V, (unsigned)((a.nrhs + 16 * RT - 1) / (16 * RT)));
-  coarse_mfma_kernel<FMT, RT><<<grid, 64 * mt_n, lds, st>>>(a);
+  coarse_mfma_kernel<FMT, RT, MT><<<grid, 64 * (mt_n / MT), lds, st>>>(a);
+}
+
+template <int FMT>
+static void coarse_mfma_dispatch(const CoarseMfmaArgs& a, hipStream_t st) {
+  // two m-tiles per wavefront once several rhs tiles share the B reads
+  const bool mt2 = a.nrhs > 16 && (a.n / 16) % 2 == 0;
+  if (a.nrhs <= 16) coarse_mfma_launch<FMT, 1, 1>(a, st);
+  else if (a.nrhs <= 32) {
+    if (mt2) coarse_mfma_launch<FMT, 2, 2>(a, st);
+    else coarse_mfma_launch<FMT, 2, 1>(a, st);
+  } else {
+    if (mt2) coarse_mfma_launch<FMT, 4, 2>(a, st);
+    else coarse_mfma_launch<FMT, 4, 1>(a, st);
+  }
 }
 
 void launch_coarse_mfma(const CoarseMfmaArgs& a, int fmt, hipStream_t st) {
   if (a.nrhs <= 0) return;
   if (a.n % 16 || a.n < 16 || a.n > 16 * kMfmaMaxWaves)
     throw std::runtime_error("coarse_mfma: n must be a multiple of 16 in 16..256");
-  const int rt = a.nrhs <= 16 ? 1 : (a.nrhs <= 32 ? 2 : 4);
-  if (fmt == 0) {
-    if (rt == 1) coarse_mfma_launch<0, 1>(a, st);
-    else if (rt == 2) coarse_mfma_launch<0, 2>(a, st);
-    else coarse_mfma_launch<0, 4>(a, st);
-  } else {
-    if (rt == 1) coarse_mfma_launch<1, 1>(a, st);
-    else if (rt == 2) coarse_mfma_launch<1, 2>(a, st);
-    else coarse_mfma_launch<1, 4>(a, st);
-  }
+  if (fmt == 0) coarse_mfma_dispatch<0>(a, st);
+  else coarse_mfma_dispatch<1>(a, st);
 }
 
 int64_t swizzled_link_elems(int64_t nsite, int n) {
