@@ -17,9 +17,15 @@ __global__ void __launch_bounds__(256) dslash_kernel(const DslashArgs<R> a) {
   using T = cplx<R>;
   const int64_t V = a.g.V;
   const int64_t nout = CB ? V / 2 : V;
-  const int64_t tid = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  // block b -> (site block, rhs tile) with the rhs tile fastest, after the
+  // XCD renumbering: the tiles of a site block run back to back on one XCD
+  // and share its links (and neighbour spinors) through that L2
+  const int ntile = (a.nrhs + NR - 1) / NR;
+  const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t sb = b / ntile;
+  const int64_t tid = sb * blockDim.x + threadIdx.x;
   if (tid >= nout) return;
-  const int r0 = blockIdx.y * NR;
+  const int r0 = (int)(b - sb * ntile) * NR;
   const int nr = (a.nrhs - r0) < NR ? (a.nrhs - r0) : NR;
   int c[4];
   int64_t s;
@@ -145,7 +151,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(const DslashArgs<R> a) {
 template <typename R, int NR>
 static void launch_nr(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st) {
   const int64_t nout = cb ? a.g.V / 2 : a.g.V;
-  dim3 grid((unsigned)((nout + 255) / 256), (unsigned)((a.nrhs + NR - 1) / NR));
+  dim3 grid((unsigned)((nout + 255) / 256 * ((a.nrhs + NR - 1) / NR)));
   dim3 block(256);
   if (piece) {
     if (naik) dslash_kernel<R, NR, true, false, true><<<grid, block, 0, st>>>(a);
