@@ -211,6 +211,31 @@ mg_status mg_update_links(mg_ctx ctx, const void* fat, const void* naik, void* s
 mg_status mg_export(mg_ctx ctx, int32_t what, int32_t level, void* dst, size_t bytes, size_t* bytes_needed,
                     void* stream);
 
+/* Kernel timing (a measurement aid, not part of the method): between
+ * mg_profile_start and mg_profile_stop every launch of one operator is
+ * bracketed by a pair of HIP events recorded on the stream it runs on, so
+ * the durations are those of the kernels inside a real solve.
+ *   op    : an mg_prof_op.
+ *   level : MG_PROF_COARSE: coarse level 2 or 3; MG_PROF_RESTRICT /
+ *           MG_PROF_PROLONG: transfer level 1 or 2; MG_PROF_DSLASH: 0 for the
+ *           stencil with the Naik term, 1 for the one-hop stencil of the KD
+ *           level; MG_PROF_KD: 0.
+ * mg_profile_stop waits for the recorded events and returns the number of
+ * launches and their summed duration in milliseconds, then stops recording.
+ * Events are created on first use and kept until mg_destroy (host-side
+ * runtime objects; no device workspace is used).  Starting again discards
+ * any unread measurement. */
+typedef enum {
+  MG_PROF_COARSE = 0,
+  MG_PROF_DSLASH = 1,
+  MG_PROF_KD = 2,
+  MG_PROF_RESTRICT = 3,
+  MG_PROF_PROLONG = 4
+} mg_prof_op;
+
+mg_status mg_profile_start(mg_ctx ctx, int32_t op, int32_t level);
+mg_status mg_profile_stop(mg_ctx ctx, int32_t* launches, double* total_ms);
+
 mg_status mg_destroy(mg_ctx ctx);
 
 const char* mg_last_error(void);

@@ -325,6 +325,39 @@ mg_status mg_export(mg_ctx ctx, int32_t what, int32_t level, void* dst, size_t b
   });
 }
 
+mg_status mg_profile_start(mg_ctx ctx, int32_t op, int32_t level) {
+  if (!ctx) return fail(MG_E_ARG, "null context");
+  if (op < MG_PROF_COARSE || op > MG_PROF_PROLONG) return fail(MG_E_ARG, "op must be an mg_prof_op");
+  Ctx& c = ctx->c;
+  c.prof_op = op;
+  c.prof_level = level;
+  c.prof_used = 0;
+  return MG_OK;
+}
+
+mg_status mg_profile_stop(mg_ctx ctx, int32_t* launches, double* total_ms) {
+  if (!ctx || !launches || !total_ms) return fail(MG_E_ARG, "null argument");
+  Ctx& c = ctx->c;
+  return guarded([&] {
+    double sum = 0.0;
+    const size_t pairs = c.prof_used / 2;
+    if (pairs > 0) {
+      hipError_t e = hipEventSynchronize(c.prof_events[2 * pairs - 1]);
+      if (e != hipSuccess) throw Error{MG_E_HIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e)};
+      for (size_t i = 0; i < pairs; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, c.prof_events[2 * i], c.prof_events[2 * i + 1]);
+        if (e != hipSuccess) throw Error{MG_E_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(e)};
+        sum += ms;
+      }
+    }
+    *launches = (int32_t)pairs;
+    *total_ms = sum;
+    c.prof_op = -1;
+    c.prof_used = 0;
+  });
+}
+
 mg_status mg_destroy(mg_ctx ctx) {
   delete ctx;
   return MG_OK;

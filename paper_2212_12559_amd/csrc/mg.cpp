@@ -212,6 +212,21 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   return true;
 }
 
+// ================================================================ profiling
+void Ctx::prof_mark(int op, int level) {
+  if (op != prof_op || level != prof_level) return;
+  if (prof_used == prof_events.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    prof_events.push_back(e);
+  }
+  HIPCHK(hipEventRecord(prof_events[prof_used++], st));
+}
+
+Ctx::~Ctx() {
+  for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
+}
+
 // ================================================================== operators
 template <typename R>
 static DslashArgs<R> dslash_args(const Ctx& c, void* out, const void* in, int nsys) {
@@ -230,6 +245,7 @@ static DslashArgs<R> dslash_args(const Ctx& c, void* out, const void* in, int ns
 
 void Ctx::apply_D(int prec, void* out, const void* in, int nsys, bool naik, const void* mass_rhs, double mass,
                   bool eps_out) {
+  prof_mark(MG_PROF_DSLASH, naik && P.c3 != 0.0 ? 0 : 1);
   naik = naik && P.c3 != 0.0;
   if (prec == P64) {
     auto a = dslash_args<double>(*this, out, in, nsys);
@@ -244,10 +260,12 @@ void Ctx::apply_D(int prec, void* out, const void* in, int nsys, bool naik, cons
     a.eps_out = eps_out;
     launch_dslash(a, naik, false, false, st);
   }
+  prof_mark(MG_PROF_DSLASH, naik && P.c3 != 0.0 ? 0 : 1);
   check_launch();
 }
 
 void Ctx::apply_KD(int prec, void* out, const void* in, int nsys, bool eps_in, bool eps_out, int rps) {
+  prof_mark(MG_PROF_KD, 0);
   if (prec == P64) {
     KdArgs<double> a{};
     a.out = (double2*)out; a.in = (const double2*)in; a.kinv = kinv64 + (int64_t)kd_base * kinv_slot;
@@ -261,10 +279,12 @@ void Ctx::apply_KD(int prec, void* out, const void* in, int nsys, bool eps_in, b
     a.rhs_per_slot = rps; a.slot_stride = kinv_slot; a.eps_in = eps_in; a.eps_out = eps_out;
     launch_kd_apply(a, st);
   }
+  prof_mark(MG_PROF_KD, 0);
   check_launch();
 }
 
 void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, bool dag) {
+  prof_mark(MG_PROF_COARSE, lvl);
   const int l = lvl - 2;
   const int n = ncoarse[l];
   if (prec == P64) {
@@ -284,10 +304,12 @@ void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, b
     a.g = gc[l]; a.n = n; a.in_stride = a.out_stride = gc[l].V * n; a.nrhs = nsys;
     launch_coarse(a, false, dag, st);
   }
+  prof_mark(MG_PROF_COARSE, lvl);
   check_launch();
 }
 
 void Ctx::restrict_(int lvl, int prec, void* out, const void* in, int nsys) {
+  prof_mark(MG_PROF_RESTRICT, lvl);
   const int l = lvl - 1;   // lvl 1: fine -> level 2, lvl 2: level 2 -> level 3
   const Agg& a = A[l];
   const int64_t nin = a.nagg * 2 * a.nrows, nout = a.nagg * 2 * a.nvec;
@@ -302,10 +324,12 @@ void Ctx::restrict_(int lvl, int prec, void* out, const void* in, int nsys) {
     r.in_stride = nin; r.out_stride = nout; r.out_site_stride = 2 * a.nvec; r.nrhs = nsys;
     launch_restrict(r, st);
   }
+  prof_mark(MG_PROF_RESTRICT, lvl);
   check_launch();
 }
 
 void Ctx::prolong_(int lvl, int prec, void* out, const void* in, int nsys, bool acc) {
+  prof_mark(MG_PROF_PROLONG, lvl);
   const int l = lvl - 1;
   const Agg& a = A[l];
   const int64_t nfine = a.nagg * 2 * a.nrows, ncrs = a.nagg * 2 * a.nvec;
@@ -320,6 +344,7 @@ void Ctx::prolong_(int lvl, int prec, void* out, const void* in, int nsys, bool 
     r.in_stride = ncrs; r.out_stride = nfine; r.nrhs = nsys; r.accumulate = acc; r.unit_col = -1;
     launch_prolong(r, st);
   }
+  prof_mark(MG_PROF_PROLONG, lvl);
   check_launch();
 }
 

@@ -96,6 +96,14 @@ struct Ctx {
 
   std::vector<double> host_buf;
 
+  // kernel timing: while prof_op >= 0, every launch of that operator (at
+  // prof_level where it has one) is bracketed by a pair of HIP events
+  int prof_op = -1, prof_level = 0;
+  std::vector<hipEvent_t> prof_events;
+  size_t prof_used = 0;
+  void prof_mark(int op, int level);   // records the next event when (op, level) is profiled
+  ~Ctx();
+
   // ---- layout
   static bool plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string* why);
 

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmgstag.so")
 MG_OK, MG_E_ARG, MG_E_CONFIG, MG_E_ALIGN, MG_E_RANK, MG_E_NOCONV, MG_E_NONFINITE, MG_E_HIP, MG_E_STATE, \
     MG_E_WORKSPACE = range(10)
 MG_C128, MG_C64, MG_CBF16, MG_CF16 = range(4)
+MG_PROF_COARSE, MG_PROF_DSLASH, MG_PROF_KD, MG_PROF_RESTRICT, MG_PROF_PROLONG = range(5)
 STATUS_NAMES = ["MG_OK", "MG_E_ARG", "MG_E_CONFIG", "MG_E_ALIGN", "MG_E_RANK", "MG_E_NOCONV",
                 "MG_E_NONFINITE", "MG_E_HIP", "MG_E_STATE", "MG_E_WORKSPACE"]
 
@@ -84,6 +85,8 @@ def _load():
         "mg_export": (i32, [vp, i32, i32, vp, sz, P(sz), vp]),
         "mg_solve_backward": (i32, [vp, f64, vp, vp, vp, vp, vp, i32, f64, P(MGSolveInfo), vp]),
         "mg_update_links": (i32, [vp, vp, vp, vp]),
+        "mg_profile_start": (i32, [vp, i32, i32]),
+        "mg_profile_stop": (i32, [vp, P(i32), P(f64)]),
         "mg_destroy": (i32, [vp]),
         "mg_last_error": (ctypes.c_char_p, []),
     }
@@ -299,6 +302,17 @@ class Context:
         out = torch.empty(need.value // esz, dtype=dt, device=self.persistent.device)
         _check(LIB.mg_export(self.ctx, what, level, _dev(out, "dst"), need.value, None, _stream()), "mg_export")
         return out
+
+    def profile_start(self, op, level=0):
+        """Time every launch of one operator (MG_PROF_*) with HIP events."""
+        _check(LIB.mg_profile_start(self.ctx, op, level), "mg_profile_start")
+
+    def profile_stop(self):
+        """(launches, total milliseconds) since profile_start."""
+        n = ctypes.c_int32()
+        ms = ctypes.c_double()
+        _check(LIB.mg_profile_stop(self.ctx, ctypes.byref(n), ctypes.byref(ms)), "mg_profile_stop")
+        return n.value, ms.value
 
     def destroy(self):
         if getattr(self, "ctx", None):

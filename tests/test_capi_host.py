@@ -74,3 +74,12 @@ def test_workspace_sizes_scale(m):
     naive = m.default_params((4, 4, 4, 4), c1=1.0, c3=0.0, nagg=1, block=[(2, 2, 2, 2)], nvec=(24,))
     pb, sb = m.workspace_bytes(naive)
     assert pb > 0 and sb > 0
+
+
+def test_profile_entry_points_validate(m):
+    """The kernel-timing entry points reject a null context and null outputs
+    before touching any device state."""
+    n = ctypes.c_int32()
+    ms = ctypes.c_double()
+    assert m.LIB.mg_profile_start(None, m.MG_PROF_COARSE, 2) == m.MG_E_ARG
+    assert m.LIB.mg_profile_stop(None, ctypes.byref(n), ctypes.byref(ms)) == m.MG_E_ARG

@@ -165,6 +165,21 @@ def test_restrict_prolong_parity(case, prec):
             assert rel_err(ea[k], base[k] + pe) < tol
 
 
+def test_profile_counts_launches(case, mg):
+    """Kernel timing brackets exactly the launches of the chosen operator."""
+    torch = case.torch
+    lvl = 2
+    x = case.to_gpu(latgen.complex_normal(case.rng, (5,) + case.H.fine_shape(lvl)), torch.complex64)
+    case.ctx.profile_start(mg.MG_PROF_COARSE, lvl)
+    for _ in range(3):
+        case.ctx.apply_coarse(lvl, x)
+    case.ctx.restrict(1, case.to_gpu(latgen.complex_normal(case.rng, (5,) + case.H.fine_shape(1)), torch.complex64))
+    n, ms = case.ctx.profile_stop()
+    assert n == 3 and ms > 0.0
+    n, ms = case.ctx.profile_stop()
+    assert n == 0 and ms == 0.0
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_coarse_parity(case, prec):
     """Coarse stencil (GPU-built direction-split Galerkin links) against the
