@@ -184,6 +184,10 @@ def test_round_to_nearest_even():
     assert np.max(np.abs(ops.round_bf16(v) - v) / np.abs(v)) <= 2.0 ** -8
     assert np.max(np.abs(ops.round_fp16(v) - v) / np.maximum(np.abs(v), 2.0 ** -14)) <= 2.0 ** -11
     assert ops.round_fp16(1.0 + 2.0 ** -11) == 1.0
+    # fp16 of FP32 values (the kernels' inputs are FP32) against numpy's IEEE half
+    # conversion (round to nearest even), inside the normal range
+    w = (rng.standard_normal(10000) * 100.0).astype(np.float32).astype(np.float64)
+    assert np.array_equal(ops.round_fp16(w), w.astype(np.float16).astype(np.float64))
 
 
 def test_force_matches_central_differences():
