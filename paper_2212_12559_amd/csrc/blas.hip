@@ -312,161 +312,6 @@ void launch_gram(const GramArgs<T>& a, double2* part, double2* res, int ldr, hip
 template void launch_gram<float2>(const GramArgs<float2>&, double2*, double2*, int, hipStream_t);
 template void launch_gram<double2>(const GramArgs<double2>&, double2*, double2*, int, hipStream_t);
 
-// ---------------------------------------------- deferred-update GCR passes
-// <x_i, y> for i < nv, y fetched once per element
-template <typename T, int MAXV>
-__global__ void __launch_bounds__(256) multidot_kernel(const MultiDotArgs<T> a, double2* __restrict__ part,
-                                                       int nblk) {
-  __shared__ double2 red[4][MAXV];
-  const int r = blockIdx.y;
-  const int64_t off = (int64_t)r * a.stride;
-  double2 acc[MAXV];
-#pragma unroll
-  for (int i = 0; i < MAXV; ++i) acc[i] = make_double2(0.0, 0.0);
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.n; e += (int64_t)nblk * 256) {
-    const double2 y = to_d2(a.y[off + e]);
-#pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-      if (i < a.nv) cfmac(acc[i], to_d2(a.x[i][off + e]), y);
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int i = 0; i < MAXV; ++i) {
-    if (i < a.nv) {
-      const double sx = wsum(acc[i].x), sy = wsum(acc[i].y);
-      if (lane == 0) red[wave][i] = make_double2(sx, sy);
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < a.nv; i += 256) {
-    double2 t = red[0][i];
-    for (int w = 1; w < 4; ++w) { t.x += red[w][i].x; t.y += red[w][i].y; }
-    part[((int64_t)i * a.nrhs + r) * nblk + blockIdx.x] = t;
-  }
-}
-
-template <typename T>
-void launch_multidot(const MultiDotArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
-  if (a.nv <= 0) return;
-  const int nblk = reduce_blocks(a.n);
-  dim3 grid(nblk, a.nrhs);
-  if (a.nv <= 4) multidot_kernel<T, 4><<<grid, 256, 0, st>>>(a, part, nblk);
-  else multidot_kernel<T, kMaxNK><<<grid, 256, 0, st>>>(a, part, nblk);
-  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, a.nv, a.nrhs, res, ldr);
-}
-template void launch_multidot<float2>(const MultiDotArgs<float2>&, double2*, double2*, int, hipStream_t);
-template void launch_multidot<double2>(const MultiDotArgs<double2>&, double2*, double2*, int, hipStream_t);
-
-// q <- q - sum_i beta_i x_i (written only when nv > 0), then partial sums of
-// |q|^2 and <q, r> over the stored (rounded) q
-template <typename T, int MAXV>
-__global__ void __launch_bounds__(256) project_dots_kernel(const ProjArgs<T> a, double2* __restrict__ part,
-                                                           int nblk) {
-  __shared__ double2 red[4][2];
-  const int r = blockIdx.y;
-  const int64_t off = (int64_t)r * a.stride;
-  double2 b[MAXV];
-#pragma unroll
-  for (int i = 0; i < MAXV; ++i) b[i] = i < a.nv ? a.beta[i][r] : make_double2(0.0, 0.0);
-  double2 qq = make_double2(0.0, 0.0), qr = make_double2(0.0, 0.0);
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.n; e += (int64_t)nblk * 256) {
-    double2 qv = to_d2(a.q[off + e]);
-#pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-      if (i < a.nv) cfma(qv, make_double2(-b[i].x, -b[i].y), to_d2(a.x[i][off + e]));
-    const T qt = from_d2<T>(qv);
-    if (a.nv > 0) a.q[off + e] = qt;
-    const double2 qs = to_d2(qt);
-    qq.x += qs.x * qs.x + qs.y * qs.y;
-    cfmac(qr, qs, to_d2(a.r[off + e]));
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const double s0 = wsum(qq.x), s1 = wsum(qr.x), s2 = wsum(qr.y);
-  if (lane == 0) {
-    red[wave][0] = make_double2(s0, 0.0);
-    red[wave][1] = make_double2(s1, s2);
-  }
-  __syncthreads();
-  if (threadIdx.x < 2) {
-    const int i = threadIdx.x;
-    double2 t = red[0][i];
-    for (int w = 1; w < 4; ++w) { t.x += red[w][i].x; t.y += red[w][i].y; }
-    part[((int64_t)i * a.nrhs + r) * nblk + blockIdx.x] = t;
-  }
-}
-
-template <typename T>
-void launch_project_dots(const ProjArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
-  const int nblk = reduce_blocks(a.n);
-  dim3 grid(nblk, a.nrhs);
-  if (a.nv <= 4) project_dots_kernel<T, 4><<<grid, 256, 0, st>>>(a, part, nblk);
-  else project_dots_kernel<T, kMaxNK><<<grid, 256, 0, st>>>(a, part, nblk);
-  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, 2, a.nrhs, res, ldr);
-}
-template void launch_project_dots<float2>(const ProjArgs<float2>&, double2*, double2*, int, hipStream_t);
-template void launch_project_dots<double2>(const ProjArgs<double2>&, double2*, double2*, int, hipStream_t);
-
-// Scalars of direction k from qq = |q'|^2, qr = <q', r> (q' orthogonalised):
-// g_k = |q'|, alpha'_k = <q'/g_k, r> (the coefficient of the normalised
-// direction, kept for the deferred solution update), alpha = qr / qq for the
-// residual update and inv = 1 / g_k.  A masked (converged) system or a zero
-// direction gets g_k = 1, alpha'_k = alpha = 0, inv = 0.
-__global__ void gcr_scalars_tri_kernel(const double2* qq, const double2* qr, const int* mask, int nrhs, int k,
-                                       double2* tri, int ld, double2* alpha, double2* inv) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  const double q = qq[r].x;
-  const bool on = (mask == nullptr || mask[r] != 0) && q > 0.0 && q < 1e300;
-  const double g = on ? sqrt(q) : 1.0;
-  tri[(int64_t)(kTriG + k) * ld + r] = make_double2(g, 0.0);
-  tri[(int64_t)(kTriA + k) * ld + r] = on ? make_double2(qr[r].x / g, qr[r].y / g) : make_double2(0.0, 0.0);
-  alpha[r] = on ? make_double2(qr[r].x / q, qr[r].y / q) : make_double2(0.0, 0.0);
-  inv[r] = make_double2(on ? 1.0 / g : 0.0, 0.0);
-}
-void launch_gcr_scalars_tri(const double2* qq, const double2* qr, const int* mask, int nrhs, int k, double2* tri,
-                            int ld, double2* alpha, double2* inv, hipStream_t st) {
-  gcr_scalars_tri_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(qq, qr, mask, nrhs, k, tri, ld, alpha, inv);
-}
-
-// r -= alpha q, q *= inv, and partial sums of |r|^2
-template <typename T>
-__global__ void __launch_bounds__(256) gcr_update_r_kernel(T* __restrict__ r, T* __restrict__ q,
-                                                           const double2* __restrict__ alpha,
-                                                           const double2* __restrict__ inv, int64_t n,
-                                                           double2* __restrict__ part, int nblk) {
-  __shared__ double red[4];
-  const int rr = blockIdx.y;
-  const int64_t off = (int64_t)rr * n;
-  const double2 al = alpha[rr];
-  const double iv = inv[rr].x;
-  double s = 0.0;
-  for (int64_t e = off + (int64_t)blockIdx.x * 256 + threadIdx.x; e < off + n; e += (int64_t)nblk * 256) {
-    const double2 qv = to_d2(q[e]);
-    double2 rv = to_d2(r[e]);
-    cfma(rv, make_double2(-al.x, -al.y), qv);
-    const T rt = from_d2<T>(rv);
-    r[e] = rt;
-    q[e] = from_d2<T>(make_double2(qv.x * iv, qv.y * iv));
-    const double2 rs = to_d2(rt);
-    s += rs.x * rs.x + rs.y * rs.y;
-  }
-  s = wsum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) part[(int64_t)rr * nblk + blockIdx.x] = make_double2(red[0] + red[1] + red[2] + red[3], 0.0);
-}
-template <typename T>
-void launch_gcr_update_r(T* r, T* q, const double2* alpha, const double2* inv, int64_t n, int nrhs, double2* part,
-                         double2* res, int ldr, hipStream_t st) {
-  const int nblk = reduce_blocks(n);
-  gcr_update_r_kernel<T><<<dim3(nblk, nrhs), 256, 0, st>>>(r, q, alpha, inv, n, part, nblk);
-  finalize_kernel<<<nrhs, 64, 0, st>>>(part, nblk, 1, nrhs, res, ldr);
-}
-template void launch_gcr_update_r<float2>(float2*, float2*, const double2*, const double2*, int64_t, int, double2*,
-                                          double2*, int, hipStream_t);
-template void launch_gcr_update_r<double2>(double2*, double2*, const double2*, const double2*, int64_t, int,
-                                           double2*, double2*, int, hipStream_t);
-
 // Coefficients of the deferred solution update x += sum_k gamma_k z_k: the
 // raw directions satisfy z_k = g_k zt_k + sum_{i<k} beta(i, k) zt_i with
 // A zt_k the normalised q_k, so gamma solves the upper-triangular system
@@ -491,6 +336,146 @@ void launch_gcr_backsub(double2* tri, int nk, int nrhs, int ld, hipStream_t st) 
   if (nk <= 0) return;
   gcr_backsub_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(tri, nk, nrhs, ld);
 }
+
+// ------------------------------------------- single-reduction GCR direction
+// Pass 1: <q_i, q_k>, <q_i, r> for i < k, |q_k|^2 and <q_k, r> (results
+// p = i, k + i, 2k, 2k + 1).  A block stages CH elements of each of the k + 2
+// vectors in LDS (every element fetched once); its four wavefronts take the
+// 2k + 2 products round-robin, at most nine accumulators each.
+template <typename T, int CH>
+__global__ void __launch_bounds__(256) gcr_dots_kernel(const GcrDotArgs<T> a, double2* __restrict__ part,
+                                                       int nblk) {
+  constexpr int PW = (2 * kMaxNK + 2 + 3) / 4;
+  __shared__ T vs[kMaxNK + 2][CH];
+  const int rr = blockIdx.y;
+  const int64_t off = (int64_t)rr * a.stride;
+  const int k = a.k, nv = k + 2, np = 2 * k + 2;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  double2 acc[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int64_t e0 = (int64_t)blockIdx.x * CH; e0 < a.n; e0 += (int64_t)nblk * CH) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nv * CH; idx += 256) {
+      const int v = idx / CH, el = idx - v * CH;
+      const T* src = v < k ? a.q[v] : (v == k ? a.qk : a.r);
+      const int64_t e = e0 + el;
+      T x{};
+      if (e < a.n) x = src[off + e];
+      vs[v][el] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      const int p = wave + 4 * q;
+      if (p < np) {
+        const int xi = p < k ? p : (p < 2 * k ? p - k : k);
+        const int yi = p < k ? k : (p < 2 * k ? k + 1 : (p == 2 * k ? k : k + 1));
+        for (int el = lane; el < CH; el += 64) cfmac(acc[q], to_d2(vs[xi][el]), to_d2(vs[yi][el]));
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    const int p = wave + 4 * q;
+    if (p < np) {
+      const double sx = wsum(acc[q].x), sy = wsum(acc[q].y);
+      if (lane == 0) part[((int64_t)p * a.nrhs + rr) * nblk + blockIdx.x] = make_double2(sx, sy);
+    }
+  }
+}
+
+template <typename T>
+void launch_gcr_dots(const GcrDotArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
+  constexpr int CH = sizeof(T) == 8 ? 256 : 128;   // 36 KiB of LDS either way
+  int64_t b = (a.n + 4 * CH - 1) / (4 * CH);
+  if (b < 1) b = 1;
+  if (b > 480) b = 480;
+  const int nblk = (int)b;
+  gcr_dots_kernel<T, CH><<<dim3(nblk, a.nrhs), 256, 0, st>>>(a, part, nblk);
+  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, 2 * a.k + 2, a.nrhs, res, ldr);
+}
+template void launch_gcr_dots<float2>(const GcrDotArgs<float2>&, double2*, double2*, int, hipStream_t);
+template void launch_gcr_dots<double2>(const GcrDotArgs<double2>&, double2*, double2*, int, hipStream_t);
+
+// Scalars of direction k from pass 1 (q_0..q_{k-1} orthonormal): the
+// projection coefficients beta_i = <q_i, q_k>, |q'|^2 = |q_k|^2 - sum |beta_i|^2
+// and <q', r> = <q_k, r> - sum conj(beta_i) <q_i, r> for q' = q_k - sum beta_i q_i.
+// g_k = |q'|, alpha'_k = <q', r> / g_k, alpha = <q', r> / g_k^2, inv = 1 / g_k.
+// A masked system, or a direction whose projection keeps less than 1e-10 of
+// |q_k|^2 (within the rounding of the sums), contributes nothing (g_k = 1,
+// alpha'_k = alpha = inv = 0).
+__global__ void gcr_scalars_cgs_kernel(const double2* dots, int k, const int* mask, int nrhs, int ld, double2* tri,
+                                       double2* alpha, double2* inv) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const double qq = dots[(int64_t)(2 * k) * ld + r].x;
+  double g2 = qq;
+  double2 qr = dots[(int64_t)(2 * k + 1) * ld + r];
+  for (int i = 0; i < k; ++i) {
+    const double2 b = dots[(int64_t)i * ld + r];
+    const double2 c = dots[(int64_t)(k + i) * ld + r];
+    tri[(int64_t)(i * kMaxNK + k) * ld + r] = b;
+    g2 -= b.x * b.x + b.y * b.y;
+    qr.x -= b.x * c.x + b.y * c.y;   // conj(b) c
+    qr.y -= b.x * c.y - b.y * c.x;
+  }
+  const bool on = (mask == nullptr || mask[r] != 0) && qq > 0.0 && qq < 1e300 && g2 > 1e-10 * qq;
+  const double g = on ? sqrt(g2) : 1.0;
+  tri[(int64_t)(kTriG + k) * ld + r] = make_double2(g, 0.0);
+  tri[(int64_t)(kTriA + k) * ld + r] = on ? make_double2(qr.x / g, qr.y / g) : make_double2(0.0, 0.0);
+  alpha[r] = on ? make_double2(qr.x / g2, qr.y / g2) : make_double2(0.0, 0.0);
+  inv[r] = make_double2(on ? 1.0 / g : 0.0, 0.0);
+}
+void launch_gcr_scalars_cgs(const double2* dots, int k, const int* mask, int nrhs, int ld, double2* tri,
+                            double2* alpha, double2* inv, hipStream_t st) {
+  gcr_scalars_cgs_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(dots, k, mask, nrhs, ld, tri, alpha, inv);
+}
+
+// Pass 2: q' = q_k - sum_i beta_i q_i, r -= alpha q', q_k <- inv q', the new r
+// optionally copied to znext, and partial sums of |r|^2
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(256) gcr_update_cgs_kernel(const GcrUpdArgs<T> a, double2* __restrict__ part,
+                                                             int nblk) {
+  __shared__ double red[4];
+  const int rr = blockIdx.y;
+  const int64_t off = (int64_t)rr * a.stride;
+  double2 b[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) b[i] = i < a.k ? a.beta[i][rr] : make_double2(0.0, 0.0);
+  const double2 al = a.alpha[rr];
+  const double iv = a.inv[rr].x;
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.n; e += (int64_t)nblk * 256) {
+    double2 qv = to_d2(a.qk[off + e]);
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < a.k) cfma(qv, make_double2(-b[i].x, -b[i].y), to_d2(a.q[i][off + e]));
+    double2 rv = to_d2(a.r[off + e]);
+    cfma(rv, make_double2(-al.x, -al.y), qv);
+    const T rt = from_d2<T>(rv);
+    a.r[off + e] = rt;
+    if (a.znext) a.znext[off + e] = rt;
+    a.qk[off + e] = from_d2<T>(make_double2(qv.x * iv, qv.y * iv));
+    const double2 rs = to_d2(rt);
+    s += rs.x * rs.x + rs.y * rs.y;
+  }
+  s = wsum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(int64_t)rr * nblk + blockIdx.x] = make_double2(red[0] + red[1] + red[2] + red[3], 0.0);
+}
+
+template <typename T>
+void launch_gcr_update_cgs(const GcrUpdArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
+  const int nblk = reduce_blocks(a.n);
+  dim3 grid(nblk, a.nrhs);
+  if (a.k <= 4) gcr_update_cgs_kernel<T, 4><<<grid, 256, 0, st>>>(a, part, nblk);
+  else gcr_update_cgs_kernel<T, kMaxNK><<<grid, 256, 0, st>>>(a, part, nblk);
+  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, 1, a.nrhs, res, ldr);
+}
+template void launch_gcr_update_cgs<float2>(const GcrUpdArgs<float2>&, double2*, double2*, int, hipStream_t);
+template void launch_gcr_update_cgs<double2>(const GcrUpdArgs<double2>&, double2*, double2*, int, hipStream_t);
 
 // Convergence on the device: mask[r] stays 1 while |r|^2 > tol^2 |r0|^2
 // (and both are finite); init sets mask from |r0|^2 > 0.

@@ -145,22 +145,26 @@ __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const C
   const int j = lane & 15, g = lane >> 4;
   for (int kc0 = 0; kc0 < kc_n; kc0 += kMfmaCK) {
     __syncthreads();   // neighbour table ready / previous pass consumed
-    // stage k in [32 kc0, 32 kc0 + KCH): element pairs (k, k + 1) lie in one
-    // direction (n is even); a wavefront covers one rhs row of the pass
-    for (int e = tid; e < NR * (KCH / 2); e += nthreads) {
-      const int jj = e / (KCH / 2);
-      const int kl = 2 * (e - jj * (KCH / 2));
+    // stage k in [32 kc0, 32 kc0 + KCH): quads (k .. k + 3) lie in one
+    // direction (n is a multiple of 16) and are two 16-byte loads (inputs are
+    // 16-byte aligned) and one 8-byte LDS store per plane
+    for (int e = tid; e < NR * (KCH / 4); e += nthreads) {
+      const int jj = e / (KCH / 4);
+      const int kl = 4 * (e - jj * (KCH / 4));
       const int k = kc0 * 32 + kl;
-      uint32_t pre = 0, pim = 0;
+      uint2 pre = make_uint2(0u, 0u), pim = make_uint2(0u, 0u);
       if (r0 + jj < a.nrhs && k < K) {
         const int d = k / n, col = k - d * n;
-        const float2* src = a.in + (int64_t)(r0 + jj) * a.in_stride + nbs[d] * n + col;
-        const float2 v0 = src[0], v1 = src[1];
-        pre = (uint32_t)to16<FMT>(v0.x) | ((uint32_t)to16<FMT>(v1.x) << 16);
-        pim = (uint32_t)to16<FMT>(v0.y) | ((uint32_t)to16<FMT>(v1.y) << 16);
+        const float4* src =
+            reinterpret_cast<const float4*>(a.in + (int64_t)(r0 + jj) * a.in_stride + nbs[d] * n + col);
+        const float4 v0 = src[0], v1 = src[1];
+        pre.x = (uint32_t)to16<FMT>(v0.x) | ((uint32_t)to16<FMT>(v0.z) << 16);
+        pre.y = (uint32_t)to16<FMT>(v1.x) | ((uint32_t)to16<FMT>(v1.z) << 16);
+        pim.x = (uint32_t)to16<FMT>(v0.y) | ((uint32_t)to16<FMT>(v0.w) << 16);
+        pim.y = (uint32_t)to16<FMT>(v1.y) | ((uint32_t)to16<FMT>(v1.w) << 16);
       }
-      *reinterpret_cast<uint32_t*>(Bre + jj * KPC + kl) = pre;
-      *reinterpret_cast<uint32_t*>(Bim + jj * KPC + kl) = pim;
+      *reinterpret_cast<uint2*>(Bre + jj * KPC + kl) = pre;
+      *reinterpret_cast<uint2*>(Bim + jj * KPC + kl) = pim;
     }
     __syncthreads();
 #pragma unroll
@@ -233,6 +237,8 @@ void launch_coarse_mfma(const CoarseMfmaArgs& a, int fmt, hipStream_t st) {
   if (a.nrhs <= 0) return;
   if (a.n % 16 || a.n < 16 || a.n > 16 * kMfmaMaxWaves)
     throw std::runtime_error("coarse_mfma: n must be a multiple of 16 in 16..256");
+  if (reinterpret_cast<uintptr_t>(a.in) % 16 || a.in_stride % 2)
+    throw std::runtime_error("coarse_mfma: input must be 16-byte aligned");
   if (fmt == 0) coarse_mfma_dispatch<0>(a, st);
   else coarse_mfma_dispatch<1>(a, st);
 }

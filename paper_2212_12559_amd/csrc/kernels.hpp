@@ -156,23 +156,27 @@ struct GramArgs {
   int64_t n, stride;
   int nrhs;
 };
-// <x_i, y> for i < nv
+// One reduction pass of a GCR direction: <q_i, q_k>, <q_i, r> (i < k), |q_k|^2, <q_k, r>
 template <typename T>
-struct MultiDotArgs {
-  const T* x[kMaxNK];
-  const T* y;
-  int nv;
+struct GcrDotArgs {
+  const T* q[kMaxNK];
+  const T* qk;
+  const T* r;
+  int k;
   int64_t n, stride;
   int nrhs;
 };
-// q <- q - sum_i beta_i x_i, then |q|^2 and <q, r>
+// q_k <- (q_k - sum_i beta_i q_i) inv, r <- r - alpha (q_k - sum_i beta_i q_i), znext <- r
 template <typename T>
-struct ProjArgs {
-  T* q;
-  const T* x[kMaxNK];
-  const double2* beta[kMaxNK];   // per-rhs device coefficients
-  const T* r;
-  int nv;
+struct GcrUpdArgs {
+  T* qk;
+  const T* q[kMaxNK];
+  const double2* beta[kMaxNK];
+  T* r;
+  T* znext;                      // optional copy of the new r (next direction of unpreconditioned GCR)
+  const double2* alpha;
+  const double2* inv;
+  int k;
   int64_t n, stride;
   int nrhs;
 };
@@ -206,16 +210,13 @@ void launch_cg_update(double2* x, double2* r, const double2* p, const double2* a
                       int nrhs, double2* part, double2* res, int ldr, hipStream_t st);
 template <typename T>
 void launch_gram(const GramArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st);
-template <typename T>
-void launch_multidot(const MultiDotArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st);
-template <typename T>
-void launch_project_dots(const ProjArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st);
-void launch_gcr_scalars_tri(const double2* qq, const double2* qr, const int* mask, int nrhs, int k, double2* tri,
-                            int ld, double2* alpha, double2* inv, hipStream_t st);
-template <typename T>
-void launch_gcr_update_r(T* r, T* q, const double2* alpha, const double2* inv, int64_t n, int nrhs, double2* part,
-                         double2* res, int ldr, hipStream_t st);
 void launch_gcr_backsub(double2* tri, int nk, int nrhs, int ld, hipStream_t st);
+template <typename T>
+void launch_gcr_dots(const GcrDotArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st);
+void launch_gcr_scalars_cgs(const double2* dots, int k, const int* mask, int nrhs, int ld, double2* tri,
+                            double2* alpha, double2* inv, hipStream_t st);
+template <typename T>
+void launch_gcr_update_cgs(const GcrUpdArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st);
 void launch_conv(int* mask, const double2* rn2, const double2* r0sq, double tol2, int nrhs, int init,
                  hipStream_t st);
 

@@ -589,9 +589,8 @@ bool Ctx::any_active(int lvl, int nsys) {
 // projection coefficients beta(i, k) = <q_i, A z_k>, the norm g_k and
 // alpha'_k = <q_k, r>, and the solution x = sum_k gamma_k z_k is formed once
 // at the end of a cycle from the triangular system they define.  Per step the
-// vector passes are: q_k = A z_k; the k coefficients (one pass reading q_k
-// once); the projection of q_k fused with |q_k|^2 and <q_k, r>; the update
-// of r and the normalisation of q_k.
+// vector passes are: q_k = A z_k; one reduction pass (classical Gram-Schmidt
+// coefficients with |q'|^2 from Pythagoras); one update pass.
 void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   LevelBufs& B = L[lvl];
   const bool coarsest = lvl == nlev - 1;
@@ -615,9 +614,9 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
     int nk = 0;
     for (int k = 0; k < maxit; ++k) {
       stats.level[lvl - 1] += 1;
-      if (coarsest) copy(B.z[k], B.r, nsys);
-      else kcycle(lvl, B.r, B.z[k], nsys, stats);
-      gcr_direction(lvl, B, k, nsys);
+      if (!coarsest) kcycle(lvl, B.r, B.z[k], nsys, stats);
+      else if (k == 0) copy(B.z[0], B.r, nsys);   // later directions come from the update pass
+      gcr_direction(lvl, B, k, nsys, coarsest && k + 1 < maxit ? B.z[k + 1].p : nullptr);
       nk = k + 1;
       launch_conv(lmask(lvl), slot(lvl, kSlotRN), r0, tol * tol, nsys, 0, st);
       check_launch();
@@ -629,34 +628,38 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   }
 }
 
-// Direction k of the deferred-update GCR (z_k already holds K(r)).
-void Ctx::gcr_direction(int lvl, LevelBufs& B, int k, int nsys) {
+// Direction k of the deferred-update GCR (z_k already holds K(r)): q_k = A z_k,
+// one reduction pass for every inner product the step needs (the projection
+// coefficients, |q_k|^2, <q_k, r> and <q_i, r>), the scalars, and one update
+// pass (projection, normalisation of q_k, r -= alpha q', |r|^2).  With znext
+// the new r is also written there (the next direction of unpreconditioned GCR).
+void Ctx::gcr_direction(int lvl, LevelBufs& B, int k, int nsys, void* znext) {
   const int prec = B.prec;
   const int64_t n = B.n;
   double2* T = tslot(lvl, 0);
   apply_level(lvl, B.q[k], B.z[k], nsys);
   auto run = [&](auto* tag) {
     using TP = std::remove_pointer_t<decltype(tag)>;
-    if (k > 0) {
-      MultiDotArgs<TP> md{};
-      for (int i = 0; i < k; ++i) md.x[i] = (const TP*)B.q[i].p;
-      md.y = (const TP*)B.q[k].p;
-      md.nv = k; md.n = n; md.stride = n; md.nrhs = nsys;
-      launch_multidot(md, part, T + (int64_t)k * max_sys, kMaxNK * max_sys, st);   // beta(i, k)
-    }
-    ProjArgs<TP> pa{};
-    pa.q = (TP*)B.q[k].p;
+    GcrDotArgs<TP> d{};
+    for (int i = 0; i < k; ++i) d.q[i] = (const TP*)B.q[i].p;
+    d.qk = (const TP*)B.q[k].p;
+    d.r = (const TP*)B.r.p;
+    d.k = k; d.n = n; d.stride = n; d.nrhs = nsys;
+    launch_gcr_dots(d, part, slot(lvl, 0), max_sys, st);
+    launch_gcr_scalars_cgs(slot(lvl, 0), k, lmask(lvl), nsys, max_sys, T, slot(lvl, kSlotQQ + 2),
+                           slot(lvl, kSlotQQ + 4), st);
+    GcrUpdArgs<TP> u{};
+    u.qk = (TP*)B.q[k].p;
     for (int i = 0; i < k; ++i) {
-      pa.x[i] = (const TP*)B.q[i].p;
-      pa.beta[i] = T + (int64_t)(i * kMaxNK + k) * max_sys;
+      u.q[i] = (const TP*)B.q[i].p;
+      u.beta[i] = T + (int64_t)(i * kMaxNK + k) * max_sys;
     }
-    pa.r = (const TP*)B.r.p;
-    pa.nv = k; pa.n = n; pa.stride = n; pa.nrhs = nsys;
-    launch_project_dots(pa, part, slot(lvl, kSlotQQ), max_sys, st);
-    launch_gcr_scalars_tri(slot(lvl, kSlotQQ), slot(lvl, kSlotQQ + 1), lmask(lvl), nsys, k, T, max_sys,
-                           slot(lvl, kSlotQQ + 2), slot(lvl, kSlotQQ + 4), st);
-    launch_gcr_update_r<TP>((TP*)B.r.p, (TP*)B.q[k].p, slot(lvl, kSlotQQ + 2), slot(lvl, kSlotQQ + 4), n, nsys,
-                            part, slot(lvl, kSlotRN), max_sys, st);
+    u.r = (TP*)B.r.p;
+    u.znext = (TP*)znext;
+    u.alpha = slot(lvl, kSlotQQ + 2);
+    u.inv = slot(lvl, kSlotQQ + 4);
+    u.k = k; u.n = n; u.stride = n; u.nrhs = nsys;
+    launch_gcr_update_cgs(u, part, slot(lvl, kSlotRN), max_sys, st);
   };
   if (prec == P64) run((double2*)nullptr);
   else run((float2*)nullptr);

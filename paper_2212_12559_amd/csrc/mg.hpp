@@ -134,7 +134,7 @@ struct Ctx {
   void kcycle(int lvl, const Vec& r, const Vec& e, int nsys, SolveStats& stats);
   void level_solve(int lvl, int nsys, SolveStats& stats);   // L[lvl].b -> L[lvl].x
   void gcr_step(int lvl, LevelBufs& B, const Vec& X, int k, int nsys);
-  void gcr_direction(int lvl, LevelBufs& B, int k, int nsys);
+  void gcr_direction(int lvl, LevelBufs& B, int k, int nsys, void* znext);
   void gcr_flush(int lvl, LevelBufs& B, int nk, int nsys, bool accumulate);
   void project(int prec, int64_t n, int nsys, LevelBufs& B, int k, const double2* beta);
   std::vector<double> read_norms(const double2* dev, int nsys);
