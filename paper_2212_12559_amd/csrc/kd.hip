@@ -187,6 +187,13 @@ __global__ void __launch_bounds__(256) kd_apply_mfma_kernel(const KdArgs<float> 
   const int slot = a.rhs_per_slot > 0 ? r0 / a.rhs_per_slot : 0;
   const float2* K = a.kinv + (int64_t)slot * a.slot_stride + hc * 2304;
   const float2* xin = a.in + (int64_t)(live ? r : 0) * a.in_stride;
+  // site of local index sl: the hypercube's origin (even coordinates, so the
+  // 2^4 cube never wraps) plus the unit offsets selected by the bits of sl
+  const int64_t s0 = hc_site(hc, 0, a.g);
+  const int64_t L0 = a.g.L[0], L01 = L0 * a.g.L[1], L012 = L01 * a.g.L[2];
+  auto site_of = [&](int sl) -> int64_t {
+    return s0 + (sl & 1) + ((sl >> 1) & 1) * L0 + ((sl >> 2) & 1) * L01 + (int64_t)(sl >> 3) * L012;
+  };
   float bre[12], bim[12];
 #pragma unroll
   for (int ks = 0; ks < 12; ++ks) {
@@ -194,7 +201,7 @@ __global__ void __launch_bounds__(256) kd_apply_mfma_kernel(const KdArgs<float> 
     const int sl = j / 3, col = j - 3 * (j / 3);
     float2 v = make_float2(0.f, 0.f);
     if (live) {
-      v = xin[hc_site(hc, sl, a.g) * 3 + col];
+      v = xin[site_of(sl) * 3 + col];
       if (a.eps_in && (__popc(sl) & 1)) { v.x = -v.x; v.y = -v.y; }
     }
     bre[ks] = v.x;
@@ -219,7 +226,7 @@ __global__ void __launch_bounds__(256) kd_apply_mfma_kernel(const KdArgs<float> 
         const int sl = i / 3, col = i - 3 * (i / 3);
         float2 v = make_float2(yr[t], yi[t]);
         if (a.eps_out && (__popc(sl) & 1)) { v.x = -v.x; v.y = -v.y; }
-        yout[hc_site(hc, sl, a.g) * 3 + col] = v;
+        yout[site_of(sl) * 3 + col] = v;
       }
     }
   }
