@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--coarse-prec", default=None, choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--nmass", type=int, default=None, help="solve only the first NMASS masses (profiling runs)")
     ap.add_argument("--setup-iters", default=None, help="CGNE iterations per level, e.g. 10,10 (kernel timing runs)")
+    ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
+                    help="override one solver parameter (mg_params field), e.g. coarsest_restarts=4")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="turn two rocprofv3 --pmc runs of --kernels-only (FETCH_SIZE, WRITE_SIZE) into the "
                          "committed traffic record of the dominant kernel, then exit")
@@ -308,6 +310,10 @@ def main():
     p = mg.default_params(dims, mass0=m, nvec=wl["nvec"], block=wl["blocks"], setup_maxiter=setup_iters,
                           max_nrhs=wl["nrhs"] * mb, max_nmass=len(masses), kd_naik=wl["kd_naik"], coarse_prec=cp,
                           outer_nkrylov=8 if wl["nrhs"] > 1 else 16)
+    for kv in args.set:
+        k, v = kv.split("=", 1)
+        setattr(p, k, type(getattr(p, k))(float(v)) if isinstance(getattr(p, k), float) else int(v))
+        log(f"[bench] parameter {k} = {getattr(p, k)}")
     log("[bench] setup")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
