@@ -37,20 +37,6 @@ __global__ void __launch_bounds__(256) dslash_kernel(const DslashArgs<R> a) {
     c[3] = (int)(rest / a.g.L[2]);
     c[0] = 2 * (int)(tid % hx) + ((c[1] + c[2] + c[3] + a.parity) & 1);
     s = site_index(c, a.g);
-  } else if (a.tb[0] > 0) {
-    // blocked order: a block is tb[0] x tb[1] x tb[2] sites of one time
-    // slice, and consecutive site blocks step in t first, then z, then y, so
-    // the +-t (and +-3t) neighbours of a block were fetched by the blocks just
-    // before it and are still in L2
-    const int nt = a.g.L[3], nz = a.g.L[2] / a.tb[2];
-    c[3] = (int)(sb % nt);
-    const int64_t rest = sb / nt;
-    const int zb = (int)(rest % nz), yb = (int)(rest / nz);
-    const int th = threadIdx.x;
-    c[0] = th % a.tb[0];
-    c[1] = yb * a.tb[1] + (th / a.tb[0]) % a.tb[1];
-    c[2] = zb * a.tb[2] + th / (a.tb[0] * a.tb[1]);
-    s = site_index(c, a.g);
   } else {
     s = tid;
     site_coords(s, a.g, c);
@@ -179,27 +165,9 @@ static void launch_nr(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hi
   }
 }
 
-// Blocked site order of the full-lattice stencil: whole x rows, a y x z patch
-// making 256 sites (z extent 2 or more when it divides), or linear order when
-// the lattice does not tile that way.
-static void blocked_order(const Geom& g, int tb[3]) {
-  tb[0] = tb[1] = tb[2] = 0;
-  if (g.L[0] > 256 || 256 % g.L[0]) return;
-  const int rem = 256 / g.L[0];
-  for (int by = rem / 2 > 0 ? rem / 2 : 1; by >= 1; --by) {
-    const int bz = rem / by;
-    if (rem % by || g.L[1] % by || bz > g.L[2] || g.L[2] % bz) continue;
-    tb[0] = g.L[0]; tb[1] = by; tb[2] = bz;
-    return;
-  }
-}
-
 template <typename R>
-void launch_dslash(const DslashArgs<R>& a0, bool naik, bool cb, bool piece, hipStream_t st) {
-  if (a0.nrhs <= 0 || a0.g.V <= 0) return;
-  DslashArgs<R> a = a0;
-  if (!cb) blocked_order(a.g, a.tb);
-  else a.tb[0] = a.tb[1] = a.tb[2] = 0;
+void launch_dslash(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st) {
+  if (a.nrhs <= 0 || a.g.V <= 0) return;
   if (a.nrhs == 1) launch_nr<R, 1>(a, naik, cb, piece, st);
   else if (a.nrhs < 8) launch_nr<R, 4>(a, naik, cb, piece, st);
   else launch_nr<R, 8>(a, naik, cb, piece, st);

@@ -25,7 +25,6 @@ struct DslashArgs {
   int piece;                // Galerkin piece: 0 self, 1 + 2 mu (+mu face), 2 + 2 mu (-mu face)
   int blk[4];               // aggregation block of the piece decomposition
   int eps_out;              // multiply the result by epsilon(x)
-  int tb[3];                // full-lattice mode: site-block extents (x, y, z) of the blocked order, 0 = linear
 };
 template <typename R>
 void launch_dslash(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st);
