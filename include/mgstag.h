@@ -137,9 +137,10 @@ mg_status mg_setup(const mg_params* p, const void* fat, const void* naik, const 
  *   op 0: D(m) x                        (Sec. 2.2; HISQ stencil)
  *   op 1: A x = (B + m)^{-1} D x        (Sec. 2.2 Eq. 2, Sec. 3.1; Naik per kd_naik)
  *   op 2: (B + m)^{-1} x                (the KD block inverse alone, Sec. 3.1)
- *   op 3: D(m)^dag x
- * For ops 1 and 2, mass must have a KD inverse (mass0 or a mass of an
- * earlier mg_solve); MG_E_ARG otherwise. */
+ *   op 3: D(m)^dag x = eps D eps x
+ *   op 4: A^dag x = eps D (B + m)^{-1} eps x   (the adjoint used by the CGNE set-up)
+ * For ops 1, 2 and 4 the KD inverse of mass is built on first use, in a free
+ * mass slot or, when every slot is taken, in slot 0. */
 mg_status mg_apply_dslash(mg_ctx ctx, int32_t op, double mass, int32_t dtype, const void* in, void* out,
                           int32_t nrhs, void* stream);
 

@@ -133,7 +133,7 @@ mg_status mg_apply_dslash(mg_ctx ctx, int32_t op, double mass, int32_t dtype, co
   Ctx& c = ctx->c;
   mg_status s = check_vec(dtype, in, out, nrhs, c.P.max_nrhs);
   if (s != MG_OK) return s;
-  if (op < 0 || op > 3) return fail(MG_E_ARG, "op must be 0..3");
+  if (op < 0 || op > 4) return fail(MG_E_ARG, "op must be 0..4");
   if (!std::isfinite(mass)) return fail(MG_E_ARG, "mass must be finite");
   c.st = (hipStream_t)stream;
   const int prec = dtype == MG_C128 ? P64 : P32;
@@ -150,7 +150,11 @@ mg_status mg_apply_dslash(mg_ctx ctx, int32_t op, double mass, int32_t dtype, co
       c.ensure_kd(std::vector<double>{mass});
       c.rhs_per_slot = 0;
       const int64_t off = (int64_t)c.kd_base * c.kinv_slot;
-      if (op == 2) {
+      if (op == 4) {
+        // A^dag = eps D (B + m)^{-1} eps
+        c.apply_KD(prec, tmp, in, nrhs, true, false, 0);
+        c.apply_D(prec, out, tmp, nrhs, c.P.kd_naik != 0, nullptr, mass, true);
+      } else if (op == 2) {
         if (prec == P64) {
           KdArgs<double> a{};
           a.out = (double2*)out; a.in = (const double2*)in; a.kinv = c.kinv64 + off; a.g = c.g0;

@@ -232,6 +232,80 @@ __global__ void __launch_bounds__(256) kd_apply_mfma_kernel(const KdArgs<float> 
   }
 }
 
+// Blocks of four x-adjacent hypercubes: the 16-rhs input tile (per rhs, eight
+// 192-byte rows of 8 sites) is loaded with 16-byte coalesced loads into LDS,
+// the matrix-core product runs as above, and the result leaves through LDS
+// with the same coalesced stores.  Needs (L0 / 2) % 4 == 0.
+__global__ void __launch_bounds__(256) kd_apply_mfma_lds_kernel(const KdArgs<float> a) {
+  __shared__ float2 xs[16][4][49];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t hc0 = xcd_block(blockIdx.x, gridDim.x) * 4;
+  const int64_t hc = hc0 + wave;
+  const int r0 = blockIdx.y * 16;
+  const int slot = a.rhs_per_slot > 0 ? r0 / a.rhs_per_slot : 0;
+  const int64_t L0 = a.g.L[0], L01 = L0 * a.g.L[1], L012 = L01 * a.g.L[2];
+  const int64_t s0 = hc_site(hc0, 0, a.g);
+  for (int it = tid; it < 16 * 8 * 12; it += 256) {
+    const int q = it % 12, rho = (it / 12) % 8, rr = it / 96;
+    const int64_t rs = s0 + ((rho & 1) ? L0 : 0) + ((rho & 2) ? L01 : 0) + ((rho & 4) ? L012 : 0);
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r0 + rr < a.nrhs) v = *reinterpret_cast<const float4*>(a.in + (int64_t)(r0 + rr) * a.in_stride + rs * 3 + 2 * q);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int fl = 2 * q + e, xo = fl / 3, col = fl - 3 * (fl / 3);
+      const int sl = (xo & 1) | (rho << 1);
+      float2 c = e ? make_float2(v.z, v.w) : make_float2(v.x, v.y);
+      if (a.eps_in && (__popc(sl) & 1)) { c.x = -c.x; c.y = -c.y; }
+      xs[rr][xo >> 1][sl * 3 + col] = c;
+    }
+  }
+  __syncthreads();
+  const int rl = lane & 15, kq = lane >> 4;
+  const float2* K = a.kinv + (int64_t)slot * a.slot_stride + hc * 2304;
+  float bre[12], bim[12];
+#pragma unroll
+  for (int ks = 0; ks < 12; ++ks) {
+    const float2 v = xs[rl][wave][4 * ks + kq];
+    bre[ks] = v.x;
+    bim[ks] = v.y;
+  }
+  f32x4 yr[3], yi[3];
+#pragma unroll
+  for (int mt = 0; mt < 3; ++mt) {
+    yr[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    yi[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 12; ++ks) {
+      const float2 k = K[(4 * ks + kq) * 48 + 16 * mt + rl];
+      yr[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(k.x, bre[ks], yr[mt], 0, 0, 0);
+      yr[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-k.y, bim[ks], yr[mt], 0, 0, 0);
+      yi[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(k.x, bim[ks], yi[mt], 0, 0, 0);
+      yi[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(k.y, bre[ks], yi[mt], 0, 0, 0);
+    }
+  }
+  __syncthreads();   // every wavefront has read its inputs
+#pragma unroll
+  for (int mt = 0; mt < 3; ++mt)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) xs[rl][wave][16 * mt + 4 * kq + t] = make_float2(yr[mt][t], yi[mt][t]);
+  __syncthreads();
+  for (int it = tid; it < 16 * 8 * 12; it += 256) {
+    const int q = it % 12, rho = (it / 12) % 8, rr = it / 96;
+    if (r0 + rr >= a.nrhs) continue;
+    const int64_t rs = s0 + ((rho & 1) ? L0 : 0) + ((rho & 2) ? L01 : 0) + ((rho & 4) ? L012 : 0);
+    float2 c[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int fl = 2 * q + e, xo = fl / 3, col = fl - 3 * (fl / 3);
+      const int sl = (xo & 1) | (rho << 1);
+      c[e] = xs[rr][xo >> 1][sl * 3 + col];
+      if (a.eps_out && (__popc(sl) & 1)) { c[e].x = -c[e].x; c[e].y = -c[e].y; }
+    }
+    *reinterpret_cast<float4*>(a.out + (int64_t)(r0 + rr) * a.out_stride + rs * 3 + 2 * q) =
+        make_float4(c[0].x, c[0].y, c[1].x, c[1].y);
+  }
+}
+
 template <typename R>
 void launch_kd_apply(const KdArgs<R>& a, hipStream_t st) {
   if (a.nrhs <= 0) return;
@@ -242,7 +316,10 @@ void launch_kd_apply(const KdArgs<R>& a, hipStream_t st) {
   const bool tile4 = a.nrhs >= 4 && (a.rhs_per_slot <= 0 || a.rhs_per_slot % 4 == 0);
   if (tile16) {
     dim3 grid(gx, (unsigned)((a.nrhs + 15) / 16));
-    if constexpr (sizeof(R) == 4) kd_apply_mfma_kernel<<<grid, 256, 0, st>>>(a);
+    if constexpr (sizeof(R) == 4) {
+      if ((a.g.L[0] / 2) % 4 == 0 && nhc % 4 == 0) kd_apply_mfma_lds_kernel<<<grid, 256, 0, st>>>(a);
+      else kd_apply_mfma_kernel<<<grid, 256, 0, st>>>(a);
+    }
     else kd_apply_kernel<R, 16><<<grid, 256, 0, st>>>(a);
   } else if (tile8) {
     dim3 grid(gx, (unsigned)((a.nrhs + 7) / 8));

@@ -120,7 +120,10 @@ def test_dslash_parity(case, prec, nrhs):
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_kd_parity(case, prec):
-    """(B+m)^{-1} x and A x = (B+m)^{-1} D x (Naik kept or truncated per config)."""
+    """(B+m)^{-1} x, A x = (B+m)^{-1} D x (Naik kept or truncated per config) and
+    A^dag x = eps D (B+m)^{-1} eps x.  At 21 rhs FP32 runs the 16-rhs matrix-core
+    path: with LDS-staged inputs where four hypercubes line up in x (8^4 and the
+    ragged lattice), directly otherwise (4^4)."""
     torch = case.torch
     dt = torch.complex128 if prec == "c128" else torch.complex64
     tol = TOL64 if prec == "c128" else TOL32
@@ -131,11 +134,14 @@ def test_kd_parity(case, prec):
     log(f"[kd] {case.name} {prec}")
     yk = case.back(case.ctx.apply_dslash(2, m, case.to_gpu(x, dt)))
     ya = case.back(case.ctx.apply_dslash(1, m, case.to_gpu(x, dt)))
+    yd = case.back(case.ctx.apply_dslash(4, m, case.to_gpu(x, dt)))
     c3kd = cfg["c3"] if cfg["kd_naik"] else 0.0
     for r in range(21):
         assert rel_err(yk[r], ops.kd_apply(case.H.Kinv, x[r])) < tol
         want = ops.kd_operator(x[r], case.W, case.N, case.H.Kinv, m, cfg["c1"], c3kd)
         assert rel_err(ya[r], want) < tol
+        want = ops.kd_operator_dagger(x[r], case.W, case.N, case.H.Kinv, m, cfg["c1"], c3kd)
+        assert rel_err(yd[r], want) < tol
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
