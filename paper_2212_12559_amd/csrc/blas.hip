@@ -3,6 +3,8 @@
 // device as one double2 per (slot, rhs), so the drivers never wait on the host
 // except for their convergence tests.  All reductions accumulate in FP64 and
 // combine their per-block partial sums in a fixed order (bit-reproducible).
+#include <stdexcept>
+
 #include "kernels.hpp"
 
 namespace mg {
@@ -10,6 +12,25 @@ namespace mg {
 __device__ __forceinline__ double wsum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// Elements e and e + 1 (e even) of a vector: one 16-byte access for FP32
+// complex (vectors and per-system offsets are even and 16-byte aligned).
+__device__ __forceinline__ void ld2(const float2* p, int64_t e, double2& a, double2& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p + e);
+  a = make_double2(v.x, v.y);
+  b = make_double2(v.z, v.w);
+}
+__device__ __forceinline__ void ld2(const double2* p, int64_t e, double2& a, double2& b) {
+  a = p[e];
+  b = p[e + 1];
+}
+__device__ __forceinline__ void st2(float2* p, int64_t e, double2 a, double2 b) {
+  *reinterpret_cast<float4*>(p + e) = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+}
+__device__ __forceinline__ void st2(double2* p, int64_t e, double2 a, double2 b) {
+  p[e] = a;
+  p[e + 1] = b;
 }
 
 // partial sums of <x_p, y_p> (conjugate on x) for p < np
@@ -80,11 +101,10 @@ template void launch_pairdot<float2>(const PairDotArgs<float2>&, double2*, doubl
 template void launch_pairdot<double2>(const PairDotArgs<double2>&, double2*, double2*, int, hipStream_t);
 
 // out = sum_t coef_t(r) v_t  (out may alias one of the v_t); MAXT bounds the
-// term count (registers), TWO adds the second output over v2; each thread
-// keeps U elements in flight (two for short single-output combinations)
+// term count (registers), TWO adds the second output over v2.  A thread
+// handles element pairs (n is even).
 template <typename T, int MAXT, bool TWO>
 __global__ void __launch_bounds__(256) lincomb_kernel(const LinCombArgs<T> a) {
-  constexpr int U = (MAXT <= 4 && !TWO) ? 2 : 1;
   const int r = blockIdx.y;
   const int64_t off = (int64_t)r * a.stride;
   double2 cf[MAXT];
@@ -99,32 +119,26 @@ __global__ void __launch_bounds__(256) lincomb_kernel(const LinCombArgs<T> a) {
       cf[t] = c;
     }
   }
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t e0 = (int64_t)blockIdx.x * 256 + threadIdx.x; e0 < a.n; e0 += stride * U) {
-    double2 acc[U], acc2[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) { acc[u] = make_double2(0.0, 0.0); acc2[u] = make_double2(0.0, 0.0); }
+  const int64_t npair = a.n / 2;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < npair; q += (int64_t)gridDim.x * 256) {
+    const int64_t e = off + 2 * q;
+    double2 acc0 = make_double2(0.0, 0.0), acc1 = acc0, bcc0 = acc0, bcc1 = acc0;
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) {
       if (t < a.nt) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int64_t e = e0 + u * stride;
-          if (e < a.n) {
-            cfma(acc[u], cf[t], to_d2(a.v[t][off + e]));
-            if (TWO) cfma(acc2[u], cf[t], to_d2(a.v2[t][off + e]));
-          }
+        double2 v0, v1;
+        ld2(a.v[t], e, v0, v1);
+        cfma(acc0, cf[t], v0);
+        cfma(acc1, cf[t], v1);
+        if (TWO) {
+          ld2(a.v2[t], e, v0, v1);
+          cfma(bcc0, cf[t], v0);
+          cfma(bcc1, cf[t], v1);
         }
       }
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t e = e0 + u * stride;
-      if (e < a.n) {
-        a.out[off + e] = from_d2<T>(acc[u]);
-        if (TWO) a.out2[off + e] = from_d2<T>(acc2[u]);
-      }
-    }
+    st2(a.out, e, acc0, acc1);
+    if (TWO) st2(a.out2, e, bcc0, bcc1);
   }
 }
 
@@ -136,7 +150,8 @@ static void lincomb_launch(const LinCombArgs<T>& a, dim3 grid, hipStream_t st) {
 
 template <typename T>
 void launch_lincomb(const LinCombArgs<T>& a, hipStream_t st) {
-  int64_t b = (a.n + 511) / 512;
+  if (a.n % 2 || a.stride % 2) throw std::runtime_error("lincomb: vector lengths must be even");
+  int64_t b = (a.n / 2 + 255) / 256;
   if (b > 1024) b = 1024;
   if (b < 1) b = 1;
   dim3 grid((unsigned)b, a.nrhs);
@@ -261,14 +276,18 @@ __global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2*
 #pragma unroll
   for (int q = 0; q < PW; ++q) acc[q] = make_double2(0.0, 0.0);
   for (int64_t e0 = (int64_t)blockIdx.x * 256; e0 < a.n; e0 += (int64_t)nblk * 256) {
-    const int64_t e = e0 + threadIdx.x;
     __syncthreads();
+    if (threadIdx.x < 128) {   // element pairs, one 16-byte load each for FP32
+      const int el = 2 * threadIdx.x;
+      const int64_t e = e0 + el;
 #pragma unroll
-    for (int i = 0; i <= S; ++i) {
-      T v{};
-      const int src = i < S ? i : s;
-      if ((i < s || i == S) && e < a.n) v = a.u[src][off + e];
-      us[i][threadIdx.x] = v;
+      for (int i = 0; i <= S; ++i) {
+        double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+        const int src = i < S ? i : s;
+        if ((i < s || i == S) && e < a.n) ld2(a.u[src], off + e, v0, v1);
+        us[i][el] = from_d2<T>(v0);
+        us[i][el + 1] = from_d2<T>(v1);
+      }
     }
     __syncthreads();
 #pragma unroll 1
@@ -305,6 +324,7 @@ __global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2*
 
 template <typename T>
 void launch_gram(const GramArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
+  if (a.n % 2 || a.stride % 2) throw std::runtime_error("gram: vector lengths must be even");
   const int nblk = reduce_blocks(a.n);
   gram_kernel<T><<<dim3(nblk, a.nrhs), 256, 0, st>>>(a, part, nblk);
   finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, a.s * (a.s + 1) / 2 + a.s, a.nrhs, res, ldr);
@@ -356,13 +376,14 @@ __global__ void __launch_bounds__(256) gcr_dots_kernel(const GcrDotArgs<T> a, do
   for (int q = 0; q < PW; ++q) acc[q] = make_double2(0.0, 0.0);
   for (int64_t e0 = (int64_t)blockIdx.x * CH; e0 < a.n; e0 += (int64_t)nblk * CH) {
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nv * CH; idx += 256) {
-      const int v = idx / CH, el = idx - v * CH;
+    for (int idx = threadIdx.x; idx < nv * (CH / 2); idx += 256) {   // element pairs
+      const int v = idx / (CH / 2), el = 2 * (idx - v * (CH / 2));
       const T* src = v < k ? a.q[v] : (v == k ? a.qk : a.r);
       const int64_t e = e0 + el;
-      T x{};
-      if (e < a.n) x = src[off + e];
-      vs[v][el] = x;
+      double2 x0 = make_double2(0.0, 0.0), x1 = x0;
+      if (e < a.n) ld2(src, off + e, x0, x1);
+      vs[v][el] = from_d2<T>(x0);
+      vs[v][el + 1] = from_d2<T>(x1);
     }
     __syncthreads();
 #pragma unroll
@@ -388,6 +409,7 @@ __global__ void __launch_bounds__(256) gcr_dots_kernel(const GcrDotArgs<T> a, do
 template <typename T>
 void launch_gcr_dots(const GcrDotArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
   constexpr int CH = sizeof(T) == 8 ? 256 : 128;   // 36 KiB of LDS either way
+  if (a.n % 2 || a.stride % 2) throw std::runtime_error("gcr_dots: vector lengths must be even");
   int64_t b = (a.n + 4 * CH - 1) / (4 * CH);
   if (b < 1) b = 1;
   if (b > 480) b = 480;
@@ -446,19 +468,29 @@ __global__ void __launch_bounds__(256) gcr_update_cgs_kernel(const GcrUpdArgs<T>
   const double2 al = a.alpha[rr];
   const double iv = a.inv[rr].x;
   double s = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.n; e += (int64_t)nblk * 256) {
-    double2 qv = to_d2(a.qk[off + e]);
+  const int64_t npair = a.n / 2;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < npair; q += (int64_t)nblk * 256) {
+    const int64_t e = off + 2 * q;
+    double2 qv[2], rv[2], x[2];
+    ld2(a.qk, e, qv[0], qv[1]);
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-      if (i < a.k) cfma(qv, make_double2(-b[i].x, -b[i].y), to_d2(a.q[i][off + e]));
-    double2 rv = to_d2(a.r[off + e]);
-    cfma(rv, make_double2(-al.x, -al.y), qv);
-    const T rt = from_d2<T>(rv);
-    a.r[off + e] = rt;
-    if (a.znext) a.znext[off + e] = rt;
-    a.qk[off + e] = from_d2<T>(make_double2(qv.x * iv, qv.y * iv));
-    const double2 rs = to_d2(rt);
-    s += rs.x * rs.x + rs.y * rs.y;
+    for (int i = 0; i < MAXV; ++i) {
+      if (i < a.k) {
+        ld2(a.q[i], e, x[0], x[1]);
+        cfma(qv[0], make_double2(-b[i].x, -b[i].y), x[0]);
+        cfma(qv[1], make_double2(-b[i].x, -b[i].y), x[1]);
+      }
+    }
+    ld2(a.r, e, rv[0], rv[1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      cfma(rv[h], make_double2(-al.x, -al.y), qv[h]);
+      rv[h] = to_d2(from_d2<T>(rv[h]));   // the stored value
+      s += rv[h].x * rv[h].x + rv[h].y * rv[h].y;
+    }
+    st2(a.r, e, rv[0], rv[1]);
+    if (a.znext) st2(a.znext, e, rv[0], rv[1]);
+    st2(a.qk, e, make_double2(qv[0].x * iv, qv[0].y * iv), make_double2(qv[1].x * iv, qv[1].y * iv));
   }
   s = wsum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -468,7 +500,8 @@ __global__ void __launch_bounds__(256) gcr_update_cgs_kernel(const GcrUpdArgs<T>
 
 template <typename T>
 void launch_gcr_update_cgs(const GcrUpdArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
-  const int nblk = reduce_blocks(a.n);
+  if (a.n % 2 || a.stride % 2) throw std::runtime_error("gcr_update: vector lengths must be even");
+  const int nblk = reduce_blocks(a.n / 2);
   dim3 grid(nblk, a.nrhs);
   if (a.k <= 4) gcr_update_cgs_kernel<T, 4><<<grid, 256, 0, st>>>(a, part, nblk);
   else gcr_update_cgs_kernel<T, kMaxNK><<<grid, 256, 0, st>>>(a, part, nblk);
