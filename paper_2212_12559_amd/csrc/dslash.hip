@@ -148,6 +148,142 @@ __global__ void __launch_bounds__(256) dslash_kernel(const DslashArgs<R> a) {
   }
 }
 
+// One-hop full-lattice stencil with the in-plane neighbours taken from LDS: a
+// workgroup owns RB = 256 / L0 consecutive x-rows (a y range at fixed z, t)
+// and NR right-hand sides.  The rows y0 - 1 .. y0 + RB of every right-hand side
+// are staged with 16-byte loads, so the own, +-x and +-y spinors come from LDS
+// and only the +-z, +-t neighbours and the links are read per site (the
+// per-site reads are what bound the plain kernel: address processing, not
+// bytes).
+template <int NR>
+__global__ void __launch_bounds__(256) dslash_plane_kernel(const DslashArgs<float> a) {
+  using T = float2;
+  extern __shared__ float4 lds4[];
+  T* xs = reinterpret_cast<T*>(lds4);   // [NR][RB + 2][L0 * 3]
+  const int L0 = a.g.L[0], L1 = a.g.L[1], L2 = a.g.L[2];
+  const int RB = 256 / L0, rowc = 3 * L0;
+  const int64_t V = a.g.V;
+  const int ntile = (a.nrhs + NR - 1) / NR;
+  const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t pb = b / ntile;
+  const int r0 = (int)(b - pb * ntile) * NR;
+  const int nr = (a.nrhs - r0) < NR ? (a.nrhs - r0) : NR;
+  const int nyb = L1 / RB;
+  const int yb = (int)(pb % nyb);
+  const int64_t zt = pb / nyb;
+  const int z = (int)(zt % L2), t = (int)(zt / L2);
+  const int y0 = yb * RB;
+  const int nq = rowc / 2;   // 16-byte pieces per row (L0 even)
+  for (int it = threadIdx.x; it < NR * (RB + 2) * nq; it += 256) {
+    const int q = it % nq, rw = (it / nq) % (RB + 2), rr = it / (nq * (RB + 2));
+    const int y = (y0 - 1 + rw + L1) % L1;
+    const int64_t rs = (((int64_t)t * L2 + z) * L1 + y) * L0;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (rr < nr) v = *reinterpret_cast<const float4*>(a.in + (int64_t)(r0 + rr) * a.in_stride + rs * 3 + 2 * q);
+    T* d = xs + ((int64_t)rr * (RB + 2) + rw) * rowc + 2 * q;
+    d[0] = make_float2(v.x, v.y);
+    d[1] = make_float2(v.z, v.w);
+  }
+  __syncthreads();
+  const int x = threadIdx.x % L0, yr = threadIdx.x / L0;
+  int c[4] = {x, y0 + yr, z, t};
+  const int64_t s = site_index(c, a.g);
+  // LDS position of a spinor in the staged rows
+  auto at = [&](int r, int row, int col) -> const T* { return xs + ((int64_t)r * (RB + 2) + row) * rowc + col * 3; };
+  T acc[NR][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { acc[r][i].x = 0; acc[r][i].y = 0; }
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const T* L = a.fat + (int64_t)mu * 9 * V;
+    {   // forward hop: W'(x) x(x + mu)
+      const int64_t sf = mu >= 2 ? site_shift(c, mu, 1, a.g) : 0;
+      T U[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) U[k] = L[k * V + s];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r < nr) {
+          T v0, v1, v2;
+          if (mu < 2) {
+            const T* p = mu == 0 ? at(r, yr + 1, (x + 1) % L0) : at(r, yr + 2, x);
+            v0 = p[0]; v1 = p[1]; v2 = p[2];
+          } else {
+            const T* p = a.in + (int64_t)(r0 + r) * a.in_stride + sf * 3;
+            v0 = p[0]; v1 = p[1]; v2 = p[2];
+          }
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            cfma(acc[r][i], U[3 * i + 0], v0);
+            cfma(acc[r][i], U[3 * i + 1], v1);
+            cfma(acc[r][i], U[3 * i + 2], v2);
+          }
+        }
+      }
+    }
+    {   // backward hop: -W'(x - mu)^dag x(x - mu)
+      const int64_t sb = site_shift(c, mu, -1, a.g);
+      T U[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) U[k] = L[k * V + sb];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r < nr) {
+          T v0, v1, v2;
+          if (mu < 2) {
+            const T* p = mu == 0 ? at(r, yr + 1, (x + L0 - 1) % L0) : at(r, yr, x);
+            v0 = p[0]; v1 = p[1]; v2 = p[2];
+          } else {
+            const T* p = a.in + (int64_t)(r0 + r) * a.in_stride + sb * 3;
+            v0 = p[0]; v1 = p[1]; v2 = p[2];
+          }
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            T tt; tt.x = 0; tt.y = 0;
+            cfmac(tt, U[0 + i], v0);
+            cfmac(tt, U[3 + i], v1);
+            cfmac(tt, U[6 + i], v2);
+            acc[r][i].x -= tt.x;
+            acc[r][i].y -= tt.y;
+          }
+        }
+      }
+    }
+  }
+  const float sg = (a.eps_out && site_parity(c)) ? -1.f : 1.f;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nr) continue;
+    const float m = a.mass_rhs ? a.mass_rhs[r0 + r] : a.mass;
+    const T* xin = at(r, yr + 1, x);
+    const int64_t o = (int64_t)(r0 + r) * a.out_stride + s * 3;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T res = acc[r][i];
+      res.x = fmaf(m, xin[i].x, res.x);
+      res.y = fmaf(m, xin[i].y, res.y);
+      res.x *= sg;
+      res.y *= sg;
+      a.out[o + i] = res;
+    }
+  }
+}
+
+template <int NR>
+static bool launch_plane(const DslashArgs<float>& a, hipStream_t st) {
+  const int L0 = a.g.L[0];
+  if (L0 > 256 || 256 % L0 || a.g.L[1] % (256 / L0)) return false;
+  const int RB = 256 / L0;
+  const size_t lds = (size_t)NR * (RB + 2) * 3 * L0 * sizeof(float2);
+  if (lds > 65536) return false;
+  const int64_t nplane = a.g.V / 256;
+  dim3 grid((unsigned)(nplane * ((a.nrhs + NR - 1) / NR)));
+  dslash_plane_kernel<NR><<<grid, 256, lds, st>>>(a);
+  return true;
+}
+
 template <typename R, int NR>
 static void launch_nr(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st) {
   const int64_t nout = cb ? a.g.V / 2 : a.g.V;
@@ -168,6 +304,16 @@ static void launch_nr(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hi
 template <typename R>
 void launch_dslash(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st) {
   if (a.nrhs <= 0 || a.g.V <= 0) return;
+  if constexpr (sizeof(R) == 4) {
+    // one-hop FP32 full-lattice stencil: in-plane neighbours through LDS
+    if (!naik && !cb && !piece && (uintptr_t)a.in % 16 == 0 && a.in_stride % 2 == 0) {
+      bool done;
+      // 4-rhs tiles: at 8 the LDS tile (61 KB) leaves two workgroups per CU
+      if (a.nrhs == 1) done = launch_plane<1>(a, st);
+      else done = launch_plane<4>(a, st);
+      if (done) return;
+    }
+  }
   if (a.nrhs == 1) launch_nr<R, 1>(a, naik, cb, piece, st);
   else if (a.nrhs < 8) launch_nr<R, 4>(a, naik, cb, piece, st);
   else launch_nr<R, 8>(a, naik, cb, piece, st);
