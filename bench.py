@@ -35,6 +35,10 @@ WORKLOADS = {
                     nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 300),
                     masses=(0.005, 0.0084691, 0.014345, 0.024298, 0.041156, 0.069711, 0.11808, 0.2),
                     coarse_prec="bf16", mass_batch=4),
+    # fermion force (the HMC gradient of phi^dag (D^dag D)^-1 phi) at 24^4 HISQ-style, mass 0.01, one phi
+    "force24": dict(dims=(24, 24, 24, 24), mass=0.01, nrhs=1, eps=0.5, seed=20221228, kd_naik=0,
+                    nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 300), kind="force",
+                    coarse_prec="bf16"),
     # 16^4 HISQ-style, mass 0.01
     "c1": dict(dims=(16, 16, 16, 16), mass=0.01, nrhs=1, eps=0.5, seed=20221225, kd_naik=0,
                nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 2000)),
@@ -263,6 +267,68 @@ def cpu_baseline(wl, batch_infos, s):
                          "coarse": t_c2}}
 
 
+def force_bench(args, wl, torch, latgen, mg):
+    """Fermion force at the workload's lattice: mg_solve_backward (two MG
+    solves and the outer-product kernel) timed over the steps, then the
+    gradient checked at full size by a central finite difference of the
+    action along a random direction of the fat links (the property
+    dS = Re sum conj(G) dW holds at any size)."""
+    dims, m = wl["dims"], wl["mass"]
+    dev = "cuda:0"
+    log(f"[bench] force workload {dims} mass {m}: generating links")
+    W, N, rng = latgen.hisq_style_links(dims, wl["eps"], wl["seed"])
+    phi = torch.from_numpy(latgen.fine_vectors(dims, wl["nrhs"], rng)).to(dev)
+    dW = torch.from_numpy(latgen.complex_normal(rng, W.shape)).to(dev)
+    Wt, Nt = torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev)
+    del W, N
+    cp = {"fp32": mg.MG_C64, "bf16": mg.MG_CBF16, "fp16": mg.MG_CF16}[args.coarse_prec or wl.get("coarse_prec", "fp32")]
+    setup_iters = tuple(int(v) for v in args.setup_iters.split(",")) if args.setup_iters else wl["setup_iters"]
+    p = mg.default_params(dims, mass0=m, nvec=wl["nvec"], block=wl["blocks"], setup_maxiter=setup_iters,
+                          max_nrhs=wl["nrhs"], kd_naik=wl["kd_naik"], coarse_prec=cp)
+    log("[bench] setup")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = mg.setup(p, Wt, Nt)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"[bench] setup {setup_s:.2f} s")
+    for i in range(args.warmup):
+        ctx.solve_backward(m, phi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        X, Y, gw, gn, info = ctx.solve_backward(m, phi)
+        res = ", ".join(f"{d['true_rel_residual']:.2e}" for d in info)
+        log(f"[bench] step {i}: outer {[d['outer_iters'] for d in info]}, residuals {res}")
+    torch.cuda.synchronize()
+    t_force = (time.perf_counter() - t0) / args.steps
+    S0 = float(torch.sum(torch.conj(phi) * X).real)
+    # directional derivative along dW (fat links only) by central differences
+    h = 1e-3 * float(torch.linalg.vector_norm(Wt)) / float(torch.linalg.vector_norm(dW))
+    Sp = []
+    for sgn in (1.0, -1.0):
+        ctx.update_links((Wt + sgn * h * dW).contiguous(), Nt)
+        Xs, _, _, _, _ = ctx.solve_backward(m, phi)
+        Sp.append(float(torch.sum(torch.conj(phi) * Xs).real))
+    ctx.update_links(Wt, Nt)
+    fd = (Sp[0] - Sp[1]) / (2 * h)
+    an = float(torch.sum(torch.conj(gw) * dW).real)
+    rel = abs(fd - an) / abs(an)
+    log(f"[bench] force {t_force:.3f} s; S = {S0:.6e}; dS/dh finite difference {fd:.8e} vs gradient {an:.8e} "
+        f"(rel {rel:.1e})")
+    out = {"metric": "fermion force (MG adjoint solves + outer product) time at 24^4 HISQ", "value": t_force,
+           "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_force * 1e3,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128 outer / c64 K-cycle",
+           "data": "synthetic",
+           "config": {"workload": f"{'x'.join(map(str, dims))} HISQ-style eps 0.5, mass {m}, {wl['nrhs']} phi, "
+                                  f"truncated-KD={not wl['kd_naik']}, coarse links "
+                                  f"{args.coarse_prec or wl.get('coarse_prec', 'fp32')}"},
+           "setup_s": setup_s, "solve_infos": info, "action": S0,
+           "gradient_check": {"direction": "Gaussian on every fat-link entry", "step": h, "finite_difference": fd,
+                              "gradient": an, "rel_diff": rel}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +360,9 @@ def main():
     from paper_2212_12559_amd import latgen, mgstag as mg
 
     wl = WORKLOADS[args.workload]
+    if wl.get("kind") == "force":
+        force_bench(args, wl, torch, latgen, mg)
+        return
     dims, m = wl["dims"], wl["mass"]
     dev = "cuda:0"
     log(f"[bench] workload {args.workload} dims {dims} mass {m}: generating links")
