@@ -145,6 +145,8 @@ def algorithmic_bytes(dims, nvec, nrhs=1, csz=8, naik=True, link_csz=8):
     b = {
         "dslash": V * (links + 2 * vec * nrhs),
         "kd": V * (144 * csz + 2 * vec * nrhs),
+        # A = (B+m)^-1 D of the KD level: the one-hop (truncated) or full stencil, then (B+m)^-1
+        "kd_operator": V * ((4 if not naik else 8) * 9 * csz + 2 * vec * nrhs) + V * (144 * csz + 2 * vec * nrhs),
         "restrict": V * (3 * nvec[0] * csz + vec * nrhs) + (V // 256) * 2 * nvec[0] * csz * nrhs,
         "prolong": V * (3 * nvec[0] * csz + vec * nrhs) + (V // 256) * 2 * nvec[0] * csz * nrhs,
     }
@@ -179,6 +181,7 @@ def kernel_rates(torch, ctx, wl, reps, mg, link_csz=8):
     ops = {
         "dslash": lambda: ctx.apply_dslash(0, m, x, y),
         "kd": lambda: ctx.apply_dslash(2, m, x, y),
+        "kd_operator": lambda: ctx.apply_dslash(1, m, x, y),
         "restrict": lambda: ctx.restrict(1, x, yc),
         "prolong": lambda: ctx.prolong(1, xc, y),
         "coarse2": lambda: ctx.apply_coarse(2, xc, yc),
