@@ -203,6 +203,101 @@ def cg_schur(W, N, mass, c1, c3, b, tol=1e-10, maxiter=100000):
 
 
 # --------------------------------------------------------------------------
+# Multi-shift CG of the propagator workflow (Sec. 3.3)
+# --------------------------------------------------------------------------
+
+def multishift_cg(W, N, masses, c1, c3, b, tol=1e-10, maxiter=100000):
+    """D(m_j) x_j = b for every mass at once, by multi-shift CG (Sec. 3.3).
+
+    K = D(0) is anti-Hermitian and couples even sites to odd ones only, so
+    D(m)^dag D(m) = m^2 - K^2 is block-diagonal in parity and
+    D(m)^{-1} b = (m - K) y with (m^2 - K^2) y = b.  On each parity p the
+    systems (sigma_j + A_p) y_p = b_p, A_p = -K_pq K_qp, sigma_j = m_j^2,
+    differ by a shift only, and CG on the smallest shift sigma_0 builds the
+    Krylov space of all of them (the propagators of the paper's workflow:
+    one even and one odd solve per source).
+
+    Shifted systems have residuals collinear with the base one,
+    r_j = zeta_j r.  With the base CG steps
+        r' = r - alpha A0 p,  p' = r' + beta p,  A0 = A_p + sigma_0,
+    matching the three-term residual recurrence of CG on A0 + d_j
+    (d_j = sigma_j - sigma_0) gives
+        zeta'_j = zeta_j zeta''_j a_prev
+                  / (alpha b_prev (zeta''_j - zeta_j) + zeta''_j a_prev (1 + alpha d_j))
+    (zeta'' the previous value, a_prev, b_prev the previous base alpha and
+    beta; a_prev = 1, b_prev = 0 and zeta'' = zeta = 1 at the start) and
+        alpha_j = alpha zeta'_j / zeta_j,  beta_j = beta (zeta'_j / zeta_j)^2,
+        x_j += alpha_j p_j,  p_j = zeta'_j r' + beta_j p_j.
+    A shift stops updating when |zeta_j| |r| <= tol |b| / 2 on its parity,
+    so both parities together leave |b - D x_j| <= tol |b| / sqrt(2) in exact
+    arithmetic; the true residual is reported.
+
+    Returns (list of x_j, iterations per parity, list of true relative
+    residuals).  Pinned by dense solves (tests/test_oracle_solvers.py).
+    """
+    masses = [float(m) for m in masses]
+    T, Z, Y, X = b.shape[:4]
+    epsf = ops.epsilon((X, Y, Z, T))[..., None]
+    par = [(epsf > 0).astype(np.float64), (epsf < 0).astype(np.float64)]
+
+    def K(v):
+        return ops.dslash(v, W, N, 0.0, c1, c3)
+
+    bnorm = _norm(b)
+    sig = [m * m for m in masses]
+    base = int(np.argmin(sig))
+    ns = len(masses)
+    y = [np.zeros_like(b) for _ in range(ns)]
+    iters = []
+    for Pp in par:
+        # A0 v = sigma_0 v - K_pq K_qp v on parity p
+        def A0(v):
+            return sig[base] * v - Pp * K((1.0 - Pp) * K(Pp * v))
+
+        r = Pp * b
+        ps = [r.copy() for _ in range(ns)]
+        zeta = [1.0] * ns
+        zeta_old = [1.0] * ns
+        a_prev, b_prev = 1.0, 0.0
+        rr = np.vdot(r, r).real
+        target = 0.5 * tol * bnorm
+        on = [np.sqrt(rr) > target for _ in range(ns)]
+        it = 0
+        while any(on) and it < maxiter:
+            Ap = A0(ps[base])
+            alpha = rr / np.vdot(ps[base], Ap).real
+            zeta_new = [1.0] * ns
+            for j in range(ns):
+                if j == base or not on[j]:
+                    continue
+                d = sig[j] - sig[base]
+                zeta_new[j] = zeta[j] * zeta_old[j] * a_prev / (
+                    alpha * b_prev * (zeta_old[j] - zeta[j]) + zeta_old[j] * a_prev * (1.0 + alpha * d))
+            for j in range(ns):
+                if on[j]:
+                    y[j] = y[j] + alpha * zeta_new[j] / zeta[j] * ps[j]
+            r = r - alpha * Ap
+            rr_new = np.vdot(r, r).real
+            beta = rr_new / rr
+            for j in range(ns):
+                if on[j]:
+                    ps[j] = zeta_new[j] * r + beta * (zeta_new[j] / zeta[j]) ** 2 * ps[j]
+            for j in range(ns):
+                if on[j]:
+                    zeta_old[j], zeta[j] = zeta[j], zeta_new[j]
+                    on[j] = abs(zeta[j]) * np.sqrt(rr_new) > target
+            a_prev, b_prev, rr = alpha, beta, rr_new
+            it += 1
+        iters.append(it)
+    xs, rels = [], []
+    for j, m in enumerate(masses):
+        x = m * y[j] - K(y[j])
+        xs.append(x)
+        rels.append(_norm(b - ops.dslash(x, W, N, m, c1, c3)) / bnorm)
+    return xs, iters, rels
+
+
+# --------------------------------------------------------------------------
 # Hierarchy and K-cycle (Sec. 2.1, Sec. 2.3, Table 1)
 # --------------------------------------------------------------------------
 
