@@ -340,6 +340,7 @@ def main():
     ap.add_argument("--workload", default="c2batch", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG comparator")
+    ap.add_argument("--no-msc", action="store_true", help="skip the multi-shift CG workflow comparison")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up, time the hot kernels and copy a known-size buffer (for counter runs)")
@@ -412,13 +413,17 @@ def main():
     del xk
     nr = wl["nrhs"]
 
+    batch_s = []
+
     def mg_step(tag):
         # lockstep batches of mb masses x nrhs systems; a line per batch and mass
         info_all = []
+        batch_s.clear()
         for j0 in range(0, len(masses), mb):
             chunk = masses[j0:j0 + mb]
             x, info, st = ctx.solve(chunk, bt, tol=1e-10)
             info_all += info
+            batch_s.append(info[0]["seconds"])
             for j, mj in enumerate(chunk):
                 ij = info[j * nr:(j + 1) * nr]
                 log(f"[bench] {tag} mass {mj}: {max(i['outer_iters'] for i in ij)} outer, batch level iters "
@@ -440,6 +445,7 @@ def main():
         infos.append(mg_step(f"step {i}"))
     torch.cuda.synchronize()
     mg_s = (time.perf_counter() - t0) / args.steps
+    last_batch_s = list(batch_s)
     dom_launches, dom_ms = ctx.profile_stop()
     res = max(s["true_rel_residual"] for i in infos for s in i)
 
@@ -457,6 +463,35 @@ def main():
         cg_s = time.perf_counter() - t0
         cg_info = {"outer_iters": cg_iters}
         log(f"[bench] CG {cg_s:.3f} s {cg_info}")
+
+    # ---- propagator workflow (Sec. 3.3, the Table 2 comparison): multi-shift CG
+    # over every mass, against MG for the lightest lockstep batch plus
+    # multi-shift CG for the rest
+    workflow = None
+    if not args.no_msc and len(masses) > mb:
+        def msc(ms, tag):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xm, minfo, st = ctx.multishift_cg_solve(list(ms), bt, tol=1e-10, maxiter=200000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            per = [max(i["outer_iters"] for i in minfo[j * nr:(j + 1) * nr]) for j in range(len(ms))]
+            worst = max(i["true_rel_residual"] for i in minfo)
+            fixed = sum(1 for i in minfo if i["reliable_updates"] > 0)
+            log(f"[bench] multi-shift CG {tag}: {dt:.2f} s, base iterations {minfo[0]['level_iters'][0]}, "
+                f"per-mass {per}, worst residual {worst:.2e}, finished by CG {fixed}")
+            del xm
+            return dt, per, worst, fixed
+        msc_all, per_all, worst_all, fix_all = msc(masses, "all masses")
+        msc_heavy, per_heavy, worst_heavy, fix_heavy = msc(masses[mb:], "heavier masses")
+        mg_light = last_batch_s[0]
+        workflow = {"masses_mg": masses[:mb], "masses_msc": masses[mb:],
+                    "msc_all_s": msc_all, "msc_all_iters_per_mass": per_all,
+                    "mg_light_s": mg_light, "msc_heavy_s": msc_heavy,
+                    "mg_plus_msc_s": mg_light + msc_heavy, "speedup_vs_msc": msc_all / (mg_light + msc_heavy),
+                    "worst_true_rel_residual": max(worst_all, worst_heavy),
+                    "systems_finished_by_cg": fix_all + fix_heavy}
+        log(f"[bench] workflow {workflow}")
 
     # ---- per-kernel timings outside the solve (HIP events on the library's stream)
     kern = kernel_rates(torch, ctx, wl, args.kernel_reps, mg, 8 if cprec == "fp32" else 4)
@@ -501,6 +536,8 @@ def main():
         "cg_s": cg_s,
         "cg_iters_per_mass": cg_info["outer_iters"] if cg_info else None,
         "speedup_vs_cg": (cg_s / mg_s) if cg_s else None,
+        "mg_batch_s": last_batch_s,
+        "workflow": workflow,
         "true_rel_residual": res,
         "roofline": roof,
         "kernels": {k: {kk: round(vv, 2) for kk, vv in v.items() if kk != "bytes"} for k, v in kern.items()},

@@ -27,8 +27,9 @@
  *     mg_setup, which must stay allocated until mg_destroy.
  *   - stream: a hipStream_t passed as void* (NULL = the null stream).  All
  *     work is enqueued on it.  mg_apply_*, mg_restrict and mg_prolong return
- *     without waiting; mg_setup, mg_solve and mg_cg_solve synchronise the
- *     stream before returning (they fill host-side results).
+ *     without waiting; mg_setup and the solvers (mg_solve, mg_cg_solve,
+ *     mg_msc_solve, mg_solve_backward) synchronise the stream before
+ *     returning (they fill host-side results).
  *   - the library never allocates device memory; it carves everything it
  *     needs from the caller's workspaces (sizes from mg_workspace_bytes).
  *   - errors: every function returns an mg_status; MG_OK is 0.  Arguments are
@@ -182,6 +183,27 @@ mg_status mg_solve(mg_ctx ctx, const double* masses, int32_t nmass, const void* 
  * Same layouts and semantics as mg_solve; maxiter caps the CG iterations. */
 mg_status mg_cg_solve(mg_ctx ctx, const double* masses, int32_t nmass, const void* b, void* x, int32_t nrhs,
                       double tol, int32_t maxiter, mg_solve_info* info, void* stream);
+
+/* Multi-shift CG of the propagator workflow (Sec. 3.3: the masses a workflow
+ * does not give to MG are solved together by multi-shift CG, one Krylov space
+ * per parity).  D(m)^{-1} b = (m - K) y with (m^2 - K^2) y = b, which is
+ * block-diagonal in parity; on each parity one CG on the smallest shift m_0^2
+ * also solves (m_j^2 - K_pq K_qp) y_j = b_p through collinear residuals.  A
+ * shift stops at |r_j| <= tol |b| / 2 on each parity; x_j = (m_j - K) y_j is
+ * then checked on the true residual ||b - D(m_j) x_j|| / ||b|| <= tol, and a
+ * system that misses it is finished by the Schur CG of mg_cg_solve started
+ * from x_j (info.reliable_updates > 0 marks it).
+ *   masses: host, 1..16 positive values (any order, repeats allowed)
+ *   b: device complex128 [nrhs][T][Z][Y][X][3], nrhs <= max_nrhs
+ *   x: device complex128 [nmass][nrhs][T][Z][Y][X][3] (overwritten)
+ *   info: host, nmass * nrhs entries; outer_iters = iterations the system
+ *     was updated (both parities), level_iters[0] = base iterations.
+ * The search directions of all shifts live in the outer GCR work vectors:
+ * MG_E_CONFIG when nmass blocks of nrhs half-lattice vectors do not fit in
+ * (2 outer_nkrylov - 1) buffers of max_nrhs lattice vectors.  Synchronises
+ * before returning; MG_E_NOCONV if a system still misses tol after maxiter. */
+mg_status mg_msc_solve(mg_ctx ctx, const double* masses, int32_t nmass, const void* b, void* x, int32_t nrhs,
+                       double tol, int32_t maxiter, mg_solve_info* info, void* stream);
 
 /* Fermion force for HMC (the solver inside gauge generation, Sec. 4.2):
  * for S = sum_r phi_r^dag (D(m)^dag D(m))^{-1} phi_r computes

@@ -3,6 +3,7 @@
 // device as one double2 per (slot, rhs), so the drivers never wait on the host
 // except for their convergence tests.  All reductions accumulate in FP64 and
 // combine their per-block partial sums in a fixed order (bit-reproducible).
+#include <algorithm>
 #include <stdexcept>
 
 #include "kernels.hpp"
@@ -221,7 +222,7 @@ template void launch_gcr_update<float2>(float2*, float2*, float2*, float2*, cons
 template void launch_gcr_update<double2>(double2*, double2*, double2*, double2*, const double2*, const double2*,
                                          int64_t, int, double2*, double2*, int, hipStream_t);
 
-// CG update in one pass: x += alpha p, r -= alpha Ap, partial sums of |r|^2
+// CG update in one pass: x += alpha p (x may be null), r -= alpha Ap, partial sums of |r|^2
 __global__ void __launch_bounds__(256) cg_update_kernel(double2* __restrict__ x, double2* __restrict__ r,
                                                        const double2* __restrict__ p, const double2* __restrict__ ap,
                                                        const double2* __restrict__ alpha, int64_t n,
@@ -232,13 +233,17 @@ __global__ void __launch_bounds__(256) cg_update_kernel(double2* __restrict__ x,
   const double al = alpha[rr].x;
   double s = 0.0;
   for (int64_t e = off + (int64_t)blockIdx.x * 256 + threadIdx.x; e < off + n; e += (int64_t)nblk * 256) {
-    const double2 pv = p[e], av = ap[e];
-    double2 xv = x[e], rv = r[e];
-    xv.x = fma(al, pv.x, xv.x);
-    xv.y = fma(al, pv.y, xv.y);
+    const double2 av = ap[e];
+    if (x) {
+      const double2 pv = p[e];
+      double2 xv = x[e];
+      xv.x = fma(al, pv.x, xv.x);
+      xv.y = fma(al, pv.y, xv.y);
+      x[e] = xv;
+    }
+    double2 rv = r[e];
     rv.x = fma(-al, av.x, rv.x);
     rv.y = fma(-al, av.y, rv.y);
-    x[e] = xv;
     r[e] = rv;
     s += rv.x * rv.x + rv.y * rv.y;
   }
@@ -632,6 +637,122 @@ void launch_cg_alpha(const double2* rr, const double2* pap, const int* mask, int
 }
 void launch_cg_beta(double2* rr, const double2* rrnew, const int* mask, int nrhs, double2* beta, hipStream_t st) {
   cg_beta_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(rr, rrnew, mask, nrhs, beta);
+}
+
+// ------------------------------------------------------ multi-shift CG
+// Shifted systems (sigma_base + d_j + A) y_j = b share the base CG's Krylov
+// space; their residuals are zeta_j r (Sec. 3.3 workflow).  One thread per
+// right-hand side walks the shifts.
+__global__ void msc_init_kernel(double2* st, const double2* rr, const double2* target2, int* mask, int nshift,
+                                int nrhs, int ld) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  auto S = [&](int s) -> double2& { return st[(int64_t)s * ld + r]; };
+  const bool on = rr[r].x > target2[r].x && rr[r].x < 1e300;
+  for (int j = 0; j < nshift; ++j) {
+    S(kMscPer * j + 0) = make_double2(1.0, 0.0);
+    S(kMscPer * j + 1) = make_double2(1.0, 0.0);
+    S(kMscPer * j + 5) = make_double2(0.0, 0.0);
+    S(kMscPer * j + 6) = make_double2(on ? 1.0 : 0.0, 0.0);
+    S(kMscPer * j + 7) = make_double2(0.0, 0.0);
+  }
+  S(kMscPer * kMaxShift + 0) = make_double2(1.0, 0.0);
+  S(kMscPer * kMaxShift + 1) = make_double2(0.0, 0.0);
+  mask[r] = on ? 1 : 0;
+}
+void launch_msc_init(double2* st, const double2* rr, const double2* target2, int* mask, int nshift, int nrhs, int ld,
+                     hipStream_t st_) {
+  msc_init_kernel<<<(nrhs + 63) / 64, 64, 0, st_>>>(st, rr, target2, mask, nshift, nrhs, ld);
+}
+
+// After the base step (alpha, |r'|^2): beta, then for every shift still on
+// zeta'_j, alpha_j = alpha zeta'_j / zeta_j and beta_j = beta (zeta'_j /
+// zeta_j)^2 (the base keeps zeta = 1).  A shift whose |zeta'_j| |r'| reaches
+// the target is updated this once more and then frozen.
+__global__ void msc_scalars_kernel(const MscScalArgs a) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.nrhs) return;
+  auto S = [&](int s) -> double2& { return a.st[(int64_t)s * a.ld + r]; };
+  if (!a.mask[r]) {
+    for (int j = 0; j < a.nshift; ++j) S(kMscPer * j + 5) = make_double2(0.0, 0.0);
+    return;
+  }
+  const double al = a.alpha[r].x, rro = a.rr[r].x, rrn = a.rrnew[r].x;
+  const double be = rro > 0.0 ? rrn / rro : 0.0;
+  const double ap = S(kMscPer * kMaxShift + 0).x, bp = S(kMscPer * kMaxShift + 1).x;
+  const double t2 = a.target2[r].x;
+  int any = 0;
+  for (int j = 0; j < a.nshift; ++j) {
+    // the base direction drives every shift: it steps while any shift is on
+    if (j != a.base && S(kMscPer * j + 6).x == 0.0) {
+      S(kMscPer * j + 5) = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double z = S(kMscPer * j + 0).x, zo = S(kMscPer * j + 1).x;
+    double zn = 1.0;
+    if (j != a.base) zn = z * zo * ap / (al * bp * (zo - z) + zo * ap * (1.0 + al * a.delta[j]));
+    const double q = zn / z;
+    S(kMscPer * j + 2) = make_double2(al * q, 0.0);
+    S(kMscPer * j + 3) = make_double2(zn, 0.0);
+    S(kMscPer * j + 4) = make_double2(be * q * q, 0.0);
+    S(kMscPer * j + 5) = make_double2(1.0, 0.0);
+    S(kMscPer * j + 7).x += 1.0;
+    S(kMscPer * j + 1) = make_double2(z, 0.0);
+    S(kMscPer * j + 0) = make_double2(zn, 0.0);
+    const bool on = zn * zn * rrn > t2 && rrn < 1e300 && zn == zn;
+    S(kMscPer * j + 6) = make_double2(on ? 1.0 : 0.0, 0.0);
+    any |= on;
+  }
+  S(kMscPer * kMaxShift + 0) = make_double2(al, 0.0);
+  S(kMscPer * kMaxShift + 1) = make_double2(be, 0.0);
+  a.rr[r] = make_double2(rrn, 0.0);
+  a.mask[r] = any;
+}
+void launch_msc_scalars(const MscScalArgs& a, hipStream_t st) {
+  msc_scalars_kernel<<<(a.nrhs + 63) / 64, 64, 0, st>>>(a);
+}
+
+// x_j += alpha_j p_j, p_j = zeta'_j r + beta_j p_j for every shift flagged
+// for update; r is read once per element for all shifts.
+__global__ void __launch_bounds__(256) msc_update_kernel(const MscUpdArgs a) {
+  const int rr = blockIdx.y;
+  double ax[kMaxShift], pz[kMaxShift], pb[kMaxShift];
+  bool up[kMaxShift];
+#pragma unroll
+  for (int j = 0; j < kMaxShift; ++j) {
+    up[j] = false;
+    ax[j] = pz[j] = pb[j] = 0.0;
+    if (j < a.nshift) {
+      const int64_t o = (int64_t)kMscPer * j * a.ld + rr;
+      up[j] = a.st[o + 5 * (int64_t)a.ld].x != 0.0;
+      ax[j] = a.st[o + 2 * (int64_t)a.ld].x;
+      pz[j] = a.st[o + 3 * (int64_t)a.ld].x;
+      pb[j] = a.st[o + 4 * (int64_t)a.ld].x;
+    }
+  }
+  const double2* rv_ = a.r + (int64_t)rr * a.r_stride;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.n; e += (int64_t)gridDim.x * 256) {
+    const double2 rv = rv_[e];
+#pragma unroll
+    for (int j = 0; j < kMaxShift; ++j) {
+      if (!up[j]) continue;
+      double2* pp = a.p[j] + (int64_t)rr * a.p_stride + e;
+      const double2 pv = *pp;
+      if (ax[j] != 0.0) {
+        double2* xp = a.x[j] + (int64_t)rr * a.x_stride + e;
+        double2 xv = *xp;
+        xv.x = fma(ax[j], pv.x, xv.x);
+        xv.y = fma(ax[j], pv.y, xv.y);
+        *xp = xv;
+      }
+      *pp = make_double2(fma(pz[j], rv.x, pb[j] * pv.x), fma(pz[j], rv.y, pb[j] * pv.y));
+    }
+  }
+}
+void launch_msc_update(const MscUpdArgs& a, hipStream_t st) {
+  if (a.nshift < 1 || a.nshift > kMaxShift) throw std::runtime_error("multi-shift: 1..16 shifts");
+  dim3 grid((unsigned)std::min<int64_t>((a.n + 255) / 256, 1024), (unsigned)a.nrhs);
+  msc_update_kernel<<<grid, 256, 0, st>>>(a);
 }
 
 }  // namespace mg

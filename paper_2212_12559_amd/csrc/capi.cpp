@@ -264,6 +264,27 @@ mg_status mg_cg_solve(mg_ctx ctx, const double* masses, int32_t nmass, const voi
   return MG_OK;
 }
 
+mg_status mg_msc_solve(mg_ctx ctx, const double* masses, int32_t nmass, const void* b, void* x, int32_t nrhs,
+                       double tol, int32_t maxiter, mg_solve_info* info, void* stream) {
+  if (!ctx) return fail(MG_E_ARG, "null context");
+  Ctx& c = ctx->c;
+  if (!masses || !b || !x || !info) return fail(MG_E_ARG, "null argument");
+  if (nmass < 1 || nmass > 16) return fail(MG_E_ARG, "nmass must be in 1..16");
+  if (nrhs < 1 || nrhs > c.P.max_nrhs) return fail(MG_E_ARG, "nrhs out of range (1..max_nrhs)");
+  for (int j = 0; j < nmass; ++j)
+    if (!(masses[j] > 0.0) || !std::isfinite(masses[j])) return fail(MG_E_ARG, "masses must be positive and finite");
+  if (!(tol > 0.0)) return fail(MG_E_ARG, "tol must be positive");
+  if (maxiter < 1) return fail(MG_E_ARG, "maxiter must be >= 1");
+  if (!aligned(b) || !aligned(x)) return fail(MG_E_ALIGN, "vectors must be 16-byte aligned");
+  if (b == x) return fail(MG_E_ARG, "b and x must be distinct");
+  c.st = (hipStream_t)stream;
+  mg_status s = guarded([&] { c.msc_solve(masses, nmass, b, x, nrhs, tol, maxiter, info); });
+  if (s != MG_OK) return s;
+  for (int i = 0; i < nmass * nrhs; ++i)
+    if (info[i].status != MG_OK) return fail((mg_status)info[i].status, "a system did not converge");
+  return MG_OK;
+}
+
 mg_status mg_solve_backward(mg_ctx ctx, double mass, const void* phi, void* X, void* Y, void* grad_fat,
                             void* grad_naik, int32_t nrhs, double tol, mg_solve_info* info, void* stream) {
   if (!ctx) return fail(MG_E_ARG, "null context");

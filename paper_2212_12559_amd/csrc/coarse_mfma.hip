@@ -37,6 +37,20 @@ template <int FMT>
 __device__ __forceinline__ uint16_t to16(float f) { return FMT == 0 ? f32_to_bf16_rne(f) : f32_to_f16_rne(f); }
 
 
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+
+// Streaming (non-temporal) accesses for the links, each read by one workgroup
+// only, and for the result: they leave the L2 to the neighbour inputs, which
+// nine workgroups read.
+__device__ __forceinline__ uint4 load_stream(const uint4* p) {
+  const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void store_stream(float2* p, float re, float im) {
+  __builtin_nontemporal_store(f32x2{re, im}, reinterpret_cast<f32x2*>(p));
+}
+
 template <int FMT>
 __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
   if constexpr (FMT == 0) {
@@ -174,8 +188,8 @@ __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const C
         uint4 are[MT], aim[MT], aimn[MT];   // Re A, Im A and -Im A (sign bits flipped)
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
-          are[m] = Lm[m][(kc * 2 + 0) * 64 + lane];
-          aim[m] = Lm[m][(kc * 2 + 1) * 64 + lane];
+          are[m] = load_stream(Lm[m] + (kc * 2 + 0) * 64 + lane);
+          aim[m] = load_stream(Lm[m] + (kc * 2 + 1) * 64 + lane);
           aimn[m] = make_uint4(aim[m].x ^ 0x80008000u, aim[m].y ^ 0x80008000u, aim[m].z ^ 0x80008000u,
                                aim[m].w ^ 0x80008000u);
         }
@@ -205,7 +219,7 @@ __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const C
       if (r < a.nrhs) {
         float2* o = a.out + (int64_t)r * a.out_stride + site * n + mt * 16 + 4 * g;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) o[t] = make_float2(yr[m][rt][t] * a.inv_scale, yi[m][rt][t] * a.inv_scale);
+        for (int t = 0; t < 4; ++t) store_stream(o + t, yr[m][rt][t] * a.inv_scale, yi[m][rt][t] * a.inv_scale);
       }
     }
   }

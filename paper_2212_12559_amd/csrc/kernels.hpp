@@ -220,4 +220,34 @@ void launch_gcr_update_cgs(const GcrUpdArgs<T>& a, double2* part, double2* res, 
 void launch_conv(int* mask, const double2* rn2, const double2* r0sq, double tol2, int nrhs, int init,
                  hipStream_t st);
 
+// Multi-shift CG (Sec. 3.3).  Device state of the shifted systems, slots of
+// ld entries: per shift j at kMscPer * j + {zeta, previous zeta, alpha_j,
+// zeta'_j, beta_j, update flag, on flag, iteration count}; per rhs at
+// kMscPer * kMaxShift + {previous base alpha, previous base beta}.
+constexpr int kMaxShift = 16;
+constexpr int kMscPer = 8;
+constexpr int kMscSlots = kMscPer * kMaxShift + 2;
+struct MscScalArgs {
+  double2* st;             // state slots [kMscSlots][ld]
+  double2* rr;             // |r|^2 per rhs (replaced by the new value)
+  const double2* rrnew;    // |r|^2 after the base step
+  const double2* alpha;    // base alpha per rhs (0 when masked)
+  const double2* target2;  // stopping |r_j|^2 per rhs
+  int* mask;               // per rhs: 1 while any shift is on
+  double delta[kMaxShift]; // sigma_j - sigma_base
+  int nshift, base, nrhs, ld;
+};
+struct MscUpdArgs {
+  double2* x[kMaxShift];   // solution of shift j, rhs r at x[j] + r * x_stride
+  double2* p[kMaxShift];   // search direction of shift j at p[j] + r * p_stride
+  const double2* r;        // base residual at r + rhs * r_stride
+  const double2* st;
+  int64_t n, x_stride, p_stride, r_stride;
+  int nshift, nrhs, ld;
+};
+void launch_msc_init(double2* st, const double2* rr, const double2* target2, int* mask, int nshift, int nrhs, int ld,
+                     hipStream_t st_);
+void launch_msc_scalars(const MscScalArgs& a, hipStream_t st);
+void launch_msc_update(const MscUpdArgs& a, hipStream_t st);
+
 }  // namespace mg

@@ -147,7 +147,9 @@ struct Ctx {
   void solve_batch(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol,
                    mg_solve_info* info);
   void cg_solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, int maxiter,
-                mg_solve_info* info);
+                mg_solve_info* info, bool guess = false);
+  void msc_solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, int maxiter,
+                 mg_solve_info* info);
   void solve_backward(double mass, const void* phi, void* X, void* Y, void* gw, void* gn, int nrhs, double tol,
                       mg_solve_info* info);
   void update_links(const void* fat, const void* naik);

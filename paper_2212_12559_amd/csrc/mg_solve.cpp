@@ -163,7 +163,7 @@ void Ctx::update_links(const void* fat, const void* naik) {
 // Single-parity Schur CG (Sec. 3.2) for every (mass, rhs) system, one mass
 // at a time with the right-hand sides batched.
 void Ctx::cg_solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, int maxiter,
-                   mg_solve_info* info) {
+                   mg_solve_info* info, bool guess) {
   if (P.outer_nkrylov < 2) throw Error{MG_E_CONFIG, "the CG baseline needs outer_nkrylov >= 2 (work vectors)"};
   const int64_t V = g0.V;
   const int64_t n = V * 3, nh = V / 2 * 3;
@@ -206,7 +206,13 @@ void Ctx::cg_solve(const double* masses, int nmass, const void* b, void* x, int 
       if (!std::isfinite(bn[s])) stat[s] = MG_E_NONFINITE;
       nact += act[s];
     }
-    HIPCHK(hipMemsetAsync(xe, 0, hb, st));
+    if (guess) {
+      // start from the even half of the caller's x (xo is scratch here)
+      launch_cb_split(xj, xe, xo, g0, nrhs, st);
+      check_launch();
+    } else {
+      HIPCHK(hipMemsetAsync(xe, 0, hb, st));
+    }
     int total = 0, restarts = 0;
     std::vector<double> rel(nrhs, 0.0);
     while (true) {
@@ -285,6 +291,175 @@ void Ctx::cg_solve(const double* masses, int nmass, const void* b, void* x, int 
       I.seconds = t1 - t0;
       if (stat[s] == MG_OK && !(rel[s] <= tol)) stat[s] = MG_E_NOCONV;
       I.status = stat[s];
+    }
+  }
+}
+
+// Multi-shift CG over all masses at once (Sec. 3.3 workflow).  D(m)^{-1} b =
+// (m - K) y with (m^2 - K^2) y = b; m^2 - K^2 is block-diagonal in parity,
+// so each parity is one CG on the smallest shift sigma_0 = m_0^2 whose
+// Krylov space also gives every (sigma_j - K_pq K_qp) y_j = b_p, with
+// collinear residuals zeta_j r.  A shift stops at |zeta_j r| <= tol |b| / 2
+// per parity; x_j = m_j y_j - K y_j is then checked on the true residual and a
+// system that misses tol is finished by the single-mass Schur CG from x_j.
+void Ctx::msc_solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, int maxiter,
+                    mg_solve_info* info) {
+  if (nmass > kMaxShift) throw Error{MG_E_ARG, "multi-shift CG takes at most 16 masses"};
+  if (P.outer_nkrylov < 2) throw Error{MG_E_CONFIG, "multi-shift CG needs outer_nkrylov >= 2 (work vectors)"};
+  const double t0 = now();
+  const int64_t V = g0.V;
+  const int64_t n = V * 3, nh = V / 2 * 3;
+  LevelBufs& B = L[0];
+  const size_t hb = (size_t)nrhs * nh * 16;
+  // sources of both parities, base residual, A p and K p
+  double2* be = (double2*)B.b.p;
+  double2* bo = (double2*)((char*)B.b.p + hb);
+  double2* r = (double2*)B.r.p;
+  double2* Ap = (double2*)((char*)B.r.p + hb);
+  double2* to = (double2*)B.q[0].p;
+  // search directions: blocks of nrhs half vectors in z[0..], q[1..]
+  std::vector<double2*> pblk;
+  const int per = (int)((2 * (int64_t)P.max_nrhs) / nrhs);
+  for (int k = 0; k < P.outer_nkrylov; ++k)
+    for (int h = 0; h < per; ++h) {
+      pblk.push_back((double2*)((char*)B.z[k].p + h * hb));
+      if (k > 0) pblk.push_back((double2*)((char*)B.q[k].p + h * hb));
+    }
+  if ((int)pblk.size() < nmass)
+    throw Error{MG_E_CONFIG, "multi-shift CG: nmass x nrhs exceeds the work space (raise outer_nkrylov or max_nrhs)"};
+  int base = 0;
+  for (int j = 1; j < nmass; ++j)
+    if (masses[j] < masses[base]) base = j;
+  const double s0 = masses[base] * masses[base];
+  double2* stt = tslot(1, 0);   // shifted-system state (the inner GCR scalars are idle here)
+  const int ld = max_sys;
+  int* mk = lmask(0);
+  double2 *rr = slot(0, kSlotQQ), *rrn = slot(0, kSlotQQ + 1), *al = slot(0, kSlotQQ + 2),
+          *nal = slot(0, kSlotQQ + 3), *pap = slot(0, kSlotQQ + 5), *tg = slot(0, kSlotR0);
+  std::vector<double> bn;
+  norms_host(P64, n, nrhs, b, slot(0, kSlotNorm), bn);
+  std::vector<int> stat(nrhs, MG_OK);
+  std::vector<double2> tgt(nrhs);
+  for (int s = 0; s < nrhs; ++s) {
+    if (!std::isfinite(bn[s])) stat[s] = MG_E_NONFINITE;
+    const double t = 0.5 * tol * bn[s];
+    tgt[s] = make_double2(std::isfinite(t) ? t * t : 0.0, 0.0);
+  }
+  HIPCHK(hipMemcpyAsync(tg, tgt.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(x, 0, (size_t)nmass * nrhs * n * 16, st));
+  launch_cb_split((const double2*)b, be, bo, g0, nrhs, st);
+  check_launch();
+  // v (half, parity 1 - par) -> out (half, parity par): out = ac xs + bc K v
+  auto cbd = [&](double2* out, const double2* in, const double2* xs, int par, double ac, double bc, int64_t sin,
+                 int64_t sxs) {
+    DslashArgs<double> d{};
+    d.out = out; d.in = in; d.xs = xs; d.fat = fat64; d.lng = lng64; d.g = g0;
+    d.in_stride = sin; d.xs_stride = sxs; d.out_stride = nh; d.nrhs = nrhs; d.a_coef = ac; d.b_coef = bc;
+    d.parity = par;
+    launch_dslash(d, P.c3 != 0.0, true, false, st);
+    check_launch();
+  };
+  std::vector<double> iters_sys((size_t)nmass * nrhs, 0.0);
+  int total = 0;
+  for (int par = 0; par < 2; ++par) {
+    const double2* bp = par == 0 ? be : bo;
+    HIPCHK(hipMemcpyAsync(r, bp, hb, hipMemcpyDeviceToDevice, st));
+    for (int j = 0; j < nmass; ++j) HIPCHK(hipMemcpyAsync(pblk[j], bp, hb, hipMemcpyDeviceToDevice, st));
+    dots(P64, nh, nrhs, {{r, r}}, rr);
+    launch_msc_init(stt, rr, tg, mk, nmass, nrhs, ld, st);
+    check_launch();
+    MscScalArgs sa{};
+    sa.st = stt; sa.rr = rr; sa.rrnew = rrn; sa.alpha = al; sa.target2 = tg; sa.mask = mk;
+    for (int j = 0; j < nmass; ++j) sa.delta[j] = masses[j] * masses[j] - s0;
+    sa.nshift = nmass; sa.base = base; sa.nrhs = nrhs; sa.ld = ld;
+    MscUpdArgs ua{};
+    for (int j = 0; j < nmass; ++j) {
+      ua.x[j] = (double2*)x + (size_t)j * nrhs * n + par * nh;
+      ua.p[j] = pblk[j];
+    }
+    ua.r = r; ua.st = stt; ua.n = nh; ua.x_stride = n; ua.p_stride = nh; ua.r_stride = nh;
+    ua.nshift = nmass; ua.nrhs = nrhs; ua.ld = ld;
+    double2* pb = pblk[base];
+    int live = nrhs, it = 0, since = 0;
+    while (live > 0 && it < maxiter) {
+      // A0 p = sigma_0 p - K_pq K_qp p
+      cbd(to, pb, nullptr, 1 - par, 0.0, 1.0, nh, nh);
+      cbd(Ap, to, pb, par, s0, -1.0, nh, nh);
+      dots(P64, nh, nrhs, {{pb, Ap}}, pap);
+      launch_cg_alpha(rr, pap, mk, nrhs, al, nal, st);
+      check_launch();
+      // r -= alpha A p and |r|^2 (every x, the base's included, is updated below)
+      launch_cg_update(nullptr, r, pb, Ap, al, nh, nrhs, part, rrn, max_sys, st);
+      check_launch();
+      launch_msc_scalars(sa, st);
+      check_launch();
+      launch_msc_update(ua, st);
+      check_launch();
+      ++it;
+      if (++since == 4 || it >= maxiter) {
+        since = 0;
+        std::vector<int> h(nrhs);
+        HIPCHK(hipMemcpyAsync(h.data(), mk, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        live = 0;
+        for (int s = 0; s < nrhs; ++s) live += h[s] != 0;
+      }
+    }
+    total += it;
+    std::vector<double2> cnt((size_t)nmass * ld);
+    for (int j = 0; j < nmass; ++j)
+      HIPCHK(hipMemcpyAsync(cnt.data() + (size_t)j * ld, stt + (int64_t)(kMscPer * j + 7) * ld, ld * sizeof(double2),
+                            hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int j = 0; j < nmass; ++j)
+      for (int s = 0; s < nrhs; ++s) iters_sys[(size_t)j * nrhs + s] += cnt[(size_t)j * ld + s].x;
+  }
+  // x_j = (m_j - K) y_j, parity by parity into the r / A p halves, then merged
+  double2* te = r;
+  double2* tod = Ap;
+  double2* rfull = (double2*)B.b.p;
+  std::vector<int> redo(nmass, 0);
+  std::vector<double> rel((size_t)nmass * nrhs, 0.0);
+  for (int j = 0; j < nmass; ++j) {
+    const double m = masses[j];
+    double2* yj = (double2*)x + (size_t)j * nrhs * n;
+    cbd(te, yj + nh, yj, 0, m, -1.0, n, n);
+    cbd(tod, yj, yj + nh, 1, m, -1.0, n, n);
+    launch_cb_merge(yj, te, tod, g0, nrhs, st);
+    check_launch();
+    apply_D(P64, rfull, yj, nrhs, true, nullptr, m);
+    lincomb(P64, n, nrhs, rfull, {{b, nullptr}, {rfull, nullptr}}, {0, 1}, {});
+    std::vector<double> tr;
+    norms_host(P64, n, nrhs, rfull, slot(0, kSlotNorm), tr);
+    for (int s = 0; s < nrhs; ++s) {
+      const double q = bn[s] > 0 ? tr[s] / bn[s] : 0.0;
+      rel[(size_t)j * nrhs + s] = q;
+      if (stat[s] == MG_OK && bn[s] > 0 && !(q <= tol)) redo[j] = 1;
+    }
+  }
+  const double t1 = now();
+  for (int j = 0; j < nmass; ++j)
+    for (int s = 0; s < nrhs; ++s) {
+      mg_solve_info& I = info[j * nrhs + s];
+      I.outer_iters = (int)iters_sys[(size_t)j * nrhs + s];
+      I.reliable_updates = 0;
+      for (int l = 0; l < 4; ++l) I.level_iters[l] = 0;
+      I.level_iters[0] = total;
+      I.true_rel_residual = rel[(size_t)j * nrhs + s];
+      I.seconds = t1 - t0;
+      I.status = stat[s] != MG_OK ? stat[s] : MG_OK;
+    }
+  // finish the systems the iterated residual let through (rounding drift)
+  for (int j = 0; j < nmass; ++j) {
+    if (!redo[j]) continue;
+    std::vector<mg_solve_info> fix(nrhs);
+    cg_solve(masses + j, 1, b, (double2*)x + (size_t)j * nrhs * n, nrhs, tol, maxiter, fix.data(), true);
+    for (int s = 0; s < nrhs; ++s) {
+      mg_solve_info& I = info[j * nrhs + s];
+      I.outer_iters += fix[s].outer_iters;
+      I.reliable_updates = 1 + fix[s].reliable_updates;
+      I.true_rel_residual = fix[s].true_rel_residual;
+      I.status = fix[s].status;
     }
   }
 }

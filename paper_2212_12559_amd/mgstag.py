@@ -82,6 +82,7 @@ def _load():
         "mg_prolong": (i32, [vp, i32, i32, vp, vp, i32, i32, vp]),
         "mg_solve": (i32, [vp, P(f64), i32, vp, vp, i32, f64, P(MGSolveInfo), vp]),
         "mg_cg_solve": (i32, [vp, P(f64), i32, vp, vp, i32, f64, i32, P(MGSolveInfo), vp]),
+        "mg_msc_solve": (i32, [vp, P(f64), i32, vp, vp, i32, f64, i32, P(MGSolveInfo), vp]),
         "mg_export": (i32, [vp, i32, i32, vp, sz, P(sz), vp]),
         "mg_solve_backward": (i32, [vp, f64, vp, vp, vp, vp, vp, i32, f64, P(MGSolveInfo), vp]),
         "mg_update_links": (i32, [vp, vp, vp, vp]),
@@ -270,6 +271,13 @@ class Context:
         st, x, info = self._solve(LIB.mg_cg_solve, masses, b, tol, (maxiter,))
         if check:
             _check(st, "mg_cg_solve")
+        return x, info, st
+
+    def multishift_cg_solve(self, masses, b, tol=1e-10, maxiter=100000, check=True):
+        """Multi-shift CG over all masses at once (at most 16); same layouts as solve."""
+        st, x, info = self._solve(LIB.mg_msc_solve, masses, b, tol, (maxiter,))
+        if check:
+            _check(st, "mg_msc_solve")
         return x, info, st
 
     def solve_backward(self, mass, phi, tol=1e-10):

@@ -216,6 +216,49 @@ def test_error_paths(torch, mg, cubic):
     assert e.value.status == mg.MG_E_RANK
 
 
+def test_multishift_cg_matches_oracle(torch, mg, cubic):
+    """Multi-shift CG over unsorted masses with a repeat (Sec. 3.3 workflow):
+    every (mass, rhs) system at true residual 1e-10 and within 2e-10 ||b|| / m
+    of the oracle's multi-shift solution; the lightest shift takes the
+    oracle's iteration count (both parities, within 5%), a repeated mass the
+    same count, and heavier shifts freeze earlier."""
+    cfg, W, N, nvs, b = cubic
+    masses = [0.3, 0.02, 0.07, 0.02]
+    log("[msc] cubic 4 masses x 2 rhs")
+    ctx = make_ctx(torch, mg, cfg, W, N, nvs, max_nrhs=2)
+    x, info, st = ctx.multishift_cg_solve(masses, torch.from_numpy(b).to("cuda:0"), tol=1e-10)
+    x = x.cpu().numpy()
+    for r in range(2):
+        xo, io, relo = sol.multishift_cg(W, N, masses, cfg["c1"], cfg["c3"], b[r], tol=1e-10)
+        for j, m in enumerate(masses):
+            I = info[j * 2 + r]
+            assert I["status"] == "MG_OK" and I["reliable_updates"] == 0, I
+            assert true_rel(cfg, W, N, m, x[j, r], b[r]) <= 1e-10, (m, r)
+            assert np.linalg.norm(x[j, r] - xo[j]) <= 2e-10 * np.linalg.norm(b[r]) / m, (m, r)
+        # ~900 CG steps per parity: rounding in a different summation order
+        # moves the step at which 1e-10 is reached by a few percent
+        assert abs(info[1 * 2 + r]["outer_iters"] - sum(io)) <= 0.05 * sum(io), (info[2 + r], io)
+        assert info[3 * 2 + r]["outer_iters"] == info[1 * 2 + r]["outer_iters"]
+        assert info[0 * 2 + r]["outer_iters"] < info[2 * 2 + r]["outer_iters"] < info[1 * 2 + r]["outer_iters"]
+
+
+def test_multishift_cg_limits(torch, mg, cubic):
+    """Work-space and argument limits of the multi-shift CG: 16 shifts at most,
+    and the shifts' directions must fit in the outer GCR work vectors."""
+    cfg, W, N, nvs, b = cubic
+    log("[msc] limits")
+    ctx = make_ctx(torch, mg, cfg, W, N, nvs, max_nrhs=1, outer_nkrylov=2)
+    bt = torch.from_numpy(b[:1]).to("cuda:0")
+    x, info, st = ctx.multishift_cg_solve([0.1] * 6, bt, tol=1e-8, check=False)
+    assert st == mg.MG_OK
+    x, info, st = ctx.multishift_cg_solve([0.1] * 7, bt, tol=1e-8, check=False)
+    assert st == mg.MG_E_CONFIG
+    x, info, st = ctx.multishift_cg_solve([0.1] * 17, bt, tol=1e-8, check=False)
+    assert st == mg.MG_E_ARG
+    x, info, st = ctx.multishift_cg_solve([0.1, -0.2], bt, tol=1e-8, check=False)
+    assert st == mg.MG_E_ARG
+
+
 def test_force_matches_oracle(torch, mg, cubic):
     """Fermion-force gradients from the MG solves and the outer-product kernel
     against the oracle's (FD-pinned) force on the same links and source;
