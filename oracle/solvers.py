@@ -11,8 +11,10 @@ Readings of the paper used here (it leaves these open):
     ||r - A v|| over the Krylov space K_s(A, r) from a zero guess; the oracle
     computes that minimiser with s steps of Arnoldi (MGS) and a small
     least-squares solve;
-  * the coarsest level (SVD deflation is out of scope) is unpreconditioned
-    GCR to a tolerance / iteration cap, or a dense LU solve;
+  * the coarsest level is unpreconditioned GCR to a tolerance / iteration
+    cap, or a dense LU solve; its deflation (Table 1 deflates it with
+    singular vectors) is read as a minimal-residual start on the span of
+    given low modes of the coarsest operator (mr_deflation);
   * near-null vectors: CG on A A^dag y = -A phi0, phi = phi0 + A^dag y
     (CGNE on the homogeneous system, Sec. 2.1 and Table 1), stopping at
     ||A phi|| <= tol ||A phi0|| or maxiter.  PARITY UNPINNED: a long random
@@ -98,6 +100,30 @@ def gcr(op, b, precond=None, tol=1e-10, maxiter=1000, nkrylov=16, true_residual=
     if true_residual:
         info.true_rel_residual = _norm(b - op(x)) / bnorm
     return x, info
+
+
+def mr_deflation(op, Wv):
+    """Coarsest-level deflation space (Sec. 2.3 / Table 1: the coarsest solve is
+    deflated with low modes of its operator).  Reading used here: the space is
+    spanned by given vectors W (rows of Wv, near-null vectors of the coarsest
+    operator A), and the deflated start is the minimal-residual one,
+        x0 = W y,  y = argmin ||b - A W y||,
+    formed through a Cholesky QR of Z = A W:  Z^H Z = R^H R (R upper),
+    Q = Z R^{-1}, W' = W R^{-1}, so x0 = W' Q^H b and r0 = b - Q Q^H b.
+    Returns (Q, W') as rows.  Pinned by a least-squares solve
+    (tests/test_oracle_solvers.py)."""
+    Wm = np.stack([w.reshape(-1) for w in Wv], axis=1)             # n x k
+    Zm = np.stack([op(w).reshape(-1) for w in Wv], axis=1)         # n x k
+    G = Zm.conj().T @ Zm
+    R = np.linalg.cholesky(G).conj().T                               # G = R^H R
+    Rinv = np.linalg.inv(R)
+    return (Zm @ Rinv).T, (Wm @ Rinv).T
+
+
+def mr_deflate(Q, Wp, b):
+    """x0 = W' Q^H b and r0 = b - Q Q^H b for the space of mr_deflation."""
+    c = Q.conj() @ b.reshape(-1)
+    return (Wp.T @ c).reshape(b.shape), (b.reshape(-1) - Q.T @ c).reshape(b.shape)
 
 
 def mr_smoother(op, r, s):
@@ -352,6 +378,12 @@ class Hierarchy:
         self.nlevels = 2 + len(self.transfers)
         self._dense_lu = None
         self._dense = {}
+        self.deflation = None
+
+    def set_coarsest_deflation(self, Wv):
+        """Deflate the coarsest solve with the span of the vectors Wv."""
+        lvl = self.nlevels - 1
+        self.deflation = mr_deflation(lambda v: self.op(lvl, v), Wv)
 
     # --- level operators --------------------------------------------------
     def op(self, lvl, v):
@@ -422,6 +454,17 @@ class Hierarchy:
                 if self._dense_lu is None:
                     self._dense_lu = ops.dense_matrix(lambda v: self.op(lvl, v), b.shape)
                 return np.linalg.solve(self._dense_lu, b.reshape(-1)).reshape(b.shape)
+            if self.deflation is not None:
+                # deflated start, then GCR on the remaining residual with the
+                # stop test still relative to ||b||
+                Q, Wp = self.deflation
+                x0, r0 = mr_deflate(Q, Wp, b)
+                bn, rn = _norm(b), _norm(r0)
+                if bn == 0.0 or rn == 0.0:
+                    return x0
+                e, _ = gcr(lambda v: self.op(lvl, v), r0, None, p.coarsest_tol * bn / rn,
+                           p.coarsest_maxiter, p.coarsest_maxiter)
+                return x0 + e
             x, _ = gcr(lambda v: self.op(lvl, v), b, None, p.coarsest_tol,
                        p.coarsest_maxiter, p.coarsest_maxiter)
             return x

@@ -245,3 +245,22 @@ def test_multishift_cg_single_shift_is_normal_cg():
     D = ops.dense_matrix(lambda v: ops.dslash(v, W, N, m, C1H, C3H), b.shape)
     y = np.linalg.solve(D.conj().T @ D, b.reshape(-1))
     assert np.linalg.norm(xs[0].reshape(-1) - D.conj().T @ y) <= 1e-11 * np.linalg.norm(b) / m
+
+
+def test_mr_deflation_is_least_squares():
+    """The deflated start is the minimiser of ||b - A W y|| (numpy lstsq on the
+    explicit A W) and leaves a residual orthogonal to A W."""
+    rng = np.random.default_rng(8)
+    n, k = 80, 12
+    A = np.eye(n) + 0.5 * latgen.complex_normal(rng, (n, n)) / np.sqrt(n)
+    Wv = latgen.complex_normal(rng, (k, n))
+    b = latgen.complex_normal(rng, (n,))
+    Q, Wp = sol.mr_deflation(lambda v: A @ v, Wv)
+    x0, r0 = sol.mr_deflate(Q, Wp, b)
+    AW = A @ Wv.T
+    y = np.linalg.lstsq(AW, b, rcond=None)[0]
+    assert np.linalg.norm(x0 - Wv.T @ y) <= 1e-12 * np.linalg.norm(x0)
+    assert np.linalg.norm(r0 - (b - A @ x0)) <= 1e-12 * np.linalg.norm(b)
+    assert np.linalg.norm(AW.conj().T @ r0) <= 1e-12 * np.linalg.norm(AW) * np.linalg.norm(b)
+    # the deflation directions are orthonormal
+    assert np.linalg.norm(Q.conj() @ Q.T - np.eye(k)) < 1e-12
