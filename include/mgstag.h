@@ -95,6 +95,11 @@ typedef struct {
                                 are kept in fine_prec */
   int32_t max_nrhs;          /* systems solved in lockstep (mass x rhs pairs) and largest nrhs of an apply */
   int32_t max_nmass;         /* KD inverse slots: masses in one lockstep batch (>= 1) */
+  int32_t coarsest_deflate;  /* deflation of the coarsest solve (Table 1): 0 for none, else the number k of
+                                low modes (multiple of 16, <= 64, <= max_nrhs), near-null vectors of the
+                                coarsest operator from CGNE at set-up; each coarsest solve then starts from
+                                the least-squares solution on their span */
+  int32_t deflate_maxiter;   /* CGNE iterations for the deflation vectors */
   uint64_t seed;             /* seed of the GPU-generated null-vector starts */
 } mg_params;
 

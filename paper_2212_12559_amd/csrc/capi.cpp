@@ -68,6 +68,8 @@ void mg_default_params(mg_params* p, const int32_t dims[4]) {
   p->coarse_prec = MG_C64;
   p->max_nrhs = 1;
   p->max_nmass = 1;
+  p->coarsest_deflate = 0;
+  p->deflate_maxiter = 300;
   p->seed = 20221224ull;
 }
 
@@ -322,9 +324,13 @@ mg_status mg_export(mg_ctx ctx, int32_t what, int32_t level, void* dst, size_t b
   if (what == 0) {
     need = (size_t)c.g0.V * 22 * 4;
   } else if (what == 1) {
-    if (level < 1 || level > c.P.nagg) return fail(MG_E_ARG, "level must be 1..nagg");
-    const Agg& a = c.A[level - 1];
-    need = (size_t)a.nvec * a.nagg * 2 * a.nrows * 16;
+    if (level == c.P.nagg + 1 && c.defl_k > 0) {
+      need = (size_t)c.defl_k * c.defl_n * 16;
+    } else {
+      if (level < 1 || level > c.P.nagg) return fail(MG_E_ARG, "level must be 1..nagg (nagg + 1: deflation vectors)");
+      const Agg& a = c.A[level - 1];
+      need = (size_t)a.nvec * a.nagg * 2 * a.nrows * 16;
+    }
   } else if (what == 2) {
     if (level < 2 || level > 1 + c.P.nagg) return fail(MG_E_ARG, "level must be 2..1+nagg");
     const int n = c.ncoarse[level - 2];
@@ -340,7 +346,7 @@ mg_status mg_export(mg_ctx ctx, int32_t what, int32_t level, void* dst, size_t b
     if (what == 0) {
       launch_export_fine_index((int32_t*)dst, c.g0, c.A[0], c.st);
     } else if (what == 1) {
-      hipError_t e = hipMemcpyAsync(dst, c.nv[level - 1], need, hipMemcpyDeviceToDevice, c.st);
+      hipError_t e = hipMemcpyAsync(dst, c.nv[level - 1], need, hipMemcpyDeviceToDevice, c.st);   // nv[nagg]: deflation
       if (e != hipSuccess) throw Error{MG_E_HIP, hipGetErrorString(e)};
     } else {
       launch_export_links(c.cl64[level - 2], (double2*)dst, c.gc[level - 2].V, c.ncoarse[level - 2], c.st);

@@ -220,6 +220,16 @@ void launch_gcr_update_cgs(const GcrUpdArgs<T>& a, double2* part, double2* res, 
 void launch_conv(int* mask, const double2* rn2, const double2* r0sq, double tol2, int nrhs, int init,
                  hipStream_t st);
 
+// Coarsest-level deflation (deflate.hip): at most kMaxDefl vectors.
+constexpr int kMaxDefl = 64;
+template <typename T>
+void launch_ts_gram(const T* A, int64_t lda, int ka, const T* B, int64_t ldb, int kb, int64_t n, double2* part,
+                    size_t part_elems, double2* C, hipStream_t st);
+template <typename T>
+void launch_ts_combine(T* out, int64_t ldo, const T* in, int64_t ldi, int ka, int kb, const double2* M, int64_t n,
+                       int mode, hipStream_t st);
+void launch_chol_rinv(const double2* G, int k, double2* R, double2* Rinv, int* status, hipStream_t st);
+
 // Multi-shift CG (Sec. 3.3).  Device state of the shifted systems, slots of
 // ld entries: per shift j at kMscPer * j + {zeta, previous zeta, alpha_j,
 // zeta'_j, beta_j, update flag, on flag, iteration count}; per rhs at

@@ -41,6 +41,9 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   if (p.outer_maxiter < 1) return fail("outer_maxiter must be >= 1");
   if (p.max_nrhs < 1 || p.max_nmass < 1) return fail("max_nrhs and max_nmass must be >= 1");
   if (!(p.mass0 > 0.0)) return fail("mass0 must be positive");
+  if (p.coarsest_deflate < 0 || p.coarsest_deflate > kMaxDefl || p.coarsest_deflate % 16)
+    return fail("coarsest_deflate must be 0, 16, 32, 48 or 64");
+  if (p.coarsest_deflate > 0 && p.deflate_maxiter < 1) return fail("deflate_maxiter must be >= 1");
   const bool naik_kd = p.c3 != 0.0 && p.kd_naik;
   Geom g0{};
   g0.V = 1;
@@ -80,6 +83,9 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     gcur = g;
     nin = a.nvec;
   }
+  const int kd = p.coarsest_deflate;
+  const int64_t ncl = gc[p.nagg - 1].V * 2 * A[p.nagg - 1].nvec;   // coarsest-level dof
+  if (kd > ncl) return fail("coarsest_deflate exceeds the coarsest level's dimension");
   if (c) {
     c->P = p;
     c->g0 = g0;
@@ -111,16 +117,28 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     cl32[l] = P(gc[l].V * 9 * n * n * 8);
     if (c16) cl16[l] = P(swizzled_link_elems(gc[l].V, (int)n) * 2);
   }
+  const int cprec_ = p.coarse_prec == MG_C128 ? P64 : P32;
+  void *nvd = nullptr, *dq = nullptr, *dw = nullptr, *dg = nullptr, *drm = nullptr, *dri = nullptr;
+  if (kd > 0) {
+    nvd = P((size_t)kd * ncl * 16);
+    dq = P((size_t)kd * ncl * csize(cprec_));
+    dw = P((size_t)kd * ncl * csize(cprec_));
+    dg = P((size_t)kd * kd * 16);
+    drm = P((size_t)kd * kd * 16);
+    dri = P((size_t)kd * kd * 16);
+  }
   void* status = P(256);
   // ---- scratch
-  const int ms = std::max({p.max_nrhs, p.nvec[0], p.nagg > 1 ? p.nvec[1] : 1});
+  const int ms = std::max({p.max_nrhs, p.nvec[0], p.nagg > 1 ? p.nvec[1] : 1, kd});
   auto S = [&](size_t n) { return scr.take(n); };
-  void* part = S((size_t)kMaxPairs * ms * 480 * 16);
+  const size_t part_elems = std::max((size_t)kMaxPairs * ms * 480, kd > 0 ? (size_t)128 * kMaxDefl * kMaxDefl : 0);
+  void* part = S(part_elems * 16);
   void* scal = S((size_t)4 * kMaxSlots * ms * 16);
   void* tri = S((size_t)4 * kTriSlots * ms * 16);
   void* m64 = S((size_t)ms * 8);
   void* m32 = S((size_t)ms * 4);
   void* mask = S((size_t)4 * ms * 4);
+  void* dcoef = kd > 0 ? S((size_t)kd * ms * 16) : nullptr;
   const size_t solver_base = scr.off;
   // solver buffers
   LevelBufs L[4];
@@ -180,6 +198,15 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     }
     setup_end = std::max(setup_end, e);
   }
+  if (kd > 0) {   // CGNE on the coarsest operator: six k-vector blocks, its adjoint links (+ 16-bit fragments)
+    const int lc = p.nagg - 1;
+    const int64_t nc = 2 * A[lc].nvec;
+    size_t e = solver_base + 6 * (((size_t)kd * ncl * csize(cprec_) + 255) & ~(size_t)255) +
+               3 * (((size_t)ncl * 16 + 255) & ~(size_t)255) + 256;
+    e += (size_t)gc[lc].V * 9 * nc * nc * csize(cprec_) + 256;
+    if (c16) e += (size_t)swizzled_link_elems(gc[lc].V, (int)nc) * 2 + 256;
+    setup_end = std::max(setup_end, e);
+  }
   scr.off = std::max(solver_end, setup_end);
   if (c) {
     c->fat64 = (double2*)fat64; c->fat32 = (float2*)fat32;
@@ -198,6 +225,16 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     c->status_dev = (int*)status;
     c->max_sys = ms;
     c->part = (double2*)part;
+    c->part_elems = part_elems;
+    c->defl_k = kd;
+    c->defl_n = ncl;
+    c->nv[p.nagg] = (double2*)nvd;
+    c->defl_q = dq;
+    c->defl_w = dw;
+    c->defl_g = (double2*)dg;
+    c->defl_rm = (double2*)drm;
+    c->defl_rinv = (double2*)dri;
+    c->defl_c = (double2*)dcoef;
     c->scal = (double2*)scal;
     c->tri = (double2*)tri;
     c->mass64 = (double*)m64;
@@ -605,6 +642,8 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   dots(prec, n, nsys, {{B.b.p, B.b.p}}, r0);
   launch_conv(lmask(lvl), nullptr, r0, tol * tol, nsys, 1, st);
   check_launch();
+  const bool deflated = coarsest && defl_k > 0;
+  if (deflated) deflate_start(lvl, nsys);   // x = W' Q^H b, r = b - Q Q^H b
   bool live = true;
   for (int cyc = 0; cyc < cycles && live; ++cyc) {
     if (cyc > 0) {   // restart: r = b - A x
@@ -624,7 +663,31 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
         if (!any_active(lvl, nsys)) { live = false; break; }
       }
     }
-    gcr_flush(lvl, B, nk, nsys, cyc > 0);
+    gcr_flush(lvl, B, nk, nsys, cyc > 0 || deflated);
+  }
+}
+
+// Deflated start of the coarsest solve, 64 systems per pass:
+// c = Q^H r, x = W' c, r -= Q c.
+void Ctx::deflate_start(int lvl, int nsys) {
+  LevelBufs& B = L[lvl];
+  const int64_t n = B.n;
+  for (int s0 = 0; s0 < nsys; s0 += kMaxDefl) {
+    const int ns = std::min(kMaxDefl, nsys - s0);
+    if (B.prec == P64) {
+      double2* r = (double2*)B.r.p + (int64_t)s0 * n;
+      double2* x = (double2*)B.x.p + (int64_t)s0 * n;
+      launch_ts_gram<double2>((const double2*)defl_q, n, defl_k, r, n, ns, n, part, part_elems, defl_c, st);
+      launch_ts_combine<double2>(x, n, (const double2*)defl_w, n, defl_k, ns, defl_c, n, 0, st);
+      launch_ts_combine<double2>(r, n, (const double2*)defl_q, n, defl_k, ns, defl_c, n, -1, st);
+    } else {
+      float2* r = (float2*)B.r.p + (int64_t)s0 * n;
+      float2* x = (float2*)B.x.p + (int64_t)s0 * n;
+      launch_ts_gram<float2>((const float2*)defl_q, n, defl_k, r, n, ns, n, part, part_elems, defl_c, st);
+      launch_ts_combine<float2>(x, n, (const float2*)defl_w, n, defl_k, ns, defl_c, n, 0, st);
+      launch_ts_combine<float2>(r, n, (const float2*)defl_q, n, defl_k, ns, defl_c, n, -1, st);
+    }
+    check_launch();
   }
 }
 

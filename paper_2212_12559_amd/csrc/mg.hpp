@@ -64,7 +64,17 @@ struct Ctx {
   float2* kinv32 = nullptr;
   int64_t kinv_slot = 0;    // complex per slot
   std::vector<double> kd_mass;   // mass of each slot (NaN: empty)
-  double2* nv[2]{};         // null vectors, canonical per-level layout
+  double2* nv[3]{};         // null vectors, canonical per-level layout; nv[nagg]: coarsest deflation vectors
+  // coarsest deflation: k vectors of n; Q = A W R^{-1}, W' = W R^{-1} (level precision),
+  // coefficients c [k][max_sys], Gram / R / R^{-1} k x k (FP64)
+  int defl_k = 0;
+  int64_t defl_n = 0;
+  void* defl_q = nullptr;
+  void* defl_w = nullptr;
+  double2* defl_c = nullptr;
+  double2* defl_g = nullptr;
+  double2* defl_rm = nullptr;
+  double2* defl_rinv = nullptr;
   double2 *pp64[2]{}, *pr64[2]{};
   float2 *pp32[2]{}, *pr32[2]{};
   double2* cl64[2]{};       // coarse links of levels 2 and 3
@@ -88,6 +98,7 @@ struct Ctx {
   // scratch (set-up, aliases the solver scratch)
   char* scratch_base = nullptr;
   size_t scratch_cap = 0;
+  size_t part_elems = 0;     // double2 entries of the reduction partials
 
   // current batch
   int nsys = 0;
@@ -154,7 +165,9 @@ struct Ctx {
                       mg_solve_info* info);
   void update_links(const void* fat, const void* naik);
   void build_level(int l, const void* nv_import);
-  void cgne_null(int l);
+  void cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2* out);
+  void build_deflation();
+  void deflate_start(int lvl, int nsys);
   void galerkin(int l);
 };
 

@@ -31,6 +31,7 @@ void Ctx::setup(const void* fat, const void* naik, const void* const* nvs) {
   rhs_per_slot = 0;
   setup_phase = true;
   for (int l = 0; l < P.nagg; ++l) build_level(l, nvs ? nvs[l] : nullptr);
+  if (defl_k > 0) build_deflation();
   setup_phase = false;
   HIPCHK(hipStreamSynchronize(st));
 }
@@ -41,7 +42,7 @@ void Ctx::build_level(int l, const void* imp) {
   if (imp) {
     HIPCHK(hipMemcpyAsync(nv[l], imp, (size_t)a.nvec * nflat * 16, hipMemcpyDeviceToDevice, st));
   } else {
-    cgne_null(l);
+    cgne_null(l, a.nvec, nflat, P.setup_maxiter[l], P.setup_tol[l], nv[l]);
   }
   launch_gather_null(nv[l], nflat, pp64[l], a, st);
   check_launch();
@@ -60,13 +61,14 @@ void Ctx::build_level(int l, const void* imp) {
 // Near-null vectors by CGNE on A phi = 0 from seeded random starts, all nvec
 // vectors as one batch (Sec. 2.1, Table 1: CGNE to tol or maxiter):
 //   t = A^dag p, alpha = |r|^2 / |t|^2, phi += alpha t, r -= alpha A t, ...
-// Level 1: A = (B + m0)^{-1} D, A^dag = eps D (B + m0)^{-1} eps.
-// Level 2: the level-2 coarse operator and its adjoint stencil.
-void Ctx::cgne_null(int l) {
-  const Agg& a = A[l];
-  const int nv_ = a.nvec;
-  const int64_t n = a.nagg * 2 * a.nrows;
+// l = 0: A = (B + m0)^{-1} D, A^dag = eps D (B + m0)^{-1} eps.
+// l >= 1: the coarse operator of level l + 1 and its adjoint stencil.
+// nvec vectors of n entries; the result goes to `out` (FP64) and stays in
+// the first scratch block in the level's precision.
+void Ctx::cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2* out) {
+  const int nv_ = nvec;
   const int prec = L[l + 1].prec;
+  const int lc = l - 1;   // coarse-level index of the operator for l >= 1
   const size_t vb = ((size_t)nv_ * n * csize(prec) + 255) & ~(size_t)255;
   char* base = scratch_base;
   void* phi = base;
@@ -78,17 +80,17 @@ void Ctx::cgne_null(int l) {
   // past the six CGNE vectors and the three Galerkin vectors
   void* dagl = nullptr;
   uint16_t* dag16 = nullptr;
-  if (l == 1) {
+  if (l >= 1) {
     const size_t gb = ((size_t)n * 16 + 255) & ~(size_t)255;
     dagl = base + 6 * vb + 3 * gb;
-    const int nc = ncoarse[0];
-    if (prec == P64) launch_dagger_links<double2>(cl64[0], (double2*)dagl, gc[0], nc, st);
-    else launch_dagger_links<float2>(cl32[0], (float2*)dagl, gc[0], nc, st);
+    const int nc = ncoarse[lc];
+    if (prec == P64) launch_dagger_links<double2>(cl64[lc], (double2*)dagl, gc[lc], nc, st);
+    else launch_dagger_links<float2>(cl32[lc], (float2*)dagl, gc[lc], nc, st);
     check_launch();
     if (fmt16 >= 0) {
       // 16-bit operator: the set-up iterates with the links the solver applies
-      dag16 = (uint16_t*)((char*)dagl + (((size_t)gc[0].V * 9 * nc * nc * csize(prec) + 255) & ~(size_t)255));
-      launch_swizzle_links<float2>((const float2*)dagl, dag16, gc[0].V, nc, fmt16, 1.0 / cl16_inv_scale[0], st);
+      dag16 = (uint16_t*)((char*)dagl + (((size_t)gc[lc].V * 9 * nc * nc * csize(prec) + 255) & ~(size_t)255));
+      launch_swizzle_links<float2>((const float2*)dagl, dag16, gc[lc].V, nc, fmt16, 1.0 / cl16_inv_scale[lc], st);
       check_launch();
     }
   }
@@ -105,30 +107,30 @@ void Ctx::cgne_null(int l) {
     } else if (fmt16 >= 0 && prec == P32) {
       setup_phase = false;   // the 16-bit matrix-core stencil, forward or adjoint links
       if (!dag) {
-        apply_coarse(2, prec, out, in, nv_, false);
+        apply_coarse(l + 1, prec, out, in, nv_, false);
       } else {
         CoarseMfmaArgs c{};
         c.out = (float2*)out; c.in = (const float2*)in; c.links = dag16;
-        c.g = gc[0]; c.n = ncoarse[0]; c.in_stride = c.out_stride = gc[0].V * ncoarse[0]; c.nrhs = nv_;
-        c.inv_scale = cl16_inv_scale[0];
+        c.g = gc[lc]; c.n = ncoarse[lc]; c.in_stride = c.out_stride = gc[lc].V * ncoarse[lc]; c.nrhs = nv_;
+        c.inv_scale = cl16_inv_scale[lc];
         launch_coarse_mfma(c, fmt16, st);
         check_launch();
       }
       setup_phase = true;
     } else if (!dag) {
-      apply_coarse(2, prec, out, in, nv_, false);
+      apply_coarse(l + 1, prec, out, in, nv_, false);
     } else {
       // the adjoint stencil through its explicit links (coalesced)
-      const int nc = ncoarse[0];
+      const int nc = ncoarse[lc];
       if (prec == P64) {
         CoarseArgs<double, double2> c{};
         c.out = (double2*)out; c.in = (const double2*)in; c.links = (const double2*)dagl;
-        c.g = gc[0]; c.n = nc; c.in_stride = c.out_stride = gc[0].V * nc; c.nrhs = nv_;
+        c.g = gc[lc]; c.n = nc; c.in_stride = c.out_stride = gc[lc].V * nc; c.nrhs = nv_;
         launch_coarse(c, false, false, st);
       } else {
         CoarseArgs<float, float2> c{};
         c.out = (float2*)out; c.in = (const float2*)in; c.links = (const float2*)dagl;
-        c.g = gc[0]; c.n = nc; c.in_stride = c.out_stride = gc[0].V * nc; c.nrhs = nv_;
+        c.g = gc[lc]; c.n = nc; c.in_stride = c.out_stride = gc[lc].V * nc; c.nrhs = nv_;
         launch_coarse(c, false, false, st);
       }
       check_launch();
@@ -152,7 +154,7 @@ void Ctx::cgne_null(int l) {
   int* mk = lmask(3);
   HIPCHK(hipMemcpyAsync(mk, act.data(), nv_ * sizeof(int), hipMemcpyHostToDevice, st));
   int nact = nv_;
-  for (int it = 0; it < P.setup_maxiter[l] && nact > 0; ++it) {
+  for (int it = 0; it < maxiter && nact > 0; ++it) {
     A_apply(t, p, true);
     A_apply(At, t, false);
     dots(prec, n, nv_, {{t, t}}, tt);
@@ -166,12 +168,47 @@ void Ctx::cgne_null(int l) {
     lincomb(prec, n, nv_, p, {{r, nullptr}, {p, be}}, {}, {});
     bool changed = false;
     for (int s = 0; s < nv_; ++s)
-      if (act[s] && !(rn[s] > P.setup_tol[l] * r0[s])) { act[s] = 0; --nact; changed = true; }
+      if (act[s] && !(rn[s] > tol * r0[s])) { act[s] = 0; --nact; changed = true; }
     if (changed) HIPCHK(hipMemcpyAsync(mk, act.data(), nv_ * sizeof(int), hipMemcpyHostToDevice, st));
   }
-  if (prec == P64) launch_convert<double2, double2>(nv[l], (const double2*)phi, (int64_t)nv_ * n, st);
-  else launch_convert<float2, double2>(nv[l], (const float2*)phi, (int64_t)nv_ * n, st);
+  if (prec == P64) launch_convert<double2, double2>(out, (const double2*)phi, (int64_t)nv_ * n, st);
+  else launch_convert<float2, double2>(out, (const float2*)phi, (int64_t)nv_ * n, st);
   check_launch();
+}
+
+// Deflation space of the coarsest solve (Table 1 deflates it with low modes of
+// its operator): k near-null vectors W of the coarsest operator A by CGNE,
+// Z = A W with the stencil the solver applies, Z^H Z = R^H R (Cholesky, FP64),
+// Q = Z R^{-1} and W' = W R^{-1}.
+void Ctx::build_deflation() {
+  const int lv = nlev - 1;
+  const int k = defl_k;
+  const int64_t n = defl_n;
+  const int prec = L[lv].prec;
+  cgne_null(P.nagg, k, n, P.deflate_maxiter, 1e-6, nv[P.nagg]);
+  const size_t vb = ((size_t)k * n * csize(prec) + 255) & ~(size_t)255;
+  void* W = scratch_base;        // CGNE result, level precision
+  void* Z = scratch_base + vb;
+  setup_phase = false;
+  apply_coarse(lv, prec, Z, W, k, false);
+  setup_phase = true;
+  HIPCHK(hipMemsetAsync(status_dev, 0, sizeof(int), st));
+  if (prec == P64) {
+    launch_ts_gram<double2>((const double2*)Z, n, k, (const double2*)Z, n, k, n, part, part_elems, defl_g, st);
+    launch_chol_rinv(defl_g, k, defl_rm, defl_rinv, status_dev, st);
+    launch_ts_combine<double2>((double2*)defl_q, n, (const double2*)Z, n, k, k, defl_rinv, n, 0, st);
+    launch_ts_combine<double2>((double2*)defl_w, n, (const double2*)W, n, k, k, defl_rinv, n, 0, st);
+  } else {
+    launch_ts_gram<float2>((const float2*)Z, n, k, (const float2*)Z, n, k, n, part, part_elems, defl_g, st);
+    launch_chol_rinv(defl_g, k, defl_rm, defl_rinv, status_dev, st);
+    launch_ts_combine<float2>((float2*)defl_q, n, (const float2*)Z, n, k, k, defl_rinv, n, 0, st);
+    launch_ts_combine<float2>((float2*)defl_w, n, (const float2*)W, n, k, k, defl_rinv, n, 0, st);
+  }
+  check_launch();
+  int status = 0;
+  HIPCHK(hipMemcpyAsync(&status, status_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (status) throw Error{MG_E_RANK, "coarsest deflation vectors are numerically dependent"};
 }
 
 // Galerkin coarse operator (Sec. 2.1: A_c = R A P), built column by column

@@ -46,6 +46,8 @@ class MGParams(ctypes.Structure):
         ("coarse_prec", ctypes.c_int32),
         ("max_nrhs", ctypes.c_int32),
         ("max_nmass", ctypes.c_int32),
+        ("coarsest_deflate", ctypes.c_int32),
+        ("deflate_maxiter", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 

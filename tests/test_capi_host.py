@@ -32,7 +32,7 @@ def test_header_symbols_exported(m):
 
 def test_params_struct_matches_header(m):
     # sizeof(mg_params) as laid out by the C compiler equals the ctypes mirror
-    assert ctypes.sizeof(m.MGParams) == 200
+    assert ctypes.sizeof(m.MGParams) == 208
     assert ctypes.sizeof(m.MGSolveInfo) == 48
 
 
@@ -56,6 +56,10 @@ def test_default_params_table1(m):
     (dict(inner_maxiter=0), "inner_maxiter"),
     (dict(fine_prec=7), "fine_prec"),
     (dict(mass0=0.0), "mass0"),
+    (dict(coarsest_deflate=20), "coarsest_deflate"),
+    (dict(coarsest_deflate=80), "coarsest_deflate"),
+    (dict(coarsest_deflate=16, deflate_maxiter=0), "deflate_maxiter"),
+    (dict(dims=(8, 8, 8, 8), nvec=(8, 8), coarsest_deflate=32), "dimension"),
 ])
 def test_workspace_validation(m, bad, why):
     bad = dict(bad)
@@ -65,6 +69,17 @@ def test_workspace_validation(m, bad, why):
         m.workspace_bytes(p)
     assert e.value.status == m.MG_E_CONFIG
     assert why.lower() in str(e.value).lower()
+
+
+def test_deflation_workspace(m):
+    """Deflation vectors add persistent storage (FP64 vectors, Q and W' in the
+    coarse precision) and set-up scratch for their CGNE."""
+    base = m.workspace_bytes(m.default_params((32, 32, 32, 32)))
+    p = m.default_params((32, 32, 32, 32), coarsest_deflate=64)
+    pd, sd = m.workspace_bytes(p)
+    n = 4 ** 4 * 2 * 96                      # coarsest level of the default 32^4 hierarchy
+    assert pd - base[0] >= 64 * n * (16 + 8 + 8)
+    assert sd >= base[1]
 
 
 def test_workspace_sizes_scale(m):
