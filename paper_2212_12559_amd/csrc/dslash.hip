@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(const DslashArgs<R> a) {
 // and only the +-z, +-t neighbours and the links are read per site (the
 // per-site reads are what bound the plain kernel: address processing, not
 // bytes).
-template <int NR>
+template <int NR, bool PAIRS>
 __global__ void __launch_bounds__(256) dslash_plane_kernel(const DslashArgs<float> a) {
   using T = float2;
   extern __shared__ float4 lds4[];
@@ -198,11 +198,25 @@ __global__ void __launch_bounds__(256) dslash_plane_kernel(const DslashArgs<floa
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     const T* L = a.fat + (int64_t)mu * 9 * V;
+    const float4* Lp = a.fat_pairs + (int64_t)mu * 5 * V;
+    // the nine link elements at site q: nine 8-byte loads, or five 16-byte ones
+    auto load_link = [&](T (&U)[9], int64_t q) {
+      if constexpr (PAIRS) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const float4 w = Lp[k * V + q];
+          U[2 * k] = make_float2(w.x, w.y);
+          if (2 * k + 1 < 9) U[2 * k + 1] = make_float2(w.z, w.w);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) U[k] = L[k * V + q];
+      }
+    };
     {   // forward hop: W'(x) x(x + mu)
       const int64_t sf = mu >= 2 ? site_shift(c, mu, 1, a.g) : 0;
       T U[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) U[k] = L[k * V + s];
+      load_link(U, s);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         if (r < nr) {
@@ -226,8 +240,7 @@ __global__ void __launch_bounds__(256) dslash_plane_kernel(const DslashArgs<floa
     {   // backward hop: -W'(x - mu)^dag x(x - mu)
       const int64_t sb = site_shift(c, mu, -1, a.g);
       T U[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) U[k] = L[k * V + sb];
+      load_link(U, sb);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         if (r < nr) {
@@ -280,7 +293,8 @@ static bool launch_plane(const DslashArgs<float>& a, hipStream_t st) {
   if (lds > 65536) return false;
   const int64_t nplane = a.g.V / 256;
   dim3 grid((unsigned)(nplane * ((a.nrhs + NR - 1) / NR)));
-  dslash_plane_kernel<NR><<<grid, 256, lds, st>>>(a);
+  if (a.fat_pairs) dslash_plane_kernel<NR, true><<<grid, 256, lds, st>>>(a);
+  else dslash_plane_kernel<NR, false><<<grid, 256, lds, st>>>(a);
   return true;
 }
 
@@ -322,9 +336,10 @@ template void launch_dslash<float>(const DslashArgs<float>&, bool, bool, bool, h
 template void launch_dslash<double>(const DslashArgs<double>&, bool, bool, bool, hipStream_t);
 
 // Canonical links [4][T][Z][Y][X][3][3] (complex128) -> internal structure of
-// arrays with (c/2) eta_mu(x) folded in; FP64 and FP32 copies.
+// arrays with (c/2) eta_mu(x) folded in; FP64 and FP32 copies, and optionally
+// the FP32 elements in pairs (one 16-byte load for two of them).
 __global__ void pack_links_kernel(const double2* __restrict__ src, double2* __restrict__ d64,
-                                  float2* __restrict__ d32, Geom g, double coef) {
+                                  float2* __restrict__ d32, float4* __restrict__ d32p, Geom g, double coef) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= 4 * g.V) return;
   const int mu = (int)(tid / g.V);
@@ -338,12 +353,20 @@ __global__ void pack_links_kernel(const double2* __restrict__ src, double2* __re
     d64[((int64_t)mu * 9 + k) * g.V + s] = w;
     if (d32) d32[((int64_t)mu * 9 + k) * g.V + s] = make_float2((float)w.x, (float)w.y);
   }
+  if (d32p) {
+    for (int q = 0; q < 5; ++q) {
+      const double2 v0 = src[tid * 9 + 2 * q];
+      const double2 v1 = 2 * q + 1 < 9 ? src[tid * 9 + 2 * q + 1] : make_double2(0.0, 0.0);
+      d32p[((int64_t)mu * 5 + q) * g.V + s] =
+          make_float4((float)(f * v0.x), (float)(f * v0.y), (float)(f * v1.x), (float)(f * v1.y));
+    }
+  }
 }
 
-void launch_pack_links(const double2* src, double2* d64, float2* d32, const Geom& g, double coef,
+void launch_pack_links(const double2* src, double2* d64, float2* d32, float4* d32p, const Geom& g, double coef,
                        hipStream_t st) {
   const int64_t n = 4 * g.V;
-  pack_links_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, d64, d32, g, coef);
+  pack_links_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, d64, d32, d32p, g, coef);
 }
 
 // Index tables of the fine lattice exactly as the kernels compute them, for

@@ -15,6 +15,7 @@ struct DslashArgs {
   const cplx<R>* xs;        // checkerboard mode: optional same-parity addend
   const cplx<R>* fat;       // [4][9][V], (c1/2) eta folded in
   const cplx<R>* lng;       // [4][9][V], (c3/2) eta folded in
+  const float4* fat_pairs;  // optional FP32 one-hop links as element pairs [4][5][V] (last pair padded)
   Geom g;
   int64_t in_stride, out_stride, xs_stride;   // per rhs, complex elements
   int nrhs;
@@ -28,7 +29,7 @@ struct DslashArgs {
 };
 template <typename R>
 void launch_dslash(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st);
-void launch_pack_links(const double2* src, double2* d64, float2* d32, const Geom& g, double coef,
+void launch_pack_links(const double2* src, double2* d64, float2* d32, float4* d32p, const Geom& g, double coef,
                        hipStream_t st);
 void launch_export_fine_index(int32_t* out, const Geom& g, const Agg& A, hipStream_t st);
 template <typename T>

@@ -97,6 +97,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   // ---- persistent
   void* fat64 = P(36 * V * 16);
   void* fat32 = P(36 * V * 8);
+  void* fat32p = P(20 * V * 16);   // FP32 one-hop links in element pairs
   void* lng64 = p.c3 != 0.0 ? P(36 * V * 16) : nullptr;
   void* lng32 = p.c3 != 0.0 ? P(36 * V * 8) : nullptr;
   const int64_t kslot = V / 16 * 2304;
@@ -209,7 +210,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   }
   scr.off = std::max(solver_end, setup_end);
   if (c) {
-    c->fat64 = (double2*)fat64; c->fat32 = (float2*)fat32;
+    c->fat64 = (double2*)fat64; c->fat32 = (float2*)fat32; c->fat32p = (float4*)fat32p;
     c->lng64 = (double2*)lng64; c->lng32 = (float2*)lng32;
     c->kinv64 = (double2*)kinv64; c->kinv32 = (float2*)kinv32;
     c->kinv_slot = kslot;
@@ -273,6 +274,7 @@ static DslashArgs<R> dslash_args(const Ctx& c, void* out, const void* in, int ns
   const bool d = sizeof(R) == 8;
   a.fat = d ? (const cplx<R>*)c.fat64 : (const cplx<R>*)c.fat32;
   a.lng = d ? (const cplx<R>*)c.lng64 : (const cplx<R>*)c.lng32;
+  a.fat_pairs = d ? nullptr : c.fat32p;
   a.g = c.g0;
   a.in_stride = a.out_stride = a.xs_stride = c.g0.V * 3;
   a.nrhs = nsys;

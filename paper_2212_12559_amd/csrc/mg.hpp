@@ -60,6 +60,7 @@ struct Ctx {
   // persistent
   double2 *fat64 = nullptr, *lng64 = nullptr;
   float2 *fat32 = nullptr, *lng32 = nullptr;
+  float4* fat32p = nullptr;   // FP32 fat links as element pairs [4][5][V]
   double2* kinv64 = nullptr;
   float2* kinv32 = nullptr;
   int64_t kinv_slot = 0;    // complex per slot

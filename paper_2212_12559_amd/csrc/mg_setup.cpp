@@ -21,10 +21,10 @@ static void check_launch() {
 }
 
 void Ctx::setup(const void* fat, const void* naik, const void* const* nvs) {
-  launch_pack_links((const double2*)fat, fat64, fat32, g0, 0.5 * P.c1, st);
+  launch_pack_links((const double2*)fat, fat64, fat32, fat32p, g0, 0.5 * P.c1, st);
   check_launch();
   if (P.c3 != 0.0) {
-    launch_pack_links((const double2*)naik, lng64, lng32, g0, 0.5 * P.c3, st);
+    launch_pack_links((const double2*)naik, lng64, lng32, nullptr, g0, 0.5 * P.c3, st);
     check_launch();
   }
   ensure_kd({P.mass0});

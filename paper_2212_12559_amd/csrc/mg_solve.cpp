@@ -150,10 +150,10 @@ void Ctx::solve_backward(double mass, const void* phi, void* X, void* Y, void* g
 // operators stay those built at set-up (the hierarchy is then a
 // preconditioner for a nearby operator; the outer solve is exact).
 void Ctx::update_links(const void* fat, const void* naik) {
-  launch_pack_links((const double2*)fat, fat64, fat32, g0, 0.5 * P.c1, st);
+  launch_pack_links((const double2*)fat, fat64, fat32, fat32p, g0, 0.5 * P.c1, st);
   check_launch();
   if (P.c3 != 0.0) {
-    launch_pack_links((const double2*)naik, lng64, lng32, g0, 0.5 * P.c3, st);
+    launch_pack_links((const double2*)naik, lng64, lng32, nullptr, g0, 0.5 * P.c3, st);
     check_launch();
   }
   for (auto& m : kd_mass) m = NAN;
