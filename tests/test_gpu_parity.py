@@ -149,8 +149,8 @@ def test_plane_staged_stencil(torch, mg, dims):
     """The one-hop FP32 stencil with in-plane neighbours staged in LDS (used
     when 256 / L0 x-rows tile the y extent): one y block that wraps onto
     itself (16 x 16) and two y blocks (32 x 16); 1, 5, 9 and 17 rhs cover the
-    1- and 4-rhs tiles with ragged ends.  Checked through A = (B+m)^{-1} D
-    with the Naik term truncated in the KD level."""
+    1- and 4-rhs tiles with ragged ends.  Checked through A = (B+m)^{-1} D and
+    A^dag = eps D (B+m)^{-1} eps with the Naik term truncated in the KD level."""
     W, N, rng = latgen.hisq_style_links(dims, 0.5, 777)
     cfg = dict(dims=dims, c1=9.0 / 8.0, c3=-1.0 / 24.0, kd_naik=0, blocks=[(4, 4, 4, 4)], nvec=(8,), mass0=0.05)
     nvs = [latgen.fine_vectors(dims, 8, rng)]
@@ -163,11 +163,15 @@ def test_plane_staged_stencil(torch, mg, dims):
         x = latgen.fine_vectors(dims, nrhs, rng)
         log(f"[plane] {dims} nrhs {nrhs}")
         y = ctx.apply_dslash(1, m, torch.from_numpy(x).to("cuda:0").to(torch.complex64))
+        yd = ctx.apply_dslash(4, m, torch.from_numpy(x).to("cuda:0").to(torch.complex64))
         torch.cuda.synchronize()
         y = y.to(torch.complex128).cpu().numpy()
+        yd = yd.to(torch.complex128).cpu().numpy()
         for r in range(nrhs):
             want = ops.kd_operator(x[r], W, N, Kinv, m, cfg["c1"], 0.0)
             assert rel_err(y[r], want) < TOL32, (dims, nrhs, r)
+            want = ops.kd_operator_dagger(x[r], W, N, Kinv, m, cfg["c1"], 0.0)
+            assert rel_err(yd[r], want) < TOL32, ("dag", dims, nrhs, r)
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])

@@ -141,6 +141,30 @@ def test_lockstep_16rhs_two_masses_bf16(torch, mg, cubic):
             assert true_rel(cfg, W, N, m, x[j, r], b[r]) <= 1e-10, (m, r)
 
 
+def test_lockstep_truncated_kd_matches_solo(torch, mg, cubic):
+    """Truncated KD level in FP32 (plane-staged stencil with per-rhs masses,
+    KD inverse with per-mass slots): a lockstep batch of 2 masses x 16 rhs
+    gives every system the iterations and solution of that mass solved alone
+    (systems are independent in a batch), all at true residual 1e-10."""
+    cfg, W, N, nvs, b0 = cubic
+    cfg = dict(cfg, kd_naik=0)
+    rng = np.random.default_rng(41)
+    b = latgen.fine_vectors(cfg["dims"], 16, rng)
+    bt = torch.from_numpy(b).to("cuda:0")
+    masses = [0.05, 0.11]
+    log("[solve] truncated KD, 2 masses x 16 rhs lockstep vs solo")
+    ctx = make_ctx(torch, mg, cfg, W, N, nvs, max_nrhs=32, max_nmass=2)
+    x, info, st = ctx.solve(masses, bt, tol=1e-10)
+    x = x.cpu().numpy()
+    for j, m in enumerate(masses):
+        xs, infos, sts = ctx.solve([m], bt, tol=1e-10)
+        xs = xs.cpu().numpy()[0]
+        for r in (0, 7, 15):
+            assert info[j * 16 + r]["outer_iters"] == infos[r]["outer_iters"], (m, r)
+            assert true_rel(cfg, W, N, m, x[j, r], b[r]) <= 1e-10
+            assert np.linalg.norm(x[j, r] - xs[r]) <= 1e-6 * np.linalg.norm(xs[r]), (m, r)
+
+
 def test_c0_exact_two_level(torch, mg):
     """4^4 naive, KD + 2^4 aggregation with Nvec = 24 (square, unitary P): with
     the coarsest level solved to 1e-14 the K-cycle is the exact inverse and the
