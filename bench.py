@@ -39,6 +39,12 @@ WORKLOADS = {
     "force24": dict(dims=(24, 24, 24, 24), mass=0.01, nrhs=1, eps=0.5, seed=20221228, kd_naik=0,
                     nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 300), kind="force",
                     coarse_prec="bf16"),
+    # uneven batch: 12 systems on each of 8^4, 12^4, 16^4 and 24^4, every lattice with its own fields and
+    # hierarchy (KD + one aggregation, Nvec 48: coarse 2^4, 3^4, 4^4, 6^4 with 96 dof per site), solved one
+    # lattice after another and then all four at once on separate streams
+    "uneven": dict(dims_list=((8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (24, 24, 24, 24)), mass=0.01,
+                   nrhs=12, eps=0.5, seed=20221229, kd_naik=0, nvec=(48,), blocks=[(4, 4, 4, 4)],
+                   setup_iters=(300,), kind="uneven", coarse_prec="bf16"),
     # 16^4 HISQ-style, mass 0.01
     "c1": dict(dims=(16, 16, 16, 16), mass=0.01, nrhs=1, eps=0.5, seed=20221225, kd_naik=0,
                nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 2000)),
@@ -332,6 +338,84 @@ def force_bench(args, wl, torch, latgen, mg):
     print(json.dumps(out), flush=True)
 
 
+def uneven_bench(args, wl, torch, latgen, mg):
+    """Uneven batch: one context (fields, hierarchy, workspaces) per lattice
+    size, 12 systems each.  The lattices are solved one after another, then
+    all at once from one host thread and one HIP stream per lattice (the
+    library holds no global state; each solve synchronises its own stream).
+    Reports per-lattice latency in both modes and the aggregate systems/s."""
+    import threading
+    m, nr = wl["mass"], wl["nrhs"]
+    dev = "cuda:0"
+    cp = {"fp32": mg.MG_C64, "bf16": mg.MG_CBF16, "fp16": mg.MG_CF16}[args.coarse_prec or wl.get("coarse_prec", "fp32")]
+    setup_iters = tuple(int(v) for v in args.setup_iters.split(",")) if args.setup_iters else wl["setup_iters"]
+    probs = []
+    for i, dims in enumerate(wl["dims_list"]):
+        W, N, rng = latgen.hisq_style_links(dims, wl["eps"], wl["seed"] + i)
+        b = torch.from_numpy(latgen.fine_vectors(dims, nr, rng)).to(dev)
+        p = mg.default_params(dims, mass0=m, nagg=1, nvec=wl["nvec"], block=wl["blocks"],
+                              setup_maxiter=setup_iters + (1,), max_nrhs=nr, kd_naik=wl["kd_naik"], coarse_prec=cp,
+                              outer_nkrylov=8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = mg.setup(p, torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev))
+        xk = torch.zeros((1,) + ctx.fine_shape, dtype=torch.complex64, device=dev)
+        ctx.apply_dslash(2, m, xk)   # the KD inverse of the mass, outside the timed solves
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        log(f"[bench] uneven {dims}: setup {setup_s:.2f} s")
+        probs.append({"dims": dims, "ctx": ctx, "b": b, "setup_s": setup_s})
+    for pr in probs:   # warm-up solve of each lattice
+        pr["ctx"].solve([m], pr["b"], tol=1e-10)
+    torch.cuda.synchronize()
+    seq = []
+    t0 = time.perf_counter()
+    for pr in probs:
+        t1 = time.perf_counter()
+        x, info, st = pr["ctx"].solve([m], pr["b"], tol=1e-10)
+        torch.cuda.synchronize()
+        seq.append({"s": time.perf_counter() - t1, "outer": max(i["outer_iters"] for i in info),
+                    "residual": max(i["true_rel_residual"] for i in info)})
+        del x
+    seq_s = time.perf_counter() - t0
+    conc = [None] * len(probs)
+
+    def run(k):
+        pr = probs[k]
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            t1 = time.perf_counter()
+            x, info, st = pr["ctx"].solve([m], pr["b"], tol=1e-10)
+            stream.synchronize()
+            conc[k] = {"s": time.perf_counter() - t1, "outer": max(i["outer_iters"] for i in info),
+                       "residual": max(i["true_rel_residual"] for i in info)}
+    threads = [threading.Thread(target=run, args=(k,)) for k in range(len(probs))]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    conc_s = time.perf_counter() - t0
+    nsys = nr * len(probs)
+    for pr, a, c in zip(probs, seq, conc):
+        log(f"[bench] uneven {pr['dims']}: alone {a['s']:.2f} s ({a['outer']} outer), concurrent {c['s']:.2f} s, "
+            f"residual {max(a['residual'], c['residual']):.2e}")
+    log(f"[bench] uneven: one after another {seq_s:.2f} s, concurrent {conc_s:.2f} s")
+    out = {"metric": "uneven batch: 4 lattices (8^4..24^4) x 12 systems to 1e-10, wall time with one stream per "
+                     "lattice", "value": conc_s, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": conc_s * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c128 outer / c64 K-cycle", "data": "synthetic",
+           "config": {"workload": f"HISQ-style eps 0.5 lattices {[list(p['dims']) for p in probs]}, mass {m}, "
+                                  f"{nr} rhs each, truncated-KD={not wl['kd_naik']}, KD + 4^4/Nvec {wl['nvec'][0]}, "
+                                  f"coarse links {args.coarse_prec or wl.get('coarse_prec', 'fp32')}"},
+           "sequential_s": seq_s, "systems_per_s_concurrent": nsys / conc_s, "systems_per_s_sequential": nsys / seq_s,
+           "per_lattice": [{"dims": list(p["dims"]), "setup_s": p["setup_s"], "alone": a, "concurrent": c}
+                           for p, a, c in zip(probs, seq, conc)]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +450,9 @@ def main():
     wl = WORKLOADS[args.workload]
     if wl.get("kind") == "force":
         force_bench(args, wl, torch, latgen, mg)
+        return
+    if wl.get("kind") == "uneven":
+        uneven_bench(args, wl, torch, latgen, mg)
         return
     dims, m = wl["dims"], wl["mass"]
     dev = "cuda:0"

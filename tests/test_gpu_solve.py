@@ -300,6 +300,36 @@ def test_deflated_bf16_solve(torch, mg, cubic1):
     log(f"[deflate] coarsest iterations per KD-level iteration {its}")
 
 
+def test_concurrent_contexts_match_sequential(torch, mg, cubic, cubic1):
+    """Two contexts (different hierarchies) solved at the same time from two
+    host threads on two streams give exactly the results of solving them one
+    after the other: the library keeps no state outside a context."""
+    import threading
+    log("[solve] two contexts on two streams")
+    probs = []
+    for cfg, W, N, nvs, b in (cubic, cubic1):
+        ctx = make_ctx(torch, mg, cfg, W, N, nvs, max_nrhs=2)
+        probs.append((ctx, torch.from_numpy(b).to("cuda:0")))
+    seq = [ctx.solve([0.05], bt, tol=1e-10)[0].cpu().numpy() for ctx, bt in probs]
+    out = [None, None]
+
+    def run(k):
+        ctx, bt = probs[k]
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            x, info, st = ctx.solve([0.05], bt, tol=1e-10)
+            s.synchronize()
+            out[k] = x.cpu().numpy()
+    ts = [threading.Thread(target=run, args=(k,)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    for k in range(2):
+        assert out[k] is not None
+        assert np.array_equal(out[k], seq[k]), k
+
+
 def test_multishift_cg_matches_oracle(torch, mg, cubic):
     """Multi-shift CG over unsorted masses with a repeat (Sec. 3.3 workflow):
     every (mass, rhs) system at true residual 1e-10 and within 2e-10 ||b|| / m
