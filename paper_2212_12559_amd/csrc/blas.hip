@@ -267,6 +267,16 @@ void launch_cg_update(double2* x, double2* r, const double2* p, const double2* a
 // 256 elements of every vector in LDS (each element fetched once); its four
 // wavefronts then take the pairs of the largest basis round-robin, so each
 // holds at most 11 FP64 accumulators.
+__device__ __forceinline__ void ldraw(const float2* p, int64_t e, float2& a, float2& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p + e);
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void ldraw(const double2* p, int64_t e, double2& a, double2& b) {
+  a = p[e];
+  b = p[e + 1];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2* __restrict__ part, int nblk) {
   constexpr int S = kMaxS;
@@ -280,21 +290,33 @@ __global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2*
   double2 acc[PW];
 #pragma unroll
   for (int q = 0; q < PW; ++q) acc[q] = make_double2(0.0, 0.0);
-  for (int64_t e0 = (int64_t)blockIdx.x * 256; e0 < a.n; e0 += (int64_t)nblk * 256) {
-    __syncthreads();
+  // the loads of the next pass are issued before the products of this one
+  T pa[S + 1], pb[S + 1];
+  auto fetch = [&](int64_t e0) {
     if (threadIdx.x < 128) {   // element pairs, one 16-byte load each for FP32
-      const int el = 2 * threadIdx.x;
-      const int64_t e = e0 + el;
+      const int64_t e = e0 + 2 * threadIdx.x;
 #pragma unroll
       for (int i = 0; i <= S; ++i) {
-        double2 v0 = make_double2(0.0, 0.0), v1 = v0;
         const int src = i < S ? i : s;
-        if ((i < s || i == S) && e < a.n) ld2(a.u[src], off + e, v0, v1);
-        us[i][el] = from_d2<T>(v0);
-        us[i][el + 1] = from_d2<T>(v1);
+        if ((i < s || i == S) && e < a.n) ldraw(a.u[src], off + e, pa[i], pb[i]);
+        else { pa[i] = from_d2<T>(make_double2(0.0, 0.0)); pb[i] = pa[i]; }
+      }
+    }
+  };
+  const int64_t step = (int64_t)nblk * 256;
+  if ((int64_t)blockIdx.x * 256 < a.n) fetch((int64_t)blockIdx.x * 256);
+  for (int64_t e0 = (int64_t)blockIdx.x * 256; e0 < a.n; e0 += step) {
+    __syncthreads();
+    if (threadIdx.x < 128) {
+      const int el = 2 * threadIdx.x;
+#pragma unroll
+      for (int i = 0; i <= S; ++i) {
+        us[i][el] = pa[i];
+        us[i][el + 1] = pb[i];
       }
     }
     __syncthreads();
+    if (e0 + step < a.n) fetch(e0 + step);
 #pragma unroll 1
     for (int q4 = 0; q4 < 4; ++q4) {
       const int el = lane + 64 * q4;
