@@ -577,7 +577,11 @@ def main():
                     "mg_light_s": mg_light, "msc_heavy_s": msc_heavy,
                     "mg_plus_msc_s": mg_light + msc_heavy, "speedup_vs_msc": msc_all / (mg_light + msc_heavy),
                     "worst_true_rel_residual": max(worst_all, worst_heavy),
-                    "systems_finished_by_cg": fix_all + fix_heavy}
+                    "systems_finished_by_cg": fix_all + fix_heavy,
+                    # Table 2: propagators after which the set-up is paid back (None: MG + multi-shift is
+                    # not faster per propagator, so it never is)
+                    "break_even_propagators": (setup_s / (msc_all - mg_light - msc_heavy)
+                                               if msc_all > mg_light + msc_heavy else None)}
         log(f"[bench] workflow {workflow}")
 
     # ---- per-kernel timings outside the solve (HIP events on the library's stream)
