@@ -329,7 +329,7 @@ def force_bench(args, wl, torch, latgen, mg):
            "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_force * 1e3,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128 outer / c64 K-cycle",
            "data": "synthetic",
-           "config": {"workload": f"{'x'.join(map(str, dims))} HISQ-style eps 0.5, mass {m}, {wl['nrhs']} phi, "
+           "config": {"workload": f"{'x'.join(map(str, dims))} HISQ-style eps {wl['eps']}, mass {m}, {wl['nrhs']} phi, "
                                   f"truncated-KD={not wl['kd_naik']}, coarse links "
                                   f"{args.coarse_prec or wl.get('coarse_prec', 'fp32')}"},
            "setup_s": setup_s, "solve_infos": info, "action": S0,
@@ -429,6 +429,8 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up, time the hot kernels and copy a known-size buffer (for counter runs)")
     ap.add_argument("--coarse-prec", default=None, choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--eps", type=float, default=None,
+                    help="roughness of the synthetic links (U = exp(i eps H)); default: the workload's")
     ap.add_argument("--nmass", type=int, default=None, help="solve only the first NMASS masses (profiling runs)")
     ap.add_argument("--setup-iters", default=None, help="CGNE iterations per level, e.g. 10,10 (kernel timing runs)")
     ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
@@ -447,7 +449,9 @@ def main():
     import torch
     from paper_2212_12559_amd import latgen, mgstag as mg
 
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    if args.eps is not None:
+        wl["eps"] = args.eps
     if wl.get("kind") == "force":
         force_bench(args, wl, torch, latgen, mg)
         return
@@ -616,7 +620,7 @@ def main():
         "vs_baseline": None,
         "dtype": "c128 outer / c64 K-cycle",
         "data": "synthetic",
-        "config": {"workload": f"{'x'.join(map(str, dims))} HISQ-style eps 0.5, masses {masses}, "
+        "config": {"workload": f"{'x'.join(map(str, dims))} HISQ-style eps {wl['eps']}, masses {masses}, "
                                f"{wl['nrhs']} rhs per mass, {mb} masses per lockstep solve, truncated-KD={not wl['kd_naik']}, "
                                f"KD + {wl['blocks'][0]}/Nvec {wl['nvec'][0]} + {wl['blocks'][1]}/Nvec {wl['nvec'][1]}, "
                                f"coarse links {cprec}"},
