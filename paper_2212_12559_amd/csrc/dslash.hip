@@ -54,6 +54,28 @@ __global__ void __launch_bounds__(256) dslash_kernel(const DslashArgs<R> a) {
     for (int h = 0; h < (NAIK ? 2 : 1); ++h) {
       const int hop = h ? 3 : 1;
       const T* L = (h ? a.lng : a.fat) + (int64_t)mu * 9 * V;
+      // compressed long links: rows 0 and 1 and w; row 2 = w conj(row0 x row1)
+      const bool cmp = h && a.lng_c != nullptr;
+      const T* Lc = cmp ? a.lng_c + (int64_t)mu * 7 * V : nullptr;
+      auto load_link = [&](T (&U)[9], int64_t q) {
+        if (cmp) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) U[k] = Lc[k * V + q];
+          const T w = Lc[6 * V + q];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            const T p = cmul(U[j1], U[3 + j2]), m = cmul(U[j2], U[3 + j1]);
+            T cc;
+            cc.x = p.x - m.x;
+            cc.y = m.y - p.y;   // conj of the cross product's component j
+            U[6 + j] = cmul(w, cc);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) U[k] = L[k * V + q];
+        }
+      };
       bool use_f = true, use_b = true;
       if (PIECE) {
         const int u = c[mu] % a.blk[mu];
@@ -66,8 +88,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(const DslashArgs<R> a) {
         const int64_t sf = site_shift(c, mu, hop, a.g);
         const int64_t vi = CB ? (sf >> 1) * 3 : sf * 3;
         T U[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) U[k] = L[k * V + s];
+        load_link(U, s);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           if (r < nr) {
@@ -86,8 +107,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(const DslashArgs<R> a) {
         const int64_t sb = site_shift(c, mu, -hop, a.g);
         const int64_t vi = CB ? (sb >> 1) * 3 : sb * 3;
         T U[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) U[k] = L[k * V + sb];
+        load_link(U, sb);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           if (r < nr) {
@@ -361,6 +381,50 @@ __global__ void pack_links_kernel(const double2* __restrict__ src, double2* __re
           make_float4((float)(f * v0.x), (float)(f * v0.y), (float)(f * v1.x), (float)(f * v1.y));
     }
   }
+}
+
+__global__ void pack_naik_compressed_kernel(const double2* __restrict__ src, double2* __restrict__ d64,
+                                            float2* __restrict__ d32, Geom g, double coef,
+                                            unsigned long long* dev_max) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double dev = 0.0;
+  if (tid < 4 * g.V) {
+    const int mu = (int)(tid / g.V);
+    const int64_t s = tid - (int64_t)mu * g.V;
+    int c[4];
+    site_coords(s, g, c);
+    const double f = coef * stag_eta(c, mu);
+    double2 N[9];
+    for (int k = 0; k < 9; ++k) N[k] = src[tid * 9 + k];
+    // unitarity: |(N N^dag)_ij - delta_ij|
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double2 t = make_double2(i == j ? -1.0 : 0.0, 0.0);
+        for (int k = 0; k < 3; ++k) cfmac(t, N[3 * j + k], N[3 * i + k]);   // N_ik conj(N_jk)
+        dev = fmax(dev, fmax(fabs(t.x), fabs(t.y)));
+      }
+    // det N along the first row: sum_j N_0j (N_1,j+1 N_2,j+2 - N_1,j+2 N_2,j+1)
+    double2 det = make_double2(0.0, 0.0);
+    for (int j = 0; j < 3; ++j) {
+      const int j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+      const double2 p = cmul(N[3 + j1], N[6 + j2]), m = cmul(N[3 + j2], N[6 + j1]);
+      cfma(det, N[j], make_double2(p.x - m.x, p.y - m.y));
+    }
+    const double2 w = make_double2(det.x / f, det.y / f);
+    for (int k = 0; k < 7; ++k) {
+      const double2 v = k < 6 ? make_double2(f * N[k].x, f * N[k].y) : w;
+      d64[((int64_t)mu * 7 + k) * g.V + s] = v;
+      d32[((int64_t)mu * 7 + k) * g.V + s] = make_float2((float)v.x, (float)v.y);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o, 64));
+  if ((threadIdx.x & 63) == 0 && dev > 0.0) atomicMax(dev_max, (unsigned long long)__double_as_longlong(dev));
+}
+
+void launch_pack_naik_compressed(const double2* src, double2* d64, float2* d32, const Geom& g, double coef,
+                                 unsigned long long* dev_max, hipStream_t st) {
+  const int64_t n = 4 * g.V;
+  pack_naik_compressed_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(src, d64, d32, g, coef, dev_max);
 }
 
 void launch_pack_links(const double2* src, double2* d64, float2* d32, float4* d32p, const Geom& g, double coef,

@@ -16,6 +16,7 @@ struct DslashArgs {
   const cplx<R>* fat;       // [4][9][V], (c1/2) eta folded in
   const cplx<R>* lng;       // [4][9][V], (c3/2) eta folded in
   const float4* fat_pairs;  // optional FP32 one-hop links as element pairs [4][5][V] (last pair padded)
+  const cplx<R>* lng_c;     // optional compressed Naik links [4][7][V]: rows 0, 1 and w, row 2 = w conj(row0 x row1)
   Geom g;
   int64_t in_stride, out_stride, xs_stride;   // per rhs, complex elements
   int nrhs;
@@ -32,6 +33,12 @@ void launch_dslash(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipSt
 void launch_pack_links(const double2* src, double2* d64, float2* d32, float4* d32p, const Geom& g, double coef,
                        hipStream_t st);
 void launch_export_fine_index(int32_t* out, const Geom& g, const Agg& A, hipStream_t st);
+// Naik links in 13-real form (Sec. 3.1: long links are U(3) and compress to 13
+// reals): with L = s N, s = (c3 / 2) eta_mu(x), store rows 0 and 1 of L and
+// w = det(N) / s, so row 2 of L is w conj(row0 x row1).  dev_max receives the
+// largest |N N^dag - 1| entry (as the bits of a non-negative double).
+void launch_pack_naik_compressed(const double2* src, double2* d64, float2* d32, const Geom& g, double coef,
+                                 unsigned long long* dev_max, hipStream_t st);
 template <typename T>
 void launch_eps(T* out, const T* in, const Geom& g, int nrhs, hipStream_t st);
 void launch_cb_split(const double2* full, double2* ev, double2* od, const Geom& g, int nrhs, hipStream_t st);

@@ -100,6 +100,8 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   void* fat32p = P(20 * V * 16);   // FP32 one-hop links in element pairs
   void* lng64 = p.c3 != 0.0 ? P(36 * V * 16) : nullptr;
   void* lng32 = p.c3 != 0.0 ? P(36 * V * 8) : nullptr;
+  void* lng64c = p.c3 != 0.0 ? P(28 * V * 16) : nullptr;   // compressed Naik links (7 per link)
+  void* lng32c = p.c3 != 0.0 ? P(28 * V * 8) : nullptr;
   const int64_t kslot = V / 16 * 2304;
   void* kinv64 = P((size_t)p.max_nmass * kslot * 16);
   void* kinv32 = P((size_t)p.max_nmass * kslot * 8);
@@ -212,6 +214,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   if (c) {
     c->fat64 = (double2*)fat64; c->fat32 = (float2*)fat32; c->fat32p = (float4*)fat32p;
     c->lng64 = (double2*)lng64; c->lng32 = (float2*)lng32;
+    c->lng64c = (double2*)lng64c; c->lng32c = (float2*)lng32c;
     c->kinv64 = (double2*)kinv64; c->kinv32 = (float2*)kinv32;
     c->kinv_slot = kslot;
     c->kd_mass.assign(p.max_nmass, NAN);
@@ -275,6 +278,7 @@ static DslashArgs<R> dslash_args(const Ctx& c, void* out, const void* in, int ns
   a.fat = d ? (const cplx<R>*)c.fat64 : (const cplx<R>*)c.fat32;
   a.lng = d ? (const cplx<R>*)c.lng64 : (const cplx<R>*)c.lng32;
   a.fat_pairs = d ? nullptr : c.fat32p;
+  a.lng_c = c.naik_compressed ? (d ? (const cplx<R>*)c.lng64c : (const cplx<R>*)c.lng32c) : nullptr;
   a.g = c.g0;
   a.in_stride = a.out_stride = a.xs_stride = c.g0.V * 3;
   a.nrhs = nsys;

@@ -61,6 +61,9 @@ struct Ctx {
   double2 *fat64 = nullptr, *lng64 = nullptr;
   float2 *fat32 = nullptr, *lng32 = nullptr;
   float4* fat32p = nullptr;   // FP32 fat links as element pairs [4][5][V]
+  double2* lng64c = nullptr;  // Naik links in 13-real form [4][7][V] (used when they are unitary)
+  float2* lng32c = nullptr;
+  bool naik_compressed = false;
   double2* kinv64 = nullptr;
   float2* kinv32 = nullptr;
   int64_t kinv_slot = 0;    // complex per slot
@@ -166,6 +169,7 @@ struct Ctx {
                       mg_solve_info* info);
   void update_links(const void* fat, const void* naik);
   void build_level(int l, const void* nv_import);
+  void pack_naik(const void* naik);
   void cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2* out);
   void build_deflation();
   void deflate_start(int lvl, int nsys);

@@ -24,7 +24,7 @@ void Ctx::setup(const void* fat, const void* naik, const void* const* nvs) {
   launch_pack_links((const double2*)fat, fat64, fat32, fat32p, g0, 0.5 * P.c1, st);
   check_launch();
   if (P.c3 != 0.0) {
-    launch_pack_links((const double2*)naik, lng64, lng32, nullptr, g0, 0.5 * P.c3, st);
+    pack_naik(naik);
     check_launch();
   }
   ensure_kd({P.mass0});
@@ -34,6 +34,22 @@ void Ctx::setup(const void* fat, const void* naik, const void* const* nvs) {
   if (defl_k > 0) build_deflation();
   setup_phase = false;
   HIPCHK(hipStreamSynchronize(st));
+}
+
+// Naik links: the full FP64 / FP32 copies, and the 13-real form (Sec. 3.1)
+// that the stencil uses when every link is unitary to 1e-10.
+void Ctx::pack_naik(const void* naik) {
+  launch_pack_links((const double2*)naik, lng64, lng32, nullptr, g0, 0.5 * P.c3, st);
+  unsigned long long* dmax = (unsigned long long*)((char*)status_dev + 128);
+  HIPCHK(hipMemsetAsync(dmax, 0, sizeof(unsigned long long), st));
+  launch_pack_naik_compressed((const double2*)naik, lng64c, lng32c, g0, 0.5 * P.c3, dmax, st);
+  check_launch();
+  unsigned long long bits = 0;
+  HIPCHK(hipMemcpyAsync(&bits, dmax, sizeof(bits), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double dev;
+  std::memcpy(&dev, &bits, sizeof(dev));
+  naik_compressed = dev <= 1e-10;
 }
 
 void Ctx::build_level(int l, const void* imp) {
@@ -236,7 +252,7 @@ void Ctx::galerkin(int l) {
       const double2* src;
       if (l == 0) {
         DslashArgs<double> d{};
-        d.out = w; d.in = v; d.fat = fat64; d.lng = lng64; d.g = g0;
+        d.out = w; d.in = v; d.fat = fat64; d.lng = lng64; d.lng_c = naik_compressed ? lng64c : nullptr; d.g = g0;
         d.in_stride = d.out_stride = g0.V * 3; d.nrhs = 1; d.mass = P.mass0; d.b_coef = 1;
         d.piece = piece;
         for (int mu = 0; mu < 4; ++mu) d.blk[mu] = a.b[mu];

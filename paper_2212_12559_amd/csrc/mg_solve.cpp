@@ -153,7 +153,7 @@ void Ctx::update_links(const void* fat, const void* naik) {
   launch_pack_links((const double2*)fat, fat64, fat32, fat32p, g0, 0.5 * P.c1, st);
   check_launch();
   if (P.c3 != 0.0) {
-    launch_pack_links((const double2*)naik, lng64, lng32, nullptr, g0, 0.5 * P.c3, st);
+    pack_naik(naik);
     check_launch();
   }
   for (auto& m : kd_mass) m = NAN;
@@ -189,7 +189,9 @@ void Ctx::cg_solve(const double* masses, int nmass, const void* b, void* x, int 
     double2* xj = (double2*)x + (size_t)j * nrhs * n;
     auto cbd = [&](double2* out, const double2* in, const double2* xs, int par, double ac, double bc) {
       DslashArgs<double> d{};
-      d.out = out; d.in = in; d.xs = xs; d.fat = fat64; d.lng = lng64; d.g = g0;
+      d.out = out; d.in = in; d.xs = xs; d.fat = fat64; d.lng = lng64;
+      d.lng_c = naik_compressed ? lng64c : nullptr;
+      d.g = g0;
       d.in_stride = d.out_stride = d.xs_stride = nh; d.nrhs = nrhs; d.a_coef = ac; d.b_coef = bc; d.parity = par;
       launch_dslash(d, P.c3 != 0.0, true, false, st);
       check_launch();
@@ -353,7 +355,9 @@ void Ctx::msc_solve(const double* masses, int nmass, const void* b, void* x, int
   auto cbd = [&](double2* out, const double2* in, const double2* xs, int par, double ac, double bc, int64_t sin,
                  int64_t sxs) {
     DslashArgs<double> d{};
-    d.out = out; d.in = in; d.xs = xs; d.fat = fat64; d.lng = lng64; d.g = g0;
+    d.out = out; d.in = in; d.xs = xs; d.fat = fat64; d.lng = lng64;
+    d.lng_c = naik_compressed ? lng64c : nullptr;
+    d.g = g0;
     d.in_stride = sin; d.xs_stride = sxs; d.out_stride = nh; d.nrhs = nrhs; d.a_coef = ac; d.b_coef = bc;
     d.parity = par;
     launch_dslash(d, P.c3 != 0.0, true, false, st);

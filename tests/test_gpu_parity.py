@@ -342,3 +342,32 @@ def test_coarse_mfma_16bit(torch, mg, name, fmt):
                 exact = ops.coarse_apply_links(L, cd, x[r].astype(np.complex128))
                 log(f"    rel err vs rounded-input FP64: {rel_err(y[r], want):.2e}, "
                     f"vs unrounded FP64 operator: {rel_err(y[r], exact):.2e}")
+
+
+def test_naik_compression_and_fallback(torch, mg):
+    """The stencil keeps the Naik links in 13-real form (two rows and
+    det(N) / s) when every long link is unitary, and the full form otherwise:
+    D against the oracle in FP64 and FP32 with unitary long links, after
+    mg_update_links to generic (non-unitary) long links, and back."""
+    dims = (8, 8, 8, 8)
+    W, N, rng = latgen.hisq_style_links(dims, 0.5, 4242)
+    Ng = N + 0.05 * latgen.complex_normal(rng, N.shape)
+    cfg = dict(dims=dims, c1=9.0 / 8.0, c3=-1.0 / 24.0, kd_naik=1, blocks=[(4, 4, 4, 4)], nvec=(8,), mass0=0.05)
+    nvs = [latgen.fine_vectors(dims, 8, rng)]
+    p = gpu_params(mg, cfg, max_nrhs=3, fine_prec=mg.MG_C64, coarse_prec=mg.MG_C64)
+    dev = "cuda:0"
+    Wt = torch.from_numpy(W).to(dev)
+    ctx = mg.setup(p, Wt, torch.from_numpy(N).to(dev), [torch.from_numpy(v).to(dev) for v in nvs])
+    x = latgen.fine_vectors(dims, 3, rng)
+    m = 0.03
+    for tag, Nn in (("unitary", N), ("generic", Ng), ("unitary again", N)):
+        if tag != "unitary":
+            ctx.update_links(Wt, torch.from_numpy(Nn).to(dev))
+        log(f"[naik] {tag}")
+        for dt, tol in ((torch.complex128, TOL64), (torch.complex64, TOL32)):
+            y = ctx.apply_dslash(0, m, torch.from_numpy(x).to(dev).to(dt))
+            torch.cuda.synchronize()
+            y = y.to(torch.complex128).cpu().numpy()
+            for r in range(3):
+                want = ops.dslash(x[r], W, Nn, m, cfg["c1"], cfg["c3"])
+                assert rel_err(y[r], want) < tol, (tag, dt, r)
