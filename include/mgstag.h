@@ -225,14 +225,18 @@ mg_status mg_solve_backward(mg_ctx ctx, double mass, const void* phi, void* X, v
 /* Replace the gauge links of an existing context (device, complex128): the
  * fine operator and the KD inverses follow the new links, the near-null
  * vectors, transfers and coarse operators stay those of the set-up (the
- * hierarchy then preconditions a nearby operator; solves stay exact). */
+ * hierarchy then preconditions a nearby operator; solves stay exact).  As at
+ * mg_setup, the long links are kept in 13-real form (two rows and det / scale,
+ * Sec. 3.1) when every one is unitary to 1e-10, in full form otherwise; this
+ * call synchronises the stream for that check. */
 mg_status mg_update_links(mg_ctx ctx, const void* fat, const void* naik, void* stream);
 
 /* Copy internal data to a caller buffer (device dst of at least `bytes`):
  *   what 0: fine index tables, int32 [V][22] (neighbours x+-mu, x+-3mu, eta
  *           bits, eps, hypercube, hypercube-local index, aggregate, chirality)
  *   what 1: near-null vectors of `level` (1 or 2), complex128, layout as the
- *           null_vectors argument of mg_setup
+ *           null_vectors argument of mg_setup; level nagg + 1: the coarsest
+ *           level's deflation vectors [k][coarsest vector] (coarsest_deflate > 0)
  *   what 2: coarse links of `level` (2 or 3), complex128 [site][9][n][n]
  *           row-major blocks, n = 2 Nvec, d = 0 self, 1 + 2 mu: +mu, 2 + 2 mu: -mu
  * Returns the needed size in *bytes_needed when dst is NULL. */
