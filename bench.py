@@ -443,7 +443,7 @@ def main():
         summarize_counters(*args.summarize_counters, WORKLOADS[args.workload])
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
