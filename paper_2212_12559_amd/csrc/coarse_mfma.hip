@@ -157,7 +157,22 @@ __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const C
   for (int m = 0; m < MT; ++m)
     Lm[m] = reinterpret_cast<const uint4*>(a.links) + (site * mt_n + wave + nw * m) * (int64_t)kc_n * 2 * 64;
   const int j = lane & 15, g = lane >> 4;
-  for (int kc0 = 0; kc0 < kc_n; kc0 += kMfmaCK) {
+  // Where a staging pass is exactly one direction (n = KCH), neighbouring
+  // workgroups read the same input vector in the same pass: a site with odd x
+  // takes -x, self, +x in its first three passes (its -x is the self of the
+  // site before it, its self the +x of that site), and rows y = 2, 3 mod 4
+  // (z likewise) take -y before +y (reading the row that y - 2 reads with +y).
+  const bool perm = n == KCH && kc_n == 9 * kMfmaCK;
+  const int64_t sx = site % a.g.L[0], sy = (site / a.g.L[0]) % a.g.L[1],
+                sz = (site / ((int64_t)a.g.L[0] * a.g.L[1])) % a.g.L[2];
+  const bool xodd = perm && (sx & 1), yswap = perm && ((sy >> 1) & 1), zswap = perm && ((sz >> 1) & 1);
+  const int npass = (kc_n + kMfmaCK - 1) / kMfmaCK;
+  for (int pi = 0; pi < npass; ++pi) {
+    int pd = pi;
+    if (xodd && pi <= 2) pd = pi == 0 ? 2 : pi - 1;
+    if (yswap && (pi == 3 || pi == 4)) pd = 7 - pi;
+    if (zswap && (pi == 5 || pi == 6)) pd = 11 - pi;
+    const int kc0 = pd * kMfmaCK;
     __syncthreads();   // neighbour table ready / previous pass consumed
     // stage k in [32 kc0, 32 kc0 + KCH): quads (k .. k + 3) lie in one
     // direction (n is a multiple of 16) and are two 16-byte loads (inputs are
