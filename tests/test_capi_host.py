@@ -37,11 +37,17 @@ def test_params_struct_matches_header(m):
 
 
 def test_default_params_table1(m):
+    """Defaults against the values of the paper's Table 1 (tests/golden)."""
+    import json
+    t = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1_mg_parameters.json")))
     p = m.default_params((16, 16, 16, 16))
-    assert p.smoother_s == 8 and p.inner_tol == 0.25 and p.inner_maxiter == 8
-    assert p.setup_maxiter[0] == 2000 and p.setup_tol[0] == 1e-6
+    assert p.smoother_s == t["smoother_s"] and p.inner_tol == t["inner_tol"]
+    assert p.inner_maxiter == t["inner_maxiter"]
+    assert p.setup_maxiter[0] == t["setup_maxiter"] and p.setup_tol[0] == t["setup_tol"]
+    assert p.setup_maxiter[1] == t["setup_maxiter"] and p.setup_tol[1] == t["setup_tol"]
+    assert p.coarsest_maxiter == t["coarsest_basis"]
+    assert list(p.nvec) == [t["nvec_level1"], t["nvec_level2"]]
     assert abs(p.c1 - 9 / 8) < 1e-15 and abs(p.c3 + 1 / 24) < 1e-15
-    assert list(p.nvec) == [64, 96]
 
 
 @pytest.mark.parametrize("bad,why", [
