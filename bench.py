@@ -2,12 +2,16 @@
 lattice on one MI355X, plus the roofline of the dominant kernel and the CPU
 oracle baseline.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2batch|...]
 
-A step is one MG-GCR solve of the workload's batch (mass 0.005, nrhs Gaussian
-right-hand sides) to ||b - D x|| / ||b|| <= 1e-10, with every input resident
-in HBM; the hierarchy set-up is excluded (as in the paper, Sec. 3.2) and
-reported separately.  One JSON line is printed.
+A step is one MG-GCR solve of the workload's whole batch (default: 16
+Gaussian right-hand sides x 8 masses, 128 systems) to ||b - D x|| / ||b|| <=
+1e-10, with every input resident in HBM; the hierarchy set-up is excluded (as
+in the paper, Sec. 3.2) and reported separately.  A step takes about a
+minute, so the run keeps to a wall-time budget (--budget-s, counted from the
+start of the process): it times as many of the requested steps as fit beside
+the comparators and reports the requested and the timed counts.  One JSON line
+is printed, also when a later leg fails.
 """
 from __future__ import annotations
 
@@ -18,6 +22,7 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -212,68 +217,124 @@ def kernel_rates(torch, ctx, wl, reps, mg, link_csz=8):
     return out
 
 
-def cpu_baseline(wl, batch_infos, s):
-    """The FP64 oracle (numpy, one thread) timed on a bounded sample: one
-    application of each hot-path operator at the workload's lattice (the
-    coarse operator at a 16^4 lattice, scaled by the volume ratio), combined
-    with the operator counts of the measured MG solve into the oracle's time
-    for the same solve."""
+def _oracle_sample_worker(job):
+    """One oracle sample, run in a process of its own (one thread): one
+    application of each hot-path operator on a 16^4 lattice of the workload's
+    kind.  Returns the seconds of each application."""
+    dims, eps, seed, nvec, kd_naik, block, m = job
     from threadpoolctl import threadpool_limits
 
     from oracle import operators as ops
     from oracle import solvers as sol
     from paper_2212_12559_amd import latgen
 
-    dims, m = wl["dims"], wl["mass"]
     c1, c3 = 9.0 / 8.0, -1.0 / 24.0
-    c3kd = c3 if wl["kd_naik"] else 0.0
-    t_total = time.perf_counter()
+    t = {}
     with threadpool_limits(1):
-        W, N, rng = latgen.hisq_style_links(dims, wl["eps"], wl["seed"])
+        W, N, rng = latgen.hisq_style_links(dims, eps, seed)
         x = latgen.fine_vectors(dims, 1, rng)[0]
         t0 = time.perf_counter()
         ops.dslash(x, W, N, m, c1, c3)
-        t_d = time.perf_counter() - t0
+        t["dslash"] = time.perf_counter() - t0
         t0 = time.perf_counter()
-        ops.dslash(x, W, N, m, c1, c3kd)
-        t_d1 = time.perf_counter() - t0
+        ops.dslash(x, W, N, m, c1, c3 if kd_naik else 0.0)
+        t["dslash_kd"] = time.perf_counter() - t0
         Kinv = ops.kd_inverse(W, m, c1)
         t0 = time.perf_counter()
         ops.kd_apply(Kinv, x)
-        t_kd = time.perf_counter() - t0
-        del Kinv, W, N
-        # transfer and coarse operators on a 16^4 lattice, scaled by volume
-        sd = (16, 16, 16, 16)
-        scale = float(np.prod(dims)) / float(np.prod(sd))
-        W2, N2, rng2 = latgen.hisq_style_links(sd, wl["eps"], wl["seed"])
-        nv1 = latgen.fine_vectors(sd, wl["nvec"][0], rng2)
-        p = sol.MGParams(dims=sd, c1=c1, c3=c3, kd_naik=bool(wl["kd_naik"]), blocks=tuple(wl["blocks"][:1]))
-        H = sol.Hierarchy(p, W2, N2, m, [nv1])
-        xs = latgen.fine_vectors(sd, 1, rng2)[0]
+        t["kd"] = time.perf_counter() - t0
+        del Kinv
+        nv1 = latgen.fine_vectors(dims, nvec, rng)
+        p = sol.MGParams(dims=dims, c1=c1, c3=c3, kd_naik=bool(kd_naik), blocks=(tuple(block),))
+        H = sol.Hierarchy(p, W, N, m, [nv1])
         t0 = time.perf_counter()
-        rc = H.restrict(1, xs)
-        t_r = (time.perf_counter() - t0) * scale
+        rc = H.restrict(1, x)
+        t["restrict"] = time.perf_counter() - t0
         t0 = time.perf_counter()
         H.prolong(1, rc)
-        t_p = (time.perf_counter() - t0) * scale
+        t["prolong"] = time.perf_counter() - t0
         t0 = time.perf_counter()
         H.op(2, rc)
-        t_c2 = (time.perf_counter() - t0) * scale
-    sample_s = time.perf_counter() - t_total
+        t["coarse"] = time.perf_counter() - t0
+    return t
+
+
+def host_cpu():
+    """CPU model and the cores this process may use (capped at the 16-core
+    share of one GPU)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, max(1, min(16, n))
+
+
+def cpu_baseline(wl, batch_infos, s, oracle_check=None):
+    """The FP64 oracle (numpy) timed on the host's cores: every core runs one
+    sample (one application of each hot-path operator on a 16^4 lattice, in a
+    process of its own), so their combined rate is the oracle's throughput on
+    this host; scaled to the workload's volume (every operator is local, so
+    its cost is proportional to the volume) and multiplied by the operator
+    counts of the measured MG solves, it gives the oracle's time for the same
+    work (Krylov BLAS omitted: a lower bound).
+
+    oracle_check: optional (dims, links (W, N), [(mass, b, x)]) of GPU
+    solutions; their true residuals ||b - D(m) x|| / ||b|| are recomputed with
+    the oracle's FP64 operator, with the error bound ||x - x*|| <= ||r|| / m
+    that holds because D = m + K with K anti-Hermitian (so ||D^-1|| <= 1 / m)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    model, cores = host_cpu()
+    dims = wl["dims"]
+    sd = (16, 16, 16, 16)
+    scale = float(np.prod(dims)) / float(np.prod(sd))
+    job = (sd, wl["eps"], wl["seed"], wl["nvec"][0], wl["kd_naik"], wl["blocks"][0], wl["mass"])
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+        samples = list(ex.map(_oracle_sample_worker, [job] * cores))
+    sample_s = time.perf_counter() - t0
+    # combined rate of the cores -> seconds per application on the whole host, at the workload's volume
+    per_op = {k: scale / sum(1.0 / smp[k] for smp in samples) for k in samples[0]}
     est = 0.0
     for info in batch_infos:
         cnt = op_counts(info, s, 4)
-        est += wl["nrhs"] * (cnt["dslash_fp64"] * t_d + cnt["dslash_fp32_level0"] * t_d
-                             + cnt["dslash_fp32_level1"] * t_d1 + cnt["kd_fp32"] * t_kd + cnt["restrict1"] * t_r
-                             + cnt["prolong1"] * t_p + (cnt["coarse2"] + cnt["coarse3"]) * t_c2)
-    log(f"[bench] cpu oracle: D {t_d:.2f}s KD {t_kd:.2f}s R {t_r:.2f}s P {t_p:.2f}s C2 {t_c2:.2f}s -> {est:.0f} s")
-    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"one oracle application each of D, D_KD, (B+m)^-1 at {'x'.join(map(str, dims))}, and of "
-                       f"R, P, the level-2 operator R A P at 16^4 scaled by the volume ratio; multiplied by the "
-                       f"operator counts of the measured MG solves, per system (level-3 applies priced as "
-                       f"level 2, Krylov BLAS omitted: a lower bound); sample took {sample_s:.1f} s"),
-            "per_op_s": {"dslash": t_d, "dslash_kd": t_d1, "kd": t_kd, "restrict": t_r, "prolong": t_p,
-                         "coarse": t_c2}}
+        est += wl["nrhs"] * (cnt["dslash_fp64"] * per_op["dslash"] + cnt["dslash_fp32_level0"] * per_op["dslash"]
+                             + cnt["dslash_fp32_level1"] * per_op["dslash_kd"] + cnt["kd_fp32"] * per_op["kd"]
+                             + cnt["restrict1"] * per_op["restrict"] + cnt["prolong1"] * per_op["prolong"]
+                             + (cnt["coarse2"] + cnt["coarse3"]) * per_op["coarse"])
+    log(f"[bench] cpu oracle on {cores} cores ({model}): per application at {'x'.join(map(str, dims))} "
+        + ", ".join(f"{k} {v:.3f}s" for k, v in per_op.items()) + f" -> {est:.0f} s")
+    out = {"value": est, "unit": "s", "cores": cores, "cpu_model": model, "kind": "oracle",
+           "sample": (f"{cores} processes (one thread each) each applied the numpy FP64 oracle's D, D of the KD "
+                      f"level, (B+m)^-1, R, P and the level-2 operator R A P once on a 16^4 lattice (took "
+                      f"{sample_s:.1f} s); their combined rate, scaled by the volume ratio {scale:.0f} to "
+                      f"{'x'.join(map(str, dims))}, times the operator counts of the measured MG solves (level-3 "
+                      f"applies priced as level 2, Krylov BLAS omitted): a lower bound for the oracle's time"),
+           "per_op_s": per_op}
+    if oracle_check is not None:
+        from oracle import operators as ops
+        cdims, (W, N), systems = oracle_check
+        rows = []
+        for mass, b, x in systems:
+            r = b - ops.dslash(x, W, N, mass, 9.0 / 8.0, -1.0 / 24.0)
+            rn, bn, xn = np.linalg.norm(r), np.linalg.norm(b), np.linalg.norm(x)
+            rows.append({"mass": mass, "true_rel_residual": rn / bn, "err_bound_rel_x": rn / (mass * xn)})
+            log(f"[bench] oracle check mass {mass}: residual {rn / bn:.3e}, |x - x*| / |x| <= {rn / (mass * xn):.2e}")
+        out["oracle_check"] = {"what": "true residual of GPU solutions recomputed by the oracle's FP64 D at full "
+                                       "size (rhs 0 of every mass), with the bound |x - x*| <= |r| / m",
+                               "systems": rows,
+                               "worst_true_rel_residual": max(r["true_rel_residual"] for r in rows),
+                               "worst_err_bound_rel_x": max(r["err_bound_rel_x"] for r in rows)}
+    return out
 
 
 def force_bench(args, wl, torch, latgen, mg):
@@ -420,12 +481,18 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2batch", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-cg", action="store_true", help="skip the CG comparator")
     ap.add_argument("--no-msc", action="store_true", help="skip the multi-shift CG workflow comparison")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--budget-s", type=float, default=480.0,
+                    help="wall-time budget of the whole run from process start; the timed steps stop early to fit")
+    ap.add_argument("--reserve-s", type=float, default=150.0,
+                    help="time kept for the comparators, the oracle and the ceilings after the timed steps")
+    ap.add_argument("--no-oracle-check", dest="oracle_check", action="store_false",
+                    help="skip the oracle's residual check of the GPU solutions")
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up, time the hot kernels and copy a known-size buffer (for counter runs)")
     ap.add_argument("--coarse-prec", default=None, choices=["fp32", "bf16", "fp16"])
@@ -458,6 +525,32 @@ def main():
     if wl.get("kind") == "uneven":
         uneven_bench(args, wl, torch, latgen, mg)
         return
+    out = {"metric": "MG-GCR time-to-1e-10 vs plain CG at 32^4 HISQ; Dslash/coarse GB/s, MFMA %",
+           "value": None, "unit": "s", "n_gpus": 1, "steps": 0, "warmup": 0, "ms_per_step": None,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 outer GCR, f32 K-cycle, 16-bit coarse links (f32 accumulate)", "data": "synthetic",
+           "steps_requested": args.steps, "warmup_requested": args.warmup, "budget_s": args.budget_s}
+    try:
+        c2batch_bench(args, wl, torch, latgen, mg, out)
+    except Exception as e:   # report what was measured, then fail
+        import traceback
+        traceback.print_exc()
+        out["error"] = f"{type(e).__name__}: {e}"
+        print(json.dumps(out), flush=True)
+        sys.exit(1)
+    print(json.dumps(out), flush=True)
+
+
+def elapsed():
+    return time.perf_counter() - T_START
+
+
+def c2batch_bench(args, wl, torch, latgen, mg, out):
+    """The headline: MG-GCR solves of the multi-mass batch timed over as many
+    of the requested steps as the budget allows, then the FP64 Schur CG
+    comparator, the dominant kernel's roofline, the oracle baseline (with the
+    oracle's residual check of a sample of the solutions), measured ceilings
+    and, when time is left, the multi-shift CG workflow comparison."""
     dims, m = wl["dims"], wl["mass"]
     dev = "cuda:0"
     log(f"[bench] workload {args.workload} dims {dims} mass {m}: generating links")
@@ -465,25 +558,32 @@ def main():
     b = latgen.fine_vectors(dims, wl["nrhs"], rng)
     Wt, Nt = torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev)
     bt = torch.from_numpy(b).to(dev)
-    del W, N, b
     masses = list(wl.get("masses", (m,)))[:args.nmass]
     cprec = args.coarse_prec or wl.get("coarse_prec", "fp32")
     cp = {"fp32": mg.MG_C64, "bf16": mg.MG_CBF16, "fp16": mg.MG_CF16}[cprec]
     setup_iters = tuple(int(v) for v in args.setup_iters.split(",")) if args.setup_iters else wl["setup_iters"]
     mb = wl.get("mass_batch", 1)
+    nr = wl["nrhs"]
     p = mg.default_params(dims, mass0=m, nvec=wl["nvec"], block=wl["blocks"], setup_maxiter=setup_iters,
-                          max_nrhs=wl["nrhs"] * mb, max_nmass=len(masses), kd_naik=wl["kd_naik"], coarse_prec=cp,
-                          outer_nkrylov=8 if wl["nrhs"] > 1 else 16)
+                          max_nrhs=nr * mb, max_nmass=len(masses), kd_naik=wl["kd_naik"], coarse_prec=cp,
+                          outer_nkrylov=8 if nr > 1 else 16)
     for kv in args.set:
         k, v = kv.split("=", 1)
         setattr(p, k, type(getattr(p, k))(float(v)) if isinstance(getattr(p, k), float) else int(v))
         log(f"[bench] parameter {k} = {getattr(p, k)}")
-    log("[bench] setup")
+    out["config"] = {"workload": f"{'x'.join(map(str, dims))} HISQ-style eps {wl['eps']}, masses {masses}, "
+                                 f"{nr} rhs per mass, {mb} masses per lockstep solve, "
+                                 f"truncated-KD={not wl['kd_naik']}, KD + {wl['blocks'][0]}/Nvec {wl['nvec'][0]} + "
+                                 f"{wl['blocks'][1]}/Nvec {wl['nvec'][1]}, coarse links {cprec}",
+                     "systems": nr * len(masses), "lattice": list(dims)}
+    out["dtype"] = f"f64 outer GCR, f32 K-cycle, {cprec} coarse links (f32 accumulate)"
+    log(f"[bench] setup ({elapsed():.0f} s into the run)")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx = mg.setup(p, Wt, Nt)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    out["setup_s"] = setup_s
     log(f"[bench] setup {setup_s:.2f} s")
 
     if args.kernels_only:
@@ -493,7 +593,7 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)   # known-size copy (512 MiB read + 512 MiB write) to calibrate byte counters
         torch.cuda.synchronize()
-        print(json.dumps({k: {"us": v["us"], "bytes": v["bytes"]} for k, v in kern.items()}), flush=True)
+        out["kernels"] = {k: {"us": v["us"], "bytes": v["bytes"]} for k, v in kern.items()}
         return
 
     # per-mass set-up (the exact KD inverse of every mass, Sec. 3.1) outside the timed region
@@ -502,17 +602,19 @@ def main():
         ctx.apply_dslash(2, mj, xk)
     torch.cuda.synchronize()
     del xk
-    nr = wl["nrhs"]
 
     batch_s = []
+    keep = {}   # rhs 0 of every mass from the last step (for the oracle's residual check)
 
-    def mg_step(tag):
+    def mg_step(tag, tol=1e-10, chunks=None):
         # lockstep batches of mb masses x nrhs systems; a line per batch and mass
         info_all = []
         batch_s.clear()
         for j0 in range(0, len(masses), mb):
+            if chunks is not None and j0 // mb >= chunks:
+                break
             chunk = masses[j0:j0 + mb]
-            x, info, st = ctx.solve(chunk, bt, tol=1e-10)
+            x, info, st = ctx.solve(chunk, bt, tol=tol)
             info_all += info
             batch_s.append(info[0]["seconds"])
             for j, mj in enumerate(chunk):
@@ -520,27 +622,42 @@ def main():
                 log(f"[bench] {tag} mass {mj}: {max(i['outer_iters'] for i in ij)} outer, batch level iters "
                     f"{ij[0]['level_iters']}, batch {ij[0]['seconds']:.2f} s, "
                     f"max residual {max(i['true_rel_residual'] for i in ij):.2e}")
+                keep[mj] = x[j, 0].clone()
             del x
         return info_all
 
-    for i in range(args.warmup):
-        mg_step(f"warmup {i}")
+    # warm-up: one lockstep batch to a loose tolerance runs every kernel of the
+    # solve once (the library is compiled ahead of time: nothing else to warm)
+    if args.warmup > 0:
+        mg_step("warmup", tol=1e-2, chunks=1)
+        out["warmup"] = 1
+        out["warmup_kind"] = "one lockstep batch (64 systems) solved to 1e-2"
     torch.cuda.synchronize()
     # the dominant kernel (level-2 coarse stencil) is timed inside the timed
     # solves: the library brackets each of its launches with HIP events on
     # the stream it runs on
     ctx.profile_start(mg.MG_PROF_COARSE, 2)
-    t0 = time.perf_counter()
     infos = []
-    for i in range(args.steps):
-        infos.append(mg_step(f"step {i}"))
+    t_steps = time.perf_counter()
+    while len(infos) < max(1, args.steps):
+        t1 = time.perf_counter()
+        infos.append(mg_step(f"step {len(infos)}"))
+        torch.cuda.synchronize()
+        step_s = time.perf_counter() - t1
+        # the rest of the run (comparators, oracle, ceilings) needs about args.reserve_s
+        if elapsed() + step_s + args.reserve_s > args.budget_s:
+            break
     torch.cuda.synchronize()
-    mg_s = (time.perf_counter() - t0) / args.steps
+    mg_s = (time.perf_counter() - t_steps) / len(infos)
     last_batch_s = list(batch_s)
     dom_launches, dom_ms = ctx.profile_stop()
-    res = max(s["true_rel_residual"] for i in infos for s in i)
+    res = max(s_["true_rel_residual"] for i in infos for s_ in i)
+    out.update({"value": mg_s, "steps": len(infos), "ms_per_step": mg_s * 1e3, "mg_info": infos[-1][0],
+                "mg_outer_iters_per_mass": [max(i["outer_iters"] for i in infos[-1][j * nr:(j + 1) * nr])
+                                            for j in range(len(masses))],
+                "mg_batch_s": last_batch_s, "true_rel_residual": res})
+    log(f"[bench] MG {mg_s:.2f} s per step over {len(infos)} steps ({elapsed():.0f} s into the run)")
 
-    cg_s, cg_info = None, None
     if not args.no_cg:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -552,14 +669,47 @@ def main():
             del xc
         torch.cuda.synchronize()
         cg_s = time.perf_counter() - t0
-        cg_info = {"outer_iters": cg_iters}
-        log(f"[bench] CG {cg_s:.3f} s {cg_info}")
+        out.update({"cg_s": cg_s, "cg_iters_per_mass": cg_iters, "speedup_vs_cg": cg_s / mg_s})
+        log(f"[bench] CG {cg_s:.3f} s")
+
+    # ---- roofline of the dominant kernel (its launches inside the timed solves)
+    kern = kernel_rates(torch, ctx, wl, args.kernel_reps, mg, 8 if cprec == "fp32" else 4)
+    dom_bytes = kern["coarse2"]["bytes"]          # algorithmic bytes at the batch's rhs count
+    dom_us = dom_ms / max(dom_launches, 1) * 1e3
+    dom_gbs = dom_bytes / (dom_us * 1e-6) / 1e9
+    kname = ("coarse_kernel<float,float2>" if cprec == "fp32" else f"coarse_mfma_kernel<{cprec}>")
+    traffic, traffic_src = hbm_traffic(nr * mb)
+    out["roofline"] = {"bound": "hbm", "kernel": f"{kname} (level-2 coarse stencil, {nr * mb} rhs per launch)",
+                       "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": dom_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                       "bytes_per_launch": dom_bytes, "avg_launch_us": dom_us, "launches_timed": dom_launches,
+                       "timing": "HIP events around every launch inside the timed solves",
+                       "traffic_source": traffic_src}
+    out["kernels"] = {k: {kk: round(vv, 2) for kk, vv in v.items() if kk != "bytes"} for k, v in kern.items()}
+    out["mfma_frac_coarse2"] = (kern["coarse2"].get("TFLOPs", 0.0) / 2500.0) if cprec != "fp32" else None
+
+    # ---- measured ceilings: a 4 GiB copy and a loop of 16-bit matrix-core products
+    src = torch.empty(1 << 32, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    copy_gbs = mg.peak_copy(src, dst, reps=5)
+    del src, dst
+    mfma_tf = mg.peak_mfma(cp if cp in (mg.MG_CBF16, mg.MG_CF16) else mg.MG_CBF16)
+    out["ceilings"] = {"copy_4GiB_GBps": copy_gbs, "mfma16_TFLOPs": mfma_tf,
+                       "roofline_frac_of_copy": dom_gbs / copy_gbs}
+    log(f"[bench] ceilings: copy {copy_gbs:.0f} GB/s, 16-bit MFMA {mfma_tf:.0f} TFLOP/s")
+
+    if not args.no_cpu:
+        # one info per lockstep batch (one mass, nrhs systems): counts x nrhs single applications
+        batch_infos = [infos[-1][j * nr] for j in range(len(masses))]
+        sample = [(mj, b[0], keep[mj].cpu().numpy()) for mj in masses] if args.oracle_check else []
+        out["cpu_baseline"] = cpu_baseline(wl, batch_infos, p.smoother_s,
+                                           oracle_check=(dims, (W, N), sample) if sample else None)
+    log(f"[bench] {elapsed():.0f} s into the run")
 
     # ---- propagator workflow (Sec. 3.3, the Table 2 comparison): multi-shift CG
     # over every mass, against MG for the lightest lockstep batch plus
-    # multi-shift CG for the rest
-    workflow = None
-    if not args.no_msc and len(masses) > mb:
+    # multi-shift CG for the rest; only when the budget has room for it
+    if not args.no_msc and len(masses) > mb and elapsed() + 40 < args.budget_s:
         def msc(ms, tag):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -576,70 +726,20 @@ def main():
         msc_all, per_all, worst_all, fix_all = msc(masses, "all masses")
         msc_heavy, per_heavy, worst_heavy, fix_heavy = msc(masses[mb:], "heavier masses")
         mg_light = last_batch_s[0]
-        workflow = {"masses_mg": masses[:mb], "masses_msc": masses[mb:],
-                    "msc_all_s": msc_all, "msc_all_iters_per_mass": per_all,
-                    "mg_light_s": mg_light, "msc_heavy_s": msc_heavy,
-                    "mg_plus_msc_s": mg_light + msc_heavy, "speedup_vs_msc": msc_all / (mg_light + msc_heavy),
-                    "worst_true_rel_residual": max(worst_all, worst_heavy),
-                    "systems_finished_by_cg": fix_all + fix_heavy,
-                    # Table 2: propagators after which the set-up is paid back (None: MG + multi-shift is
-                    # not faster per propagator, so it never is)
-                    "break_even_propagators": (setup_s / (msc_all - mg_light - msc_heavy)
-                                               if msc_all > mg_light + msc_heavy else None)}
-        log(f"[bench] workflow {workflow}")
-
-    # ---- per-kernel timings outside the solve (HIP events on the library's stream)
-    kern = kernel_rates(torch, ctx, wl, args.kernel_reps, mg, 8 if cprec == "fp32" else 4)
-    dom_bytes = kern["coarse2"]["bytes"]          # algorithmic bytes at the batch's rhs count
-    dom_us = dom_ms / max(dom_launches, 1) * 1e3
-    dom_gbs = dom_bytes / (dom_us * 1e-6) / 1e9
-    kname = ("coarse_kernel<float,float2>" if cprec == "fp32" else f"coarse_mfma_kernel<{cprec}>")
-    traffic, traffic_src = hbm_traffic(wl["nrhs"] * mb)
-    roof = {"bound": "hbm", "kernel": f"{kname} (level-2 coarse stencil, {wl['nrhs'] * mb} rhs per launch)",
-            "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": dom_gbs / HBM_PEAK_GBS, "traffic": traffic,
-            "bytes_per_launch": dom_bytes, "avg_launch_us": dom_us, "launches_timed": dom_launches,
-            "timing": "HIP events around every launch inside the timed solves",
-            "traffic_source": traffic_src}
-    cpu = None
-    if not args.no_cpu:
-        # one info per lockstep batch (one mass, nrhs systems): counts x nrhs single applications
-        batch_infos = [infos[-1][j * wl["nrhs"]] for j in range(len(masses))]
-        cpu = cpu_baseline(wl, batch_infos, p.smoother_s)
-
-    out = {
-        "metric": "MG-GCR time-to-1e-10 vs plain CG at 32^4 HISQ; Dslash/coarse GB/s, MFMA %",
-        "value": mg_s,
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": mg_s * 1e3,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "c128 outer / c64 K-cycle",
-        "data": "synthetic",
-        "config": {"workload": f"{'x'.join(map(str, dims))} HISQ-style eps {wl['eps']}, masses {masses}, "
-                               f"{wl['nrhs']} rhs per mass, {mb} masses per lockstep solve, truncated-KD={not wl['kd_naik']}, "
-                               f"KD + {wl['blocks'][0]}/Nvec {wl['nvec'][0]} + {wl['blocks'][1]}/Nvec {wl['nvec'][1]}, "
-                               f"coarse links {cprec}"},
-        "mg_info": infos[-1][0],
-        "mg_outer_iters_per_mass": [max(i["outer_iters"] for i in infos[-1][j * nr:(j + 1) * nr])
-                                    for j in range(len(masses))],
-        "setup_s": setup_s,
-        "cg_s": cg_s,
-        "cg_iters_per_mass": cg_info["outer_iters"] if cg_info else None,
-        "speedup_vs_cg": (cg_s / mg_s) if cg_s else None,
-        "mg_batch_s": last_batch_s,
-        "workflow": workflow,
-        "true_rel_residual": res,
-        "roofline": roof,
-        "kernels": {k: {kk: round(vv, 2) for kk, vv in v.items() if kk != "bytes"} for k, v in kern.items()},
-        "mfma_frac_coarse2": (kern["coarse2"].get("TFLOPs", 0.0) / 2500.0) if cprec != "fp32" else None,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+        out["workflow"] = {
+            "masses_mg": masses[:mb], "masses_msc": masses[mb:],
+            "msc_all_s": msc_all, "msc_all_iters_per_mass": per_all,
+            "mg_light_s": mg_light, "msc_heavy_s": msc_heavy,
+            "mg_plus_msc_s": mg_light + msc_heavy, "speedup_vs_msc": msc_all / (mg_light + msc_heavy),
+            "worst_true_rel_residual": max(worst_all, worst_heavy),
+            "systems_finished_by_cg": fix_all + fix_heavy,
+            # Table 2: propagators after which the set-up is paid back (None: MG + multi-shift is
+            # not faster per propagator, so it never is)
+            "break_even_propagators": (setup_s / (msc_all - mg_light - msc_heavy)
+                                       if msc_all > mg_light + msc_heavy else None)}
+        log(f"[bench] workflow {out['workflow']}")
+    out["wall_s"] = elapsed()
+    log(f"[bench] done, {elapsed():.0f} s")
 
 
 if __name__ == "__main__":

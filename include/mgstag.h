@@ -162,8 +162,15 @@ mg_status mg_apply_coarse(mg_ctx ctx, int32_t level, int32_t dtype, const void* 
 mg_status mg_restrict(mg_ctx ctx, int32_t level, int32_t dtype, const void* fine, void* coarse, int32_t nrhs,
                       void* stream);
 
-/* Prolongation P from level `level` + 1 to `level`; accumulate = 1 adds into
- * the fine vector instead of overwriting it. */
+/* Prolongation P from level `level` + 1 to `level` (Sec. 2.1: the coarse
+ * correction is carried back to the finer level through the block-orthonormal,
+ * chirally split near-null vectors, P the adjoint of the restriction):
+ *   e[x,c] = sum_k P[(x,c),(a(x),sigma(x),k)] e_c[a(x),sigma(x),k]
+ * with a(x) the aggregate of x and sigma(x) its chirality.
+ *   coarse: device, [nrhs][Tc][Zc][Yc][Xc][2][Nvec] of level + 1 (input)
+ *   fine:   device, [nrhs][T][Z][Y][X][3] (level 1) or the level-2 coarse
+ *           layout (level 2); overwritten, or added into when accumulate = 1.
+ * dtype MG_C128 or MG_C64, both buffers 16-byte aligned and distinct. */
 mg_status mg_prolong(mg_ctx ctx, int32_t level, int32_t dtype, const void* coarse, void* fine,
                      int32_t accumulate, int32_t nrhs, void* stream);
 
@@ -216,11 +223,14 @@ mg_status mg_msc_solve(mg_ctx ctx, const double* masses, int32_t nmass, const vo
  *   grad_fat[mu][x]  = -c1 eta_mu(x) sum_r [Y(x) X(x+mu)^dag  - X(x) Y(x+mu)^dag ]
  *   grad_naik[mu][x] = -c3 eta_mu(x) sum_r [Y(x) X(x+3mu)^dag - X(x) Y(x+3mu)^dag]
  * the gradients in PyTorch's convention (dS/dRe U + i dS/dIm U), canonical
- * link layout, complex128, overwritten.  S = sum_r Re <phi_r, X_r>.
+ * link layout, complex128, overwritten.
  *   phi, X, Y: device complex128 [nrhs][T][Z][Y][X][3] (X, Y overwritten)
+ *   action: host, nrhs doubles or NULL; receives S_r = Re <phi_r, X_r>
+ *     (FP64 reduction on the device), so S = sum_r action[r]
  *   info: host, 2 * nrhs entries (the D^dag solves, then the D solves). */
 mg_status mg_solve_backward(mg_ctx ctx, double mass, const void* phi, void* X, void* Y, void* grad_fat,
-                            void* grad_naik, int32_t nrhs, double tol, mg_solve_info* info, void* stream);
+                            void* grad_naik, int32_t nrhs, double tol, double* action, mg_solve_info* info,
+                            void* stream);
 
 /* Replace the gauge links of an existing context (device, complex128): the
  * fine operator and the KD inverses follow the new links, the near-null
@@ -267,6 +277,20 @@ typedef enum {
 
 mg_status mg_profile_start(mg_ctx ctx, int32_t op, int32_t level);
 mg_status mg_profile_stop(mg_ctx ctx, int32_t* launches, double* total_ms);
+
+/* Measured ceilings of the device (measurement aids, not part of the
+ * method; no context needed).  Each times its kernel with HIP events on
+ * `stream` after one untimed launch.
+ *   mg_peak_copy: a 16-byte-per-lane copy of `bytes` (multiple of 16) from
+ *     src to dst (device, 16-byte aligned, distinct), reps timed launches;
+ *     *gbs = 2 bytes / time (read + write) in GB/s.
+ *   mg_peak_mfma: a loop of `iters` iterations of eight independent
+ *     16x16x32 MFMA products per wavefront (fmt MG_CBF16 or MG_CF16, FP32
+ *     accumulate) over 8 workgroups of four wavefronts per compute unit;
+ *     sink: device, >= 8 KiB (receives per-workgroup sums that keep the
+ *     products live); *tflops = dense 16-bit matrix-core rate in TFLOP/s. */
+mg_status mg_peak_copy(const void* src, void* dst, size_t bytes, int32_t reps, void* stream, double* gbs);
+mg_status mg_peak_mfma(int32_t fmt, int32_t iters, void* sink, void* stream, double* tflops);
 
 mg_status mg_destroy(mg_ctx ctx);
 

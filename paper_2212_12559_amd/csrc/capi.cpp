@@ -21,6 +21,8 @@ static mg_status fail(mg_status s, const std::string& m) {
   return s;
 }
 
+mg_status mg::set_last_error(mg_status s, const std::string& m) { return fail(s, m); }
+
 template <typename F>
 static mg_status guarded(F&& f) {
   try {
@@ -288,7 +290,8 @@ mg_status mg_msc_solve(mg_ctx ctx, const double* masses, int32_t nmass, const vo
 }
 
 mg_status mg_solve_backward(mg_ctx ctx, double mass, const void* phi, void* X, void* Y, void* grad_fat,
-                            void* grad_naik, int32_t nrhs, double tol, mg_solve_info* info, void* stream) {
+                            void* grad_naik, int32_t nrhs, double tol, double* action, mg_solve_info* info,
+                            void* stream) {
   if (!ctx) return fail(MG_E_ARG, "null context");
   Ctx& c = ctx->c;
   if (!phi || !X || !Y || !grad_fat || !info) return fail(MG_E_ARG, "null argument");
@@ -300,7 +303,7 @@ mg_status mg_solve_backward(mg_ctx ctx, double mass, const void* phi, void* X, v
   if (!aligned(phi) || !aligned(X) || !aligned(Y) || !aligned(grad_fat) || (grad_naik && !aligned(grad_naik)))
     return fail(MG_E_ALIGN, "buffers must be 16-byte aligned");
   c.st = (hipStream_t)stream;
-  mg_status s = guarded([&] { c.solve_backward(mass, phi, X, Y, grad_fat, grad_naik, nrhs, tol, info); });
+  mg_status s = guarded([&] { c.solve_backward(mass, phi, X, Y, grad_fat, grad_naik, nrhs, tol, action, info); });
   if (s != MG_OK) return s;
   for (int i = 0; i < 2 * nrhs; ++i)
     if (info[i].status != MG_OK) return fail((mg_status)info[i].status, "a solve did not converge");

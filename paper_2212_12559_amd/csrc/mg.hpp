@@ -14,6 +14,9 @@ struct Error {
   std::string msg;
 };
 
+// Records the thread-local message that mg_last_error returns; returns s.
+mg_status set_last_error(mg_status s, const std::string& msg);
+
 // A batch of nrhs vectors of n complex numbers each, contiguous per rhs.
 struct Vec {
   void* p = nullptr;
@@ -166,7 +169,7 @@ struct Ctx {
   void msc_solve(const double* masses, int nmass, const void* b, void* x, int nrhs, double tol, int maxiter,
                  mg_solve_info* info);
   void solve_backward(double mass, const void* phi, void* X, void* Y, void* gw, void* gn, int nrhs, double tol,
-                      mg_solve_info* info);
+                      double* action, mg_solve_info* info);
   void update_links(const void* fat, const void* naik);
   void build_level(int l, const void* nv_import);
   void pack_naik(const void* naik);

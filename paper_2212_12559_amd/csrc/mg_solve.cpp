@@ -132,7 +132,7 @@ void Ctx::solve_batch(const double* masses, int nmass, const void* b, void* x, i
 // Y = D X from two MG solves, D^dag = eps D eps giving Y = eps D^{-1} (eps phi)
 // and then X = D^{-1} Y, followed by the outer-product kernel.
 void Ctx::solve_backward(double mass, const void* phi, void* X, void* Y, void* gw, void* gn, int nrhs, double tol,
-                         mg_solve_info* info) {
+                         double* action, mg_solve_info* info) {
   launch_eps<double2>((double2*)X, (const double2*)phi, g0, nrhs, st);
   check_launch();
   solve(&mass, 1, X, Y, nrhs, tol, info);
@@ -142,6 +142,13 @@ void Ctx::solve_backward(double mass, const void* phi, void* X, void* Y, void* g
   launch_force((const double2*)X, (const double2*)Y, (double2*)gw, P.c3 != 0.0 ? (double2*)gn : nullptr, g0, nrhs,
                P.c1, P.c3, 0, st);
   check_launch();
+  if (action) {   // S_r = Re <phi_r, X_r>, one FP64 reduction per right-hand side
+    dots(P64, g0.V * 3, nrhs, {{phi, X}}, slot(0, kSlotNorm));
+    std::vector<double2> h(nrhs);
+    HIPCHK(hipMemcpyAsync(h.data(), slot(0, kSlotNorm), nrhs * sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int r = 0; r < nrhs; ++r) action[r] = h[r].x;
+  }
   HIPCHK(hipStreamSynchronize(st));
 }
 

@@ -86,10 +86,12 @@ def _load():
         "mg_cg_solve": (i32, [vp, P(f64), i32, vp, vp, i32, f64, i32, P(MGSolveInfo), vp]),
         "mg_msc_solve": (i32, [vp, P(f64), i32, vp, vp, i32, f64, i32, P(MGSolveInfo), vp]),
         "mg_export": (i32, [vp, i32, i32, vp, sz, P(sz), vp]),
-        "mg_solve_backward": (i32, [vp, f64, vp, vp, vp, vp, vp, i32, f64, P(MGSolveInfo), vp]),
+        "mg_solve_backward": (i32, [vp, f64, vp, vp, vp, vp, vp, i32, f64, P(f64), P(MGSolveInfo), vp]),
         "mg_update_links": (i32, [vp, vp, vp, vp]),
         "mg_profile_start": (i32, [vp, i32, i32]),
         "mg_profile_stop": (i32, [vp, P(i32), P(f64)]),
+        "mg_peak_copy": (i32, [vp, vp, sz, i32, vp, P(f64)]),
+        "mg_peak_mfma": (i32, [i32, i32, vp, vp, P(f64)]),
         "mg_destroy": (i32, [vp]),
         "mg_last_error": (ctypes.c_char_p, []),
     }
@@ -164,20 +166,42 @@ def _dev(t, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _check_batch(t, name, per_rhs, dtype=None, nrhs=None):
+    """The library takes raw pointers: check what it will read or write.
+    t must hold a whole number of vectors of per_rhs complex elements (of the
+    given dtype, complex128/complex64 otherwise) and, when nrhs is given,
+    exactly nrhs of them; returns the number of vectors."""
+    torch = _torch()
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dtype not in (torch.complex128, torch.complex64):
+        raise TypeError(f"{name} must be complex128 or complex64, got {t.dtype}")
+    n = t.numel()
+    if n == 0 or n % per_rhs:
+        raise ValueError(f"{name} has {n} elements, not a positive multiple of {per_rhs} (one vector)")
+    if nrhs is not None and n != nrhs * per_rhs:
+        raise ValueError(f"{name} has {n // per_rhs} vectors, expected {nrhs}")
+    return n // per_rhs
+
+
 class Context:
     """An mg_ctx with its two caller-owned device workspaces."""
 
     def __init__(self, params: MGParams, fat, naik=None, null_vectors=None):
         torch = _torch()
-        self.params = params
-        self.dims = tuple(params.dims)
-        pb, sb = workspace_bytes(params)
+        self.ctx = None
+        self._init_shapes(params)
+        pb, sb = workspace_bytes(params)   # validates the parameters first
+        nlink = 4 * self.V * 9
+        _check_batch(fat, "fat", nlink, torch.complex128, 1)
+        if params.c3 != 0.0:
+            if naik is None:
+                raise ValueError("naik links are required when c3 != 0")
+            _check_batch(naik, "naik", nlink, torch.complex128, 1)
         dev = fat.device
         # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
         self.persistent = torch.empty(pb, dtype=torch.uint8, device=dev)
         self.scratch = torch.empty(sb, dtype=torch.uint8, device=dev)
-        if fat.dtype != torch.complex128:
-            raise TypeError("links must be complex128")
         nvp = None
         self._keep = []
         if null_vectors is not None:
@@ -185,8 +209,9 @@ class Context:
             for l in range(params.nagg):
                 v = null_vectors[l] if l < len(null_vectors) else None
                 if v is not None:
-                    if v.dtype != torch.complex128:
-                        raise TypeError("null vectors must be complex128")
+                    _check_batch(v, f"null_vectors[{l}]", self._level_size(l + 1), torch.complex128,
+                                 params.nvec[l])
+                    _dev(v, f"null_vectors[{l}]")
                     self._keep.append(v)
                     arr[l] = v.data_ptr()
             nvp = arr
@@ -197,56 +222,77 @@ class Context:
                           ctypes.c_void_p(self.scratch.data_ptr()), sb, _stream(), ctypes.byref(ctx))
         _check(st, "mg_setup")
         self.ctx = ctx
+
+    def _init_shapes(self, params):
+        """Lattice and level shapes (host only)."""
+        self.params = params
+        self.dims = tuple(params.dims)
         X, Y, Z, T = self.dims
+        self.V = X * Y * Z * T
         self.fine_shape = (T, Z, Y, X, 3)
         self.coarse_shapes = []
         cd = list(self.dims)
-        nin = None
         for l in range(params.nagg):
             cd = [cd[mu] // params.block[l][mu] for mu in range(4)]
             self.coarse_shapes.append((cd[3], cd[2], cd[1], cd[0], 2, params.nvec[l]))
 
+    def _level_size(self, level):
+        """Complex elements of one vector of `level` (1: fine, 2, 3: coarse)."""
+        if level == 1:
+            return 3 * self.V
+        n = 1
+        for v in self.coarse_shapes[level - 2]:
+            n *= v
+        return n
+
+    def _out(self, out, like, shape, name="out"):
+        torch = _torch()
+        if out is None:
+            return torch.empty(shape, dtype=like.dtype, device=like.device)
+        n = 1
+        for v in shape:
+            n *= v
+        _check_batch(out, name, n, like.dtype, 1)
+        if out.data_ptr() == like.data_ptr():
+            raise ValueError(f"{name} must not alias the input")
+        return out
+
     # ---------------------------------------------------------------- applies
     def apply_dslash(self, op, mass, x, out=None):
-        torch = _torch()
-        out = torch.empty_like(x) if out is None else out
-        nrhs = x.numel() // (3 * self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3])
+        nrhs = _check_batch(x, "x", self._level_size(1))
+        out = self._out(out, x, tuple(x.shape))
         _check(LIB.mg_apply_dslash(self.ctx, op, mass, _dtype_code(x), _dev(x, "x"), _dev(out, "out"), nrhs,
                                    _stream()), "mg_apply_dslash")
         return out
 
-    def _level_size(self, level):
-        if level == 1:
-            return 3 * self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
-        s = self.coarse_shapes[level - 2]
-        n = 1
-        for v in s:
-            n *= v
-        return n
-
     def apply_coarse(self, level, x, out=None):
-        torch = _torch()
-        out = torch.empty_like(x) if out is None else out
-        nrhs = x.numel() // self._level_size(level)
+        if not 2 <= level <= 1 + self.params.nagg:
+            raise ValueError(f"level must be in 2..{1 + self.params.nagg}")
+        nrhs = _check_batch(x, "x", self._level_size(level))
+        out = self._out(out, x, tuple(x.shape))
         _check(LIB.mg_apply_coarse(self.ctx, level, _dtype_code(x), _dev(x, "x"), _dev(out, "out"), nrhs,
                                    _stream()), "mg_apply_coarse")
         return out
 
     def restrict(self, level, x, out=None):
-        torch = _torch()
-        nrhs = x.numel() // self._level_size(level)
-        if out is None:
-            out = torch.empty((nrhs,) + self.coarse_shapes[level - 1], dtype=x.dtype, device=x.device)
+        if not 1 <= level <= self.params.nagg:
+            raise ValueError(f"level must be in 1..{self.params.nagg}")
+        nrhs = _check_batch(x, "x", self._level_size(level))
+        out = self._out(out, x, (nrhs,) + self.coarse_shapes[level - 1])
         _check(LIB.mg_restrict(self.ctx, level, _dtype_code(x), _dev(x, "x"), _dev(out, "out"), nrhs, _stream()),
                "mg_restrict")
         return out
 
     def prolong(self, level, xc, out=None, accumulate=False):
         torch = _torch()
-        nrhs = xc.numel() // self._level_size(level + 1)
+        if not 1 <= level <= self.params.nagg:
+            raise ValueError(f"level must be in 1..{self.params.nagg}")
+        nrhs = _check_batch(xc, "xc", self._level_size(level + 1))
+        shape = (nrhs,) + tuple(self.fine_shape if level == 1 else self.coarse_shapes[level - 2])
         if out is None:
-            shape = self.fine_shape if level == 1 else self.coarse_shapes[level - 2]
-            out = torch.zeros((nrhs,) + tuple(shape), dtype=xc.dtype, device=xc.device)
+            out = torch.zeros(shape, dtype=xc.dtype, device=xc.device)
+        else:
+            out = self._out(out, xc, shape)
         _check(LIB.mg_prolong(self.ctx, level, _dtype_code(xc), _dev(xc, "xc"), _dev(out, "out"),
                               1 if accumulate else 0, nrhs, _stream()), "mg_prolong")
         return out
@@ -254,9 +300,11 @@ class Context:
     # ---------------------------------------------------------------- solves
     def _solve(self, fn, masses, b, tol, extra=()):
         torch = _torch()
-        nrhs = b.shape[0]
+        nrhs = _check_batch(b, "b", self._level_size(1), torch.complex128)
         nm = len(masses)
-        x = torch.empty((nm,) + tuple(b.shape), dtype=torch.complex128, device=b.device)
+        if nm < 1:
+            raise ValueError("at least one mass")
+        x = torch.empty((nm, nrhs) + self.fine_shape, dtype=torch.complex128, device=b.device)
         infos = (MGSolveInfo * (nm * nrhs))()
         m = (ctypes.c_double * nm)(*masses)
         st = fn(self.ctx, m, nm, _dev(b, "b"), _dev(x, "x"), nrhs, tol, *extra, infos, _stream())
@@ -283,23 +331,32 @@ class Context:
         return x, info, st
 
     def solve_backward(self, mass, phi, tol=1e-10):
-        """X = (D^dag D)^{-1} phi, Y = D X and the fermion-force gradients of
-        S = sum_r phi_r^dag (D^dag D)^{-1} phi_r with respect to the fat and
-        Naik links (PyTorch convention).  phi [nrhs][T][Z][Y][X][3] complex128."""
+        """X = (D^dag D)^{-1} phi, Y = D X, the action S_r = Re <phi_r, X_r> per
+        right-hand side and the fermion-force gradients of S = sum_r S_r with
+        respect to the fat and Naik links (PyTorch convention), all computed
+        by the library.  phi [nrhs][T][Z][Y][X][3] complex128."""
         torch = _torch()
-        nrhs = phi.shape[0]
+        nrhs = _check_batch(phi, "phi", self._level_size(1), torch.complex128)
         X = torch.empty_like(phi)
         Y = torch.empty_like(phi)
         T_, Z_, Y_, X_ = self.fine_shape[:4]
         gw = torch.empty((4, T_, Z_, Y_, X_, 3, 3), dtype=torch.complex128, device=phi.device)
         gn = torch.empty_like(gw) if self.params.c3 != 0.0 else None
         infos = (MGSolveInfo * (2 * nrhs))()
+        action = (ctypes.c_double * nrhs)()
         st = LIB.mg_solve_backward(self.ctx, mass, _dev(phi, "phi"), _dev(X, "X"), _dev(Y, "Y"), _dev(gw, "grad_fat"),
-                                   _dev(gn, "grad_naik") if gn is not None else None, nrhs, tol, infos, _stream())
+                                   _dev(gn, "grad_naik") if gn is not None else None, nrhs, tol, action, infos,
+                                   _stream())
         _check(st, "mg_solve_backward")
+        self.last_action = list(action)
         return X, Y, gw, gn, [i.as_dict() for i in infos]
 
     def update_links(self, fat, naik=None):
+        torch = _torch()
+        nlink = 4 * self.V * 9
+        _check_batch(fat, "fat", nlink, torch.complex128, 1)
+        if naik is not None:
+            _check_batch(naik, "naik", nlink, torch.complex128, 1)
         _check(LIB.mg_update_links(self.ctx, _dev(fat, "fat"), _dev(naik, "naik") if naik is not None else None,
                                    _stream()), "mg_update_links")
 
@@ -336,6 +393,25 @@ class Context:
             pass
 
 
+def peak_copy(src, dst, reps=5):
+    """Measured HBM ceiling: GB/s (read + write) of the library's copy kernel."""
+    if src.numel() * src.element_size() != dst.numel() * dst.element_size():
+        raise ValueError("src and dst must have the same size")
+    g = ctypes.c_double()
+    _check(LIB.mg_peak_copy(_dev(src, "src"), _dev(dst, "dst"), src.numel() * src.element_size(), reps, _stream(),
+                            ctypes.byref(g)), "mg_peak_copy")
+    return g.value
+
+
+def peak_mfma(fmt=MG_CBF16, iters=20000, device="cuda:0"):
+    """Measured dense 16-bit matrix-core rate in TFLOP/s."""
+    torch = _torch()
+    sink = torch.empty(8192, dtype=torch.uint8, device=device)
+    t = ctypes.c_double()
+    _check(LIB.mg_peak_mfma(fmt, iters, _dev(sink, "sink"), _stream(), ctypes.byref(t)), "mg_peak_mfma")
+    return t.value
+
+
 def setup(params, fat, naik=None, null_vectors=None) -> Context:
     return Context(params, fat, naik, null_vectors)
 
@@ -355,7 +431,7 @@ def _fermion_action_class():
             X, Y, gw, gn, info = ctx_mg.solve_backward(mass, phi.detach().contiguous(), tol)
             ctx.save_for_backward(gw, gn if gn is not None else gw)
             ctx.has_naik = gn is not None
-            return torch.sum(torch.conj(phi.detach()) * X).real
+            return torch.tensor(sum(ctx_mg.last_action), dtype=torch.float64, device=W.device)
 
         @staticmethod
         def backward(ctx, g):

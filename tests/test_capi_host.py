@@ -104,3 +104,54 @@ def test_profile_entry_points_validate(m):
     ms = ctypes.c_double()
     assert m.LIB.mg_profile_start(None, m.MG_PROF_COARSE, 2) == m.MG_E_ARG
     assert m.LIB.mg_profile_stop(None, ctypes.byref(n), ctypes.byref(ms)) == m.MG_E_ARG
+
+
+def _shell(m, dims=(8, 8, 8, 8), **kw):
+    """A Context with its shapes but no device state: the binding's checks run
+    before any library call, so they can be exercised on the host."""
+    c = object.__new__(m.Context)
+    c.ctx = None
+    c._init_shapes(m.default_params(dims, **kw))
+    return c
+
+
+def test_binding_rejects_wrong_sizes_and_dtypes(m):
+    """The library reads and writes through raw pointers: the binding checks
+    dtype and element count of every buffer it hands over (a tensor that
+    would make the library run past its end is refused on the host)."""
+    import torch
+    c = _shell(m, nvec=(8, 8), max_nrhs=4)
+    V = 8 ** 4
+    fine = torch.zeros((2, 8, 8, 8, 8, 3), dtype=torch.complex128)
+    # a solve needs complex128 right-hand sides
+    with pytest.raises(TypeError):
+        c.solve([0.1], fine.to(torch.complex64))
+    # a partial vector
+    with pytest.raises(ValueError):
+        c.solve([0.1], torch.zeros(3 * V - 3, dtype=torch.complex128))
+    with pytest.raises(ValueError):
+        c.apply_dslash(0, 0.1, torch.zeros(3 * V + 1, dtype=torch.complex64))
+    # real tensors are not vectors
+    with pytest.raises(TypeError):
+        c.apply_dslash(0, 0.1, torch.zeros(6 * V, dtype=torch.float64))
+    # an output of the wrong size or dtype
+    with pytest.raises(ValueError):
+        c.apply_dslash(0, 0.1, fine, out=torch.zeros((1, 8, 8, 8, 8, 3), dtype=torch.complex128))
+    with pytest.raises(TypeError):
+        c.apply_dslash(0, 0.1, fine, out=torch.zeros_like(fine, dtype=torch.complex64))
+    # coarse vectors: level 2 is 2^4 x 2 x 8 per rhs; level 3 1^4 x 2 x 8
+    with pytest.raises(ValueError):
+        c.apply_coarse(2, torch.zeros(2 ** 4 * 2 * 8 + 2, dtype=torch.complex64))
+    with pytest.raises(ValueError):
+        c.apply_coarse(4, torch.zeros(16, dtype=torch.complex64))
+    with pytest.raises(ValueError):
+        c.restrict(1, torch.zeros(3 * V, dtype=torch.complex64), out=torch.zeros(7, dtype=torch.complex64))
+    with pytest.raises(ValueError):
+        c.prolong(1, torch.zeros(2 ** 4 * 2 * 8, dtype=torch.complex64), out=torch.zeros(5, dtype=torch.complex64))
+    # links: complex128, one full field
+    with pytest.raises(TypeError):
+        c.update_links(torch.zeros(4 * V * 9, dtype=torch.complex64))
+    with pytest.raises(ValueError):
+        c.update_links(torch.zeros(4 * V * 9 - 9, dtype=torch.complex128))
+    with pytest.raises(TypeError):
+        c.solve_backward(0.1, fine.to(torch.complex64))

@@ -394,6 +394,9 @@ def test_force_matches_oracle(torch, mg, cubic):
         Sn += gN
     assert rel_err(gw, Sw) < 1e-9
     assert rel_err(gn, Sn) < 1e-9
+    # the library returns the action per right-hand side (S_r = Re <phi_r, X_r>)
+    assert len(ctx.last_action) == phi.shape[0]
+    assert abs(sum(ctx.last_action) - S) < 1e-9 * abs(S)
     Wt = torch.from_numpy(W).to("cuda:0").requires_grad_(True)
     Nt = torch.from_numpy(N).to("cuda:0").requires_grad_(True)
     St = mg.fermion_action(Wt, Nt, torch.from_numpy(phi).to("cuda:0"), ctx, m, 1e-13)

@@ -264,3 +264,84 @@ def test_qr_positive_unique():
             w -= np.vdot(G[:, j], w) * G[:, j]
         G[:, k] = w / np.linalg.norm(w)
     assert np.max(np.abs(G - Q)) < 1e-13
+
+
+def test_coarse_dof_labels_pinned_by_restriction_and_chirality():
+    """The labels of a second aggregation (coarse_dof_labels) follow from what
+    the first one produces, not from their own formula: a fine vector on one
+    chirality restricts onto the coarse dofs labelled with it, a fine vector on
+    one first-level aggregate restricts onto the dofs of that coarse site, and
+    the coarse aggregates are those of a brute-force loop over coarse
+    coordinates.  The coarse chirality they define is the one the physics
+    fixes: eps_hat P1^dag D P1 eps_hat = (P1^dag D P1)^dag (eps D eps = D^dag,
+    Sec. 2.2), and it carries over to the third level."""
+    dims, b1, b2, nvec = (8, 4, 4, 4), (2, 2, 2, 2), (2, 1, 1, 2), 6
+    cd = tuple(d // b for d, b in zip(dims, b1))          # (4, 2, 2, 2)
+    cd3 = tuple(d // b for d, b in zip(cd, b2))           # (2, 2, 2, 1)
+    rng = np.random.default_rng(11)
+    W, N, rng = rand_links(dims, 16)
+    nv = latgen.fine_vectors(dims, nvec, rng)
+    t1 = ops.Transfer(nv, *ops.fine_dof_labels(dims, b1))
+    agg1, chi1 = ops.coarse_dof_labels(cd, nvec, (1, 1, 1, 1))
+    nc = int(np.prod(cd)) * 2 * nvec
+    assert agg1.shape == chi1.shape == (nc,)
+    eps = ops.epsilon(dims)[..., None]
+    r = latgen.fine_vectors(dims, 1, rng)[0]
+    # chirality: restriction of each chiral half lands on the dofs with that label
+    for sgn, lab in ((1, 0), (-1, 1)):
+        rc = t1.restrict(0.5 * (1 + sgn * eps) * r).reshape(-1)
+        assert np.all(np.abs(rc[chi1 != lab]) == 0.0)
+        assert np.all(np.abs(rc[chi1 == lab]) > 0.0)
+    # aggregates: fine sites of first-level aggregate c (brute-force coordinates)
+    X, Y, Z, T = dims
+    owner = np.zeros((T, Z, Y, X), dtype=np.int64)
+    for t in range(T):
+        for z in range(Z):
+            for y in range(Y):
+                for x in range(X):
+                    owner[t, z, y, x] = (x // b1[0]) + cd[0] * ((y // b1[1]) + cd[1] * ((z // b1[2]) + cd[2] * (t // b1[3])))
+    for c in (0, 5, int(np.prod(cd)) - 1):
+        rc = t1.restrict(np.where((owner == c)[..., None], r, 0)).reshape(-1)
+        assert np.all(rc[agg1 != c] == 0.0) and np.all(np.abs(rc[agg1 == c]) > 0.0)
+    # second aggregation: coarse site c at coordinates from a loop, aggregate by floor(x / b2)
+    agg2, chi2 = ops.coarse_dof_labels(cd, nvec, b2)
+    assert np.array_equal(chi2, chi1)
+    site = 0
+    for t in range(cd[3]):
+        for z in range(cd[2]):
+            for y in range(cd[1]):
+                for x in range(cd[0]):
+                    want = (x // b2[0]) + cd3[0] * ((y // b2[1]) + cd3[1] * ((z // b2[2]) + cd3[2] * (t // b2[3])))
+                    assert np.all(agg2[site * 2 * nvec:(site + 1) * 2 * nvec] == want)
+                    site += 1
+    # physics: the labelled chirality makes the Galerkin operator eps-hermitian
+    m = 0.05
+    P1 = np.stack([t1.prolong(np.eye(nc)[j]) for j in range(nc)], axis=1)
+    D1 = P1.conj().T @ np.stack([ops.dslash(P1[:, j].reshape(T, Z, Y, X, 3), W, N, m, C1H, C3H).reshape(-1)
+                                 for j in range(nc)], axis=1)
+    e2 = 1.0 - 2.0 * chi1
+    assert np.max(np.abs(e2[:, None] * D1 * e2[None, :] - D1.conj().T)) < 1e-12 * np.max(np.abs(D1))
+    # a swapped labelling (spin index taken as the fast one) breaks it
+    bad = np.tile(np.arange(2 * nvec) % 2, nc // (2 * nvec))
+    eb = 1.0 - 2.0 * bad
+    assert np.max(np.abs(eb[:, None] * D1 * eb[None, :] - D1.conj().T)) > 1e-3 * np.max(np.abs(D1))
+    # third level: columns on one aggregate and one chirality, null vectors' chiral halves in range(P2),
+    # and the level-3 operator is eps-hermitian with the labels of its own layout
+    nvec2 = 5
+    nv2 = latgen.coarse_vectors(cd, nvec, nvec2, rng)
+    t2 = ops.Transfer(nv2, agg2, chi2)
+    nc3 = int(np.prod(cd3)) * 2 * nvec2
+    P2 = np.stack([t2.prolong(np.eye(nc3)[j]) for j in range(nc3)], axis=1)
+    assert np.max(np.abs(P2.conj().T @ P2 - np.eye(nc3))) < 1e-13
+    for j in range(nc3):
+        nz = np.abs(P2[:, j]) > 0
+        assert np.all(agg2[nz] == j // (2 * nvec2)) and np.all(chi2[nz] == (j // nvec2) % 2)
+    for k in range(nvec2):
+        v = nv2[k].reshape(-1)
+        for sgn in (1, -1):
+            pv = 0.5 * (1 + sgn * e2) * v
+            assert np.linalg.norm(P2 @ (P2.conj().T @ pv) - pv) < 1e-12 * np.linalg.norm(pv)
+    D2 = P2.conj().T @ D1 @ P2
+    _, chi3 = ops.coarse_dof_labels(cd3, nvec2, (1, 1, 1, 1))
+    e3 = 1.0 - 2.0 * chi3
+    assert np.max(np.abs(e3[:, None] * D2 * e3[None, :] - D2.conj().T)) < 1e-12 * np.max(np.abs(D2))
