@@ -100,6 +100,9 @@ typedef struct {
                                 coarsest operator from CGNE at set-up; each coarsest solve then starts from
                                 the least-squares solution on their span */
   int32_t deflate_maxiter;   /* CGNE iterations for the deflation vectors */
+  int32_t deflate_import;    /* 1: null_vectors of mg_setup holds nagg + 1 pointers and the last one gives the
+                                coarsest_deflate deflation vectors (complex128 [k][coarsest vector]) in place of
+                                the CGNE ones; 0: nagg pointers */
   uint64_t seed;             /* seed of the GPU-generated null-vector starts */
 } mg_params;
 
@@ -125,11 +128,12 @@ mg_status mg_workspace_bytes(const mg_params* p, size_t* persistent, size_t* scr
 /* Build the hierarchy (Sec. 2.1, Sec. 2.3; setup is excluded from the
  * paper's time-to-solution, Sec. 3.2).
  *   fat, naik: device, complex128 link fields (naik ignored when c3 == 0)
- *   null_vectors: device array of nagg pointers (host array) to complex128
- *     near-null vectors, level 1 as [nvec[0]][T][Z][Y][X][3], level 2 as
- *     [nvec[1]][Tc][Zc][Yc][Xc][2][nvec[0]]; pass NULL (or a NULL entry) to
- *     generate that level on the GPU by CGNE on the level's operator
- *     (Sec. 2.1, Table 1).
+ *   null_vectors: host array of nagg pointers (nagg + 1 with deflate_import)
+ *     to device complex128 near-null vectors, level 1 as
+ *     [nvec[0]][T][Z][Y][X][3], level 2 as [nvec[1]][Tc][Zc][Yc][Xc][2][nvec[0]],
+ *     then the coarsest level's deflation vectors; pass NULL (or a NULL
+ *     entry) to generate that level's vectors on the GPU by CGNE on the
+ *     level's operator (Sec. 2.1, Table 1).  Imported vectors are copied.
  *   persistent_ws / scratch_ws: device, caller-owned, at least the sizes
  *     reported by mg_workspace_bytes (MG_E_WORKSPACE otherwise), 256-byte
  *     aligned.

@@ -551,6 +551,24 @@ void launch_conv(int* mask, const double2* rn2, const double2* r0sq, double tol2
   conv_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(mask, rn2, r0sq, tol2, nrhs, init);
 }
 
+// A power of two brings each system's right-hand side to entries of order
+// one: exact in every format with the range, and it keeps the inputs of the
+// 16-bit coarse stencil clear of FP16's subnormal range however far the
+// outer residual has fallen.
+__global__ void rhs_scale_kernel(double2* r0sq, double2* fwd, double2* inv, int64_t n, int nrhs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const double b2 = r0sq[r].x;
+  int e = 0;
+  if (b2 > 0.0 && b2 < 1e300) e = (int)rint(0.5 * log2(b2 / (double)n));
+  fwd[r] = make_double2(ldexp(1.0, -e), 0.0);
+  inv[r] = make_double2(ldexp(1.0, e), 0.0);
+  r0sq[r].x = ldexp(b2, -2 * e);
+}
+void launch_rhs_scale(double2* r0sq, double2* fwd, double2* inv, int64_t n, int nrhs, hipStream_t st) {
+  rhs_scale_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(r0sq, fwd, inv, n, nrhs);
+}
+
 // ---------------------------------------------------------------- scalars
 // GCR: after orthogonalisation, qq = <q, q>, qr = <q, r>.
 //   alpha = qr / qq (0 for masked systems), inv = 1 / sqrt(qq)

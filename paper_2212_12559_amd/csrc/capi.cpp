@@ -10,10 +10,6 @@
 
 using namespace mg;
 
-struct mg_ctx_s {
-  Ctx c;
-};
-
 static thread_local std::string g_err;
 
 static mg_status fail(mg_status s, const std::string& m) {
@@ -39,89 +35,6 @@ static mg_status guarded(F&& f) {
 
 static bool aligned(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
-extern "C" {
-
-const char* mg_last_error(void) { return g_err.c_str(); }
-
-void mg_default_params(mg_params* p, const int32_t dims[4]) {
-  if (!p) return;
-  std::memset(p, 0, sizeof(*p));
-  for (int mu = 0; mu < 4; ++mu) p->dims[mu] = dims ? dims[mu] : 4;
-  p->c1 = 9.0 / 8.0;
-  p->c3 = -1.0 / 24.0;
-  p->kd_naik = 1;
-  p->mass0 = 0.01;
-  p->nagg = 2;
-  for (int mu = 0; mu < 4; ++mu) { p->block[0][mu] = 4; p->block[1][mu] = 2; }
-  p->nvec[0] = 64;
-  p->nvec[1] = 96;
-  p->setup_maxiter[0] = p->setup_maxiter[1] = 2000;
-  p->setup_tol[0] = p->setup_tol[1] = 1e-6;
-  p->smoother_s = 8;
-  p->inner_tol = 0.25;
-  p->inner_maxiter = 8;
-  p->coarsest_tol = 0.25;
-  p->coarsest_maxiter = 16;
-  p->coarsest_restarts = 1;
-  p->outer_nkrylov = 16;
-  p->outer_maxiter = 500;
-  p->reliable_delta = 0.1;
-  p->fine_prec = MG_C64;
-  p->coarse_prec = MG_C64;
-  p->max_nrhs = 1;
-  p->max_nmass = 1;
-  p->coarsest_deflate = 0;
-  p->deflate_maxiter = 300;
-  p->seed = 20221224ull;
-}
-
-mg_status mg_workspace_bytes(const mg_params* p, size_t* persistent, size_t* scratch) {
-  if (!p || !persistent || !scratch) return fail(MG_E_ARG, "null argument");
-  Arena a, b;
-  std::string why;
-  if (!Ctx::plan(*p, nullptr, a, b, &why)) return fail(MG_E_CONFIG, why);
-  *persistent = a.off + 256;
-  *scratch = b.off + 256;
-  return MG_OK;
-}
-
-mg_status mg_setup(const mg_params* p, const void* fat, const void* naik, const void* const* null_vectors,
-                   void* persistent_ws, size_t persistent_bytes, void* scratch_ws, size_t scratch_bytes,
-                   void* stream, mg_ctx* out) {
-  if (!p || !fat || !persistent_ws || !scratch_ws || !out) return fail(MG_E_ARG, "null argument");
-  if (p->c3 != 0.0 && !naik) return fail(MG_E_ARG, "naik links required when c3 != 0");
-  if (((uintptr_t)persistent_ws & 255) || ((uintptr_t)scratch_ws & 255))
-    return fail(MG_E_ALIGN, "workspaces must be 256-byte aligned");
-  if (!aligned(fat) || (naik && !aligned(naik))) return fail(MG_E_ALIGN, "links must be 16-byte aligned");
-  size_t need_p = 0, need_s = 0;
-  mg_status s = mg_workspace_bytes(p, &need_p, &need_s);
-  if (s != MG_OK) return s;
-  if (persistent_bytes < need_p || scratch_bytes < need_s) return fail(MG_E_WORKSPACE, "workspace too small");
-  if (null_vectors)
-    for (int l = 0; l < p->nagg; ++l)
-      if (null_vectors[l] && !aligned(null_vectors[l])) return fail(MG_E_ALIGN, "null vectors must be 16-byte aligned");
-  mg_ctx ctx = new (std::nothrow) mg_ctx_s;
-  if (!ctx) return fail(MG_E_ARG, "host allocation failed");
-  Arena pa, sa;
-  pa.base = (char*)persistent_ws;
-  pa.cap = persistent_bytes;
-  sa.base = (char*)scratch_ws;
-  sa.cap = scratch_bytes;
-  std::string why;
-  if (!Ctx::plan(*p, &ctx->c, pa, sa, &why)) {
-    delete ctx;
-    return fail(MG_E_CONFIG, why);
-  }
-  ctx->c.st = (hipStream_t)stream;
-  s = guarded([&] { ctx->c.setup(fat, naik, null_vectors); });
-  if (s != MG_OK) {
-    delete ctx;
-    return s;
-  }
-  *out = ctx;
-  return MG_OK;
-}
-
 static mg_status check_vec(int32_t dtype, const void* in, const void* out, int32_t nrhs, int max) {
   if (!in || !out) return fail(MG_E_ARG, "null vector");
   if (in == out) return fail(MG_E_ARG, "input and output must be distinct");
@@ -131,17 +44,14 @@ static mg_status check_vec(int32_t dtype, const void* in, const void* out, int32
   return MG_OK;
 }
 
-mg_status mg_apply_dslash(mg_ctx ctx, int32_t op, double mass, int32_t dtype, const void* in, void* out,
-                          int32_t nrhs, void* stream) {
-  if (!ctx) return fail(MG_E_ARG, "null context");
-  Ctx& c = ctx->c;
+mg_status mg::apply_dslash_with(Ctx& c, int32_t op, double mass, int32_t dtype, const void* in, void* out,
+                                int32_t nrhs, void* stream, void* tmp) {
   mg_status s = check_vec(dtype, in, out, nrhs, c.P.max_nrhs);
   if (s != MG_OK) return s;
   if (op < 0 || op > 4) return fail(MG_E_ARG, "op must be 0..4");
   if (!std::isfinite(mass)) return fail(MG_E_ARG, "mass must be finite");
   c.st = (hipStream_t)stream;
   const int prec = dtype == MG_C128 ? P64 : P32;
-  void* tmp = c.L[0].z[0].p;   // FP64-sized work batch (max_sys systems)
   return guarded([&] {
     if (op == 0) {
       c.apply_D(prec, out, in, nrhs, true, nullptr, mass);
@@ -188,6 +98,98 @@ mg_status mg_apply_dslash(mg_ctx ctx, int32_t op, double mass, int32_t dtype, co
       if (e != hipSuccess) throw Error{MG_E_HIP, hipGetErrorString(e)};
     }
   });
+}
+
+extern "C" {
+
+const char* mg_last_error(void) { return g_err.c_str(); }
+
+void mg_default_params(mg_params* p, const int32_t dims[4]) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  for (int mu = 0; mu < 4; ++mu) p->dims[mu] = dims ? dims[mu] : 4;
+  p->c1 = 9.0 / 8.0;
+  p->c3 = -1.0 / 24.0;
+  p->kd_naik = 1;
+  p->mass0 = 0.01;
+  p->nagg = 2;
+  for (int mu = 0; mu < 4; ++mu) { p->block[0][mu] = 4; p->block[1][mu] = 2; }
+  p->nvec[0] = 64;
+  p->nvec[1] = 96;
+  p->setup_maxiter[0] = p->setup_maxiter[1] = 2000;
+  p->setup_tol[0] = p->setup_tol[1] = 1e-6;
+  p->smoother_s = 8;
+  p->inner_tol = 0.25;
+  p->inner_maxiter = 8;
+  p->coarsest_tol = 0.25;
+  p->coarsest_maxiter = 16;
+  p->coarsest_restarts = 1;
+  p->outer_nkrylov = 16;
+  p->outer_maxiter = 500;
+  p->reliable_delta = 0.1;
+  p->fine_prec = MG_C64;
+  p->coarse_prec = MG_C64;
+  p->max_nrhs = 1;
+  p->max_nmass = 1;
+  p->coarsest_deflate = 0;
+  p->deflate_maxiter = 300;
+  p->deflate_import = 0;
+  p->seed = 20221224ull;
+}
+
+mg_status mg_workspace_bytes(const mg_params* p, size_t* persistent, size_t* scratch) {
+  if (!p || !persistent || !scratch) return fail(MG_E_ARG, "null argument");
+  Arena a, b;
+  std::string why;
+  if (!Ctx::plan(*p, nullptr, a, b, &why)) return fail(MG_E_CONFIG, why);
+  *persistent = a.off + 256;
+  *scratch = b.off + 256;
+  return MG_OK;
+}
+
+mg_status mg_setup(const mg_params* p, const void* fat, const void* naik, const void* const* null_vectors,
+                   void* persistent_ws, size_t persistent_bytes, void* scratch_ws, size_t scratch_bytes,
+                   void* stream, mg_ctx* out) {
+  if (!p || !fat || !persistent_ws || !scratch_ws || !out) return fail(MG_E_ARG, "null argument");
+  if (p->c3 != 0.0 && !naik) return fail(MG_E_ARG, "naik links required when c3 != 0");
+  if (((uintptr_t)persistent_ws & 255) || ((uintptr_t)scratch_ws & 255))
+    return fail(MG_E_ALIGN, "workspaces must be 256-byte aligned");
+  if (!aligned(fat) || (naik && !aligned(naik))) return fail(MG_E_ALIGN, "links must be 16-byte aligned");
+  size_t need_p = 0, need_s = 0;
+  mg_status s = mg_workspace_bytes(p, &need_p, &need_s);
+  if (s != MG_OK) return s;
+  if (persistent_bytes < need_p || scratch_bytes < need_s) return fail(MG_E_WORKSPACE, "workspace too small");
+  if (null_vectors)
+    for (int l = 0; l < p->nagg + (p->coarsest_deflate > 0 && p->deflate_import ? 1 : 0); ++l)
+      if (null_vectors[l] && !aligned(null_vectors[l])) return fail(MG_E_ALIGN, "null vectors must be 16-byte aligned");
+  mg_ctx ctx = new (std::nothrow) mg_ctx_s;
+  if (!ctx) return fail(MG_E_ARG, "host allocation failed");
+  Arena pa, sa;
+  pa.base = (char*)persistent_ws;
+  pa.cap = persistent_bytes;
+  sa.base = (char*)scratch_ws;
+  sa.cap = scratch_bytes;
+  std::string why;
+  if (!Ctx::plan(*p, &ctx->c, pa, sa, &why)) {
+    delete ctx;
+    return fail(MG_E_CONFIG, why);
+  }
+  ctx->c.st = (hipStream_t)stream;
+  s = guarded([&] { ctx->c.setup(fat, naik, null_vectors); });
+  if (s != MG_OK) {
+    delete ctx;
+    return s;
+  }
+  *out = ctx;
+  return MG_OK;
+}
+
+
+mg_status mg_apply_dslash(mg_ctx ctx, int32_t op, double mass, int32_t dtype, const void* in, void* out,
+                          int32_t nrhs, void* stream) {
+  if (!ctx) return fail(MG_E_ARG, "null context");
+  // work batch: the first K-cycle direction of level 0 (FP64-sized, max_sys systems)
+  return apply_dslash_with(ctx->c, op, mass, dtype, in, out, nrhs, stream, ctx->c.L[0].z[0].p);
 }
 
 mg_status mg_apply_coarse(mg_ctx ctx, int32_t level, int32_t dtype, const void* in, void* out, int32_t nrhs,

@@ -227,6 +227,9 @@ template <typename T>
 void launch_gcr_update_cgs(const GcrUpdArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st);
 void launch_conv(int* mask, const double2* rn2, const double2* r0sq, double tol2, int nrhs, int init,
                  hipStream_t st);
+// Per-system power-of-two scale s = 2^-e, e = round(log2 rms(b)), from |b|^2
+// (r0sq, rescaled to |s b|^2 in place); fwd = s, inv = 1 / s.
+void launch_rhs_scale(double2* r0sq, double2* fwd, double2* inv, int64_t n, int nrhs, hipStream_t st);
 
 // Coarsest-level deflation (deflate.hip): at most kMaxDefl vectors.
 constexpr int kMaxDefl = 64;

@@ -44,6 +44,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   if (p.coarsest_deflate < 0 || p.coarsest_deflate > kMaxDefl || p.coarsest_deflate % 16)
     return fail("coarsest_deflate must be 0, 16, 32, 48 or 64");
   if (p.coarsest_deflate > 0 && p.deflate_maxiter < 1) return fail("deflate_maxiter must be >= 1");
+  if (p.deflate_import != 0 && p.deflate_import != 1) return fail("deflate_import must be 0 or 1");
   const bool naik_kd = p.c3 != 0.0 && p.kd_naik;
   Geom g0{};
   g0.V = 1;
@@ -643,9 +644,37 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   const int every = coarsest ? 4 : 1;
   const int prec = B.prec;
   const int64_t n = B.n;
-  copy(B.r, B.b, nsys);
   double2* r0 = slot(lvl, kSlotR0);
   dots(prec, n, nsys, {{B.b.p, B.b.p}}, r0);
+  // coarse levels solve for s b with a per-system power of two s (entries of
+  // b of order one) and return x / s: the iterates are those of b scaled
+  // exactly, and 16-bit stencil inputs stay in range at any residual size
+  const bool scaled = lvl >= 2;
+  if (scaled) {
+    launch_rhs_scale(r0, slot(lvl, kSlotScale), slot(lvl, kSlotScale + 1), n, nsys, st);
+    check_launch();
+    auto fill = [&](auto& a) {
+      using TP = decltype(a.out);
+      a.out = (TP)B.b.p;
+      a.out2 = (TP)B.r.p;
+      a.v[0] = (TP)B.b.p;
+      a.v2[0] = (TP)B.b.p;
+      a.c[0] = slot(lvl, kSlotScale);
+      a.nt = 1; a.n = n; a.stride = n; a.nrhs = nsys;
+    };
+    if (prec == P64) {
+      LinCombArgs<double2> a{};
+      fill(a);
+      launch_lincomb(a, st);
+    } else {
+      LinCombArgs<float2> a{};
+      fill(a);
+      launch_lincomb(a, st);
+    }
+    check_launch();
+  } else {
+    copy(B.r, B.b, nsys);
+  }
   launch_conv(lmask(lvl), nullptr, r0, tol * tol, nsys, 1, st);
   check_launch();
   const bool deflated = coarsest && defl_k > 0;
@@ -671,6 +700,7 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
     }
     gcr_flush(lvl, B, nk, nsys, cyc > 0 || deflated);
   }
+  if (scaled) lincomb(prec, n, nsys, B.x.p, {{B.x.p, slot(lvl, kSlotScale + 1)}}, {}, {});
 }
 
 // Deflated start of the coarsest solve, 64 systems per pass:

@@ -174,9 +174,18 @@ struct Ctx {
   void build_level(int l, const void* nv_import);
   void pack_naik(const void* naik);
   void cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2* out);
-  void build_deflation();
+  void build_deflation(const void* nv_import);
   void deflate_start(int lvl, int nsys);
   void galerkin(int l);
 };
 
+// Body of mg_apply_dslash with the work batch given: tmp holds nrhs fine
+// vectors of the dtype (ops 1, 3 and 4 stage an intermediate there).
+mg_status apply_dslash_with(Ctx& c, int32_t op, double mass, int32_t dtype, const void* in, void* out,
+                            int32_t nrhs, void* stream, void* tmp);
+
 }  // namespace mg
+
+struct mg_ctx_s {
+  mg::Ctx c;
+};

@@ -31,7 +31,7 @@ void Ctx::setup(const void* fat, const void* naik, const void* const* nvs) {
   rhs_per_slot = 0;
   setup_phase = true;
   for (int l = 0; l < P.nagg; ++l) build_level(l, nvs ? nvs[l] : nullptr);
-  if (defl_k > 0) build_deflation();
+  if (defl_k > 0) build_deflation(nvs && P.deflate_import ? nvs[P.nagg] : nullptr);
   setup_phase = false;
   HIPCHK(hipStreamSynchronize(st));
 }
@@ -196,12 +196,19 @@ void Ctx::cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2
 // its operator): k near-null vectors W of the coarsest operator A by CGNE,
 // Z = A W with the stencil the solver applies, Z^H Z = R^H R (Cholesky, FP64),
 // Q = Z R^{-1} and W' = W R^{-1}.
-void Ctx::build_deflation() {
+void Ctx::build_deflation(const void* imp) {
   const int lv = nlev - 1;
   const int k = defl_k;
   const int64_t n = defl_n;
   const int prec = L[lv].prec;
-  cgne_null(P.nagg, k, n, P.deflate_maxiter, 1e-6, nv[P.nagg]);
+  if (imp) {   // imported vectors: kept in FP64, W in the level's precision
+    HIPCHK(hipMemcpyAsync(nv[P.nagg], imp, (size_t)k * n * 16, hipMemcpyDeviceToDevice, st));
+    if (prec == P64) launch_convert<double2, double2>((double2*)scratch_base, nv[P.nagg], (int64_t)k * n, st);
+    else launch_convert<double2, float2>((float2*)scratch_base, nv[P.nagg], (int64_t)k * n, st);
+    check_launch();
+  } else {
+    cgne_null(P.nagg, k, n, P.deflate_maxiter, 1e-6, nv[P.nagg]);
+  }
   const size_t vb = ((size_t)k * n * csize(prec) + 255) & ~(size_t)255;
   void* W = scratch_base;        // CGNE result, level precision
   void* Z = scratch_base + vb;

@@ -48,6 +48,7 @@ class MGParams(ctypes.Structure):
         ("max_nmass", ctypes.c_int32),
         ("coarsest_deflate", ctypes.c_int32),
         ("deflate_maxiter", ctypes.c_int32),
+        ("deflate_import", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -205,12 +206,17 @@ class Context:
         nvp = None
         self._keep = []
         if null_vectors is not None:
-            arr = (ctypes.c_void_p * 2)()
-            for l in range(params.nagg):
+            # levels 1 .. nagg, then (deflate_import) the coarsest level's deflation vectors
+            nent = params.nagg + (1 if params.coarsest_deflate > 0 and params.deflate_import else 0)
+            if len(null_vectors) > nent:
+                raise ValueError(f"null_vectors: at most {nent} entries with these parameters")
+            arr = (ctypes.c_void_p * 3)()
+            for l in range(nent):
                 v = null_vectors[l] if l < len(null_vectors) else None
                 if v is not None:
+                    defl = l == params.nagg
                     _check_batch(v, f"null_vectors[{l}]", self._level_size(l + 1), torch.complex128,
-                                 params.nvec[l])
+                                 params.coarsest_deflate if defl else params.nvec[l])
                     _dev(v, f"null_vectors[{l}]")
                     self._keep.append(v)
                     arr[l] = v.data_ptr()

@@ -25,6 +25,11 @@ CONFIGS = {
     # coarse lattice 2x1x1x1
     "wide": dict(dims=(8, 4, 4, 4), c1=C1H, c3=C3H, kd_naik=1, blocks=[(4, 4, 4, 4)], nvec=(128,), mass0=0.05,
                  eps=0.5, seed=515151),
+    # the production level shapes (Nvec 64 / 96: level 2 n = 128, level 3 n = 192) on a 4x4x4x1
+    # level-2 lattice (odd x, y and z = 2, 3 mod 4 all present) at the light mass 0.005, Naik truncated
+    # in the KD level as in the 32^4 multi-mass workload
+    "prod": dict(dims=(16, 16, 16, 4), c1=C1H, c3=C3H, kd_naik=0, blocks=[(4, 4, 4, 4), (2, 2, 2, 1)],
+                 nvec=(64, 96), mass0=0.005, eps=0.5, seed=626262),
     # the 16^4 HISQ-style hierarchy shape: KD, 4^4 / Nvec 64, 2^4 / Nvec 96
     "c1": dict(dims=(16, 16, 16, 16), c1=C1H, c3=C3H, kd_naik=1, blocks=[(4, 4, 4, 4), (2, 2, 2, 2)],
                nvec=(64, 96), mass0=0.01, eps=0.5, seed=latgen.SEEDS["c1_16x4_hisq"]),
@@ -76,6 +81,48 @@ def gpu_params(mg, cfg, **kw):
         else:
             setattr(p, k, v)
     return p
+
+
+_LINKS = {}
+
+
+def cached_hierarchy_links(name, H):
+    """The oracle's explicit coarse links of the hierarchy of CONFIGS[name]
+    with its seeded random null vectors (computed once per process: about a
+    minute for "prod")."""
+    if name not in _LINKS:
+        _LINKS[name] = sol.hierarchy_links(H)
+    return _LINKS[name]
+
+
+def abs1(a):
+    """|Re a| + |Im a|: bounds |a| and makes the error bounds of complex sums
+    of products a sum over real products."""
+    return np.abs(np.real(a)) + np.abs(np.imag(a))
+
+
+def gamma(k, u):
+    """Higham's gamma_k = k u / (1 - k u): the relative error bound of a sum of
+    k real products accumulated in any order with unit roundoff u."""
+    return k * u / (1.0 - k * u)
+
+
+def abs_dslash(xa, W, N, mass, c1, c3):
+    """sum_j |D_ij|_1 xa_j for the staggered operator: every hop with its link
+    entries' |Re| + |Im| and a positive coefficient (phases and signs dropped),
+    for the a-priori bound of a floating-point application of D."""
+    out = abs(mass) * xa
+    for mu in range(4):
+        ax = ops.axis_of(mu)
+        for h, coef, F in ((1, c1, W), (3, c3, N)):
+            if coef == 0.0:
+                continue
+            Fa = abs1(F[mu])
+            fwd = np.einsum("...ab,...b->...a", Fa, np.roll(xa, -h, axis=ax))
+            Fb = np.roll(Fa, h, axis=ax)
+            bwd = np.einsum("...ba,...b->...a", Fb, np.roll(xa, h, axis=ax))
+            out = out + 0.5 * abs(coef) * (fwd + bwd)
+    return out
 
 
 def rel_err(got, want):

@@ -30,10 +30,28 @@ def test_header_symbols_exported(m):
         assert hasattr(lib, n), f"{n} declared in mgstag.h but not exported"
 
 
-def test_params_struct_matches_header(m):
-    # sizeof(mg_params) as laid out by the C compiler equals the ctypes mirror
-    assert ctypes.sizeof(m.MGParams) == 208
-    assert ctypes.sizeof(m.MGSolveInfo) == 48
+def test_params_struct_matches_header(m, tmp_path):
+    """sizeof and field offsets of mg_params / mg_solve_info as the C compiler
+    lays them out from the header equal the ctypes mirrors."""
+    import subprocess
+    fields = [f for f, _ in m.MGParams._fields_]
+    src = tmp_path / "layout.c"
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#define __HIP_PLATFORM_AMD__',
+             '#include "mgstag.h"', 'int main(void) {',
+             '  printf("%zu %zu\\n", sizeof(mg_params), sizeof(mg_solve_info));']
+    lines += [f'  printf("%zu\\n", offsetof(mg_params, {f}));' for f in fields]
+    lines += ['  return 0;', '}']
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run(["gcc", "-I", inc, "-I", "/opt/rocm/include", str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert int(out[0]) == ctypes.sizeof(m.MGParams)
+    assert int(out[1]) == ctypes.sizeof(m.MGSolveInfo)
+    for f, off in zip(fields, out[2:]):
+        assert getattr(m.MGParams, f).offset == int(off), f
 
 
 def test_default_params_table1(m):
@@ -65,6 +83,7 @@ def test_default_params_table1(m):
     (dict(coarsest_deflate=20), "coarsest_deflate"),
     (dict(coarsest_deflate=80), "coarsest_deflate"),
     (dict(coarsest_deflate=16, deflate_maxiter=0), "deflate_maxiter"),
+    (dict(deflate_import=2), "deflate_import"),
     (dict(dims=(8, 8, 8, 8), nvec=(8, 8), coarsest_deflate=32), "dimension"),
 ])
 def test_workspace_validation(m, bad, why):

@@ -122,23 +122,36 @@ def test_multi_mass_batch(torch, mg, cubic):
             assert true_rel(cfg, W, N, m, x[j, r], b[r]) <= 1e-10, (m, r)
 
 
-def test_lockstep_16rhs_two_masses_bf16(torch, mg, cubic):
+_iters16 = {}
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_lockstep_16rhs_two_masses_16bit(torch, mg, cubic, fmt):
     """The production batch shape: 16 right-hand sides for each of two masses
     in one lockstep solve (KD on the matrix cores with one inverse slot per
     mass, 16-bit coarse links); every system reaches 1e-10 on the oracle's
-    true residual."""
+    true residual.  Near the end of the solve the K-cycle's input is about
+    1e-10 of b, far below FP16's normal range: the coarse levels solve for a
+    power-of-two multiple of their right-hand side, so FP16 links keep
+    preconditioning as well as bf16 ones (outer iterations compared)."""
     cfg, W, N, nvs, _ = cubic
     masses = [0.05, 0.11]
     rng = np.random.default_rng(4321)
     b = latgen.fine_vectors(cfg["dims"], 16, rng)
-    log("[solve] cubic 16 rhs x 2 masses bf16")
-    ctx = make_ctx(torch, mg, cfg, W, N, nvs, max_nrhs=32, max_nmass=2, coarse_prec=mg.MG_CBF16)
+    log(f"[solve] cubic 16 rhs x 2 masses {fmt}")
+    cp = mg.MG_CBF16 if fmt == "bf16" else mg.MG_CF16
+    ctx = make_ctx(torch, mg, cfg, W, N, nvs, max_nrhs=32, max_nmass=2, coarse_prec=cp)
     x, info, st = ctx.solve(masses, torch.from_numpy(b).to("cuda:0"), tol=1e-10)
     x = x.cpu().numpy()
     for j, m in enumerate(masses):
         for r in range(16):
             assert info[j * 16 + r]["status"] == "MG_OK"
             assert true_rel(cfg, W, N, m, x[j, r], b[r]) <= 1e-10, (m, r)
+    _iters16[fmt] = [i["outer_iters"] for i in info]
+    log(f"    outer iterations {fmt}: {_iters16[fmt]}")
+    if len(_iters16) == 2:
+        for ib, ih in zip(_iters16["bf16"], _iters16["fp16"]):
+            assert ih <= ib + 2, (_iters16["bf16"], _iters16["fp16"])
 
 
 def test_lockstep_truncated_kd_matches_solo(torch, mg, cubic):
@@ -251,23 +264,25 @@ def cubic1(torch):
 
 
 def test_fp64_deflated_kcycle_matches_oracle(torch, mg, cubic1):
-    """Coarsest solve deflated with 32 near-null vectors of its operator: the
-    GPU's vectors are exported, the oracle builds its deflation space from
-    them, and the all-FP64 MG-GCR solves agree (outer iterations +-1,
-    ||x - x_oracle|| <= 2e-10 ||b|| / m); the exported vectors are nearer to
-    the null space than a random vector."""
+    """Coarsest solve deflated with 32 near-null vectors of its operator, made
+    by the oracle (CGNE on its coarsest operator from seeded starts) and
+    imported into the library: the all-FP64 MG-GCR solves of both sides with
+    the same deflation space agree (outer iterations +-1,
+    ||x - x_oracle|| <= 2e-10 ||b|| / m)."""
     cfg, W, N, nvs, b = cubic1
     m = cfg["mass0"]
     log("[deflate] cubic1 fp64 vs oracle")
-    ctx = make_ctx(torch, mg, cfg, W, N, nvs, fine_prec=mg.MG_C128, coarse_prec=mg.MG_C128, max_nrhs=1,
-                   coarsest_deflate=32, deflate_maxiter=100)
-    wd = ctx.export(1, 2).cpu().numpy().reshape((32,) + tuple(ctx.coarse_shapes[0]))
+    H = oracle_hierarchy(cfg, W, N, m, nvs)
+    lc = H.nlevels - 1
+    rng = np.random.default_rng(2718)
+    starts = latgen.complex_normal(rng, (32,) + H.fine_shape(lc))
+    wd = np.stack([sol.cgne_null_vector(lambda v: H.op(lc, v), lambda v: H.op_dag(lc, v), s0, 1e-6, 100)[0]
+                   for s0 in starts])
+    ctx = make_ctx(torch, mg, cfg, W, N, list(nvs) + [wd], fine_prec=mg.MG_C128, coarse_prec=mg.MG_C128,
+                   max_nrhs=1, coarsest_deflate=32, deflate_maxiter=100, deflate_import=1)
+    assert np.array_equal(ctx.export(1, 2).cpu().numpy().reshape(wd.shape), wd)
     x, info, st = ctx.solve([m], torch.from_numpy(b[:1]).to("cuda:0"), tol=1e-10)
     x = x.cpu().numpy()[0, 0]
-    H = oracle_hierarchy(cfg, W, N, m, nvs)
-    red = [np.linalg.norm(H.op(2, w)) / np.linalg.norm(w) for w in wd]
-    rnd = latgen.complex_normal(np.random.default_rng(3), wd.shape[1:])
-    assert max(red) < 0.75 * np.linalg.norm(H.op(2, rnd)) / np.linalg.norm(rnd), red
     H.set_coarsest_deflation(list(wd))
     xo, io = H.solve(b[0], tol=1e-10)
     assert io.converged
