@@ -154,6 +154,21 @@ mg_status mg_setup(const mg_params* p, const void* fat, const void* naik, const 
 mg_status mg_apply_dslash(mg_ctx ctx, int32_t op, double mass, int32_t dtype, const void* in, void* out,
                           int32_t nrhs, void* stream);
 
+/* mg_apply_dslash for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same operators, arguments and results, with the intermediate vector of
+ * ops 1, 3 and 4 staged in a static device array of the library
+ * (mg_noalloc_scratch_bytes() = 64 MiB, one per GPU, held until the process
+ * ends) instead of the context's scratch workspace.  The call allocates
+ * nothing; ops 1, 3 and 4 with nrhs fine vectors of the dtype larger than the
+ * array return MG_E_ARG before any work.  Every call on one GPU shares that
+ * array and leaves its last contents there: calls that overlap on one GPU
+ * (concurrent streams or threads) race.  Device addresses of the array are
+ * looked up per device at mg_setup or at the first call on a device. */
+mg_status mg_apply_dslash_noalloc(mg_ctx ctx, int32_t op, double mass, int32_t dtype, const void* in, void* out,
+                                  int32_t nrhs, void* stream);
+size_t mg_noalloc_scratch_bytes(void);
+
 /* Coarse operator of level 2 (P1^dag A P1) or 3 (P2^dag A2 P2) on a coarse
  * vector of that level (Sec. 2.1; 9-point stencil of dense blocks, Sec. 3.1).
  * dtype MG_C128 uses the FP64 operator; MG_C64 the coarse_prec operator

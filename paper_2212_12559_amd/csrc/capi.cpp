@@ -175,6 +175,11 @@ mg_status mg_setup(const mg_params* p, const void* fat, const void* naik, const 
     return fail(MG_E_CONFIG, why);
   }
   ctx->c.st = (hipStream_t)stream;
+  s = noalloc_init_current_device();   // static work array of mg_apply_dslash_noalloc on this device
+  if (s != MG_OK) {
+    delete ctx;
+    return s;
+  }
   s = guarded([&] { ctx->c.setup(fat, naik, null_vectors); });
   if (s != MG_OK) {
     delete ctx;

@@ -183,6 +183,9 @@ struct Ctx {
 // vectors of the dtype (ops 1, 3 and 4 stage an intermediate there).
 mg_status apply_dslash_with(Ctx& c, int32_t op, double mass, int32_t dtype, const void* in, void* out,
                             int32_t nrhs, void* stream, void* tmp);
+// Looks up the device address of the static work array of
+// mg_apply_dslash_noalloc on the current device (once per device).
+mg_status noalloc_init_current_device();
 
 }  // namespace mg
 

@@ -80,6 +80,8 @@ def _load():
         "mg_workspace_bytes": (i32, [P(MGParams), P(sz), P(sz)]),
         "mg_setup": (i32, [P(MGParams), vp, vp, P(vp), vp, sz, vp, sz, vp, P(vp)]),
         "mg_apply_dslash": (i32, [vp, i32, f64, i32, vp, vp, i32, vp]),
+        "mg_apply_dslash_noalloc": (i32, [vp, i32, f64, i32, vp, vp, i32, vp]),
+        "mg_noalloc_scratch_bytes": (sz, []),
         "mg_apply_coarse": (i32, [vp, i32, i32, vp, vp, i32, vp]),
         "mg_restrict": (i32, [vp, i32, i32, vp, vp, i32, vp]),
         "mg_prolong": (i32, [vp, i32, i32, vp, vp, i32, i32, vp]),
@@ -269,6 +271,15 @@ class Context:
         out = self._out(out, x, tuple(x.shape))
         _check(LIB.mg_apply_dslash(self.ctx, op, mass, _dtype_code(x), _dev(x, "x"), _dev(out, "out"), nrhs,
                                    _stream()), "mg_apply_dslash")
+        return out
+
+    def apply_dslash_noalloc(self, op, mass, x, out):
+        """apply_dslash through the entry point that allocates nothing (its
+        work batch is the library's static device array); out is required."""
+        nrhs = _check_batch(x, "x", self._level_size(1))
+        out = self._out(out, x, tuple(x.shape))
+        _check(LIB.mg_apply_dslash_noalloc(self.ctx, op, mass, _dtype_code(x), _dev(x, "x"), _dev(out, "out"),
+                                           nrhs, _stream()), "mg_apply_dslash_noalloc")
         return out
 
     def apply_coarse(self, level, x, out=None):
