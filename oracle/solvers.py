@@ -342,6 +342,7 @@ class MGParams:
     coarsest_direct: bool = False
     outer_nkrylov: int = 16
     dense_coarse_limit: int = 6144   # coarse levels up to this many dof are tabulated densely
+    coarse_op: str = "galerkin"      # "galerkin": A_l = R A_{l-1} P; "block": X_l^{-1} R A_{l-1} P
 
 
 class Hierarchy:
@@ -352,6 +353,15 @@ class Hierarchy:
                                  Naik dropped inside it when kd_naik is False)
       level 2   P1^dag A P1     (Galerkin, chirally split block-orthonormal P1)
       level 3   P2^dag A2 P2    (optional second aggregation)
+
+    With coarse_op "block" every coarse level l >= 2 is the block-preconditioned
+    operator  A_l = X_l^{-1} (P_l^dag A_{l-1} P_l),  X_l the coarse-site
+    (self) block of the Galerkin product, and the next level coarsens that
+    preconditioned operator (Sec. 2.3: the near-null vectors come from the
+    coarse operator, the block-preconditioned version is what is coarsened;
+    Table 1 marks levels 2 and 3 "Schur-preconditioned").  A level solve then
+    solves A_l x = X_l^{-1} b, which has the same solution as the Galerkin
+    system.
 
     Transfers: level 0 -> 1 is r1 = (B+m)^{-1} r0 with identity prolongation
     (so A e1 = r1 is D e1 = r0); deeper transfers are R = P^dag and P.
@@ -378,6 +388,7 @@ class Hierarchy:
         self.nlevels = 2 + len(self.transfers)
         self._dense_lu = None
         self._dense = {}
+        self._xinv = {}
         self.deflation = None
 
     def set_coarsest_deflation(self, Wv):
@@ -400,11 +411,54 @@ class Hierarchy:
         return self._galerkin(lvl, v)
 
     def _galerkin(self, lvl, v):
-        """R A P v for the operator A of level lvl - 1 (Galerkin, Sec. 2.1)."""
+        """R A P v for the operator A of level lvl - 1 (Galerkin, Sec. 2.1),
+        block-preconditioned by X_lvl^{-1} with coarse_op "block"."""
         t = self.transfers[lvl - 2]
         fine = t.prolong(v)
         shape = self.fine_shape(lvl - 1)
-        return t.restrict(self.op(lvl - 1, fine.reshape(shape))).reshape(v.shape)
+        y = t.restrict(self.op(lvl - 1, fine.reshape(shape))).reshape(v.shape)
+        return self.xinv_apply(lvl, y) if self.p.coarse_op == "block" else y
+
+    def xinv_apply(self, lvl, v, dagger=False):
+        """X_lvl^{-1} v (or X_lvl^{-dag} v) coarse site by coarse site, X_lvl(a)
+        the coarse-site diagonal block of P^dag A_{lvl-1} P (from the level's
+        explicit links)."""
+        if lvl not in self._xinv:
+            self.level_links(lvl)
+        Xi = self._xinv[lvl]
+        if dagger:
+            Xi = np.swapaxes(Xi.conj(), -1, -2)
+        return np.einsum("aij,aj->ai", Xi, v.reshape(Xi.shape[0], -1)).reshape(v.shape)
+
+    def level_links(self, lvl):
+        """Explicit links [Vc][9][n][n] of coarse level lvl (as applied: block-
+        preconditioned with coarse_op "block"), built once."""
+        if not hasattr(self, "_links"):
+            self._links = {}
+        if lvl not in self._links:
+            p = self.p
+            t = self.transfers[lvl - 2]
+            nc = int(np.prod(self.cdims[lvl - 2]))
+            if lvl == 2:
+                def pieces(v):
+                    ps = ops.dslash_pieces(v, self.W, self.N, self.mass, p.c1, self.c3_kd, p.blocks[0])
+                    return [ops.kd_apply(self.Kinv, q) for q in ps]
+            else:
+                Lp = self.level_links(lvl - 1)
+                pieces = lambda v: ops.coarse_pieces(Lp, self.cdims[lvl - 3], v, p.blocks[lvl - 2])
+            L = ops.galerkin_links(t, pieces, self.fine_shape(lvl - 1), nc)
+            if p.coarse_op == "block":
+                # X(a): the coarse-site diagonal block, the self piece plus the
+                # +-mu pieces that return to the site (coarse extent 1)
+                cd = self.cdims[lvl - 2]
+                X = L[:, 0].copy()
+                for mu in range(4):
+                    if cd[mu] == 1:
+                        X += L[:, 1 + 2 * mu] + L[:, 2 + 2 * mu]
+                self._xinv[lvl] = np.linalg.inv(X)
+                L = np.einsum("aij,adjk->adik", self._xinv[lvl], L)
+            self._links[lvl] = L
+        return self._links[lvl]
 
     def op_dag(self, lvl, v):
         p = self.p
@@ -412,6 +466,8 @@ class Hierarchy:
             return ops.dslash_dagger(v, self.W, self.N, self.mass, p.c1, p.c3)
         if lvl == 1:
             return ops.kd_operator_dagger(v, self.W, self.N, self.Kinv, self.mass, p.c1, self.c3_kd)
+        if self.p.coarse_op == "block":   # (X^{-1} R A P)^dag = R A^dag P X^{-dag}
+            v = self.xinv_apply(lvl, v, dagger=True)
         t = self.transfers[lvl - 2]
         fine = t.prolong(v)
         shape = self.fine_shape(lvl - 1)
@@ -449,6 +505,8 @@ class Hierarchy:
 
     def solve_level(self, lvl, b):
         p = self.p
+        if p.coarse_op == "block" and lvl >= 2:
+            b = self.xinv_apply(lvl, b)   # A_l x = X^{-1} b: the Galerkin system's solution
         if lvl == self.nlevels - 1:
             if p.coarsest_direct:
                 if self._dense_lu is None:
@@ -482,25 +540,10 @@ class Hierarchy:
 def hierarchy_links(H):
     """Explicit direction-split coarse links of every coarse level of the
     hierarchy H ([Vc][9][n][n] row-major), built from the pieces of the level
-    operators (the Galerkin definition written out block by block)."""
-    p = H.p
-    links = []
-    t0 = H.transfers[0]
-    nc0 = int(np.prod(H.cdims[0]))
-
-    def pieces1(v):
-        ps = ops.dslash_pieces(v, H.W, H.N, H.mass, p.c1, H.c3_kd, p.blocks[0])
-        return [ops.kd_apply(H.Kinv, q) for q in ps]
-
-    L2 = ops.galerkin_links(t0, pieces1, H.fine_shape(1), nc0)
-    links.append(L2)
-    if len(H.transfers) > 1:
-        t1 = H.transfers[1]
-        nc1 = int(np.prod(H.cdims[1]))
-        L3 = ops.galerkin_links(t1, lambda v: ops.coarse_pieces(L2, H.cdims[0], v, p.blocks[1]),
-                                H.fine_shape(2), nc1)
-        links.append(L3)
-    return links
+    operators (the Galerkin definition written out block by block; with
+    coarse_op "block" each level's links are multiplied by X^{-1} and the next
+    level is built from those)."""
+    return [H.level_links(lvl) for lvl in range(2, H.nlevels)]
 
 
 # --------------------------------------------------------------------------
