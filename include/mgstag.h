@@ -103,6 +103,11 @@ typedef struct {
   int32_t deflate_import;    /* 1: null_vectors of mg_setup holds nagg + 1 pointers and the last one gives the
                                 coarsest_deflate deflation vectors (complex128 [k][coarsest vector]) in place of
                                 the CGNE ones; 0: nagg pointers */
+  int32_t coarse_op;         /* 0: Galerkin coarse levels A_l = P^dag A_{l-1} P; 1: block-preconditioned
+                                A_l = X_l^{-1} P^dag A_{l-1} P with X_l the coarse-site diagonal block, each
+                                coarser level built from the preconditioned one and every coarse level solve
+                                run on A_l x = X_l^{-1} b (Sec. 2.3, Table 1); the near-null vectors of a
+                                level come from its Galerkin operator */
   uint64_t seed;             /* seed of the GPU-generated null-vector starts */
 } mg_params;
 

@@ -134,6 +134,7 @@ void mg_default_params(mg_params* p, const int32_t dims[4]) {
   p->coarsest_deflate = 0;
   p->deflate_maxiter = 300;
   p->deflate_import = 0;
+  p->coarse_op = 1;   // Table 1: preconditioned coarse operators on levels 2 and 3
   p->seed = 20221224ull;
 }
 

@@ -131,6 +131,24 @@ template <typename T>
 void launch_dagger_links(const T* in, T* out, const Geom& g, int n, hipStream_t st);
 void launch_export_links(const double2* in, double2* out, int64_t nsite, int n, hipStream_t st);
 
+// ---------------------------------------------------------------- block preconditioning
+// C[b] = alpha A[b / a_div] B[b] + beta D[b]: batched complex products of
+// column-major matrices (element (i, j) at j * ld + i); D optional
+template <typename T>
+struct BGemmArgs {
+  const T* A; int64_t lda, sA; int a_div;
+  const T* B; int64_t ldb, sB;
+  T* C; int64_t ldc, sC;
+  const T* D; int64_t ldd, sD;
+  int m, n, k, batch;
+  double alpha, beta;
+};
+template <typename T>
+void launch_bgemm(const BGemmArgs<T>& a, hipStream_t st);
+void launch_diag_block(const double2* L, double2* X, const Geom& g, int n, hipStream_t st);
+void launch_ns_init(const double2* X, double2* Y, int64_t nsite, int n, hipStream_t st);
+void launch_ns_residual(const double2* T, int64_t nsite, int n, unsigned long long* out, hipStream_t st);
+
 // ---------------------------------------------------------------- BLAS
 template <typename T>
 struct PairDotArgs {

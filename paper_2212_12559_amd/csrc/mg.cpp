@@ -45,6 +45,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     return fail("coarsest_deflate must be 0, 16, 32, 48 or 64");
   if (p.coarsest_deflate > 0 && p.deflate_maxiter < 1) return fail("deflate_maxiter must be >= 1");
   if (p.deflate_import != 0 && p.deflate_import != 1) return fail("deflate_import must be 0 or 1");
+  if (p.coarse_op != 0 && p.coarse_op != 1) return fail("coarse_op must be 0 (Galerkin) or 1 (block-preconditioned)");
   const bool naik_kd = p.c3 != 0.0 && p.kd_naik;
   Geom g0{};
   g0.V = 1;
@@ -107,6 +108,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   void* kinv64 = P((size_t)p.max_nmass * kslot * 16);
   void* kinv32 = P((size_t)p.max_nmass * kslot * 8);
   void *nvp[2]{}, *pp64[2]{}, *pr64[2]{}, *pp32[2]{}, *pr32[2]{}, *cl64[2]{}, *cl32[2]{}, *cl16[2]{};
+  void *xi64[2]{}, *xi32[2]{};
   const bool c16 = p.coarse_prec == MG_CBF16 || p.coarse_prec == MG_CF16;
   for (int l = 0; l < p.nagg; ++l) {
     const int64_t nflat = A[l].nagg * 2 * A[l].nrows;   // dof of the aggregated level
@@ -120,6 +122,10 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     cl64[l] = P(gc[l].V * 9 * n * n * 16);
     cl32[l] = P(gc[l].V * 9 * n * n * 8);
     if (c16) cl16[l] = P(swizzled_link_elems(gc[l].V, (int)n) * 2);
+    if (p.coarse_op == 1) {   // X^{-1} per coarse site
+      xi64[l] = P(gc[l].V * n * n * 16);
+      xi32[l] = P(gc[l].V * n * n * 8);
+    }
   }
   const int cprec_ = p.coarse_prec == MG_C128 ? P64 : P32;
   void *nvd = nullptr, *dq = nullptr, *dw = nullptr, *dg = nullptr, *drm = nullptr, *dri = nullptr;
@@ -202,6 +208,12 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     }
     setup_end = std::max(setup_end, e);
   }
+  if (p.coarse_op == 1) {   // Newton-Schulz inverse and preconditioned links: X, Y, T, Y' blocks (FP64)
+    for (int l = 0; l < p.nagg; ++l) {
+      const int64_t n = 2 * A[l].nvec;
+      setup_end = std::max(setup_end, solver_base + 4 * (((size_t)gc[l].V * n * n * 16 + 255) & ~(size_t)255) + 256);
+    }
+  }
   if (kd > 0) {   // CGNE on the coarsest operator: six k-vector blocks, its adjoint links (+ 16-bit fragments)
     const int lc = p.nagg - 1;
     const int64_t nc = 2 * A[lc].nvec;
@@ -225,6 +237,8 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
       c->pp32[l] = (float2*)pp32[l]; c->pr32[l] = (float2*)pr32[l];
       c->cl64[l] = (double2*)cl64[l]; c->cl32[l] = (float2*)cl32[l];
       c->cl16[l] = (uint16_t*)cl16[l];
+      c->xinv64[l] = (double2*)xi64[l];
+      c->xinv32[l] = (float2*)xi32[l];
     }
     c->fmt16 = p.coarse_prec == MG_CBF16 ? 0 : (p.coarse_prec == MG_CF16 ? 1 : -1);
     c->status_dev = (int*)status;
@@ -645,7 +659,11 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   const int prec = B.prec;
   const int64_t n = B.n;
   double2* r0 = slot(lvl, kSlotR0);
-  dots(prec, n, nsys, {{B.b.p, B.b.p}}, r0);
+  // block-preconditioned coarse levels solve X^{-1} A x = X^{-1} b
+  const bool blk = lvl >= 2 && P.coarse_op == 1;
+  if (blk) apply_xinv(lvl, prec, B.r.p, B.b.p, nsys);
+  const Vec& src = blk ? B.r : B.b;
+  dots(prec, n, nsys, {{src.p, src.p}}, r0);
   // coarse levels solve for s b with a per-system power of two s (entries of
   // b of order one) and return x / s: the iterates are those of b scaled
   // exactly, and 16-bit stencil inputs stay in range at any residual size
@@ -657,8 +675,8 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
       using TP = decltype(a.out);
       a.out = (TP)B.b.p;
       a.out2 = (TP)B.r.p;
-      a.v[0] = (TP)B.b.p;
-      a.v2[0] = (TP)B.b.p;
+      a.v[0] = (TP)src.p;
+      a.v2[0] = (TP)src.p;
       a.c[0] = slot(lvl, kSlotScale);
       a.nt = 1; a.n = n; a.stride = n; a.nrhs = nsys;
     };

@@ -88,6 +88,8 @@ struct Ctx {
   float2* cl32[2]{};
   uint16_t* cl16[2]{};      // 16-bit MFMA fragments (coarse_prec BF16 / FP16)
   float cl16_inv_scale[2]{1.0f, 1.0f};
+  double2* xinv64[2]{};     // coarse_op 1: X^{-1} per coarse site [site][col][row]
+  float2* xinv32[2]{};
   int fmt16 = -1;           // -1: none, 0: bf16, 1: fp16
   bool setup_phase = false;
   int* status_dev = nullptr;
@@ -177,6 +179,9 @@ struct Ctx {
   void build_deflation(const void* nv_import);
   void deflate_start(int lvl, int nsys);
   void galerkin(int l);
+  void finish_links(int l);          // FP32 copy and 16-bit fragments of cl64[l]
+  void precondition_links(int l);    // X^{-1} and cl64[l] <- X^{-1} cl64[l] (coarse_op 1)
+  void apply_xinv(int lvl, int prec, void* out, const void* in, int nsys);
 };
 
 // Body of mg_apply_dslash with the work batch given: tmp holds nrhs fine

@@ -30,7 +30,18 @@ void Ctx::setup(const void* fat, const void* naik, const void* const* nvs) {
   ensure_kd({P.mass0});
   rhs_per_slot = 0;
   setup_phase = true;
-  for (int l = 0; l < P.nagg; ++l) build_level(l, nvs ? nvs[l] : nullptr);
+  for (int l = 0; l < P.nagg; ++l) {
+    build_level(l, nvs ? nvs[l] : nullptr);   // near-null vectors from the Galerkin operator of level l + 1
+    if (P.coarse_op == 1 && l > 0) {
+      // the previous level is preconditioned only now (its Galerkin operator
+      // gave this level's near-null vectors); rebuild this level's links from it
+      precondition_links(l - 1);
+      finish_links(l - 1);
+      galerkin(l);
+    }
+    if (P.coarse_op == 1 && l == P.nagg - 1) precondition_links(l);
+    finish_links(l);
+  }
   if (defl_k > 0) build_deflation(nvs && P.deflate_import ? nvs[P.nagg] : nullptr);
   setup_phase = false;
   HIPCHK(hipStreamSynchronize(st));
@@ -284,6 +295,12 @@ void Ctx::galerkin(int l) {
       check_launch();
     }
   }
+}
+
+
+// FP32 copy and 16-bit fragments of the FP64 links of level l
+void Ctx::finish_links(int l) {
+  const int n = ncoarse[l];
   launch_convert_links(cl64[l], cl32[l], gc[l].V * 9 * (int64_t)n * n, st);
   check_launch();
   if (fmt16 >= 0) {
@@ -307,6 +324,93 @@ void Ctx::galerkin(int l) {
     launch_swizzle_links<double2>(cl64[l], cl16[l], gc[l].V, n, fmt16, scale, st);
     check_launch();
   }
+}
+
+// Block preconditioning of coarse level l + 2 (Sec. 2.3, Table 1): X = the
+// coarse-site diagonal block of the FP64 links, X^{-1} by Newton-Schulz
+// (Y <- Y (2 - X Y) from Y_0 = X^H / (|X|_1 |X|_inf), to max |1 - X Y| <= 1e-13),
+// then every link block L_d <- X^{-1} L_d.
+void Ctx::precondition_links(int l) {
+  const int n = ncoarse[l];
+  const int64_t Vc = gc[l].V, nn = (int64_t)n * n;
+  const size_t bb = ((size_t)Vc * nn * 16 + 255) & ~(size_t)255;
+  double2* X = (double2*)scratch_base;
+  double2* Y = (double2*)(scratch_base + bb);
+  double2* T = (double2*)(scratch_base + 2 * bb);
+  double2* Y2 = (double2*)(scratch_base + 3 * bb);
+  launch_diag_block(cl64[l], X, gc[l], n, st);
+  launch_ns_init(X, Y, Vc, n, st);
+  check_launch();
+  auto gemm = [&](double2* C, const double2* A, int a_div, const double2* B, int64_t sB, const double2* D,
+                  double alpha, double beta, int batch) {
+    BGemmArgs<double2> g{};
+    g.A = A; g.lda = n; g.sA = nn; g.a_div = a_div;
+    g.B = B; g.ldb = n; g.sB = sB;
+    g.C = C; g.ldc = n; g.sC = nn;
+    g.D = D; g.ldd = n; g.sD = nn;
+    g.m = n; g.n = n; g.k = n; g.batch = batch;
+    g.alpha = alpha; g.beta = beta;
+    launch_bgemm(g, st);
+    check_launch();
+  };
+  unsigned long long* dmax = (unsigned long long*)((char*)status_dev + 136);
+  double res = 1.0;
+  for (int it = 0; it < 100 && res > 1e-13; ++it) {
+    gemm(T, X, 1, Y, nn, nullptr, 1.0, 0.0, (int)Vc);          // T = X Y
+    if (it % 4 == 3) {
+      HIPCHK(hipMemsetAsync(dmax, 0, sizeof(unsigned long long), st));
+      launch_ns_residual(T, Vc, n, dmax, st);
+      check_launch();
+      unsigned long long bits = 0;
+      HIPCHK(hipMemcpyAsync(&bits, dmax, sizeof(bits), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      std::memcpy(&res, &bits, sizeof(res));
+      if (res <= 1e-13) break;
+    }
+    gemm(Y2, Y, 1, T, nn, Y, -1.0, 2.0, (int)Vc);             // Y' = 2 Y - Y T
+    std::swap(Y, Y2);
+  }
+  if (!(res <= 1e-13))
+    throw Error{MG_E_RANK, "coarse-site diagonal block is singular or too ill-conditioned to invert"};
+  HIPCHK(hipMemcpyAsync(xinv64[l], Y, (size_t)Vc * nn * 16, hipMemcpyDeviceToDevice, st));
+  launch_convert<double2, float2>(xinv32[l], Y, Vc * nn, st);
+  check_launch();
+  for (int d = 0; d < 9; ++d) {
+    // T = X^{-1} L_d for every site, then back into the links
+    BGemmArgs<double2> g{};
+    g.A = xinv64[l]; g.lda = n; g.sA = nn; g.a_div = 1;
+    g.B = cl64[l] + d * nn; g.ldb = n; g.sB = 9 * nn;
+    g.C = T; g.ldc = n; g.sC = nn;
+    g.m = n; g.n = n; g.k = n; g.batch = (int)Vc;
+    g.alpha = 1.0;
+    launch_bgemm(g, st);
+    check_launch();
+    HIPCHK(hipMemcpy2DAsync(cl64[l] + d * nn, (size_t)9 * nn * 16, T, (size_t)nn * 16, (size_t)nn * 16, (size_t)Vc,
+                            hipMemcpyDeviceToDevice, st));
+  }
+}
+
+// out = X^{-1} in for the systems of a coarse level (coarse_op 1), site by site
+void Ctx::apply_xinv(int lvl, int prec, void* out, const void* in, int nsys) {
+  const int l = lvl - 2;
+  const int n = ncoarse[l];
+  const int64_t nn = (int64_t)n * n, stride = gc[l].V * n;
+  if (prec == P64) {
+    BGemmArgs<double2> g{};
+    g.A = xinv64[l]; g.lda = n; g.sA = nn; g.a_div = 1;
+    g.B = (const double2*)in; g.ldb = stride; g.sB = n;
+    g.C = (double2*)out; g.ldc = stride; g.sC = n;
+    g.m = n; g.n = nsys; g.k = n; g.batch = (int)gc[l].V; g.alpha = 1.0;
+    launch_bgemm(g, st);
+  } else {
+    BGemmArgs<float2> g{};
+    g.A = xinv32[l]; g.lda = n; g.sA = nn; g.a_div = 1;
+    g.B = (const float2*)in; g.ldb = stride; g.sB = n;
+    g.C = (float2*)out; g.ldc = stride; g.sC = n;
+    g.m = n; g.n = nsys; g.k = n; g.batch = (int)gc[l].V; g.alpha = 1.0;
+    launch_bgemm(g, st);
+  }
+  check_launch();
 }
 
 }  // namespace mg

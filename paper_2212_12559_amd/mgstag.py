@@ -49,6 +49,7 @@ class MGParams(ctypes.Structure):
         ("coarsest_deflate", ctypes.c_int32),
         ("deflate_maxiter", ctypes.c_int32),
         ("deflate_import", ctypes.c_int32),
+        ("coarse_op", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 

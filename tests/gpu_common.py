@@ -70,9 +70,10 @@ def oracle_hierarchy(cfg, W, N, mass, nvs, **kw):
 
 
 def gpu_params(mg, cfg, **kw):
+    # coarse_op 0 (Galerkin) unless asked for: the oracle hierarchies default to it
     p = mg.default_params(cfg["dims"], c1=cfg["c1"], c3=cfg["c3"], kd_naik=cfg["kd_naik"],
                           nagg=len(cfg["blocks"]), block=cfg["blocks"], nvec=tuple(cfg["nvec"]) + (1,) * (2 - len(cfg["nvec"])),
-                          mass0=cfg["mass0"])
+                          mass0=cfg["mass0"], coarse_op=0)
     for k, v in kw.items():
         if k in ("setup_maxiter", "setup_tol", "nvec"):
             arr = getattr(p, k)

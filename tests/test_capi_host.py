@@ -66,6 +66,7 @@ def test_default_params_table1(m):
     assert p.coarsest_maxiter == t["coarsest_basis"]
     assert list(p.nvec) == [t["nvec_level1"], t["nvec_level2"]]
     assert abs(p.c1 - 9 / 8) < 1e-15 and abs(p.c3 + 1 / 24) < 1e-15
+    assert p.coarse_op == (1 if t["coarse_preconditioned"] else 0)
 
 
 @pytest.mark.parametrize("bad,why", [
@@ -84,6 +85,7 @@ def test_default_params_table1(m):
     (dict(coarsest_deflate=80), "coarsest_deflate"),
     (dict(coarsest_deflate=16, deflate_maxiter=0), "deflate_maxiter"),
     (dict(deflate_import=2), "deflate_import"),
+    (dict(coarse_op=2), "coarse_op"),
     (dict(dims=(8, 8, 8, 8), nvec=(8, 8), coarsest_deflate=32), "dimension"),
 ])
 def test_workspace_validation(m, bad, why):
