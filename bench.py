@@ -65,11 +65,12 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "coarse_mfma_level2_traffic.json")
 DOM_SOURCE = os.path.join(ROOT, "paper_2212_12559_amd", "csrc", "coarse_mfma.hip")
 
 
-def hbm_traffic(nrhs):
+def hbm_traffic(nrhs, mode=None):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, each scaled by what
     the counter reads for a copy of known size), or None when those runs were
-    taken on another version of the kernel's source or another rhs count."""
+    taken on another version of the kernel's source, another rhs count or
+    another link format / coarse operator (mode)."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter run committed"
@@ -79,10 +80,16 @@ def hbm_traffic(nrhs):
         return None, "counters taken on an older version of the kernel"
     if rec.get("nrhs") != nrhs:
         return None, f"counters taken at {rec.get('nrhs')} rhs per launch"
+    if mode is not None and rec.get("mode") != mode:
+        return None, f"counters taken with {rec.get('mode')}"
     return rec["bytes_per_launch"], os.path.relpath(TRAFFIC_FILE, ROOT)
 
 
-def summarize_counters(fetch_dir, write_dir, wl):
+def coarse_mode(cprec, coarse_op):
+    return f"{cprec} links, coarse_op {coarse_op}"
+
+
+def summarize_counters(fetch_dir, write_dir, wl, mode):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the level-2 coarse
     stencil and of the 512 MiB calibration copy -> bytes per launch."""
     import csv
@@ -118,7 +125,7 @@ def summarize_counters(fetch_dir, write_dir, wl):
                      "copy_kib_raw": sum(cal) / len(cal), "copy_kib_true": copy_kib, "scale": factor,
                      "bytes_per_launch": sum(dom) / len(dom) * factor * 1024}
     sha = hashlib.sha256(open(DOM_SOURCE, "rb").read()).hexdigest()
-    rec = {"kernel": "coarse_mfma_kernel (level-2 coarse stencil)", "nrhs": nr, "source_sha256": sha,
+    rec = {"kernel": "coarse_mfma_kernel (level-2 coarse stencil)", "nrhs": nr, "mode": mode, "source_sha256": sha,
            "fetch": res["fetch"], "write": res["write"],
            "bytes_per_launch": res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
@@ -147,9 +154,22 @@ def op_counts(info, s, nlev):
 
 
 # ---------------------------------------------------------------- bytes
-def algorithmic_bytes(dims, nvec, nrhs=1, csz=8, naik=True, link_csz=8):
+def coarse_link_blocks(ctx, level, link_csz):
+    """Link blocks per coarse site that the stencil reads: 8 when the level is
+    block-preconditioned with an identity self block that the 16-bit stencil
+    adds instead of reading (every coarse extent >= 2, n a multiple of 32),
+    else all 9."""
+    p = ctx.params
+    shape = ctx.coarse_shapes[level - 2]
+    n = 2 * shape[-1]
+    implicit = p.coarse_op == 1 and link_csz == 4 and min(shape[:4]) >= 2 and n % 32 == 0
+    return 8 if implicit else 9
+
+
+def algorithmic_bytes(dims, nvec, nrhs=1, csz=8, naik=True, link_csz=8, blocks2=9):
     """Per-apply algorithmic HBM bytes (each operand read or written once);
-    link_csz is the size of one stored complex coarse-link entry."""
+    link_csz is the size of one stored complex coarse-link entry, blocks2 the
+    link blocks per level-2 site the stencil reads."""
     V = int(np.prod(dims))
     links = 8 * 9 * csz          # fat + Naik, 4 directions each, 3x3 complex (op 0 always has Naik)
     vec = 3 * csz
@@ -163,7 +183,7 @@ def algorithmic_bytes(dims, nvec, nrhs=1, csz=8, naik=True, link_csz=8):
     }
     Vc = V // 256
     n = 2 * nvec[0]
-    b["coarse2"] = Vc * (9 * n * n * link_csz + 2 * n * csz * nrhs)
+    b["coarse2"] = Vc * (blocks2 * n * n * link_csz + 2 * n * csz * nrhs)
     return b
 
 
@@ -182,13 +202,14 @@ def kernel_rates(torch, ctx, wl, reps, mg, link_csz=8):
     y = torch.empty_like(x)
     yc = torch.empty_like(xc)
     yc3 = torch.empty_like(xc3)
-    b = algorithmic_bytes(dims, wl["nvec"], nrhs=nr, naik=wl["kd_naik"] != 0, link_csz=link_csz)
+    k2, k3 = coarse_link_blocks(ctx, 2, link_csz), coarse_link_blocks(ctx, 3, link_csz)
+    b = algorithmic_bytes(dims, wl["nvec"], nrhs=nr, naik=wl["kd_naik"] != 0, link_csz=link_csz, blocks2=k2)
     n3 = 2 * wl["nvec"][1]
     Vc3 = int(np.prod(ctx.coarse_shapes[1][:4]))
-    b["coarse3"] = Vc3 * (9 * n3 * n3 * link_csz + 2 * n3 * 8 * nr)
+    b["coarse3"] = Vc3 * (k3 * n3 * n3 * link_csz + 2 * n3 * 8 * nr)
     n2 = 2 * wl["nvec"][0]
     Vc2 = int(np.prod(ctx.coarse_shapes[0][:4]))
-    flops = {"coarse2": 8.0 * Vc2 * n2 * 9 * n2 * nr, "coarse3": 8.0 * Vc3 * n3 * 9 * n3 * nr}
+    flops = {"coarse2": 8.0 * Vc2 * n2 * k2 * n2 * nr, "coarse3": 8.0 * Vc3 * n3 * k3 * n3 * nr}
     ops = {
         "dslash": lambda: ctx.apply_dslash(0, m, x, y),
         "kd": lambda: ctx.apply_dslash(2, m, x, y),
@@ -507,7 +528,13 @@ def main():
                          "committed traffic record of the dominant kernel, then exit")
     args = ap.parse_args()
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters, WORKLOADS[args.workload])
+        from paper_2212_12559_amd import mgstag as mg
+        wl = WORKLOADS[args.workload]
+        cop = mg.default_params(wl["dims"]).coarse_op
+        for kv in args.set:
+            if kv.split("=", 1)[0] == "coarse_op":
+                cop = int(kv.split("=", 1)[1])
+        summarize_counters(*args.summarize_counters, wl, coarse_mode(args.coarse_prec or wl["coarse_prec"], cop))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus 1)", file=sys.stderr)
@@ -678,7 +705,7 @@ def c2batch_bench(args, wl, torch, latgen, mg, out):
     dom_us = dom_ms / max(dom_launches, 1) * 1e3
     dom_gbs = dom_bytes / (dom_us * 1e-6) / 1e9
     kname = ("coarse_kernel<float,float2>" if cprec == "fp32" else f"coarse_mfma_kernel<{cprec}>")
-    traffic, traffic_src = hbm_traffic(nr * mb)
+    traffic, traffic_src = hbm_traffic(nr * mb, coarse_mode(cprec, p.coarse_op))
     out["roofline"] = {"bound": "hbm", "kernel": f"{kname} (level-2 coarse stencil, {nr * mb} rhs per launch)",
                        "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": dom_gbs / HBM_PEAK_GBS, "traffic": traffic,

@@ -108,6 +108,13 @@ typedef struct {
                                 coarser level built from the preconditioned one and every coarse level solve
                                 run on A_l x = X_l^{-1} b (Sec. 2.3, Table 1); the near-null vectors of a
                                 level come from its Galerkin operator */
+  int32_t coarsest_solver;   /* 0: GCR (coarsest_maxiter directions per restart cycle, stop at coarsest_tol);
+                                1: CA-GCR(s), s = coarsest_maxiter, in a Chebyshev basis on [0, lambda_max]
+                                (lambda_max by power iteration at set-up), coarsest_restarts cycles or
+                                coarsest_tol (Table 1: Chebyshev-basis CA-GCR(16)) */
+  int32_t graph_coarsest;    /* 1: with coarsest_solver 1 and coarsest_restarts 1 the coarsest solve (a fixed
+                                launch sequence) is captured once per system count into a HIP graph and
+                                replayed (results identical to the eager launches); 0: always eager */
   uint64_t seed;             /* seed of the GPU-generated null-vector starts */
 } mg_params;
 

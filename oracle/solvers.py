@@ -154,6 +154,24 @@ def mr_smoother(op, r, s):
     return sum(y[i] * V[i] for i in range(k))
 
 
+def cagcr(op, b, s, tol, cycles):
+    """Restarted CA-GCR(s) (Table 1, the coarsest solver), by what a cycle
+    computes: from x, the correction minimising ||r - A v|| over K_s(A, r),
+    r = b - A x (the basis the GPU builds it in, Chebyshev or another, does
+    not change the minimiser); cycles until ||r|| <= tol ||b||."""
+    x = np.zeros_like(b)
+    bn = _norm(b)
+    if bn == 0.0:
+        return x
+    r = b.copy()
+    for _ in range(cycles):
+        x = x + mr_smoother(op, r, s)
+        r = b - op(x)
+        if _norm(r) <= tol * bn:
+            break
+    return x
+
+
 def cgne_null_vector(op, op_dag, phi0, tol, maxiter):
     """Near-null vector by CGNE on A phi = 0 from phi0 (Sec. 2.1, Table 1).
 
@@ -340,6 +358,8 @@ class MGParams:
     coarsest_tol: float = 0.25
     coarsest_maxiter: int = 16
     coarsest_direct: bool = False
+    coarsest_solver: str = "gcr"     # "gcr", or "cagcr": cycles of CA-GCR(s), s = coarsest_maxiter (Table 1)
+    coarsest_cycles: int = 1
     outer_nkrylov: int = 16
     dense_coarse_limit: int = 6144   # coarse levels up to this many dof are tabulated densely
     coarse_op: str = "galerkin"      # "galerkin": A_l = R A_{l-1} P; "block": X_l^{-1} R A_{l-1} P
@@ -523,6 +543,8 @@ class Hierarchy:
                 e, _ = gcr(lambda v: self.op(lvl, v), r0, None, p.coarsest_tol * bn / rn,
                            p.coarsest_maxiter, p.coarsest_maxiter)
                 return x0 + e
+            if p.coarsest_solver == "cagcr":
+                return cagcr(lambda v: self.op(lvl, v), b, p.coarsest_maxiter, p.coarsest_tol, p.coarsest_cycles)
             x, _ = gcr(lambda v: self.op(lvl, v), b, None, p.coarsest_tol,
                        p.coarsest_maxiter, p.coarsest_maxiter)
             return x

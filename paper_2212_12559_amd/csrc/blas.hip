@@ -277,11 +277,10 @@ __device__ __forceinline__ void ldraw(const double2* p, int64_t e, double2& a, d
   b = p[e + 1];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2* __restrict__ part, int nblk) {
-  constexpr int S = kMaxS;
+template <typename T, int S, int NW>
+__global__ void __launch_bounds__(64 * NW) gram_kernel(const GramArgs<T> a, double2* __restrict__ part, int nblk) {
   constexpr int NPF = S * (S + 1) / 2 + S;
-  constexpr int PW = (NPF + 3) / 4;
+  constexpr int PW = (NPF + NW - 1) / NW;
   __shared__ T us[S + 1][256];
   const int r = blockIdx.y;
   const int64_t off = (int64_t)r * a.stride;
@@ -328,7 +327,7 @@ __global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2*
       for (int i = 0; i < S; ++i) {
 #pragma unroll
         for (int j = i; j <= S; ++j) {
-          if ((f & 3) == wave && i < s && (j < s || j == S)) cfmac(acc[f >> 2], v[i], v[j]);
+          if ((f % NW) == wave && i < s && (j < s || j == S)) cfmac(acc[f / NW], v[i], v[j]);
           ++f;
         }
       }
@@ -339,8 +338,8 @@ __global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2*
   for (int i = 0; i < S; ++i) {
 #pragma unroll
     for (int j = i; j <= S; ++j) {
-      if ((f & 3) == wave && i < s && (j < s || j == S)) {
-        const double sx = wsum(acc[f >> 2].x), sy = wsum(acc[f >> 2].y);
+      if ((f % NW) == wave && i < s && (j < s || j == S)) {
+        const double sx = wsum(acc[f / NW].x), sy = wsum(acc[f / NW].y);
         const int p = j < S ? i * s - i * (i - 1) / 2 + (j - i) : s * (s + 1) / 2 + i;
         if (lane == 0) part[((int64_t)p * a.nrhs + r) * nblk + blockIdx.x] = make_double2(sx, sy);
       }
@@ -349,11 +348,79 @@ __global__ void __launch_bounds__(256) gram_kernel(const GramArgs<T> a, double2*
   }
 }
 
+// Gram data of a CA-GCR(s) cycle with s up to 16 (the coarsest solver): the
+// same products and output order as gram_kernel, 16 wavefronts each owning
+// ten of the 152 products (pair indices in registers, operands read from
+// the LDS stage), so no per-element register copy of all 17 vectors.
+template <typename T>
+__global__ void __launch_bounds__(1024) gram16_kernel(const GramArgs<T> a, double2* __restrict__ part, int nblk) {
+  constexpr int S = kMaxCA, NW = 16;
+  constexpr int NPF = S * (S + 1) / 2 + S;
+  constexpr int PW = (NPF + NW - 1) / NW;
+  __shared__ T us[S + 1][256];
+  const int r = blockIdx.y;
+  const int64_t off = (int64_t)r * a.stride;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int s = a.s;
+  int pi[PW], pj[PW], po[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) { pi[q] = -1; pj[q] = 0; po[q] = 0; }
+  {
+    int f = 0;
+    for (int i = 0; i < S; ++i)
+      for (int j = i; j <= S; ++j, ++f) {
+        if (f % NW != wave || !(i < s && (j < s || j == S))) continue;
+        const int q = f / NW;
+#pragma unroll
+        for (int qq = 0; qq < PW; ++qq)
+          if (qq == q) {
+            pi[qq] = i;
+            pj[qq] = j;
+            po[qq] = j < S ? i * s - i * (i - 1) / 2 + (j - i) : s * (s + 1) / 2 + i;
+          }
+      }
+  }
+  double2 acc[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) acc[q] = make_double2(0.0, 0.0);
+  const int64_t step = (int64_t)nblk * 256;
+  for (int64_t e0 = (int64_t)blockIdx.x * 256; e0 < a.n; e0 += step) {
+    __syncthreads();
+    if (threadIdx.x < 128) {
+      const int64_t e = e0 + 2 * threadIdx.x;
+      const int el = 2 * threadIdx.x;
+      for (int i = 0; i <= S; ++i) {
+        const int src = i < S ? i : s;
+        T va = from_d2<T>(make_double2(0.0, 0.0)), vb = va;
+        if ((i < s || i == S) && e < a.n) ldraw(a.u[src], off + e, va, vb);
+        us[i][el] = va;
+        us[i][el + 1] = vb;
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int q4 = 0; q4 < 4; ++q4) {
+      const int el = lane + 64 * q4;
+#pragma unroll
+      for (int q = 0; q < PW; ++q)
+        if (pi[q] >= 0) cfmac(acc[q], to_d2(us[pi[q]][el]), to_d2(us[pj[q]][el]));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    if (pi[q] < 0) continue;
+    const double sx = wsum(acc[q].x), sy = wsum(acc[q].y);
+    if (lane == 0) part[((int64_t)po[q] * a.nrhs + r) * nblk + blockIdx.x] = make_double2(sx, sy);
+  }
+}
+
 template <typename T>
 void launch_gram(const GramArgs<T>& a, double2* part, double2* res, int ldr, hipStream_t st) {
   if (a.n % 2 || a.stride % 2) throw std::runtime_error("gram: vector lengths must be even");
   const int nblk = reduce_blocks(a.n);
-  gram_kernel<T><<<dim3(nblk, a.nrhs), 256, 0, st>>>(a, part, nblk);
+  if (a.s <= kMaxS) gram_kernel<T, kMaxS, 4><<<dim3(nblk, a.nrhs), 256, 0, st>>>(a, part, nblk);
+  else if (a.s <= kMaxCA) gram16_kernel<T><<<dim3(nblk, a.nrhs), 1024, 0, st>>>(a, part, nblk);
+  else throw std::runtime_error("gram: at most 16 basis vectors");
   finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, a.s * (a.s + 1) / 2 + a.s, a.nrhs, res, ldr);
 }
 template void launch_gram<float2>(const GramArgs<float2>&, double2*, double2*, int, hipStream_t);
@@ -593,12 +660,13 @@ void launch_gcr_scalars(const double2* qq, const double2* qr, const int* mask, i
 // (FP64).  G[i][j] = <q_i, q_j> given for i <= j in slot order
 // (0,0),(0,1)..(0,s-1),(1,1),...; c_i = <q_i, r> in slots after them.
 // A pivot below 1e-13 of the largest diagonal truncates the basis there.
+template <int S>
 __global__ void cagcr_solve_kernel(const double2* gram, int s, int nrhs, int ldr, const int* mask,
                                    double2* coef) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrhs) return;
-  double2 G[kMaxS][kMaxS];
-  double2 c[kMaxS];
+  double2 G[S][S];
+  double2 c[S];
   int p = 0;
   for (int i = 0; i < s; ++i)
     for (int j = i; j < s; ++j) {
@@ -627,7 +695,7 @@ __global__ void cagcr_solve_kernel(const double2* gram, int s, int nrhs, int ldr
       G[i][j] = make_double2(v.x / ljj, v.y / ljj);
     }
   }
-  double2 y[kMaxS];
+  double2 y[S];
   for (int i = 0; i < k; ++i) {   // L y = c
     double2 v = c[i];
     for (int q = 0; q < i; ++q) {
@@ -651,7 +719,8 @@ __global__ void cagcr_solve_kernel(const double2* gram, int s, int nrhs, int ldr
 }
 void launch_cagcr_solve(const double2* gram, int s, int nrhs, int ldr, const int* mask, double2* coef,
                         hipStream_t st) {
-  cagcr_solve_kernel<<<(nrhs + 63) / 64, 64, 0, st>>>(gram, s, nrhs, ldr, mask, coef);
+  if (s <= kMaxS) cagcr_solve_kernel<kMaxS><<<(nrhs + 63) / 64, 64, 0, st>>>(gram, s, nrhs, ldr, mask, coef);
+  else cagcr_solve_kernel<kMaxCA><<<(nrhs + 15) / 16, 16, 0, st>>>(gram, s, nrhs, ldr, mask, coef);
 }
 
 // CG scalars: alpha = rr / pAp, -alpha; beta = rr_new / rr (rr updated in place)

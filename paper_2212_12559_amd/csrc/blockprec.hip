@@ -147,6 +147,19 @@ __global__ void ns_residual_kernel(const double2* __restrict__ T, int64_t nsite,
   if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
 }
 
+// self block d = 0 of every site set to the identity (links [site][9][n][n])
+__global__ void unit_self_kernel(double2* __restrict__ L, int n) {
+  const int64_t site = blockIdx.y;
+  const int64_t nn = (int64_t)n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x)
+    L[site * 9 * nn + e] = make_double2((e % n) == (e / n) ? 1.0 : 0.0, 0.0);
+}
+void launch_unit_self(double2* L, const Geom& g, int n, hipStream_t st) {
+  const int64_t nn = (int64_t)n * n;
+  dim3 grid((unsigned)((nn + 255) / 256), (unsigned)g.V);
+  unit_self_kernel<<<grid, 256, 0, st>>>(L, n);
+}
+
 void launch_diag_block(const double2* L, double2* X, const Geom& g, int n, hipStream_t st) {
   const int64_t nn = (int64_t)n * n;
   dim3 grid((unsigned)((nn + 255) / 256), (unsigned)g.V);

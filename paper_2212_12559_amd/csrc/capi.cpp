@@ -135,6 +135,8 @@ void mg_default_params(mg_params* p, const int32_t dims[4]) {
   p->deflate_maxiter = 300;
   p->deflate_import = 0;
   p->coarse_op = 1;   // Table 1: preconditioned coarse operators on levels 2 and 3
+  p->coarsest_solver = 1;   // Table 1: Chebyshev-basis CA-GCR(16) on the coarsest level
+  p->graph_coarsest = 1;
   p->seed = 20221224ull;
 }
 

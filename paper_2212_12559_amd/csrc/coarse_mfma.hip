@@ -157,22 +157,28 @@ __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const C
   for (int m = 0; m < MT; ++m)
     Lm[m] = reinterpret_cast<const uint4*>(a.links) + (site * mt_n + wave + nw * m) * (int64_t)kc_n * 2 * 64;
   const int j = lane & 15, g = lane >> 4;
+  // With an identity self block (unit_self) the k range starts at direction 1.
   // Where a staging pass is exactly one direction (n = KCH), neighbouring
   // workgroups read the same input vector in the same pass: a site with odd x
   // takes -x, self, +x in its first three passes (its -x is the self of the
   // site before it, its self the +x of that site), and rows y = 2, 3 mod 4
   // (z likewise) take -y before +y (reading the row that y - 2 reads with +y).
+  const int kc_begin = a.unit_self ? n / 32 : 0;
   const bool perm = n == KCH && kc_n == 9 * kMfmaCK;
   const int64_t sx = site % a.g.L[0], sy = (site / a.g.L[0]) % a.g.L[1],
                 sz = (site / ((int64_t)a.g.L[0] * a.g.L[1])) % a.g.L[2];
   const bool xodd = perm && (sx & 1), yswap = perm && ((sy >> 1) & 1), zswap = perm && ((sz >> 1) & 1);
-  const int npass = (kc_n + kMfmaCK - 1) / kMfmaCK;
+  const int npass = (kc_n - kc_begin + kMfmaCK - 1) / kMfmaCK;
   for (int pi = 0; pi < npass; ++pi) {
-    int pd = pi;
-    if (xodd && pi <= 2) pd = pi == 0 ? 2 : pi - 1;
-    if (yswap && (pi == 3 || pi == 4)) pd = 7 - pi;
-    if (zswap && (pi == 5 || pi == 6)) pd = 11 - pi;
-    const int kc0 = pd * kMfmaCK;
+    // direction-ordered passes: d = pi (+1 without the self block), reordered as above
+    int pd = pi + (a.unit_self && perm ? 1 : 0);
+    if (xodd) {
+      if (a.unit_self) { if (pd <= 2) pd = 3 - pd; }
+      else if (pd <= 2) pd = pd == 0 ? 2 : pd - 1;
+    }
+    if (yswap && (pd == 3 || pd == 4)) pd = 7 - pd;
+    if (zswap && (pd == 5 || pd == 6)) pd = 11 - pd;
+    const int kc0 = perm ? pd * kMfmaCK : kc_begin + pi * kMfmaCK;
     __syncthreads();   // neighbour table ready / previous pass consumed
     // stage k in [32 kc0, 32 kc0 + KCH): quads (k .. k + 3) lie in one
     // direction (n is a multiple of 16) and are two 16-byte loads (inputs are
@@ -233,8 +239,15 @@ __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const C
       const int r = r0 + rt * 16 + j;
       if (r < a.nrhs) {
         float2* o = a.out + (int64_t)r * a.out_stride + site * n + mt * 16 + 4 * g;
+        float2 xs[4] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+        if (a.unit_self) {
+          const float2* xi = a.in + (int64_t)r * a.in_stride + site * n + mt * 16 + 4 * g;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) store_stream(o + t, yr[m][rt][t] * a.inv_scale, yi[m][rt][t] * a.inv_scale);
+          for (int t = 0; t < 4; ++t) xs[t] = xi[t];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          store_stream(o + t, fmaf(yr[m][rt][t], a.inv_scale, xs[t].x), fmaf(yi[m][rt][t], a.inv_scale, xs[t].y));
       }
     }
   }
@@ -268,6 +281,8 @@ void launch_coarse_mfma(const CoarseMfmaArgs& a, int fmt, hipStream_t st) {
     throw std::runtime_error("coarse_mfma: n must be a multiple of 16 in 16..256");
   if (reinterpret_cast<uintptr_t>(a.in) % 16 || a.in_stride % 2)
     throw std::runtime_error("coarse_mfma: input must be 16-byte aligned");
+  if (a.unit_self && a.n % 32)
+    throw std::runtime_error("coarse_mfma: an implicit identity self block needs n to be a multiple of 32");
   if (fmt == 0) coarse_mfma_dispatch<0>(a, st);
   else coarse_mfma_dispatch<1>(a, st);
 }

@@ -170,6 +170,7 @@ constexpr int kSlotR0 = 65;          // |b|^2 of a level solve
 constexpr int kSlotNorm = 66;        // norms read by the host
 constexpr int kSlotScale = 67;       // power-of-two rhs scale of a coarse level solve, then its inverse (68)
 constexpr int kMaxNK = 16;           // Krylov directions per GCR
-constexpr int kMaxS = 8;             // CA-GCR basis size
+constexpr int kMaxS = 8;             // CA-GCR basis size of the smoother
+constexpr int kMaxCA = 16;           // CA-GCR basis size of the coarsest solver
 
 }  // namespace mg

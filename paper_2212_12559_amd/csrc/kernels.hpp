@@ -119,6 +119,7 @@ struct CoarseMfmaArgs {
   int64_t in_stride, out_stride;
   int nrhs;
   float inv_scale;
+  int unit_self;            // the self block is the identity: skip its links, add the input instead (n % 32 == 0)
 };
 void launch_coarse_mfma(const CoarseMfmaArgs& a, int fmt, hipStream_t st);   // fmt 0 bf16, 1 fp16
 template <typename TI>
@@ -146,6 +147,7 @@ struct BGemmArgs {
 template <typename T>
 void launch_bgemm(const BGemmArgs<T>& a, hipStream_t st);
 void launch_diag_block(const double2* L, double2* X, const Geom& g, int n, hipStream_t st);
+void launch_unit_self(double2* L, const Geom& g, int n, hipStream_t st);
 void launch_ns_init(const double2* X, double2* Y, int64_t nsite, int n, hipStream_t st);
 void launch_ns_residual(const double2* T, int64_t nsite, int n, unsigned long long* out, hipStream_t st);
 
@@ -174,10 +176,10 @@ struct LinCombArgs {
   int64_t n, stride;
   int nrhs;
 };
-// CA-GCR smoother Gram data: u[0..s-1] = A p_0..A p_{s-1}, u[s] = t
+// CA-GCR Gram data: u[0..s-1] = A p_0..A p_{s-1}, u[s] = t (s <= kMaxCA)
 template <typename T>
 struct GramArgs {
-  const T* u[kMaxS + 1];
+  const T* u[kMaxCA + 1];
   int s;
   int64_t n, stride;
   int nrhs;

@@ -46,6 +46,8 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   if (p.coarsest_deflate > 0 && p.deflate_maxiter < 1) return fail("deflate_maxiter must be >= 1");
   if (p.deflate_import != 0 && p.deflate_import != 1) return fail("deflate_import must be 0 or 1");
   if (p.coarse_op != 0 && p.coarse_op != 1) return fail("coarse_op must be 0 (Galerkin) or 1 (block-preconditioned)");
+  if (p.coarsest_solver != 0 && p.coarsest_solver != 1) return fail("coarsest_solver must be 0 (GCR) or 1 (CA-GCR)");
+  if (p.graph_coarsest != 0 && p.graph_coarsest != 1) return fail("graph_coarsest must be 0 or 1");
   const bool naik_kd = p.c3 != 0.0 && p.kd_naik;
   Geom g0{};
   g0.V = 1;
@@ -141,7 +143,8 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   // ---- scratch
   const int ms = std::max({p.max_nrhs, p.nvec[0], p.nagg > 1 ? p.nvec[1] : 1, kd});
   auto S = [&](size_t n) { return scr.take(n); };
-  const size_t part_elems = std::max((size_t)kMaxPairs * ms * 480, kd > 0 ? (size_t)128 * kMaxDefl * kMaxDefl : 0);
+  const int npart = p.coarsest_solver == 1 ? kMaxCA * (kMaxCA + 1) / 2 + kMaxCA : kMaxPairs;   // products per reduction
+  const size_t part_elems = std::max((size_t)npart * ms * 480, kd > 0 ? (size_t)128 * kMaxDefl * kMaxDefl : 0);
   void* part = S(part_elems * 16);
   void* scal = S((size_t)4 * kMaxSlots * ms * 16);
   void* tri = S((size_t)4 * kTriSlots * ms * 16);
@@ -281,6 +284,8 @@ void Ctx::prof_mark(int op, int level) {
 
 Ctx::~Ctx() {
   for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
+  for (auto& g : coarsest_graphs) (void)hipGraphExecDestroy(g.second);
+  if (capture_st) (void)hipStreamDestroy(capture_st);
 }
 
 // ================================================================== operators
@@ -355,6 +360,7 @@ void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, b
     a.out = (float2*)out; a.in = (const float2*)in; a.links = cl16[l];
     a.g = gc[l]; a.n = n; a.in_stride = a.out_stride = gc[l].V * n; a.nrhs = nsys;
     a.inv_scale = cl16_inv_scale[l];
+    a.unit_self = unit_self[l] ? 1 : 0;
     launch_coarse_mfma(a, fmt16, st);
   } else {
     CoarseArgs<float, float2> a{};
@@ -468,8 +474,11 @@ void Ctx::lincomb(int prec, int64_t n, int nsys, void* out,
 
 void Ctx::copy(const Vec& dst, const Vec& src, int nsys) {
   const int64_t n = src.n * nsys;
-  if (dst.prec == src.prec) {
-    HIPCHK(hipMemcpyAsync(dst.p, src.p, n * csize(src.prec), hipMemcpyDeviceToDevice, st));
+  // copies are kernels (no copy nodes in a captured coarsest solve)
+  if (dst.prec == src.prec && src.prec == P64) {
+    launch_convert<double2, double2>((double2*)dst.p, (const double2*)src.p, n, st);
+  } else if (dst.prec == src.prec) {
+    launch_convert<float2, float2>((float2*)dst.p, (const float2*)src.p, n, st);
   } else if (src.prec == P64) {
     launch_convert<double2, float2>((float2*)dst.p, (const double2*)src.p, n, st);
   } else {
@@ -652,6 +661,42 @@ bool Ctx::any_active(int lvl, int nsys) {
 void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   LevelBufs& B = L[lvl];
   const bool coarsest = lvl == nlev - 1;
+  // A single CA-GCR cycle makes the coarsest solve a fixed sequence of
+  // launches with no host decision: it is captured once per system count
+  // (on a private stream) and replayed as one graph launch.
+  if (coarsest && P.coarsest_solver == 1 && P.coarsest_restarts == 1 && P.graph_coarsest && !capturing &&
+      !(prof_op >= 0 && prof_level == lvl)) {
+    auto it = coarsest_graphs.find(nsys);
+    if (it == coarsest_graphs.end()) {
+      if (!capture_st) HIPCHK(hipStreamCreateWithFlags(&capture_st, hipStreamNonBlocking));
+      hipStream_t user = st;
+      st = capture_st;
+      capturing = true;
+      SolveStats dummy;
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        level_solve(lvl, nsys, dummy);
+      } catch (...) {
+        (void)hipStreamEndCapture(st, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        capturing = false;
+        st = user;
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(st, &graph));
+      capturing = false;
+      st = user;
+      hipGraphExec_t exec = nullptr;
+      const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) throw Error{MG_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+      it = coarsest_graphs.emplace(nsys, exec).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, st));
+    stats.level[lvl - 1] += P.coarsest_maxiter;
+    return;
+  }
   const double tol = coarsest ? P.coarsest_tol : P.inner_tol;
   const int maxit = coarsest ? P.coarsest_maxiter : P.inner_maxiter;
   const int cycles = coarsest ? P.coarsest_restarts : 1;
@@ -697,6 +742,11 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   check_launch();
   const bool deflated = coarsest && defl_k > 0;
   if (deflated) deflate_start(lvl, nsys);   // x = W' Q^H b, r = b - Q Q^H b
+  if (coarsest && P.coarsest_solver == 1) {
+    coarsest_cagcr(lvl, nsys, stats, deflated);
+    if (scaled) lincomb(prec, n, nsys, B.x.p, {{B.x.p, slot(lvl, kSlotScale + 1)}}, {}, {});
+    return;
+  }
   bool live = true;
   for (int cyc = 0; cyc < cycles && live; ++cyc) {
     if (cyc > 0) {   // restart: r = b - A x
@@ -719,6 +769,73 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
     gcr_flush(lvl, B, nk, nsys, cyc > 0 || deflated);
   }
   if (scaled) lincomb(prec, n, nsys, B.x.p, {{B.x.p, slot(lvl, kSlotScale + 1)}}, {}, {});
+}
+
+// CA-GCR(s) cycles on the coarsest level (Table 1: Chebyshev-basis CA-GCR):
+// p_0 = r, p_1 = (A - c) p_0 / d, p_{j+1} = 2 (A - c) p_j / d - p_{j-1}, with
+// q_j = A p_j from the s operator applications; one Gram reduction of the
+// q_j and r (FP64), an s x s Cholesky solve per system for the minimiser of
+// |r - sum alpha_j q_j|, then x += sum alpha_j p_j, r -= sum alpha_j q_j.
+// The cycle's result is the Krylov minimiser over K_s(A, r), whatever the
+// basis; the Chebyshev one keeps the Gram matrix far better conditioned than
+// powers of A.  Stops at |r| <= coarsest_tol |b| or after coarsest_restarts
+// cycles.
+void Ctx::coarsest_cagcr(int lvl, int nsys, SolveStats& stats, bool have_x) {
+  LevelBufs& B = L[lvl];
+  const int s = P.coarsest_maxiter;
+  const int prec = B.prec;
+  const int64_t n = B.n;
+  const double c = cheb_c, d = cheb_d;
+  double2* gram = tslot(lvl, 0);
+  double2* coef = tslot(lvl, 160);
+  for (int cyc = 0; cyc < P.coarsest_restarts; ++cyc) {
+    stats.level[lvl - 1] += s;
+    copy(B.z[0], B.r, nsys);
+    for (int j = 0; j < s; ++j) {
+      apply_level(lvl, B.q[j], B.z[j], nsys);
+      if (j + 1 == s) break;
+      if (j == 0)
+        lincomb(prec, n, nsys, B.z[1].p, {{B.q[0].p, nullptr}, {B.z[0].p, nullptr}}, {},
+                {make_double2(1.0 / d, 0.0), make_double2(-c / d, 0.0)});
+      else
+        lincomb(prec, n, nsys, B.z[j + 1].p, {{B.q[j].p, nullptr}, {B.z[j].p, nullptr}, {B.z[j - 1].p, nullptr}}, {},
+                {make_double2(2.0 / d, 0.0), make_double2(-2.0 * c / d, 0.0), make_double2(-1.0, 0.0)});
+    }
+    auto fill = [&](auto& a) {
+      using TP = decltype(a.u[0]);
+      for (int j = 0; j < s; ++j) a.u[j] = (TP)B.q[j].p;
+      a.u[s] = (TP)B.r.p;
+      a.s = s; a.n = n; a.stride = n; a.nrhs = nsys;
+    };
+    if (prec == P64) {
+      GramArgs<double2> a{};
+      fill(a);
+      launch_gram(a, part, gram, max_sys, st);
+    } else {
+      GramArgs<float2> a{};
+      fill(a);
+      launch_gram(a, part, gram, max_sys, st);
+    }
+    check_launch();
+    launch_cagcr_solve(gram, s, nsys, max_sys, lmask(lvl), coef, st);
+    check_launch();
+    std::vector<std::pair<const void*, const double2*>> tx, tr;
+    if (cyc > 0 || have_x) tx.push_back({B.x.p, nullptr});
+    tr.push_back({B.r.p, nullptr});
+    std::vector<int> nr{0};
+    for (int j = 0; j < s; ++j) {
+      tx.push_back({B.z[j].p, coef + (int64_t)j * max_sys});
+      tr.push_back({B.q[j].p, coef + (int64_t)j * max_sys});
+      nr.push_back(1);
+    }
+    lincomb(prec, n, nsys, B.x.p, tx, {}, {});
+    lincomb(prec, n, nsys, B.r.p, tr, nr, {});
+    if (cyc + 1 == P.coarsest_restarts) break;
+    dots(prec, n, nsys, {{B.r.p, B.r.p}}, slot(lvl, kSlotRN));
+    launch_conv(lmask(lvl), slot(lvl, kSlotRN), slot(lvl, kSlotR0), P.coarsest_tol * P.coarsest_tol, nsys, 0, st);
+    check_launch();
+    if (!any_active(lvl, nsys)) break;
+  }
 }
 
 // Deflated start of the coarsest solve, 64 systems per pass:

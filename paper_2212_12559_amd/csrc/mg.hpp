@@ -1,6 +1,7 @@
 // Host-side multigrid context: workspace layout, hierarchy set-up and the
 // GCR / CA-GCR / K-cycle / CG drivers.
 #pragma once
+#include <map>
 #include <string>
 #include <vector>
 
@@ -89,6 +90,11 @@ struct Ctx {
   uint16_t* cl16[2]{};      // 16-bit MFMA fragments (coarse_prec BF16 / FP16)
   float cl16_inv_scale[2]{1.0f, 1.0f};
   double2* xinv64[2]{};     // coarse_op 1: X^{-1} per coarse site [site][col][row]
+  bool unit_self[2]{};      // the stored self block is exactly the identity (the 16-bit stencil skips it)
+  double cheb_c = 1.0, cheb_d = 1.0;   // CA-GCR coarsest solver: Chebyshev basis of (A - c) / d
+  std::map<int, hipGraphExec_t> coarsest_graphs;   // captured coarsest solves, by system count
+  hipStream_t capture_st = nullptr;
+  bool capturing = false;
   float2* xinv32[2]{};
   int fmt16 = -1;           // -1: none, 0: bf16, 1: fp16
   bool setup_phase = false;
@@ -178,6 +184,8 @@ struct Ctx {
   void cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2* out);
   void build_deflation(const void* nv_import);
   void deflate_start(int lvl, int nsys);
+  void coarsest_cagcr(int lvl, int nsys, SolveStats& stats, bool have_x);
+  void estimate_lambda_max();
   void galerkin(int l);
   void finish_links(int l);          // FP32 copy and 16-bit fragments of cl64[l]
   void precondition_links(int l);    // X^{-1} and cl64[l] <- X^{-1} cl64[l] (coarse_op 1)

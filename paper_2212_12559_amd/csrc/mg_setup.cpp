@@ -43,8 +43,33 @@ void Ctx::setup(const void* fat, const void* naik, const void* const* nvs) {
     finish_links(l);
   }
   if (defl_k > 0) build_deflation(nvs && P.deflate_import ? nvs[P.nagg] : nullptr);
+  if (P.coarsest_solver == 1) estimate_lambda_max();
   setup_phase = false;
   HIPCHK(hipStreamSynchronize(st));
+}
+
+// Largest eigenvalue modulus of the coarsest operator by 30 power iterations
+// from a seeded random vector; the Chebyshev basis of the CA-GCR coarsest
+// solver then maps [0, 1.05 lambda_max] onto [-1, 1].
+void Ctx::estimate_lambda_max() {
+  const int lc = nlev - 1;
+  LevelBufs& B = L[lc];
+  const int64_t n = B.n;
+  const Vec &v = B.z[0], &w = B.q[0];
+  if (B.prec == P64) launch_random_normal<double2>((double2*)v.p, n, P.seed + 4242ull, st);
+  else launch_random_normal<float2>((float2*)v.p, n, P.seed + 4242ull, st);
+  check_launch();
+  std::vector<double> nv, nw;
+  double lam = 1.0;
+  for (int it = 0; it < 30; ++it) {
+    norms_host(B.prec, n, 1, v.p, slot(lc, kSlotNorm), nv);
+    apply_level(lc, w, v, 1);
+    norms_host(B.prec, n, 1, w.p, slot(lc, kSlotNorm), nw);
+    if (!(nv[0] > 0.0) || !(nw[0] > 0.0) || !std::isfinite(nw[0])) break;
+    lam = nw[0] / nv[0];
+    lincomb(B.prec, n, 1, v.p, {{w.p, nullptr}}, {}, {make_double2(1.0 / nw[0], 0.0)});
+  }
+  cheb_c = cheb_d = 0.5 * 1.05 * lam;
 }
 
 // Naik links: the full FP64 / FP32 copies, and the 13-real form (Sec. 3.1)
@@ -388,6 +413,16 @@ void Ctx::precondition_links(int l) {
     HIPCHK(hipMemcpy2DAsync(cl64[l] + d * nn, (size_t)9 * nn * 16, T, (size_t)nn * 16, (size_t)nn * 16, (size_t)Vc,
                             hipMemcpyDeviceToDevice, st));
   }
+  // with no coarse extent 1 the self piece is the whole diagonal block, so
+  // X^{-1} L_0 is the identity: stored exactly, and the 16-bit stencil adds
+  // the input instead of reading that block
+  bool ext1 = false;
+  for (int mu = 0; mu < 4; ++mu) ext1 = ext1 || gc[l].L[mu] == 1;
+  if (!ext1) {
+    launch_unit_self(cl64[l], gc[l], n, st);
+    check_launch();
+  }
+  unit_self[l] = !ext1 && n % 32 == 0;
 }
 
 // out = X^{-1} in for the systems of a coarse level (coarse_op 1), site by site

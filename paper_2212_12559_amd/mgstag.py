@@ -50,6 +50,8 @@ class MGParams(ctypes.Structure):
         ("deflate_maxiter", ctypes.c_int32),
         ("deflate_import", ctypes.c_int32),
         ("coarse_op", ctypes.c_int32),
+        ("coarsest_solver", ctypes.c_int32),
+        ("graph_coarsest", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 

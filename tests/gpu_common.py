@@ -30,6 +30,11 @@ CONFIGS = {
     # in the KD level as in the 32^4 multi-mass workload
     "prod": dict(dims=(16, 16, 16, 4), c1=C1H, c3=C3H, kd_naik=0, blocks=[(4, 4, 4, 4), (2, 2, 2, 1)],
                  nvec=(64, 96), mass0=0.005, eps=0.5, seed=626262),
+    # the same level shapes with every coarse extent >= 2 (2x4x4x2, then 2^4): with block-preconditioned
+    # coarse levels the self block is then exactly the identity and the 16-bit stencil adds the input
+    # instead of reading it
+    "prodblk": dict(dims=(8, 16, 16, 8), c1=C1H, c3=C3H, kd_naik=0, blocks=[(4, 4, 4, 4), (1, 2, 2, 1)],
+                    nvec=(64, 96), mass0=0.005, eps=0.5, seed=636363),
     # the 16^4 HISQ-style hierarchy shape: KD, 4^4 / Nvec 64, 2^4 / Nvec 96
     "c1": dict(dims=(16, 16, 16, 16), c1=C1H, c3=C3H, kd_naik=1, blocks=[(4, 4, 4, 4), (2, 2, 2, 2)],
                nvec=(64, 96), mass0=0.01, eps=0.5, seed=latgen.SEEDS["c1_16x4_hisq"]),
@@ -70,10 +75,10 @@ def oracle_hierarchy(cfg, W, N, mass, nvs, **kw):
 
 
 def gpu_params(mg, cfg, **kw):
-    # coarse_op 0 (Galerkin) unless asked for: the oracle hierarchies default to it
+    # coarse_op 0 (Galerkin) and the GCR coarsest solver unless asked for: the oracle hierarchies default to them
     p = mg.default_params(cfg["dims"], c1=cfg["c1"], c3=cfg["c3"], kd_naik=cfg["kd_naik"],
                           nagg=len(cfg["blocks"]), block=cfg["blocks"], nvec=tuple(cfg["nvec"]) + (1,) * (2 - len(cfg["nvec"])),
-                          mass0=cfg["mass0"], coarse_op=0)
+                          mass0=cfg["mass0"], coarse_op=0, coarsest_solver=0)
     for k, v in kw.items():
         if k in ("setup_maxiter", "setup_tol", "nvec"):
             arr = getattr(p, k)

@@ -67,6 +67,8 @@ def test_default_params_table1(m):
     assert list(p.nvec) == [t["nvec_level1"], t["nvec_level2"]]
     assert abs(p.c1 - 9 / 8) < 1e-15 and abs(p.c3 + 1 / 24) < 1e-15
     assert p.coarse_op == (1 if t["coarse_preconditioned"] else 0)
+    assert p.coarsest_solver == (1 if "CA-GCR" in t["coarsest_solver"] else 0)
+    assert p.coarsest_maxiter == 16 and p.coarsest_restarts == 1
 
 
 @pytest.mark.parametrize("bad,why", [
@@ -86,6 +88,8 @@ def test_default_params_table1(m):
     (dict(coarsest_deflate=16, deflate_maxiter=0), "deflate_maxiter"),
     (dict(deflate_import=2), "deflate_import"),
     (dict(coarse_op=2), "coarse_op"),
+    (dict(coarsest_solver=3), "coarsest_solver"),
+    (dict(graph_coarsest=2), "graph_coarsest"),
     (dict(dims=(8, 8, 8, 8), nvec=(8, 8), coarsest_deflate=32), "dimension"),
 ])
 def test_workspace_validation(m, bad, why):

@@ -414,7 +414,20 @@ def test_naik_compression_and_fallback(torch, mg):
 _block_cases = {}
 
 
-@pytest.mark.parametrize("name", ["cubic", "ragged", "prod"])
+def _block_case(name):
+    """Seeded links, random null vectors and the oracle's block-preconditioned
+    hierarchy with its links (built once per process)."""
+    if name not in _block_cases:
+        cfg = CONFIGS[name]
+        W, N, rng = links(cfg)
+        nvs = random_null_vectors(cfg, rng)
+        H = oracle_hierarchy(cfg, W, N, cfg["mass0"], nvs, coarse_op="block")
+        Ls = [H.level_links(lvl) for lvl in range(2, H.nlevels)]
+        _block_cases[name] = (cfg, W, N, nvs, H, Ls, rng)
+    return _block_cases[name]
+
+
+@pytest.mark.parametrize("name", ["cubic", "ragged", "prod", "prodblk"])
 def test_block_preconditioned_levels(torch, mg, name):
     """coarse_op 1 (block-preconditioned coarse levels, A_l = X_l^{-1} R A P):
     the FP64 links the GPU builds (diagonal block by Newton-Schulz, links
@@ -423,17 +436,14 @@ def test_block_preconditioned_levels(torch, mg, name):
     the FP64 and FP32 stencils apply the oracle's preconditioned operator.
     "ragged" has coarse extents 1, where the diagonal block collects the
     +-mu pieces that return to the site."""
-    cfg = CONFIGS[name]
-    W, N, rng = links(cfg)
-    nvs = random_null_vectors(cfg, rng)
+    cfg, W, N, nvs, H, Ls, rng = _block_case(name)
     dev = "cuda:0"
     log(f"[block] {name}")
     p = gpu_params(mg, cfg, max_nrhs=4, fine_prec=mg.MG_C128, coarse_prec=mg.MG_C128, coarse_op=1)
     ctx = mg.setup(p, torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev) if cfg["c3"] else None,
                    [torch.from_numpy(v).to(dev) for v in nvs])
-    H = oracle_hierarchy(cfg, W, N, cfg["mass0"], nvs, coarse_op="block")
     for lvl in range(2, H.nlevels):
-        L = H.level_links(lvl)
+        L = Ls[lvl - 2]
         got = ctx.export(2, lvl).cpu().numpy().reshape(L.shape)
         err = rel_err(got, L)
         log(f"    level {lvl}: links rel err {err:.2e}")
@@ -445,4 +455,55 @@ def test_block_preconditioned_levels(torch, mg, name):
             y = y.to(torch.complex128).cpu().numpy()
             for k in range(2):
                 assert rel_err(y[k], want[k]) < tol, (lvl, dt, k)
+    ctx.destroy()
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_block_16bit_identity_self(torch, mg, fmt):
+    """16-bit stencil of block-preconditioned levels whose self block is the
+    identity (every coarse extent >= 2): the links of directions 1..8 are read
+    from the 16-bit fragments and the input is added in FP32.  Against the
+    oracle applying its preconditioned links rounded like the GPU's (fp16 with
+    the power-of-two scale) to inputs rounded to 16 bits, the identity term
+    unrounded, under the FP32 summation bound of test_coarse_mfma_16bit, at
+    n = 128 (site-dependent pass order) and n = 192, 1 to 70 rhs."""
+    cfg, W, N, nvs, H, Ls, rng = _block_case("prodblk")
+    dev = "cuda:0"
+    log(f"[block 16-bit] prodblk {fmt}")
+    cp = mg.MG_CBF16 if fmt == "bf16" else mg.MG_CF16
+    p = gpu_params(mg, cfg, max_nrhs=70, fine_prec=mg.MG_C64, coarse_prec=cp, coarse_op=1)
+    ctx = mg.setup(p, torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev),
+                   [torch.from_numpy(v).to(dev) for v in nvs])
+    rnd = ops.round_bf16 if fmt == "bf16" else ops.round_fp16
+    for lvl in range(2, H.nlevels):
+        L = Ls[lvl - 2].copy()
+        n = L.shape[-1]
+        assert np.max(np.abs(L[:, 0] - np.eye(n))) < 1e-12
+        hops = L.copy()
+        hops[:, 0] = 0.0
+        scale = 1.0
+        if fmt == "fp16":
+            amax = max(np.max(np.abs(L.real)), np.max(np.abs(L.imag)))   # the identity block included
+            scale = 2.0 ** (-np.round(np.log2(amax)))
+        Lr = (rnd(hops.real * scale) + 1j * rnd(hops.imag * scale)) / scale
+        La = np.abs(Lr.real) + np.abs(Lr.imag)
+        u = 2.0 ** -23
+        k2 = 2 * 8 * n
+        g = k2 * u / (1 - k2 * u)
+        cd = H.cdims[lvl - 2]
+        for nrhs in (1, 17, 64, 70):
+            x = latgen.complex_normal(rng, (nrhs,) + H.fine_shape(lvl)).astype(np.complex64)
+            log(f"[block 16-bit] {fmt} level {lvl} nrhs {nrhs}")
+            y = ctx.apply_coarse(lvl, torch.from_numpy(x).to(dev)).cpu().numpy().astype(np.complex128)
+            e_exact = 0.0
+            for r in range(nrhs):
+                xr = rnd(x[r].real) + 1j * rnd(x[r].imag)
+                want = ops.coarse_apply_links(Lr, cd, xr) + x[r].astype(np.complex128)
+                xa = np.abs(xr.real) + np.abs(xr.imag)
+                bound = g * ops.coarse_apply_links(La, cd, xa)
+                d = y[r] - want
+                lim = bound + 2.0 ** -23 * np.abs(want) + 1e-30
+                assert np.all(np.abs(d.real) <= lim) and np.all(np.abs(d.imag) <= lim), (lvl, nrhs, r)
+                e_exact = max(e_exact, rel_err(y[r], ops.coarse_apply_links(L, cd, x[r].astype(np.complex128))))
+            log(f"    worst rel err vs the unrounded FP64 operator: {e_exact:.2e}")
     ctx.destroy()

@@ -113,6 +113,79 @@ def test_fp64_block_kcycle_matches_oracle(torch, mg, cubic):
         f"galerkin: outer {info_g[0]['outer_iters']} levels {info_g[0]['level_iters']}")
 
 
+def test_fp64_cagcr_coarsest_matches_oracle(torch, mg, cubic):
+    """Coarsest level solved by CA-GCR(16) in a Chebyshev basis
+    (coarsest_solver 1, Table 1), with block-preconditioned coarse levels, all
+    FP64: a cycle computes the Krylov minimiser over K_16, as the oracle's
+    CA-GCR does by Arnoldi and least squares, so the K-cycles take the same
+    outer iterations (+-1) and the solutions agree within 2e-10 ||b|| / m."""
+    cfg, W, N, nvs, b = cubic
+    m = cfg["mass0"]
+    log("[solve] cubic fp64 CA-GCR(16) coarsest vs oracle")
+    ctx = make_ctx(torch, mg, cfg, W, N, nvs, fine_prec=mg.MG_C128, coarse_prec=mg.MG_C128, max_nrhs=1,
+                   coarse_op=1, coarsest_solver=1, coarsest_maxiter=16, coarsest_restarts=1)
+    x, info, st = ctx.solve([m], torch.from_numpy(b[:1]).to("cuda:0"), tol=1e-10)
+    x = x.cpu().numpy()[0, 0]
+    H = oracle_hierarchy(cfg, W, N, m, nvs, coarse_op="block", coarsest_solver="cagcr", coarsest_maxiter=16,
+                         coarsest_cycles=1)
+    xo, io = H.solve(b[0], tol=1e-10)
+    assert io.converged
+    log(f"    outer {info[0]['outer_iters']} (oracle {io.iters}), levels {info[0]['level_iters']}")
+    assert abs(info[0]["outer_iters"] - io.iters) <= 1, (info[0], io.iters)
+    assert true_rel(cfg, W, N, m, x, b[0]) <= 1e-10
+    assert np.linalg.norm(x - xo) <= 2e-10 * np.linalg.norm(b[0]) / m
+
+
+def test_cagcr_coarsest_lockstep_bf16(torch, mg, cubic):
+    """CA-GCR(16) coarsest solver with FP32 vectors and 16-bit links in a
+    16 rhs x 2 masses lockstep solve (two restart cycles): every system
+    reaches 1e-10 on the oracle's true residual."""
+    cfg, W, N, nvs, _ = cubic
+    masses = [0.05, 0.11]
+    rng = np.random.default_rng(4323)
+    b = latgen.fine_vectors(cfg["dims"], 16, rng)
+    log("[solve] cubic 16 rhs x 2 masses bf16, CA-GCR(16) coarsest")
+    ctx = make_ctx(torch, mg, cfg, W, N, nvs, max_nrhs=32, max_nmass=2, coarse_prec=mg.MG_CBF16, coarse_op=1,
+                   coarsest_solver=1, coarsest_maxiter=16, coarsest_restarts=2)
+    x, info, st = ctx.solve(masses, torch.from_numpy(b).to("cuda:0"), tol=1e-10)
+    x = x.cpu().numpy()
+    for j, m in enumerate(masses):
+        for r in range(16):
+            assert info[j * 16 + r]["status"] == "MG_OK"
+            assert true_rel(cfg, W, N, m, x[j, r], b[r]) <= 1e-10, (m, r)
+    log(f"    outer iterations {[i['outer_iters'] for i in info]}, levels {info[0]['level_iters']}")
+
+
+def test_graph_coarsest_replays_match_eager(torch, mg, cubic):
+    """The coarsest solve captured into a HIP graph (graph_coarsest 1, one
+    CA-GCR cycle) and replayed: three solves of the same batch on one
+    context, with eager work and synchronisations between them, each equal
+    bit for bit to the solve of a context that launches eagerly; every
+    system at true residual 1e-10."""
+    cfg, W, N, nvs, _ = cubic
+    masses = [0.05, 0.11]
+    rng = np.random.default_rng(4324)
+    b = latgen.fine_vectors(cfg["dims"], 16, rng)
+    bt = torch.from_numpy(b).to("cuda:0")
+    kw = dict(max_nrhs=32, max_nmass=2, coarse_prec=mg.MG_CBF16, coarse_op=1, coarsest_solver=1,
+              coarsest_maxiter=16, coarsest_restarts=1)
+    log("[graph] eager reference")
+    ctx_e = make_ctx(torch, mg, cfg, W, N, nvs, graph_coarsest=0, **kw)
+    xe, ie, _ = ctx_e.solve(masses, bt, tol=1e-10)
+    xe = xe.cpu().numpy()
+    ctx_g = make_ctx(torch, mg, cfg, W, N, nvs, graph_coarsest=1, **kw)
+    for rep in range(3):
+        log(f"[graph] replay {rep}")
+        xg, ig, _ = ctx_g.solve(masses, bt, tol=1e-10)
+        assert np.array_equal(xg.cpu().numpy(), xe), rep
+        assert [i["outer_iters"] for i in ig] == [i["outer_iters"] for i in ie]
+        ctx_g.apply_dslash(0, 0.1, bt)   # eager work between the replays
+        torch.cuda.synchronize()
+    for j, m in enumerate(masses):
+        for r in range(16):
+            assert true_rel(cfg, W, N, m, xe[j, r], b[r]) <= 1e-10, (m, r)
+
+
 def test_block_lockstep_bf16(torch, mg, cubic):
     """Block-preconditioned coarse levels with 16-bit links (the links
     multiplied by X^{-1} before rounding) in a 16 rhs x 2 masses lockstep

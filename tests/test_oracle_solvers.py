@@ -350,3 +350,23 @@ def test_block_preconditioned_solve_same_solution():
     x_gal = np.linalg.solve(Ag, bc.reshape(-1))
     assert np.linalg.norm(x_block - x_gal) <= 1e-10 * np.linalg.norm(x_gal)
     assert np.linalg.norm(xs["block"] - xs["galerkin"]) <= 2e-10 * np.linalg.norm(b) / m
+
+
+def test_cagcr_cycle_is_gcr_of_the_same_length():
+    """A CA-GCR(s) cycle is the Krylov minimiser over K_s(A, r): on a small
+    non-Hermitian system it equals s steps of the oracle's GCR from zero (no
+    restart within the cycle) and the dense least-squares minimiser over the
+    explicit Krylov basis; restarted cycles reach a tight tolerance."""
+    rng = np.random.default_rng(5)
+    n, s = 60, 8
+    A = np.eye(n) + 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    op = lambda v: A @ v
+    x1 = sol.cagcr(op, b, s, 0.0, 1)
+    xg, _ = sol.gcr(op, b, None, 0.0, s, s)
+    K = np.stack([np.linalg.matrix_power(A, j) @ b for j in range(s)], axis=1)
+    y = np.linalg.lstsq(A @ K, b, rcond=None)[0]
+    assert np.linalg.norm(x1 - xg) < 1e-10 * np.linalg.norm(xg)
+    assert np.linalg.norm(x1 - K @ y) < 1e-8 * np.linalg.norm(x1)
+    x = sol.cagcr(op, b, s, 1e-12, 50)
+    assert np.linalg.norm(b - A @ x) <= 1e-12 * np.linalg.norm(b)
