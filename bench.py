@@ -445,8 +445,34 @@ def uneven_bench(args, wl, torch, latgen, mg):
         ctx.apply_dslash(2, m, xk)   # the KD inverse of the mass, outside the timed solves
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
-        log(f"[bench] uneven {dims}: setup {setup_s:.2f} s")
-        probs.append({"dims": dims, "ctx": ctx, "b": b, "setup_s": setup_s})
+        tune = ctx.autotune(nr) if cp != mg.MG_C64 else []
+        log(f"[bench] uneven {dims}: setup {setup_s:.2f} s, coarse tiles {tune}")
+        probs.append({"dims": dims, "ctx": ctx, "b": b, "setup_s": setup_s, "tune": tune})
+    coarse_multi = None
+    if cp != mg.MG_C64:
+        # the four lattices' level-2 operators: one launch each against one persistent launch over
+        # their common (lattice, site, rhs tile) work list
+        xs = [torch.randn((nr,) + pr["ctx"].coarse_shapes[0], dtype=torch.complex64, device=dev) for pr in probs]
+        ys = [torch.empty_like(x) for x in xs]
+        ctxs = [pr["ctx"] for pr in probs]
+
+        def timed(f, reps=20):
+            f()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                f()
+            e1.record()
+            e1.synchronize()
+            return e0.elapsed_time(e1) * 1e3 / reps
+
+        sep_us = timed(lambda: [c.apply_coarse(2, x, y) for c, x, y in zip(ctxs, xs, ys)])
+        multi_us = timed(lambda: mg.apply_coarse_multi(ctxs, 2, xs, ys))
+        coarse_multi = {"separate_launches_us": sep_us, "one_persistent_launch_us": multi_us}
+        log(f"[bench] level-2 operators of the four lattices: {sep_us:.1f} us in four launches, "
+            f"{multi_us:.1f} us in one persistent launch")
+        del xs, ys
     for pr in probs:   # warm-up solve of each lattice
         pr["ctx"].solve([m], pr["b"], tol=1e-10)
     torch.cuda.synchronize()
@@ -493,8 +519,9 @@ def uneven_bench(args, wl, torch, latgen, mg):
                                   f"{nr} rhs each, truncated-KD={not wl['kd_naik']}, KD + 4^4/Nvec {wl['nvec'][0]}, "
                                   f"coarse links {args.coarse_prec or wl.get('coarse_prec', 'fp32')}"},
            "sequential_s": seq_s, "systems_per_s_concurrent": nsys / conc_s, "systems_per_s_sequential": nsys / seq_s,
-           "per_lattice": [{"dims": list(p["dims"]), "setup_s": p["setup_s"], "alone": a, "concurrent": c}
-                           for p, a, c in zip(probs, seq, conc)]}
+           "per_lattice": [{"dims": list(p["dims"]), "setup_s": p["setup_s"], "coarse_tiles": p["tune"],
+                            "alone": a, "concurrent": c} for p, a, c in zip(probs, seq, conc)],
+           "coarse_level2_multi": coarse_multi}
     print(json.dumps(out), flush=True)
 
 
@@ -612,6 +639,9 @@ def c2batch_bench(args, wl, torch, latgen, mg, out):
     setup_s = time.perf_counter() - t0
     out["setup_s"] = setup_s
     log(f"[bench] setup {setup_s:.2f} s")
+    if cprec != "fp32":   # tile shapes of the 16-bit coarse stencil at the batch's rhs count
+        out["autotune"] = ctx.autotune(nr * mb)
+        log(f"[bench] coarse tiles {out['autotune']}")
 
     if args.kernels_only:
         kern = kernel_rates(torch, ctx, wl, args.kernel_reps, mg, 8 if cprec == "fp32" else 4)

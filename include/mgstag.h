@@ -115,6 +115,9 @@ typedef struct {
   int32_t graph_coarsest;    /* 1: with coarsest_solver 1 and coarsest_restarts 1 the coarsest solve (a fixed
                                 launch sequence) is captured once per system count into a HIP graph and
                                 replayed (results identical to the eager launches); 0: always eager */
+  int32_t compact_masses;    /* 1: in a multi-mass batch the K-cycle runs only on the masses with a system
+                                still iterating (whole masses leave the preconditioner's batch once all their
+                                right-hand sides have converged; results unchanged); 0: on every system */
   uint64_t seed;             /* seed of the GPU-generated null-vector starts */
 } mg_params;
 
@@ -283,6 +286,36 @@ mg_status mg_update_links(mg_ctx ctx, const void* fat, const void* naik, void* s
  * Returns the needed size in *bytes_needed when dst is NULL. */
 mg_status mg_export(mg_ctx ctx, int32_t what, int32_t level, void* dst, size_t bytes, size_t* bytes_needed,
                     void* stream);
+
+/* Coarse operators of several contexts in one persistent launch (the batch of
+ * uneven problems): applies the level-`level` operator of ctxs[p] to in[p]
+ * (device, MG_C64, nrhs[p] vectors of that context's level) into out[p], for
+ * nprob <= 8 contexts whose level has 16-bit links of the same format and the
+ * same 2 Nvec.  The workgroups walk one (problem, coarse site, 16-rhs tile)
+ * work list with a grid-sized stride, so small lattices that could not fill
+ * the device alone share it.  Results equal those of mg_apply_coarse with 16
+ * rhs per workgroup.  Asynchronous on `stream`. */
+mg_status mg_apply_coarse_multi(const mg_ctx* ctxs, int32_t nprob, int32_t level, const void* const* in,
+                                void* const* out, const int32_t* nrhs, void* stream);
+
+/* Tile-shape autotuner of the 16-bit coarse stencil (coarse_prec MG_CBF16 /
+ * MG_CF16): for every coarse level, times each tile shape the kernel is
+ * built for (16, 32 or 64 right-hand sides per workgroup x 1 or 2 16-row
+ * m-tiles per wavefront) on nrhs (1..max_nrhs) random vectors of the
+ * context's solver scratch, 2 untimed and 5 timed launches each with HIP
+ * events on `stream`, and keeps the fastest for every later application with
+ * a right-hand-side count in the same class (<= 16, 17..32, > 32).  info
+ * (host, 2 entries, may be NULL) receives per level the shape chosen, its
+ * time and that of the built-in choice.  Results are unchanged by the tile
+ * shape up to FP32 summation order.  Synchronises the stream. */
+typedef struct {
+  int32_t level;             /* 2 or 3 (0: entry unused) */
+  int32_t nrhs;
+  int32_t rhs_per_workgroup, mtiles_per_wave;
+  int32_t candidates;        /* shapes timed */
+  double us_best, us_default;
+} mg_tune_info;
+mg_status mg_autotune(mg_ctx ctx, int32_t nrhs, mg_tune_info* info, void* stream);
 
 /* Kernel timing (a measurement aid, not part of the method): between
  * mg_profile_start and mg_profile_stop every launch of one operator is

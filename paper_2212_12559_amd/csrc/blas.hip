@@ -70,16 +70,24 @@ __global__ void __launch_bounds__(256) pairdot_kernel(const PairDotArgs<T> a, do
   }
 }
 
-// res[p][r] = (sum of partials) (+ scale)
-__global__ void finalize_kernel(const double2* __restrict__ part, int nblk, int np, int nrhs,
-                                double2* __restrict__ res, int ldr) {
-  const int r = blockIdx.x;
-  for (int p = threadIdx.x; p < np; p += blockDim.x) {
-    const double2* s = part + ((int64_t)p * nrhs + r) * nblk;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int b = 0; b < nblk; ++b) { acc.x += s[b].x; acc.y += s[b].y; }
-    res[(int64_t)p * ldr + r] = acc;
-  }
+// res[p][r] = sum of the nblk partials of product p, system r: one
+// wavefront per (p, r), lanes over the partials, then a shuffle tree (a fixed
+// order for a given nblk)
+__global__ void __launch_bounds__(256) finalize_kernel(const double2* __restrict__ part, int nblk, int np, int nrhs,
+                                                       double2* __restrict__ res, int ldr) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= (int64_t)np * nrhs) return;
+  const int lane = threadIdx.x & 63;
+  const int p = (int)(q / nrhs), r = (int)(q - (int64_t)p * nrhs);
+  const double2* s = part + ((int64_t)p * nrhs + r) * nblk;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int b = lane; b < nblk; b += 64) { acc.x += s[b].x; acc.y += s[b].y; }
+  const double sx = wsum(acc.x), sy = wsum(acc.y);
+  if (lane == 0) res[(int64_t)p * ldr + r] = make_double2(sx, sy);
+}
+static void launch_finalize(const double2* part, int nblk, int np, int nrhs, double2* res, int ldr, hipStream_t st) {
+  const int64_t nq = (int64_t)np * nrhs;
+  finalize_kernel<<<(unsigned)((nq + 3) / 4), 256, 0, st>>>(part, nblk, np, nrhs, res, ldr);
 }
 
 int reduce_blocks(int64_t n) {
@@ -96,7 +104,7 @@ void launch_pairdot(const PairDotArgs<T>& a, double2* part, double2* res, int ld
   if (a.np <= 4) pairdot_kernel<T, 4><<<grid, 256, 0, st>>>(a, part, nblk);
   else if (a.np <= 18) pairdot_kernel<T, 18><<<grid, 256, 0, st>>>(a, part, nblk);
   else pairdot_kernel<T, kMaxPairs><<<grid, 256, 0, st>>>(a, part, nblk);
-  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, a.np, a.nrhs, res, ldr);
+  launch_finalize(part, nblk, a.np, a.nrhs, res, ldr, st);
 }
 template void launch_pairdot<float2>(const PairDotArgs<float2>&, double2*, double2*, int, hipStream_t);
 template void launch_pairdot<double2>(const PairDotArgs<double2>&, double2*, double2*, int, hipStream_t);
@@ -215,7 +223,7 @@ void launch_gcr_update(T* x, T* r, T* q, T* z, const double2* alpha, const doubl
   const int nblk = reduce_blocks(n);
   dim3 grid(nblk, nrhs);
   gcr_update_kernel<T><<<grid, 256, 0, st>>>(x, r, q, z, alpha, inv, n, part, nblk, nrhs);
-  finalize_kernel<<<nrhs, 64, 0, st>>>(part, nblk, 1, nrhs, res, ldr);
+  launch_finalize(part, nblk, 1, nrhs, res, ldr, st);
 }
 template void launch_gcr_update<float2>(float2*, float2*, float2*, float2*, const double2*, const double2*, int64_t,
                                         int, double2*, double2*, int, hipStream_t);
@@ -257,7 +265,7 @@ void launch_cg_update(double2* x, double2* r, const double2* p, const double2* a
   const int nblk = reduce_blocks(n);
   dim3 grid(nblk, nrhs);
   cg_update_kernel<<<grid, 256, 0, st>>>(x, r, p, ap, alpha, n, part, nblk);
-  finalize_kernel<<<nrhs, 64, 0, st>>>(part, nblk, 1, nrhs, res, ldr);
+  launch_finalize(part, nblk, 1, nrhs, res, ldr, st);
 }
 
 // ------------------------------------------------------------ CA-GCR Gram
@@ -386,16 +394,15 @@ __global__ void __launch_bounds__(1024) gram16_kernel(const GramArgs<T> a, doubl
   const int64_t step = (int64_t)nblk * 256;
   for (int64_t e0 = (int64_t)blockIdx.x * 256; e0 < a.n; e0 += step) {
     __syncthreads();
-    if (threadIdx.x < 128) {
-      const int64_t e = e0 + 2 * threadIdx.x;
-      const int el = 2 * threadIdx.x;
-      for (int i = 0; i <= S; ++i) {
-        const int src = i < S ? i : s;
-        T va = from_d2<T>(make_double2(0.0, 0.0)), vb = va;
-        if ((i < s || i == S) && e < a.n) ldraw(a.u[src], off + e, va, vb);
-        us[i][el] = va;
-        us[i][el + 1] = vb;
-      }
+    // every thread stages: (vector, element pair) pieces, 16 bytes each for FP32
+    for (int q = threadIdx.x; q < (S + 1) * 128; q += 64 * NW) {
+      const int i = q >> 7, el = 2 * (q & 127);
+      const int64_t e = e0 + el;
+      const int src = i < S ? i : s;
+      T va = from_d2<T>(make_double2(0.0, 0.0)), vb = va;
+      if ((i < s || i == S) && e < a.n) ldraw(a.u[src], off + e, va, vb);
+      us[i][el] = va;
+      us[i][el + 1] = vb;
     }
     __syncthreads();
 #pragma unroll 1
@@ -421,7 +428,7 @@ void launch_gram(const GramArgs<T>& a, double2* part, double2* res, int ldr, hip
   if (a.s <= kMaxS) gram_kernel<T, kMaxS, 4><<<dim3(nblk, a.nrhs), 256, 0, st>>>(a, part, nblk);
   else if (a.s <= kMaxCA) gram16_kernel<T><<<dim3(nblk, a.nrhs), 1024, 0, st>>>(a, part, nblk);
   else throw std::runtime_error("gram: at most 16 basis vectors");
-  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, a.s * (a.s + 1) / 2 + a.s, a.nrhs, res, ldr);
+  launch_finalize(part, nblk, a.s * (a.s + 1) / 2 + a.s, a.nrhs, res, ldr, st);
 }
 template void launch_gram<float2>(const GramArgs<float2>&, double2*, double2*, int, hipStream_t);
 template void launch_gram<double2>(const GramArgs<double2>&, double2*, double2*, int, hipStream_t);
@@ -509,7 +516,7 @@ void launch_gcr_dots(const GcrDotArgs<T>& a, double2* part, double2* res, int ld
   if (b > 480) b = 480;
   const int nblk = (int)b;
   gcr_dots_kernel<T, CH><<<dim3(nblk, a.nrhs), 256, 0, st>>>(a, part, nblk);
-  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, 2 * a.k + 2, a.nrhs, res, ldr);
+  launch_finalize(part, nblk, 2 * a.k + 2, a.nrhs, res, ldr, st);
 }
 template void launch_gcr_dots<float2>(const GcrDotArgs<float2>&, double2*, double2*, int, hipStream_t);
 template void launch_gcr_dots<double2>(const GcrDotArgs<double2>&, double2*, double2*, int, hipStream_t);
@@ -599,7 +606,7 @@ void launch_gcr_update_cgs(const GcrUpdArgs<T>& a, double2* part, double2* res, 
   dim3 grid(nblk, a.nrhs);
   if (a.k <= 4) gcr_update_cgs_kernel<T, 4><<<grid, 256, 0, st>>>(a, part, nblk);
   else gcr_update_cgs_kernel<T, kMaxNK><<<grid, 256, 0, st>>>(a, part, nblk);
-  finalize_kernel<<<a.nrhs, 64, 0, st>>>(part, nblk, 1, a.nrhs, res, ldr);
+  launch_finalize(part, nblk, 1, a.nrhs, res, ldr, st);
 }
 template void launch_gcr_update_cgs<float2>(const GcrUpdArgs<float2>&, double2*, double2*, int, hipStream_t);
 template void launch_gcr_update_cgs<double2>(const GcrUpdArgs<double2>&, double2*, double2*, int, hipStream_t);

@@ -137,6 +137,7 @@ void mg_default_params(mg_params* p, const int32_t dims[4]) {
   p->coarse_op = 1;   // Table 1: preconditioned coarse operators on levels 2 and 3
   p->coarsest_solver = 1;   // Table 1: Chebyshev-basis CA-GCR(16) on the coarsest level
   p->graph_coarsest = 1;
+  p->compact_masses = 1;
   p->seed = 20221224ull;
 }
 
@@ -367,6 +368,50 @@ mg_status mg_export(mg_ctx ctx, int32_t what, int32_t level, void* dst, size_t b
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw Error{MG_E_HIP, hipGetErrorString(e)};
   });
+}
+
+mg_status mg_apply_coarse_multi(const mg_ctx* ctxs, int32_t nprob, int32_t level, const void* const* in,
+                                void* const* out, const int32_t* nrhs, void* stream) {
+  if (!ctxs || !in || !out || !nrhs) return fail(MG_E_ARG, "null argument");
+  if (nprob < 1 || nprob > kMaxMulti) return fail(MG_E_ARG, "nprob must be in 1..8");
+  CoarseMultiArgs m{};
+  int fmt = -1;
+  int64_t start = 0;
+  for (int p = 0; p < nprob; ++p) {
+    if (!ctxs[p]) return fail(MG_E_ARG, "null context");
+    Ctx& c = ctxs[p]->c;
+    if (level < 2 || level > 1 + c.P.nagg) return fail(MG_E_ARG, "level must be 2..1+nagg of every context");
+    if (c.fmt16 < 0) return fail(MG_E_ARG, "every context needs 16-bit coarse links");
+    if (fmt >= 0 && c.fmt16 != fmt) return fail(MG_E_ARG, "contexts must share the 16-bit format");
+    fmt = c.fmt16;
+    const int l = level - 2;
+    if (p > 0 && c.ncoarse[l] != m.p[0].n) return fail(MG_E_ARG, "contexts must share 2 Nvec on the level");
+    mg_status s = check_vec(MG_C64, in[p], out[p], nrhs[p], c.P.max_nrhs);
+    if (s != MG_OK) return s;
+    CoarseMfmaArgs& a = m.p[p];
+    a.out = (float2*)out[p]; a.in = (const float2*)in[p]; a.links = c.cl16[l];
+    a.g = c.gc[l]; a.n = c.ncoarse[l]; a.in_stride = a.out_stride = c.gc[l].V * c.ncoarse[l]; a.nrhs = nrhs[p];
+    a.inv_scale = c.cl16_inv_scale[l];
+    a.unit_self = c.unit_self[l] ? 1 : 0;
+    m.start[p] = start;
+    start += c.gc[l].V * ((nrhs[p] + 15) / 16);
+  }
+  m.start[nprob] = start;
+  m.nprob = nprob;
+  return guarded([&] {
+    launch_coarse_mfma_multi(m, fmt, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error{MG_E_HIP, hipGetErrorString(e)};
+  });
+}
+
+mg_status mg_autotune(mg_ctx ctx, int32_t nrhs, mg_tune_info* info, void* stream) {
+  if (!ctx) return fail(MG_E_ARG, "null context");
+  Ctx& c = ctx->c;
+  if (nrhs < 1 || nrhs > c.P.max_nrhs) return fail(MG_E_ARG, "nrhs out of range (1..max_nrhs)");
+  c.st = (hipStream_t)stream;
+  if (info) std::memset(info, 0, 2 * sizeof(mg_tune_info));
+  return guarded([&] { c.autotune(nrhs, info); });
 }
 
 mg_status mg_profile_start(mg_ctx ctx, int32_t op, int32_t level) {

@@ -13,6 +13,7 @@
 // round-to-nearest-even) is staged in LDS as [rhs][k] planes, read with the
 // same k mapping.  FP16 links carry a power-of-two scale
 // (2^-round(log2 max|L|)) undone on the FP32 result.
+#include <algorithm>
 #include <stdexcept>
 
 #include "kernels.hpp"
@@ -121,21 +122,21 @@ void launch_absmax(const double2* v, int64_t n, unsigned long long* out, hipStre
 constexpr int kMfmaCK = 4;
 constexpr int kMfmaMaxWaves = 16;
 
+// The work of one workgroup: coarse site `site`, right-hand sides r0 ..
+// r0 + 16 RT - 1 (bsm: the B staging area, nbs: the neighbour table, both in
+// LDS).
 template <int FMT, int RT, int MT>
-__global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const CoarseMfmaArgs a) {
+__device__ __forceinline__ void coarse_mfma_site(const CoarseMfmaArgs& a, const int64_t site, const int r0,
+                                                 uint16_t* bsm, int64_t* nbs) {
   constexpr int NR = 16 * RT;          // right-hand sides per workgroup
   constexpr int KCH = kMfmaCK * 32;    // k per staging pass
   constexpr int KPC = KCH + 8;         // padded LDS row: staggers banks between rhs rows
-  extern __shared__ uint16_t bsm[];    // [2 planes][NR][KPC]
-  __shared__ int64_t nbs[9];
   uint16_t* Bre = bsm;
   uint16_t* Bim = bsm + NR * KPC;
   const int n = a.n;
   const int K = 9 * n;
   const int kc_n = (K + 31) / 32;
   const int mt_n = n / 16;
-  const int64_t site = xcd_block(blockIdx.x, gridDim.x);
-  const int r0 = blockIdx.y * NR;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nthreads = blockDim.x;
   const int nw = mt_n / MT;            // wavefronts; this one owns m-tiles wave + nw m
@@ -254,6 +255,48 @@ __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const C
 }
 
 template <int FMT, int RT, int MT>
+__global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const CoarseMfmaArgs a) {
+  extern __shared__ uint16_t bsm[];    // [2 planes][16 RT][KCH + 8]
+  __shared__ int64_t nbs[9];
+  coarse_mfma_site<FMT, RT, MT>(a, xcd_block(blockIdx.x, gridDim.x), blockIdx.y * 16 * RT, bsm, nbs);
+}
+
+// One persistent launch over the (problem, site, rhs tile) work list of up to
+// kMaxMulti problems of the same n and link format: each workgroup walks the
+// list with a grid-sized stride.
+template <int FMT, int RT, int MT>
+__global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_multi_kernel(const CoarseMultiArgs m) {
+  extern __shared__ uint16_t bsm[];
+  __shared__ int64_t nbs[9];
+  for (int64_t item = blockIdx.x; item < m.start[m.nprob]; item += gridDim.x) {
+    int p = 0;
+    while (item >= m.start[p + 1]) ++p;
+    const int64_t li = item - m.start[p];
+    const int ntile = (m.p[p].nrhs + 16 * RT - 1) / (16 * RT);
+    __syncthreads();   // the previous item is done with the LDS
+    coarse_mfma_site<FMT, RT, MT>(m.p[p], li / ntile, (int)(li % ntile) * 16 * RT, bsm, nbs);
+  }
+}
+
+void launch_coarse_mfma_multi(const CoarseMultiArgs& m, int fmt, hipStream_t st) {
+  if (m.nprob < 1 || m.nprob > kMaxMulti) throw std::runtime_error("coarse_mfma_multi: 1..8 problems");
+  const int n = m.p[0].n;
+  for (int p = 0; p < m.nprob; ++p) {
+    if (m.p[p].n != n) throw std::runtime_error("coarse_mfma_multi: problems must share n");
+    if (reinterpret_cast<uintptr_t>(m.p[p].in) % 16 || m.p[p].in_stride % 2)
+      throw std::runtime_error("coarse_mfma_multi: inputs must be 16-byte aligned");
+    if (m.p[p].unit_self && n % 32) throw std::runtime_error("coarse_mfma_multi: implicit identity needs n % 32 == 0");
+  }
+  if (n % 16 || n < 16 || n > 16 * kMfmaMaxWaves) throw std::runtime_error("coarse_mfma_multi: n in 16..256");
+  const int64_t total = m.start[m.nprob];
+  if (total <= 0) return;
+  const size_t lds = (size_t)2 * 16 * (kMfmaCK * 32 + 8) * sizeof(uint16_t);
+  const unsigned grid = (unsigned)std::min<int64_t>(total, 1024);
+  if (fmt == 0) coarse_mfma_multi_kernel<0, 1, 1><<<grid, 64 * (n / 16), lds, st>>>(m);
+  else coarse_mfma_multi_kernel<1, 1, 1><<<grid, 64 * (n / 16), lds, st>>>(m);
+}
+
+template <int FMT, int RT, int MT>
 static void coarse_mfma_launch(const CoarseMfmaArgs& a, hipStream_t st) {
   const int mt_n = a.n / 16;
   const size_t lds = (size_t)2 * 16 * RT * (kMfmaCK * 32 + 8) * sizeof(uint16_t);
@@ -263,6 +306,20 @@ static void coarse_mfma_launch(const CoarseMfmaArgs& a, hipStream_t st) {
 
 template <int FMT>
 static void coarse_mfma_dispatch(const CoarseMfmaArgs& a, hipStream_t st) {
+  if (a.rt > 0) {   // an explicit tile shape (autotuned)
+    const int mt_n = a.n / 16;
+    if (a.mt < 1 || mt_n % a.mt) throw std::runtime_error("coarse_mfma: m-tiles per wavefront must divide n / 16");
+    const int key = a.rt * 8 + a.mt;
+    switch (key) {
+      case 9: coarse_mfma_launch<FMT, 1, 1>(a, st); return;
+      case 10: coarse_mfma_launch<FMT, 1, 2>(a, st); return;
+      case 17: coarse_mfma_launch<FMT, 2, 1>(a, st); return;
+      case 18: coarse_mfma_launch<FMT, 2, 2>(a, st); return;
+      case 33: coarse_mfma_launch<FMT, 4, 1>(a, st); return;
+      case 34: coarse_mfma_launch<FMT, 4, 2>(a, st); return;
+      default: throw std::runtime_error("coarse_mfma: no such tile shape");
+    }
+  }
   // two m-tiles per wavefront once several rhs tiles share the B reads
   const bool mt2 = a.nrhs > 16 && (a.n / 16) % 2 == 0;
   if (a.nrhs <= 16) coarse_mfma_launch<FMT, 1, 1>(a, st);

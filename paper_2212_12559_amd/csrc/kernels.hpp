@@ -120,8 +120,21 @@ struct CoarseMfmaArgs {
   int nrhs;
   float inv_scale;
   int unit_self;            // the self block is the identity: skip its links, add the input instead (n % 32 == 0)
+  int rt, mt;               // tile shape: 16 rt rhs per workgroup, mt m-tiles per wavefront (0, 0: by rhs count)
 };
+// tile shapes the 16-bit coarse stencil is built for (rt, mt)
+constexpr int kCoarseTiles[6][2] = {{1, 1}, {1, 2}, {2, 1}, {2, 2}, {4, 1}, {4, 2}};
 void launch_coarse_mfma(const CoarseMfmaArgs& a, int fmt, hipStream_t st);   // fmt 0 bf16, 1 fp16
+// several problems' 16-bit stencils (same n and format, 16 rhs per workgroup)
+// in one persistent launch over their (problem, site, rhs tile) work list;
+// start[p] is the first item of problem p, start[nprob] the total
+constexpr int kMaxMulti = 8;
+struct CoarseMultiArgs {
+  CoarseMfmaArgs p[kMaxMulti];
+  int64_t start[kMaxMulti + 1];
+  int nprob;
+};
+void launch_coarse_mfma_multi(const CoarseMultiArgs& m, int fmt, hipStream_t st);
 template <typename TI>
 void launch_swizzle_links(const TI* cl, uint16_t* out, int64_t nsite, int n, int fmt, double scale,
                           hipStream_t st);

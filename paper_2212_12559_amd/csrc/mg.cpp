@@ -48,6 +48,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   if (p.coarse_op != 0 && p.coarse_op != 1) return fail("coarse_op must be 0 (Galerkin) or 1 (block-preconditioned)");
   if (p.coarsest_solver != 0 && p.coarsest_solver != 1) return fail("coarsest_solver must be 0 (GCR) or 1 (CA-GCR)");
   if (p.graph_coarsest != 0 && p.graph_coarsest != 1) return fail("graph_coarsest must be 0 or 1");
+  if (p.compact_masses != 0 && p.compact_masses != 1) return fail("compact_masses must be 0 or 1");
   const bool naik_kd = p.c3 != 0.0 && p.kd_naik;
   Geom g0{};
   g0.V = 1;
@@ -148,9 +149,9 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   void* part = S(part_elems * 16);
   void* scal = S((size_t)4 * kMaxSlots * ms * 16);
   void* tri = S((size_t)4 * kTriSlots * ms * 16);
-  void* m64 = S((size_t)ms * 8);
-  void* m32 = S((size_t)ms * 4);
-  void* mask = S((size_t)4 * ms * 4);
+  void* m64 = S((size_t)2 * ms * 8);    // per-system masses of the batch, then of the K-cycle's systems
+  void* m32 = S((size_t)2 * ms * 4);
+  void* mask = S((size_t)5 * ms * 4);   // levels 0..3, then level 0 of a compacted K-cycle
   void* dcoef = kd > 0 ? S((size_t)kd * ms * 16) : nullptr;
   const size_t solver_base = scr.off;
   // solver buffers
@@ -361,6 +362,8 @@ void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, b
     a.g = gc[l]; a.n = n; a.in_stride = a.out_stride = gc[l].V * n; a.nrhs = nsys;
     a.inv_scale = cl16_inv_scale[l];
     a.unit_self = unit_self[l] ? 1 : 0;
+    a.rt = tune[l][rhs_class(nsys)][0];
+    a.mt = tune[l][rhs_class(nsys)][1];
     launch_coarse_mfma(a, fmt16, st);
   } else {
     CoarseArgs<float, float2> a{};
@@ -414,11 +417,13 @@ void Ctx::prolong_(int lvl, int prec, void* out, const void* in, int nsys, bool 
 
 // A_lvl on a batch: level 0 D(m_s), level 1 (B + m_s)^{-1} D(m_s), coarse levels
 void Ctx::apply_level(int lvl, const Vec& out, const Vec& in, int nsys) {
+  // inside a compacted K-cycle the systems are those of the active masses
+  const int64_t mo = kc_compact ? max_sys : 0;
+  const void* m = in.prec == P64 ? (const void*)(mass64 + mo) : (const void*)(mass32 + mo);
   if (lvl == 0) {
-    apply_D(in.prec, out.p, in.p, nsys, true, in.prec == P64 ? (const void*)mass64 : (const void*)mass32, 0.0);
+    apply_D(in.prec, out.p, in.p, nsys, true, m, 0.0);
   } else if (lvl == 1) {
-    apply_D(in.prec, L[1].tmp.p, in.p, nsys, P.kd_naik != 0,
-            in.prec == P64 ? (const void*)mass64 : (const void*)mass32, 0.0);
+    apply_D(in.prec, L[1].tmp.p, in.p, nsys, P.kd_naik != 0, m, 0.0);
     apply_KD(in.prec, out.p, L[1].tmp.p, nsys, false, false, rhs_per_slot);
   } else {
     apply_coarse(lvl, in.prec, out.p, in.p, nsys, false);
@@ -545,8 +550,24 @@ void Ctx::smoother(int lvl, const Vec& e, const Vec& t, int nsys) {
 // level to its tolerance, prolong, post-smooth)
 void Ctx::kcycle(int lvl, const Vec& r, const Vec& e, int nsys, SolveStats& stats) {
   if (lvl == 0) {
+    // only the masses with a system still iterating (kc_groups, nrhs systems
+    // each) enter the K-cycle; their residuals are gathered, the result
+    // scattered back and the other systems' directions left zero
+    const bool compact = !kc_groups.empty();
+    const int nall = nsys;
+    if (compact) {
+      const int64_t per = (int64_t)kc_nrhs * r.n;
+      for (size_t ci = 0; ci < kc_groups.size(); ++ci) {
+        Vec src{(char*)r.p + (size_t)kc_groups[ci] * per * csize(r.prec), r.prec, r.n};
+        Vec dst{(char*)r0s.p + (size_t)ci * per * csize(r0s.prec), r0s.prec, r0s.n};
+        copy(dst, src, kc_nrhs);
+      }
+      nsys = (int)kc_groups.size() * kc_nrhs;
+      kc_compact = true;
+    } else {
+      copy(r0s, r, nsys);
+    }
     // level 0 -> 1: r1 = (B + m)^{-1} r (in the fine precision), e0 = e1
-    copy(r0s, r, nsys);
     apply_KD(r0s.prec, L[1].b.p, r0s.p, nsys, false, false, rhs_per_slot);
     level_solve(1, nsys, stats);
     copy(e0s, L[1].x, nsys);
@@ -554,7 +575,18 @@ void Ctx::kcycle(int lvl, const Vec& r, const Vec& e, int nsys, SolveStats& stat
     apply_level(0, L[0].t, e0s, nsys);
     lincomb(r0s.prec, r0s.n, nsys, L[0].t.p, {{r0s.p, nullptr}, {L[0].t.p, nullptr}}, {0, 1}, {});
     smoother(0, e0s, L[0].t, nsys);
-    copy(e, e0s, nsys);
+    if (compact) {
+      kc_compact = false;
+      zero(e, nall);
+      const int64_t per = (int64_t)kc_nrhs * e.n;
+      for (size_t ci = 0; ci < kc_groups.size(); ++ci) {
+        Vec dst{(char*)e.p + (size_t)kc_groups[ci] * per * csize(e.prec), e.prec, e.n};
+        Vec src{(char*)e0s.p + (size_t)ci * per * csize(e0s.prec), e0s.prec, e0s.n};
+        copy(dst, src, kc_nrhs);
+      }
+    } else {
+      copy(e, e0s, nsys);
+    }
     return;
   }
   LevelBufs& B = L[lvl];
@@ -937,6 +969,73 @@ void Ctx::ensure_kd(const std::vector<double>& masses) {
     kd_mass[sl] = masses[j];
   }
   kd_base = base;
+}
+
+// =================================================================== autotune
+// Every tile shape of the 16-bit coarse stencil on the context's levels at
+// nrhs right-hand sides, timed with HIP events; the fastest is kept for that
+// rhs class.
+void Ctx::autotune(int nrhs, mg_tune_info* info) {
+  const int cls = rhs_class(nrhs);
+  for (int l = 0; l < P.nagg; ++l) {
+    mg_tune_info ti{};
+    if (fmt16 < 0 || L[l + 2].prec != P32) {
+      if (info) info[l] = ti;
+      continue;
+    }
+    const int n = ncoarse[l];
+    LevelBufs& B = L[l + 2];
+    launch_random_normal<float2>((float2*)B.z[0].p, (int64_t)nrhs * B.n, P.seed + 99ull + l, st);
+    check_launch();
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto time_shape = [&](int rt, int mt) {
+      CoarseMfmaArgs a{};
+      a.out = (float2*)B.q[0].p; a.in = (const float2*)B.z[0].p; a.links = cl16[l];
+      a.g = gc[l]; a.n = n; a.in_stride = a.out_stride = gc[l].V * n; a.nrhs = nrhs;
+      a.inv_scale = cl16_inv_scale[l];
+      a.unit_self = unit_self[l] ? 1 : 0;
+      a.rt = rt; a.mt = mt;
+      for (int w = 0; w < 2; ++w) launch_coarse_mfma(a, fmt16, st);
+      HIPCHK(hipEventRecord(e0, st));
+      for (int r = 0; r < 5; ++r) launch_coarse_mfma(a, fmt16, st);
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      return 1e3 * ms / 5.0;
+    };
+    try {
+      ti.level = l + 2;
+      ti.nrhs = nrhs;
+      const int mt_def = nrhs > 16 && (n / 16) % 2 == 0 ? 2 : 1;
+      const int rt_def = cls == 0 ? 1 : (cls == 1 ? 2 : 4);
+      ti.us_default = time_shape(rt_def, cls == 0 ? 1 : mt_def);
+      ti.us_best = ti.us_default;
+      ti.rhs_per_workgroup = 16 * rt_def;
+      ti.mtiles_per_wave = cls == 0 ? 1 : mt_def;
+      for (const auto& sh : kCoarseTiles) {
+        if ((n / 16) % sh[1]) continue;
+        const double us = time_shape(sh[0], sh[1]);
+        ++ti.candidates;
+        if (us < ti.us_best) {
+          ti.us_best = us;
+          ti.rhs_per_workgroup = 16 * sh[0];
+          ti.mtiles_per_wave = sh[1];
+        }
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    tune[l][cls][0] = ti.rhs_per_workgroup / 16;
+    tune[l][cls][1] = ti.mtiles_per_wave;
+    if (info) info[l] = ti;
+  }
 }
 
 }  // namespace mg

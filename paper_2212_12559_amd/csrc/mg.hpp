@@ -92,9 +92,16 @@ struct Ctx {
   double2* xinv64[2]{};     // coarse_op 1: X^{-1} per coarse site [site][col][row]
   bool unit_self[2]{};      // the stored self block is exactly the identity (the 16-bit stencil skips it)
   double cheb_c = 1.0, cheb_d = 1.0;   // CA-GCR coarsest solver: Chebyshev basis of (A - c) / d
+  int tune[2][3][2]{};      // autotuned (rt, mt) of the 16-bit stencil per level and rhs class (0: built-in)
   std::map<int, hipGraphExec_t> coarsest_graphs;   // captured coarsest solves, by system count
   hipStream_t capture_st = nullptr;
   bool capturing = false;
+  // a K-cycle on the active masses only: their group indices (nrhs systems
+  // each, in batch order); kc_compact while it runs (masses, level-0 mask)
+  std::vector<int> kc_groups;
+  int kc_nrhs = 0;
+  bool kc_compact = false;
+  std::vector<int> kc_mask;
   float2* xinv32[2]{};
   int fmt16 = -1;           // -1: none, 0: bf16, 1: fp16
   bool setup_phase = false;
@@ -145,7 +152,7 @@ struct Ctx {
   // ---- BLAS helpers
   double2* slot(int lvl, int s) { return scal + ((int64_t)lvl * kMaxSlots + s) * max_sys; }
   double2* tslot(int lvl, int s) { return tri + ((int64_t)lvl * kTriSlots + s) * max_sys; }
-  int* lmask(int lvl) { return mask + (int64_t)lvl * max_sys; }
+  int* lmask(int lvl) { return mask + (int64_t)(lvl == 0 && kc_compact ? 4 : lvl) * max_sys; }
   void dots(int prec, int64_t n, int nsys, const std::vector<std::pair<const void*, const void*>>& pairs,
             double2* res);
   void lincomb(int prec, int64_t n, int nsys, void* out,
@@ -190,6 +197,8 @@ struct Ctx {
   void finish_links(int l);          // FP32 copy and 16-bit fragments of cl64[l]
   void precondition_links(int l);    // X^{-1} and cl64[l] <- X^{-1} cl64[l] (coarse_op 1)
   void apply_xinv(int lvl, int prec, void* out, const void* in, int nsys);
+  void autotune(int nrhs, mg_tune_info* info);
+  static int rhs_class(int nrhs) { return nrhs <= 16 ? 0 : (nrhs <= 32 ? 1 : 2); }
 };
 
 // Body of mg_apply_dslash with the work batch given: tmp holds nrhs fine

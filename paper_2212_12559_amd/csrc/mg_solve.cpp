@@ -54,6 +54,9 @@ void Ctx::solve_batch(const double* masses, int nmass, const void* b, void* x, i
   ensure_kd(ms);
   rhs_per_slot = nrhs;
   set_masses(*this, masses, nmass, nrhs);
+  kc_groups.clear();
+  kc_nrhs = nrhs;
+  int ngroups_active = nmass;
   LevelBufs& B = L[0];
   const int64_t n = B.n;
   Vec X{x, P64, n};
@@ -108,11 +111,47 @@ void Ctx::solve_batch(const double* masses, int nmass, const void* b, void* x, i
         else if (rn[s] <= tol * bn[s]) { act[s] = 0; --nact; changed = true; }
       }
       if (changed && nact > 0) HIPCHK(hipMemcpyAsync(mk, act.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+      if (changed && nact > 0 && P.compact_masses && nmass > 1) {
+        // masses whose systems have all converged leave the K-cycle's batch
+        std::vector<int> groups;
+        for (int j = 0; j < nmass; ++j) {
+          bool on = false;
+          for (int r = 0; r < nrhs; ++r) on = on || act[j * nrhs + r];
+          if (on) groups.push_back(j);
+        }
+        if ((int)groups.size() < ngroups_active) {
+          ngroups_active = (int)groups.size();
+          kc_groups = groups;
+          std::vector<double> gm;
+          for (int j : groups) gm.push_back(masses[j]);
+          ensure_kd(gm);   // the K-cycle's masses in consecutive inverse slots
+          const int nc = (int)groups.size() * nrhs;
+          std::vector<double> m64(nc);
+          std::vector<float> m32(nc);
+          for (size_t ci = 0; ci < groups.size(); ++ci)
+            for (int r = 0; r < nrhs; ++r) {
+              m64[ci * nrhs + r] = masses[groups[ci]];
+              m32[ci * nrhs + r] = (float)masses[groups[ci]];
+            }
+          HIPCHK(hipMemcpyAsync(mass64 + max_sys, m64.data(), nc * sizeof(double), hipMemcpyHostToDevice, st));
+          HIPCHK(hipMemcpyAsync(mass32 + max_sys, m32.data(), nc * sizeof(float), hipMemcpyHostToDevice, st));
+          HIPCHK(hipStreamSynchronize(st));   // before the host arrays go
+        }
+        if (!kc_groups.empty()) {   // level-0 mask of the K-cycle's systems
+          kc_mask.resize((size_t)kc_groups.size() * nrhs);
+          for (size_t ci = 0; ci < kc_groups.size(); ++ci)
+            for (int r = 0; r < nrhs; ++r) kc_mask[ci * nrhs + r] = act[kc_groups[ci] * nrhs + r];
+          HIPCHK(hipMemcpyAsync(mask + (int64_t)4 * max_sys, kc_mask.data(), kc_mask.size() * sizeof(int),
+                                hipMemcpyHostToDevice, st));
+          HIPCHK(hipStreamSynchronize(st));   // host buffers are reused
+        }
+      }
       k = restart ? 0 : k + 1;
     } else {
       k += 1;
     }
   }
+  kc_groups.clear();
   true_residual();
   HIPCHK(hipStreamSynchronize(st));
   const double t1 = now();

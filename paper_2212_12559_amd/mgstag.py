@@ -52,7 +52,20 @@ class MGParams(ctypes.Structure):
         ("coarse_op", ctypes.c_int32),
         ("coarsest_solver", ctypes.c_int32),
         ("graph_coarsest", ctypes.c_int32),
+        ("compact_masses", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
+    ]
+
+
+class MGTuneInfo(ctypes.Structure):
+    _fields_ = [
+        ("level", ctypes.c_int32),
+        ("nrhs", ctypes.c_int32),
+        ("rhs_per_workgroup", ctypes.c_int32),
+        ("mtiles_per_wave", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("us_best", ctypes.c_double),
+        ("us_default", ctypes.c_double),
     ]
 
 
@@ -94,6 +107,8 @@ def _load():
         "mg_export": (i32, [vp, i32, i32, vp, sz, P(sz), vp]),
         "mg_solve_backward": (i32, [vp, f64, vp, vp, vp, vp, vp, i32, f64, P(f64), P(MGSolveInfo), vp]),
         "mg_update_links": (i32, [vp, vp, vp, vp]),
+        "mg_autotune": (i32, [vp, i32, P(MGTuneInfo), vp]),
+        "mg_apply_coarse_multi": (i32, [P(vp), i32, i32, P(vp), P(vp), P(i32), vp]),
         "mg_profile_start": (i32, [vp, i32, i32]),
         "mg_profile_stop": (i32, [vp, P(i32), P(f64)]),
         "mg_peak_copy": (i32, [vp, vp, sz, i32, vp, P(f64)]),
@@ -390,6 +405,16 @@ class Context:
         _check(LIB.mg_export(self.ctx, what, level, _dev(out, "dst"), need.value, None, _stream()), "mg_export")
         return out
 
+    def autotune(self, nrhs):
+        """Tile shapes of the 16-bit coarse stencil timed at nrhs rhs; the
+        fastest is kept.  Returns one dict per coarse level (the shape
+        chosen, its time and the built-in shape's time in microseconds)."""
+        info = (MGTuneInfo * 2)()
+        _check(LIB.mg_autotune(self.ctx, nrhs, info, _stream()), "mg_autotune")
+        return [{"level": t.level, "nrhs": t.nrhs, "rhs_per_workgroup": t.rhs_per_workgroup,
+                 "mtiles_per_wave": t.mtiles_per_wave, "candidates": t.candidates, "us_best": t.us_best,
+                 "us_default": t.us_default} for t in info if t.level > 0]
+
     def profile_start(self, op, level=0):
         """Time every launch of one operator (MG_PROF_*) with HIP events."""
         _check(LIB.mg_profile_start(self.ctx, op, level), "mg_profile_start")
@@ -430,6 +455,28 @@ def peak_mfma(fmt=MG_CBF16, iters=20000, device="cuda:0"):
     t = ctypes.c_double()
     _check(LIB.mg_peak_mfma(fmt, iters, _dev(sink, "sink"), _stream(), ctypes.byref(t)), "mg_peak_mfma")
     return t.value
+
+
+def apply_coarse_multi(ctxs, level, xs, outs=None):
+    """Level-`level` coarse operators of several contexts (16-bit links, same
+    2 Nvec) applied in one persistent launch; xs[p] are complex64 batches of
+    ctxs[p]'s level vectors.  Returns the outputs."""
+    torch = _torch()
+    n = len(ctxs)
+    if not 1 <= n <= 8 or len(xs) != n:
+        raise ValueError("1..8 contexts, one input batch each")
+    outs = list(outs) if outs is not None else [None] * n
+    cv, iv, ov, nv = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)(), (ctypes.c_int32 * n)()
+    for p, (c, x) in enumerate(zip(ctxs, xs)):
+        if not 2 <= level <= 1 + c.params.nagg:
+            raise ValueError(f"level must be in 2..{1 + c.params.nagg}")
+        nv[p] = _check_batch(x, f"xs[{p}]", c._level_size(level), torch.complex64)
+        outs[p] = c._out(outs[p], x, tuple(x.shape), f"outs[{p}]")
+        cv[p] = c.ctx.value
+        iv[p] = _dev(x, f"xs[{p}]").value
+        ov[p] = _dev(outs[p], f"outs[{p}]").value
+    _check(LIB.mg_apply_coarse_multi(cv, n, level, iv, ov, nv, _stream()), "mg_apply_coarse_multi")
+    return outs
 
 
 def setup(params, fat, naik=None, null_vectors=None) -> Context:

@@ -382,6 +382,52 @@ def test_coarse_mfma_16bit(torch, mg, name, fmt):
             log(f"    worst rel err vs rounded-input FP64: {e_rnd:.2e}, vs unrounded FP64 operator: {e_exact:.2e}")
 
 
+def test_autotuned_coarse_tiles(torch, mg):
+    """mg_autotune times the tile shapes of the 16-bit stencil on both coarse
+    levels of the production shapes (n = 128, 192) and keeps the fastest per
+    rhs class; afterwards the stencil (in the shape chosen) still meets the
+    FP32 summation bound of test_coarse_mfma_16bit against the oracle's
+    rounded links, at 17 and 64 rhs."""
+    from gpu_common import cached_hierarchy_links
+    cfg = CONFIGS["prod"]
+    if "prod" not in _links16:
+        W, N, rng = links(cfg)
+        nvs = random_null_vectors(cfg, rng)
+        H = oracle_hierarchy(cfg, W, N, cfg["mass0"], nvs)
+        _links16["prod"] = (W, N, nvs, H, cached_hierarchy_links("prod", H), rng)
+    W, N, nvs, H, Ls, rng = _links16["prod"]
+    dev = "cuda:0"
+    p = gpu_params(mg, cfg, max_nrhs=64, fine_prec=mg.MG_C64, coarse_prec=mg.MG_CBF16)
+    ctx = mg.setup(p, torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev),
+                   [torch.from_numpy(v).to(dev) for v in nvs])
+    rnd = ops.round_bf16
+    for nrhs in (17, 64):
+        info = ctx.autotune(nrhs)
+        log(f"[tune] nrhs {nrhs}: {info}")
+        assert [t["level"] for t in info] == [2, 3]
+        for t in info:
+            assert t["candidates"] >= 4 and t["us_best"] <= t["us_default"]
+            assert t["rhs_per_workgroup"] in (16, 32, 64) and t["mtiles_per_wave"] in (1, 2)
+        for lvl in (2, 3):
+            L = Ls[lvl - 2]
+            n = L.shape[-1]
+            Lr = rnd(L.real) + 1j * rnd(L.imag)
+            La = np.abs(Lr.real) + np.abs(Lr.imag)
+            k2 = 2 * 9 * n
+            g = k2 * 2.0 ** -23 / (1 - k2 * 2.0 ** -23)
+            cd = H.cdims[lvl - 2]
+            x = latgen.complex_normal(rng, (nrhs,) + H.fine_shape(lvl)).astype(np.complex64)
+            y = ctx.apply_coarse(lvl, torch.from_numpy(x).to(dev)).cpu().numpy().astype(np.complex128)
+            for r in (0, nrhs // 2, nrhs - 1):
+                xr = rnd(x[r].real) + 1j * rnd(x[r].imag)
+                want = ops.coarse_apply_links(Lr, cd, xr)
+                bound = g * ops.coarse_apply_links(La, cd, np.abs(xr.real) + np.abs(xr.imag))
+                d = y[r] - want
+                lim = bound + 2.0 ** -24 * np.abs(want) + 1e-30
+                assert np.all(np.abs(d.real) <= lim) and np.all(np.abs(d.imag) <= lim), (nrhs, lvl, r)
+    ctx.destroy()
+
+
 def test_naik_compression_and_fallback(torch, mg):
     """The stencil keeps the Naik links in 13-real form (two rows and
     det(N) / s) when every long link is unitary, and the full form otherwise:
@@ -507,3 +553,36 @@ def test_block_16bit_identity_self(torch, mg, fmt):
                 e_exact = max(e_exact, rel_err(y[r], ops.coarse_apply_links(L, cd, x[r].astype(np.complex128))))
             log(f"    worst rel err vs the unrounded FP64 operator: {e_exact:.2e}")
     ctx.destroy()
+
+
+def test_coarse_multi_matches_separate(torch, mg):
+    """mg_apply_coarse_multi: the level-2 operators of three contexts of
+    different lattice sizes (coarse 2^4, 3^4 and 4^4, Nvec 48, bf16 links, 12
+    rhs each as in the uneven batch) applied in one persistent launch over
+    their common work list equal, bit for bit, the same operators applied
+    context by context (16 rhs per workgroup in both); mixed formats and
+    sizes are refused."""
+    dev = "cuda:0"
+    ctxs, xs, want = [], [], []
+    rng = np.random.default_rng(99)
+    for L in (8, 12, 16):
+        dims = (L, L, L, L)
+        W, N, _ = latgen.hisq_style_links(dims, 0.5, 900 + L)
+        nv = [latgen.fine_vectors(dims, 48, rng)]
+        p = mg.default_params(dims, nagg=1, nvec=(48, 1), block=[(4, 4, 4, 4)], kd_naik=0, mass0=0.05,
+                              coarse_prec=mg.MG_CBF16, max_nrhs=12)
+        log(f"[multi] setup {dims}")
+        c = mg.setup(p, torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev),
+                     [torch.from_numpy(v).to(dev) for v in nv])
+        x = torch.from_numpy(latgen.complex_normal(rng, (12,) + c.coarse_shapes[0])).to(dev).to(torch.complex64)
+        ctxs.append(c)
+        xs.append(x)
+        want.append(c.apply_coarse(2, x))
+    got = mg.apply_coarse_multi(ctxs, 2, xs)
+    torch.cuda.synchronize()
+    for g, w in zip(got, want):
+        assert torch.equal(g, w)
+    with pytest.raises((ValueError, mg.MGError)):
+        mg.apply_coarse_multi(ctxs[:2], 3, xs[:2])   # no level 3 in these hierarchies
+    for c in ctxs:
+        c.destroy()
