@@ -118,6 +118,10 @@ typedef struct {
   int32_t compact_masses;    /* 1: in a multi-mass batch the K-cycle runs only on the masses with a system
                                 still iterating (whole masses leave the preconditioner's batch once all their
                                 right-hand sides have converged; results unchanged); 0: on every system */
+  int32_t coarse_shadow;     /* 1 (16-bit coarse links): in the smoother's chain p_j = A p_{j-1} on a coarse
+                                level the stencil also stores its output rounded to the link format, and the
+                                next application reads those 16-bit inputs (results unchanged; half the
+                                staging reads, one more write); 0 (default): off */
   uint64_t seed;             /* seed of the GPU-generated null-vector starts */
 } mg_params;
 

@@ -118,9 +118,12 @@ void launch_absmax(const double2* v, int64_t n, unsigned long long* out, hipStre
 // staged through LDS in passes of kMfmaCK k-chunks; a B fragment read from LDS
 // feeds 4 MT products and an A fragment streamed from HBM feeds 4 RT, so the
 // links, which dominate the traffic, are read once per 16 RT right-hand sides
-// and the LDS reads per product fall as 1 / MT.
+// and the LDS reads per product fall as 1 / MT.  A thread has the loads of
+// kStageQ staging quads in flight before it waits (more cost occupancy, which
+// hides the latency of the link loads better).
 constexpr int kMfmaCK = 4;
 constexpr int kMfmaMaxWaves = 16;
+constexpr int kStageQ = 4;        // staging quads whose loads a thread has in flight at once
 
 // The work of one workgroup: coarse site `site`, right-hand sides r0 ..
 // r0 + 16 RT - 1 (bsm: the B staging area, nbs: the neighbour table, both in
@@ -170,6 +173,18 @@ __device__ __forceinline__ void coarse_mfma_site(const CoarseMfmaArgs& a, const 
                 sz = (site / ((int64_t)a.g.L[0] * a.g.L[1])) % a.g.L[2];
   const bool xodd = perm && (sx & 1), yswap = perm && ((sy >> 1) & 1), zswap = perm && ((sz >> 1) & 1);
   const int npass = (kc_n - kc_begin + kMfmaCK - 1) / kMfmaCK;
+  // quads of the staging pass: a thread takes quads tid + q nthreads; their
+  // global loads are issued kStageQ at a time before the first is waited for
+  const int nq = NR * (KCH / 4);
+  const int qpt = (nq + nthreads - 1) / nthreads;
+  // A fragments (Re, Im) of a k-chunk
+  auto load_a = [&](uint4 (&dst)[MT][2], int kc) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      dst[m][0] = load_stream(Lm[m] + (kc * 2 + 0) * 64 + lane);
+      dst[m][1] = load_stream(Lm[m] + (kc * 2 + 1) * 64 + lane);
+    }
+  };
   for (int pi = 0; pi < npass; ++pi) {
     // direction-ordered passes: d = pi (+1 without the self block), reordered as above
     int pd = pi + (a.unit_self && perm ? 1 : 0);
@@ -182,39 +197,70 @@ __device__ __forceinline__ void coarse_mfma_site(const CoarseMfmaArgs& a, const 
     const int kc0 = perm ? pd * kMfmaCK : kc_begin + pi * kMfmaCK;
     __syncthreads();   // neighbour table ready / previous pass consumed
     // stage k in [32 kc0, 32 kc0 + KCH): quads (k .. k + 3) lie in one
-    // direction (n is a multiple of 16) and are two 16-byte loads (inputs are
-    // 16-byte aligned) and one 8-byte LDS store per plane
-    for (int e = tid; e < NR * (KCH / 4); e += nthreads) {
-      const int jj = e / (KCH / 4);
-      const int kl = 4 * (e - jj * (KCH / 4));
-      const int k = kc0 * 32 + kl;
-      uint2 pre = make_uint2(0u, 0u), pim = make_uint2(0u, 0u);
-      if (r0 + jj < a.nrhs && k < K) {
-        const int d = k / n, col = k - d * n;
-        const float4* src =
-            reinterpret_cast<const float4*>(a.in + (int64_t)(r0 + jj) * a.in_stride + nbs[d] * n + col);
-        const float4 v0 = src[0], v1 = src[1];
-        pre.x = (uint32_t)to16<FMT>(v0.x) | ((uint32_t)to16<FMT>(v0.z) << 16);
-        pre.y = (uint32_t)to16<FMT>(v1.x) | ((uint32_t)to16<FMT>(v1.z) << 16);
-        pim.x = (uint32_t)to16<FMT>(v0.y) | ((uint32_t)to16<FMT>(v0.w) << 16);
-        pim.y = (uint32_t)to16<FMT>(v1.y) | ((uint32_t)to16<FMT>(v1.w) << 16);
+    // direction (n is a multiple of 16) and are two 16-byte loads (one for
+    // 16-bit inputs; inputs are 16-byte aligned) and one 8-byte LDS store per
+    // plane
+    for (int q0 = 0; q0 < qpt; q0 += kStageQ) {
+      uint4 raw0[kStageQ], raw1[kStageQ];
+#pragma unroll
+      for (int q = 0; q < kStageQ; ++q) {
+        const int e = tid + (q0 + q) * nthreads;
+        raw0[q] = make_uint4(0u, 0u, 0u, 0u);
+        raw1[q] = make_uint4(0u, 0u, 0u, 0u);
+        const int jj = e / (KCH / 4);
+        const int k = kc0 * 32 + 4 * (e - jj * (KCH / 4));
+        if (q0 + q < qpt && e < nq && r0 + jj < a.nrhs && k < K) {
+          const int d = k / n, col = k - d * n;
+          const int64_t off = (int64_t)(r0 + jj) * a.in_stride + nbs[d] * n + col;
+          if (a.in16) {
+            raw0[q] = *reinterpret_cast<const uint4*>(a.in16 + off);
+          } else {
+            const uint4* src = reinterpret_cast<const uint4*>(a.in + off);
+            raw0[q] = src[0];
+            raw1[q] = src[1];
+          }
+        }
       }
-      *reinterpret_cast<uint2*>(Bre + jj * KPC + kl) = pre;
-      *reinterpret_cast<uint2*>(Bim + jj * KPC + kl) = pim;
+#pragma unroll
+      for (int q = 0; q < kStageQ; ++q) {
+        const int e = tid + (q0 + q) * nthreads;
+        if (q0 + q < qpt && e < nq) {
+          const int jj = e / (KCH / 4);
+          const int kl = 4 * (e - jj * (KCH / 4));
+          uint2 pre, pim;
+          const uint4 c = raw0[q];
+          if (a.in16) {   // four packed 16-bit complex numbers, split into the two planes
+            pre.x = (c.x & 0xFFFFu) | (c.y << 16);
+            pre.y = (c.z & 0xFFFFu) | (c.w << 16);
+            pim.x = (c.x >> 16) | (c.y & 0xFFFF0000u);
+            pim.y = (c.z >> 16) | (c.w & 0xFFFF0000u);
+          } else {
+            const float4 v0 = make_float4(__uint_as_float(c.x), __uint_as_float(c.y), __uint_as_float(c.z),
+                                          __uint_as_float(c.w));
+            const uint4 c1 = raw1[q];
+            const float4 v1 = make_float4(__uint_as_float(c1.x), __uint_as_float(c1.y), __uint_as_float(c1.z),
+                                          __uint_as_float(c1.w));
+            pre.x = (uint32_t)to16<FMT>(v0.x) | ((uint32_t)to16<FMT>(v0.z) << 16);
+            pre.y = (uint32_t)to16<FMT>(v1.x) | ((uint32_t)to16<FMT>(v1.z) << 16);
+            pim.x = (uint32_t)to16<FMT>(v0.y) | ((uint32_t)to16<FMT>(v0.w) << 16);
+            pim.y = (uint32_t)to16<FMT>(v1.y) | ((uint32_t)to16<FMT>(v1.w) << 16);
+          }
+          *reinterpret_cast<uint2*>(Bre + jj * KPC + kl) = pre;
+          *reinterpret_cast<uint2*>(Bim + jj * KPC + kl) = pim;
+        }
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int kcl = 0; kcl < kMfmaCK; ++kcl) {
       const int kc = kc0 + kcl;
       if (kc < kc_n) {
-        uint4 are[MT], aim[MT], aimn[MT];   // Re A, Im A and -Im A (sign bits flipped)
+        uint4 acur[MT][2], aimn[MT];   // Re A, Im A and -Im A (sign bits flipped)
+        load_a(acur, kc);
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          are[m] = load_stream(Lm[m] + (kc * 2 + 0) * 64 + lane);
-          aim[m] = load_stream(Lm[m] + (kc * 2 + 1) * 64 + lane);
-          aimn[m] = make_uint4(aim[m].x ^ 0x80008000u, aim[m].y ^ 0x80008000u, aim[m].z ^ 0x80008000u,
-                               aim[m].w ^ 0x80008000u);
-        }
+        for (int m = 0; m < MT; ++m)
+          aimn[m] = make_uint4(acur[m][1].x ^ 0x80008000u, acur[m][1].y ^ 0x80008000u,
+                               acur[m][1].z ^ 0x80008000u, acur[m][1].w ^ 0x80008000u);
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
           const int off = (rt * 16 + j) * KPC + kcl * 32 + 8 * g;
@@ -222,10 +268,10 @@ __device__ __forceinline__ void coarse_mfma_site(const CoarseMfmaArgs& a, const 
           const uint4 bim = *reinterpret_cast<const uint4*>(Bim + off);
 #pragma unroll
           for (int m = 0; m < MT; ++m) {
-            yr[m][rt] = mfma16<FMT>(are[m], bre, yr[m][rt]);
+            yr[m][rt] = mfma16<FMT>(acur[m][0], bre, yr[m][rt]);
             yr[m][rt] = mfma16<FMT>(aimn[m], bim, yr[m][rt]);
-            yi[m][rt] = mfma16<FMT>(are[m], bim, yi[m][rt]);
-            yi[m][rt] = mfma16<FMT>(aim[m], bre, yi[m][rt]);
+            yi[m][rt] = mfma16<FMT>(acur[m][0], bim, yi[m][rt]);
+            yi[m][rt] = mfma16<FMT>(acur[m][1], bre, yi[m][rt]);
           }
         }
       }
@@ -246,9 +292,21 @@ __device__ __forceinline__ void coarse_mfma_site(const CoarseMfmaArgs& a, const 
 #pragma unroll
           for (int t = 0; t < 4; ++t) xs[t] = xi[t];
         }
+        float vr[4], vi[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          store_stream(o + t, fmaf(yr[m][rt][t], a.inv_scale, xs[t].x), fmaf(yi[m][rt][t], a.inv_scale, xs[t].y));
+        for (int t = 0; t < 4; ++t) {
+          vr[t] = fmaf(yr[m][rt][t], a.inv_scale, xs[t].x);
+          vi[t] = fmaf(yi[m][rt][t], a.inv_scale, xs[t].y);
+          store_stream(o + t, vr[t], vi[t]);
+        }
+        if (a.out16) {   // the same values rounded as the next application would round them
+          uint4 c;
+          c.x = (uint32_t)to16<FMT>(vr[0]) | ((uint32_t)to16<FMT>(vi[0]) << 16);
+          c.y = (uint32_t)to16<FMT>(vr[1]) | ((uint32_t)to16<FMT>(vi[1]) << 16);
+          c.z = (uint32_t)to16<FMT>(vr[2]) | ((uint32_t)to16<FMT>(vi[2]) << 16);
+          c.w = (uint32_t)to16<FMT>(vr[3]) | ((uint32_t)to16<FMT>(vi[3]) << 16);
+          *reinterpret_cast<uint4*>(a.out16 + (int64_t)r * a.out_stride + site * n + mt * 16 + 4 * g) = c;
+        }
       }
     }
   }
@@ -258,7 +316,13 @@ template <int FMT, int RT, int MT>
 __global__ void __launch_bounds__(64 * kMfmaMaxWaves) coarse_mfma_kernel(const CoarseMfmaArgs a) {
   extern __shared__ uint16_t bsm[];    // [2 planes][16 RT][KCH + 8]
   __shared__ int64_t nbs[9];
-  coarse_mfma_site<FMT, RT, MT>(a, xcd_block(blockIdx.x, gridDim.x), blockIdx.y * 16 * RT, bsm, nbs);
+  // block -> (site, rhs tile) with the rhs tile fastest, after the XCD
+  // renumbering: the tiles of a site run back to back on one XCD and read its
+  // links once from HBM, the other times from that XCD's L2
+  const int ntile = (a.nrhs + 16 * RT - 1) / (16 * RT);
+  const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t site = b / ntile;
+  coarse_mfma_site<FMT, RT, MT>(a, site, (int)(b - site * ntile) * 16 * RT, bsm, nbs);
 }
 
 // One persistent launch over the (problem, site, rhs tile) work list of up to
@@ -300,8 +364,9 @@ template <int FMT, int RT, int MT>
 static void coarse_mfma_launch(const CoarseMfmaArgs& a, hipStream_t st) {
   const int mt_n = a.n / 16;
   const size_t lds = (size_t)2 * 16 * RT * (kMfmaCK * 32 + 8) * sizeof(uint16_t);
-  dim3 grid((unsigned)a.g.V, (unsigned)((a.nrhs + 16 * RT - 1) / (16 * RT)));
-  coarse_mfma_kernel<FMT, RT, MT><<<grid, 64 * (mt_n / MT), lds, st>>>(a);
+  const int64_t nb = a.g.V * ((a.nrhs + 16 * RT - 1) / (16 * RT));
+  if (nb > 0x7fffffff) throw std::runtime_error("coarse_mfma: too many (site, rhs tile) blocks");
+  coarse_mfma_kernel<FMT, RT, MT><<<dim3((unsigned)nb), 64 * (mt_n / MT), lds, st>>>(a);
 }
 
 template <int FMT>

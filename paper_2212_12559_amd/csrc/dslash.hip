@@ -194,15 +194,31 @@ __global__ void __launch_bounds__(256) dslash_plane_kernel(const DslashArgs<floa
   const int z = (int)(zt % L2), t = (int)(zt / L2);
   const int y0 = yb * RB;
   const int nq = rowc / 2;   // 16-byte pieces per row (L0 even)
-  for (int it = threadIdx.x; it < NR * (RB + 2) * nq; it += 256) {
-    const int q = it % nq, rw = (it / nq) % (RB + 2), rr = it / (nq * (RB + 2));
-    const int y = (y0 - 1 + rw + L1) % L1;
-    const int64_t rs = (((int64_t)t * L2 + z) * L1 + y) * L0;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (rr < nr) v = *reinterpret_cast<const float4*>(a.in + (int64_t)(r0 + rr) * a.in_stride + rs * 3 + 2 * q);
-    T* d = xs + ((int64_t)rr * (RB + 2) + rw) * rowc + 2 * q;
-    d[0] = make_float2(v.x, v.y);
-    d[1] = make_float2(v.z, v.w);
+  // a thread has the loads of up to kPlaneQ pieces in flight before it waits
+  constexpr int kPlaneQ = 8;
+  const int npiece = NR * (RB + 2) * nq;
+  for (int it0 = threadIdx.x; it0 < npiece; it0 += kPlaneQ * 256) {
+    float4 v[kPlaneQ];
+#pragma unroll
+    for (int u = 0; u < kPlaneQ; ++u) {
+      const int it = it0 + u * 256;
+      const int q = it % nq, rw = (it / nq) % (RB + 2), rr = it / (nq * (RB + 2));
+      const int y = (y0 - 1 + rw + L1) % L1;
+      const int64_t rs = (((int64_t)t * L2 + z) * L1 + y) * L0;
+      v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (it < npiece && rr < nr)
+        v[u] = *reinterpret_cast<const float4*>(a.in + (int64_t)(r0 + rr) * a.in_stride + rs * 3 + 2 * q);
+    }
+#pragma unroll
+    for (int u = 0; u < kPlaneQ; ++u) {
+      const int it = it0 + u * 256;
+      if (it < npiece) {
+        const int q = it % nq, rw = (it / nq) % (RB + 2), rr = it / (nq * (RB + 2));
+        T* d = xs + ((int64_t)rr * (RB + 2) + rw) * rowc + 2 * q;
+        d[0] = make_float2(v[u].x, v[u].y);
+        d[1] = make_float2(v[u].z, v[u].w);
+      }
+    }
   }
   __syncthreads();
   const int x = threadIdx.x % L0, yr = threadIdx.x / L0;

@@ -245,11 +245,21 @@ __global__ void __launch_bounds__(256) kd_apply_mfma_lds_kernel(const KdArgs<flo
   const int slot = a.rhs_per_slot > 0 ? r0 / a.rhs_per_slot : 0;
   const int64_t L0 = a.g.L[0], L01 = L0 * a.g.L[1], L012 = L01 * a.g.L[2];
   const int64_t s0 = hc_site(hc0, 0, a.g);
-  for (int it = tid; it < 16 * 8 * 12; it += 256) {
+  // the six 16-byte pieces of a thread are loaded before the first is used
+  float4 vin[6];
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+    const int it = tid + 256 * u;
     const int q = it % 12, rho = (it / 12) % 8, rr = it / 96;
     const int64_t rs = s0 + ((rho & 1) ? L0 : 0) + ((rho & 2) ? L01 : 0) + ((rho & 4) ? L012 : 0);
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (r0 + rr < a.nrhs) v = *reinterpret_cast<const float4*>(a.in + (int64_t)(r0 + rr) * a.in_stride + rs * 3 + 2 * q);
+    vin[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r0 + rr < a.nrhs) vin[u] = *reinterpret_cast<const float4*>(a.in + (int64_t)(r0 + rr) * a.in_stride + rs * 3 + 2 * q);
+  }
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+    const int it = tid + 256 * u;
+    const int q = it % 12, rho = (it / 12) % 8, rr = it / 96;
+    const float4 v = vin[u];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int fl = 2 * q + e, xo = fl / 3, col = fl - 3 * (fl / 3);
@@ -270,13 +280,22 @@ __global__ void __launch_bounds__(256) kd_apply_mfma_lds_kernel(const KdArgs<flo
     bim[ks] = v.y;
   }
   f32x4 yr[3], yi[3];
+  // A fragments of an m-tile are loaded together, the next m-tile's while
+  // this one's products run
+  float2 kf[2][12];
+#pragma unroll
+  for (int ks = 0; ks < 12; ++ks) kf[0][ks] = K[(4 * ks + kq) * 48 + rl];
 #pragma unroll
   for (int mt = 0; mt < 3; ++mt) {
+    if (mt + 1 < 3) {
+#pragma unroll
+      for (int ks = 0; ks < 12; ++ks) kf[(mt + 1) & 1][ks] = K[(4 * ks + kq) * 48 + 16 * (mt + 1) + rl];
+    }
     yr[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
     yi[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 12; ++ks) {
-      const float2 k = K[(4 * ks + kq) * 48 + 16 * mt + rl];
+      const float2 k = kf[mt & 1][ks];
       yr[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(k.x, bre[ks], yr[mt], 0, 0, 0);
       yr[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-k.y, bim[ks], yr[mt], 0, 0, 0);
       yi[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(k.x, bim[ks], yi[mt], 0, 0, 0);

@@ -121,6 +121,8 @@ struct CoarseMfmaArgs {
   float inv_scale;
   int unit_self;            // the self block is the identity: skip its links, add the input instead (n % 32 == 0)
   int rt, mt;               // tile shape: 16 rt rhs per workgroup, mt m-tiles per wavefront (0, 0: by rhs count)
+  const uint32_t* in16;     // optional: the input already in the link format, packed (re | im << 16)
+  uint32_t* out16;          // optional: also store the output in that format (the next application's input)
 };
 // tile shapes the 16-bit coarse stencil is built for (rt, mt)
 constexpr int kCoarseTiles[6][2] = {{1, 1}, {1, 2}, {2, 1}, {2, 2}, {4, 1}, {4, 2}};

@@ -49,6 +49,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   if (p.coarsest_solver != 0 && p.coarsest_solver != 1) return fail("coarsest_solver must be 0 (GCR) or 1 (CA-GCR)");
   if (p.graph_coarsest != 0 && p.graph_coarsest != 1) return fail("graph_coarsest must be 0 or 1");
   if (p.compact_masses != 0 && p.compact_masses != 1) return fail("compact_masses must be 0 or 1");
+  if (p.coarse_shadow != 0 && p.coarse_shadow != 1) return fail("coarse_shadow must be 0 or 1");
   const bool naik_kd = p.c3 != 0.0 && p.kd_naik;
   Geom g0{};
   g0.V = 1;
@@ -153,6 +154,11 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   void* m32 = S((size_t)2 * ms * 4);
   void* mask = S((size_t)5 * ms * 4);   // levels 0..3, then level 0 of a compacted K-cycle
   void* dcoef = kd > 0 ? S((size_t)kd * ms * 16) : nullptr;
+  // 16-bit copies of the smoother chain's stencil outputs, two per coarse level that has a smoother
+  void* sh16[2][2]{};
+  if (c16 && p.coarse_shadow && p.fine_prec == MG_C64)
+    for (int l = 0; l + 1 < p.nagg; ++l)
+      for (int q = 0; q < 2; ++q) sh16[l][q] = S((size_t)p.max_nrhs * gc[l].V * 2 * A[l].nvec * 4);
   const size_t solver_base = scr.off;
   // solver buffers
   LevelBufs L[4];
@@ -258,6 +264,8 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     c->defl_rm = (double2*)drm;
     c->defl_rinv = (double2*)dri;
     c->defl_c = (double2*)dcoef;
+    for (int l = 0; l < 2; ++l)
+      for (int q = 0; q < 2; ++q) c->shadow16[l][q] = (uint32_t*)sh16[l][q];
     c->scal = (double2*)scal;
     c->tri = (double2*)tri;
     c->mass64 = (double*)m64;
@@ -347,7 +355,8 @@ void Ctx::apply_KD(int prec, void* out, const void* in, int nsys, bool eps_in, b
   check_launch();
 }
 
-void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, bool dag) {
+void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, bool dag, const uint32_t* in16,
+                       uint32_t* out16) {
   prof_mark(MG_PROF_COARSE, lvl);
   const int l = lvl - 2;
   const int n = ncoarse[l];
@@ -364,6 +373,8 @@ void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, b
     a.unit_self = unit_self[l] ? 1 : 0;
     a.rt = tune[l][rhs_class(nsys)][0];
     a.mt = tune[l][rhs_class(nsys)][1];
+    a.in16 = in16;
+    a.out16 = out16;
     launch_coarse_mfma(a, fmt16, st);
   } else {
     CoarseArgs<float, float2> a{};
@@ -514,9 +525,17 @@ void Ctx::smoother(int lvl, const Vec& e, const Vec& t, int nsys) {
   LevelBufs& B = L[lvl];
   const int s = P.smoother_s;
   const int prec = t.prec;
+  // on a coarse level with 16-bit links each basis vector is also kept in
+  // that format for the next application (two alternating copies)
+  const bool sh = lvl >= 2 && shadow16[lvl - 2][0] && fmt16 >= 0 && prec == P32 && !setup_phase;
   for (int j = 0; j < s; ++j) {
     const Vec& src = j == 0 ? t : B.sm[j - 1];
-    apply_level(lvl, B.sm[j], src, nsys);
+    if (sh) {
+      apply_coarse(lvl, prec, B.sm[j].p, src.p, nsys, false, j > 0 ? shadow16[lvl - 2][(j - 1) & 1] : nullptr,
+                   j + 1 < s ? shadow16[lvl - 2][j & 1] : nullptr);
+    } else {
+      apply_level(lvl, B.sm[j], src, nsys);
+    }
   }
   // Gram data <A p_i, A p_j> (i <= j) and <A p_i, t> in one pass over the basis
   double2* gram = slot(lvl, 0);

@@ -91,6 +91,7 @@ struct Ctx {
   float cl16_inv_scale[2]{1.0f, 1.0f};
   double2* xinv64[2]{};     // coarse_op 1: X^{-1} per coarse site [site][col][row]
   bool unit_self[2]{};      // the stored self block is exactly the identity (the 16-bit stencil skips it)
+  uint32_t* shadow16[2][2]{};   // 16-bit copies of the smoother chain's outputs per coarse level (coarse_shadow)
   double cheb_c = 1.0, cheb_d = 1.0;   // CA-GCR coarsest solver: Chebyshev basis of (A - c) / d
   int tune[2][3][2]{};      // autotuned (rt, mt) of the 16-bit stencil per level and rhs class (0: built-in)
   std::map<int, hipGraphExec_t> coarsest_graphs;   // captured coarsest solves, by system count
@@ -145,7 +146,8 @@ struct Ctx {
   void apply_D(int prec, void* out, const void* in, int nsys, bool naik, const void* mass_rhs, double mass,
                bool eps_out = false);
   void apply_KD(int prec, void* out, const void* in, int nsys, bool eps_in, bool eps_out, int rhs_per_slot);
-  void apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, bool dag);
+  void apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, bool dag,
+                    const uint32_t* in16 = nullptr, uint32_t* out16 = nullptr);
   void restrict_(int lvl, int prec, void* out, const void* in, int nsys);
   void prolong_(int lvl, int prec, void* out, const void* in, int nsys, bool acc);
 

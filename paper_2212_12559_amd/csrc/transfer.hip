@@ -8,6 +8,9 @@
 //   prolong   e[row] = sum_k P[row, k] e_c[a, sigma, k] (optionally += e)
 //             one workgroup per (a, sigma); threads over rows, P read in its
 //             second, row-contiguous copy, e_c staged in LDS.
+// Workgroup numbers go through xcd_block, so that the (a, +) and (a, -)
+// workgroups, which read or write the same cache lines of the fine vector
+// (the two parities of each row of sites), run on one XCD and share its L2.
 #include "kernels.hpp"
 
 namespace mg {
@@ -133,7 +136,7 @@ __global__ void __launch_bounds__(64 * kRestrictWaves) restrict_kernel(const Res
   __shared__ T red[kRestrictWaves - 1][NR][KPL * 64];
   extern __shared__ unsigned char xs_raw[];   // [NR][nrows] input values of this (a, sigma)
   T* xs = reinterpret_cast<T*>(xs_raw);
-  const int64_t as = blockIdx.x;
+  const int64_t as = xcd_block(blockIdx.x, gridDim.x);
   const int64_t agg = as >> 1;
   const int sigma = (int)(as & 1);
   const int r0 = blockIdx.y * NR;
@@ -223,10 +226,15 @@ __device__ __forceinline__ void cmfma(f32x4& yr, f32x4& yi, float ar, float ai, 
 template <int RT>
 __global__ void __launch_bounds__(512) restrict_mfma_kernel(const RestrictArgs<float> a) {
   __shared__ float2 xs[kXferChunk][16 * RT + 1];
-  const int64_t as = blockIdx.x;
+  // block -> ((aggregate, chirality), rhs tile), tile fastest: the tiles of a
+  // block of P and the two chiralities of an aggregate (which share cache
+  // lines of the fine vector) run back to back on one XCD
+  const int ntile = (a.nrhs + 16 * RT - 1) / (16 * RT);
+  const int64_t bl = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t as = bl / ntile;
   const int64_t agg = as >> 1;
   const int sigma = (int)(as & 1);
-  const int r0 = blockIdx.y * 16 * RT;
+  const int r0 = (int)(bl - as * ntile) * 16 * RT;
   const int tid = threadIdx.x, kt = tid >> 6, lane = tid & 63;
   const int nthreads = blockDim.x;
   const int nvec = a.A.nvec, nrows = a.A.nrows;
@@ -239,14 +247,25 @@ __global__ void __launch_bounds__(512) restrict_mfma_kernel(const RestrictArgs<f
     yr[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
     yi[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
+  constexpr int kQ = 8;   // gathered values a thread has in flight before it waits
   for (int row0 = 0; row0 < nrows; row0 += kXferChunk) {
     __syncthreads();
-    for (int e = tid; e < kXferChunk * 16 * RT; e += nthreads) {
-      const int rr = e / kXferChunk, q = e - rr * kXferChunk;   // consecutive threads: consecutive rows
-      float2 v = make_float2(0.f, 0.f);
-      if (row0 + q < nrows && r0 + rr < a.nrhs)
-        v = a.in[(int64_t)(r0 + rr) * a.in_stride + agg_row_index(a.A, agg, sigma, row0 + q)];
-      xs[q][rr] = v;
+    for (int e0 = tid; e0 < kXferChunk * 16 * RT; e0 += kQ * nthreads) {
+      float2 v[kQ];
+#pragma unroll
+      for (int u = 0; u < kQ; ++u) {
+        const int e = e0 + u * nthreads;
+        const int rr = e / kXferChunk, q = e - rr * kXferChunk;   // consecutive threads: consecutive rows
+        v[u] = make_float2(0.f, 0.f);
+        if (e < kXferChunk * 16 * RT && row0 + q < nrows && r0 + rr < a.nrhs)
+          v[u] = a.in[(int64_t)(r0 + rr) * a.in_stride + agg_row_index(a.A, agg, sigma, row0 + q)];
+      }
+#pragma unroll
+      for (int u = 0; u < kQ; ++u) {
+        const int e = e0 + u * nthreads;
+        const int rr = e / kXferChunk, q = e - rr * kXferChunk;
+        if (e < kXferChunk * 16 * RT) xs[q][rr] = v[u];
+      }
     }
     __syncthreads();
 #pragma unroll 2
@@ -283,19 +302,34 @@ __global__ void __launch_bounds__(512) restrict_mfma_kernel(const RestrictArgs<f
 template <int RT>
 __global__ void __launch_bounds__(512) prolong_mfma_kernel(const ProlongArgs<float> a) {
   __shared__ float2 cs[128][16 * RT + 1];
-  const int64_t as = blockIdx.x;
+  // numbered as in the restriction: both chiralities' stores merge in one L2
+  const int ntile = (a.nrhs + 16 * RT - 1) / (16 * RT);
+  const int64_t bl = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t as = bl / ntile;
   const int64_t agg = as >> 1;
   const int sigma = (int)(as & 1);
-  const int r0 = blockIdx.y * 16 * RT;
+  const int r0 = (int)(bl - as * ntile) * 16 * RT;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nvec = a.A.nvec, nrows = a.A.nrows;
   const float2* P = a.pp + as * (int64_t)nrows * nvec;
   const int ksteps = (nvec + 3) / 4;
-  for (int e = tid; e < 4 * ksteps * 16 * RT; e += 512) {
-    const int k = e / (16 * RT), rr = e - k * (16 * RT);
-    float2 v = make_float2(0.f, 0.f);
-    if (k < nvec && r0 + rr < a.nrhs) v = a.in[(int64_t)(r0 + rr) * a.in_stride + agg * 2 * nvec + sigma * nvec + k];
-    cs[k][rr] = v;
+  constexpr int kQ = 8;   // staged values a thread has in flight before it waits
+  for (int e0 = tid; e0 < 4 * ksteps * 16 * RT; e0 += kQ * 512) {
+    float2 v[kQ];
+#pragma unroll
+    for (int u = 0; u < kQ; ++u) {
+      const int e = e0 + u * 512;
+      const int k = e / (16 * RT), rr = e - k * (16 * RT);
+      v[u] = make_float2(0.f, 0.f);
+      if (e < 4 * ksteps * 16 * RT && k < nvec && r0 + rr < a.nrhs)
+        v[u] = a.in[(int64_t)(r0 + rr) * a.in_stride + agg * 2 * nvec + sigma * nvec + k];
+    }
+#pragma unroll
+    for (int u = 0; u < kQ; ++u) {
+      const int e = e0 + u * 512;
+      const int k = e / (16 * RT), rr = e - k * (16 * RT);
+      if (e < 4 * ksteps * 16 * RT) cs[k][rr] = v[u];
+    }
   }
   __syncthreads();
   const int kk = lane >> 4, il = lane & 15;
@@ -342,8 +376,8 @@ void launch_restrict(const RestrictArgs<R>& a, hipStream_t st) {
   if constexpr (sizeof(R) == 4) {
     if (a.nrhs >= 4) {
       const unsigned gx = (unsigned)(a.A.nagg * 2), nt = 64 * ((a.A.nvec + 15) / 16);
-      if (a.nrhs <= 16) restrict_mfma_kernel<1><<<dim3(gx, 1), nt, 0, st>>>(a);
-      else restrict_mfma_kernel<4><<<dim3(gx, (unsigned)((a.nrhs + 63) / 64)), nt, 0, st>>>(a);
+      if (a.nrhs <= 16) restrict_mfma_kernel<1><<<dim3(gx), nt, 0, st>>>(a);
+      else restrict_mfma_kernel<4><<<dim3(gx * (unsigned)((a.nrhs + 63) / 64)), nt, 0, st>>>(a);
       return;
     }
   }
@@ -368,7 +402,7 @@ template <typename R, int NR>
 __global__ void __launch_bounds__(512) prolong_kernel(const ProlongArgs<R> a) {
   using T = cplx<R>;
   __shared__ T ec[NR][128];
-  const int64_t as = blockIdx.x;
+  const int64_t as = xcd_block(blockIdx.x, gridDim.x);
   const int64_t agg = as >> 1;
   const int sigma = (int)(as & 1);
   const int r0 = blockIdx.y * NR;
@@ -417,8 +451,8 @@ void launch_prolong(const ProlongArgs<R>& a, hipStream_t st) {
   const unsigned gx = (unsigned)(a.A.nagg * 2);
   if constexpr (sizeof(R) == 4) {
     if (a.nrhs >= 4 && a.unit_col < 0) {
-      if (a.nrhs <= 16) prolong_mfma_kernel<1><<<dim3(gx, 1), 512, 0, st>>>(a);
-      else prolong_mfma_kernel<4><<<dim3(gx, (unsigned)((a.nrhs + 63) / 64)), 512, 0, st>>>(a);
+      if (a.nrhs <= 16) prolong_mfma_kernel<1><<<dim3(gx), 512, 0, st>>>(a);
+      else prolong_mfma_kernel<4><<<dim3(gx * (unsigned)((a.nrhs + 63) / 64)), 512, 0, st>>>(a);
       return;
     }
   }

@@ -53,6 +53,7 @@ class MGParams(ctypes.Structure):
         ("coarsest_solver", ctypes.c_int32),
         ("graph_coarsest", ctypes.c_int32),
         ("compact_masses", ctypes.c_int32),
+        ("coarse_shadow", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 

@@ -91,6 +91,7 @@ def test_default_params_table1(m):
     (dict(coarsest_solver=3), "coarsest_solver"),
     (dict(graph_coarsest=2), "graph_coarsest"),
     (dict(compact_masses=5), "compact_masses"),
+    (dict(coarse_shadow=3), "coarse_shadow"),
     (dict(dims=(8, 8, 8, 8), nvec=(8, 8), coarsest_deflate=32), "dimension"),
 ])
 def test_workspace_validation(m, bad, why):

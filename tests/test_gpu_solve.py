@@ -184,6 +184,31 @@ def test_mass_compaction_is_exact(torch, mg, cubic):
             assert true_rel(cfg, W, N, m, res[1][0][j, r], b[r]) <= 1e-10, (m, r)
 
 
+def test_coarse_shadow_is_exact(torch, mg, cubic):
+    """coarse_shadow 1: in the level-2 smoother's chain the 16-bit stencil also
+    stores its output rounded to the link format and the next application
+    stages those values instead of rounding the FP32 vector again; the
+    rounding is the same, so the solutions equal bit for bit those without
+    the copies (bf16 and fp16 links)."""
+    cfg, W, N, nvs, _ = cubic
+    rng = np.random.default_rng(4326)
+    b = latgen.fine_vectors(cfg["dims"], 4, rng)
+    bt = torch.from_numpy(b).to("cuda:0")
+    for fmt, cp in (("bf16", mg.MG_CBF16), ("fp16", mg.MG_CF16)):
+        res = []
+        for sh in (0, 1):
+            log(f"[shadow] {fmt} coarse_shadow {sh}")
+            ctx = make_ctx(torch, mg, cfg, W, N, nvs, max_nrhs=4, coarse_prec=cp, coarse_op=1, coarsest_solver=1,
+                           coarse_shadow=sh)
+            x, info, st = ctx.solve([0.05], bt, tol=1e-10)
+            res.append((x.cpu().numpy(), [i["outer_iters"] for i in info]))
+            ctx.destroy()
+        assert res[0][1] == res[1][1], fmt
+        assert np.array_equal(res[0][0], res[1][0]), fmt
+        for r in range(4):
+            assert true_rel(cfg, W, N, 0.05, res[1][0][0, r], b[r]) <= 1e-10
+
+
 def test_graph_coarsest_replays_match_eager(torch, mg, cubic):
     """The coarsest solve captured into a HIP graph (graph_coarsest 1, one
     CA-GCR cycle) and replayed: three solves of the same batch on one
