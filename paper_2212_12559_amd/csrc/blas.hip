@@ -667,67 +667,87 @@ void launch_gcr_scalars(const double2* qq, const double2* qr, const int* mask, i
 // (FP64).  G[i][j] = <q_i, q_j> given for i <= j in slot order
 // (0,0),(0,1)..(0,s-1),(1,1),...; c_i = <q_i, r> in slots after them.
 // A pivot below 1e-13 of the largest diagonal truncates the basis there.
+// One wavefront per system with G in LDS: lane i owns row i, so each column
+// of the factor, and each step of the two triangular solves, is one parallel
+// update (a thread-per-system version kept G in scratch memory and took
+// 0.23 ms per launch at s = 16).
 template <int S>
-__global__ void cagcr_solve_kernel(const double2* gram, int s, int nrhs, int ldr, const int* mask,
-                                   double2* coef) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  double2 G[S][S];
-  double2 c[S];
-  int p = 0;
-  for (int i = 0; i < s; ++i)
-    for (int j = i; j < s; ++j) {
-      const double2 g = gram[(int64_t)(p++) * ldr + r];
+__global__ void __launch_bounds__(64) cagcr_solve_kernel(const double2* gram, int s, int nrhs, int ldr,
+                                                         const int* mask, double2* coef) {
+  __shared__ double2 G[S][S + 1];
+  __shared__ double2 c[S];
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int np = s * (s + 1) / 2;
+  for (int p = lane; p < np + s; p += 64) {
+    const double2 g = gram[(int64_t)p * ldr + r];
+    if (p < np) {   // packed upper triangle: row i starts at i s - i (i - 1) / 2
+      int i = 0, off = 0;
+      while (off + (s - i) <= p) { off += s - i; ++i; }
+      const int j = i + (p - off);
       G[i][j] = g;
       G[j][i] = make_double2(g.x, -g.y);
+    } else {
+      c[p - np] = g;
     }
-  for (int i = 0; i < s; ++i) c[i] = gram[(int64_t)(p++) * ldr + r];
+  }
+  __syncthreads();
   double dmax = 0.0;
   for (int i = 0; i < s; ++i) dmax = fmax(dmax, G[i][i].x);
-  int k = s;
-  // Cholesky G = L L^dag, L stored in G's lower triangle
-  for (int j = 0; j < s && k == s; ++j) {
+  int k = s;   // the same on every lane
+  // Cholesky G = L L^dag, L in G's lower triangle
+  for (int j = 0; j < s; ++j) {
     double d = G[j][j].x;
     for (int q = 0; q < j; ++q) d -= G[j][q].x * G[j][q].x + G[j][q].y * G[j][q].y;
     if (!(d > 1e-13 * dmax)) { k = j; break; }
     const double ljj = sqrt(d);
-    G[j][j] = make_double2(ljj, 0.0);
-    for (int i = j + 1; i < s; ++i) {
-      double2 v = G[i][j];
+    if (lane > j && lane < s) {
+      double2 v = G[lane][j];
       for (int q = 0; q < j; ++q) {   // v -= L[i][q] conj(L[j][q])
-        const double2 a = G[i][q], b = G[j][q];
+        const double2 a = G[lane][q], b = G[j][q];
         v.x -= a.x * b.x + a.y * b.y;
         v.y -= a.y * b.x - a.x * b.y;
       }
-      G[i][j] = make_double2(v.x / ljj, v.y / ljj);
+      G[lane][j] = make_double2(v.x / ljj, v.y / ljj);
     }
+    __syncthreads();   // column j complete; everyone has read G[j][j]
+    if (lane == 0) G[j][j] = make_double2(ljj, 0.0);
+    __syncthreads();
   }
-  double2 y[S];
-  for (int i = 0; i < k; ++i) {   // L y = c
-    double2 v = c[i];
-    for (int q = 0; q < i; ++q) {
-      const double2 a = G[i][q], b = y[q];
-      v.x -= a.x * b.x - a.y * b.y;
-      v.y -= a.x * b.y + a.y * b.x;
+  // L y = c, column by column (y overwrites c)
+  for (int i = 0; i < k; ++i) {
+    const double li = G[i][i].x;
+    const double2 yi = make_double2(c[i].x / li, c[i].y / li);
+    __syncthreads();
+    if (lane == i) c[i] = yi;
+    if (lane > i && lane < k) {
+      const double2 a = G[lane][i];
+      c[lane].x -= a.x * yi.x - a.y * yi.y;
+      c[lane].y -= a.x * yi.y + a.y * yi.x;
     }
-    y[i] = make_double2(v.x / G[i][i].x, v.y / G[i][i].x);
+    __syncthreads();
   }
-  for (int i = k - 1; i >= 0; --i) {   // L^dag a = y
-    double2 v = y[i];
-    for (int q = i + 1; q < k; ++q) {  // v -= conj(L[q][i]) a[q]
-      const double2 a = G[q][i], b = y[q];
-      v.x -= a.x * b.x + a.y * b.y;
-      v.y -= a.x * b.y - a.y * b.x;
+  // L^dag a = y: once a_i is known, rows q < i drop conj(L[i][q]) a_i
+  for (int i = k - 1; i >= 0; --i) {
+    const double li = G[i][i].x;
+    const double2 ai = make_double2(c[i].x / li, c[i].y / li);
+    __syncthreads();
+    if (lane == i) c[i] = ai;
+    if (lane < i) {
+      const double2 a = G[i][lane];
+      c[lane].x -= a.x * ai.x + a.y * ai.y;
+      c[lane].y -= a.x * ai.y - a.y * ai.x;
     }
-    y[i] = make_double2(v.x / G[i][i].x, v.y / G[i][i].x);
+    __syncthreads();
   }
   const bool on = mask == nullptr || mask[r] != 0;
-  for (int i = 0; i < s; ++i) coef[(int64_t)i * ldr + r] = (on && i < k) ? y[i] : make_double2(0.0, 0.0);
+  if (lane < s) coef[(int64_t)lane * ldr + r] = (on && lane < k) ? c[lane] : make_double2(0.0, 0.0);
 }
 void launch_cagcr_solve(const double2* gram, int s, int nrhs, int ldr, const int* mask, double2* coef,
                         hipStream_t st) {
-  if (s <= kMaxS) cagcr_solve_kernel<kMaxS><<<(nrhs + 63) / 64, 64, 0, st>>>(gram, s, nrhs, ldr, mask, coef);
-  else cagcr_solve_kernel<kMaxCA><<<(nrhs + 15) / 16, 16, 0, st>>>(gram, s, nrhs, ldr, mask, coef);
+  if (nrhs <= 0) return;
+  if (s <= kMaxS) cagcr_solve_kernel<kMaxS><<<nrhs, 64, 0, st>>>(gram, s, nrhs, ldr, mask, coef);
+  else cagcr_solve_kernel<kMaxCA><<<nrhs, 64, 0, st>>>(gram, s, nrhs, ldr, mask, coef);
 }
 
 // CG scalars: alpha = rr / pAp, -alpha; beta = rr_new / rr (rr updated in place)

@@ -561,14 +561,23 @@ def test_coarse_multi_matches_separate(torch, mg):
     rhs each as in the uneven batch) applied in one persistent launch over
     their common work list equal, bit for bit, the same operators applied
     context by context (16 rhs per workgroup in both); mixed formats and
-    sizes are refused."""
+    sizes are refused.  The 8^4 context's result is also checked against the
+    oracle's block-preconditioned operator of the same hierarchy (links and
+    inputs rounded to bf16, identity self block added unrounded) under the
+    FP32 summation bound of test_coarse_mfma_16bit."""
+    from oracle import solvers as sol
     dev = "cuda:0"
     ctxs, xs, want = [], [], []
     rng = np.random.default_rng(99)
+    oracle_case = None
     for L in (8, 12, 16):
         dims = (L, L, L, L)
         W, N, _ = latgen.hisq_style_links(dims, 0.5, 900 + L)
         nv = [latgen.fine_vectors(dims, 48, rng)]
+        if L == 8:
+            op = sol.MGParams(dims=dims, c1=9.0 / 8.0, c3=-1.0 / 24.0, kd_naik=False, blocks=((4, 4, 4, 4),),
+                              coarse_op="block")
+            oracle_case = sol.Hierarchy(op, W, N, 0.05, nv)
         p = mg.default_params(dims, nagg=1, nvec=(48, 1), block=[(4, 4, 4, 4)], kd_naik=0, mass0=0.05,
                               coarse_prec=mg.MG_CBF16, max_nrhs=12)
         log(f"[multi] setup {dims}")
@@ -582,6 +591,26 @@ def test_coarse_multi_matches_separate(torch, mg):
     torch.cuda.synchronize()
     for g, w in zip(got, want):
         assert torch.equal(g, w)
+    # the 8^4 result against the oracle
+    H = oracle_case
+    Lk = H.level_links(2)
+    n = Lk.shape[-1]
+    assert np.max(np.abs(Lk[:, 0] - np.eye(n))) < 1e-12   # coarse extents 2: the self block is the identity
+    hops = Lk.copy()
+    hops[:, 0] = 0.0
+    Lr = ops.round_bf16(hops.real) + 1j * ops.round_bf16(hops.imag)
+    La = np.abs(Lr.real) + np.abs(Lr.imag)
+    k2 = 2 * 8 * n
+    g = gamma(k2, 2.0 ** -23)
+    cd = H.cdims[0]
+    x = xs[0].cpu().numpy()
+    y = got[0].cpu().numpy().astype(np.complex128)
+    for r in range(x.shape[0]):
+        xr = ops.round_bf16(x[r].real) + 1j * ops.round_bf16(x[r].imag)
+        want_r = ops.coarse_apply_links(Lr, cd, xr) + x[r].astype(np.complex128)
+        lim = g * ops.coarse_apply_links(La, cd, np.abs(xr.real) + np.abs(xr.imag)) + 2.0 ** -23 * np.abs(want_r) + 1e-30
+        d = y[r] - want_r
+        assert np.all(np.abs(d.real) <= lim) and np.all(np.abs(d.imag) <= lim), r
     with pytest.raises((ValueError, mg.MGError)):
         mg.apply_coarse_multi(ctxs[:2], 3, xs[:2])   # no level 3 in these hierarchies
     for c in ctxs:

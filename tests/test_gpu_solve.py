@@ -488,7 +488,9 @@ def test_deflated_bf16_solve(torch, mg, cubic1):
 def test_concurrent_contexts_match_sequential(torch, mg, cubic, cubic1):
     """Two contexts (different hierarchies) solved at the same time from two
     host threads on two streams give exactly the results of solving them one
-    after the other: the library keeps no state outside a context."""
+    after the other: the library keeps no state outside a context.  Every
+    concurrent solution's true residual, recomputed by the oracle's FP64 D,
+    meets the 1e-10 target."""
     import threading
     log("[solve] two contexts on two streams")
     probs = []
@@ -513,6 +515,11 @@ def test_concurrent_contexts_match_sequential(torch, mg, cubic, cubic1):
     for k in range(2):
         assert out[k] is not None
         assert np.array_equal(out[k], seq[k]), k
+        cfg, W, N, nvs, b = (cubic, cubic1)[k]
+        for r in range(b.shape[0]):
+            res = b[r] - ops.dslash(out[k][0, r], W, N, 0.05, cfg["c1"], cfg["c3"])
+            rel = np.linalg.norm(res) / np.linalg.norm(b[r])
+            assert rel <= 1.001e-10, (k, r, rel)
 
 
 def test_multishift_cg_matches_oracle(torch, mg, cubic):
