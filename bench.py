@@ -417,6 +417,21 @@ def force_bench(args, wl, torch, latgen, mg):
            "setup_s": setup_s, "solve_infos": info, "action": S0,
            "gradient_check": {"direction": "Gaussian on every fat-link entry", "step": h, "finite_difference": fd,
                               "gradient": an, "rel_diff": rel}}
+    # against the oracle's force stored for this lattice, mass, eps and seeds (tests/golden: written by a
+    # script that runs only the oracle): 256 fat and 256 Naik link positions and the action
+    fx = os.path.join(ROOT, "tests", "golden", "force24_oracle_sample.npz")
+    if tuple(dims) == (24, 24, 24, 24) and m == 0.01 and wl["eps"] == 0.5 and wl["seed"] == 20221228 \
+            and os.path.exists(fx):
+        ref = np.load(fx)
+        gwn, gnn = gw.cpu().numpy(), gn.cpu().numpy()
+        ew = max(float(np.max(np.abs(gwn[tuple(q)] - g))) for q, g in zip(ref["pos_fat"], ref["grad_fat"]))
+        en = max(float(np.max(np.abs(gnn[tuple(q)] - g))) for q, g in zip(ref["pos_naik"], ref["grad_naik"]))
+        out["oracle_fixture_check"] = {
+            "what": "gradient entries at the 256 + 256 stored positions and the action, against the FP64 oracle's",
+            "fat_max_err_rel_to_largest": ew / float(ref["max_abs_fat"]),
+            "naik_max_err_rel_to_largest": en / float(ref["max_abs_naik"]),
+            "action_rel_err": abs(S0 - float(ref["S"])) / abs(float(ref["S"]))}
+        log(f"[bench] against the oracle's stored force: {out['oracle_fixture_check']}")
     print(json.dumps(out), flush=True)
 
 
@@ -436,11 +451,15 @@ def uneven_bench(args, wl, torch, latgen, mg):
         W, N, rng = latgen.hisq_style_links(dims, wl["eps"], wl["seed"] + i)
         b = torch.from_numpy(latgen.fine_vectors(dims, nr, rng)).to(dev)
         # block-preconditioned coarse levels only where every coarse extent is >= 4: on the 2^4 and 3^4
-        # coarse lattices of 8^4 and 12^4 they raise the outer iteration count (373 -> 615 at 8^4)
+        # coarse lattices of 8^4 and 12^4 they raise the outer iteration count with an iterative coarsest
+        # solve (373 -> 615 at 8^4); coarsest levels of at most 8192 dof (8^4: 1536, 12^4: 7776) are solved
+        # exactly (dense inverse formed at set-up), the larger ones by CA-GCR(16)
         cdims = [d // b for d, b in zip(dims, wl["blocks"][0])]
+        ncl = int(np.prod(cdims)) * 2 * wl["nvec"][0]
         p = mg.default_params(dims, mass0=m, nagg=1, nvec=wl["nvec"], block=wl["blocks"],
                               setup_maxiter=setup_iters + (1,), max_nrhs=nr, kd_naik=wl["kd_naik"], coarse_prec=cp,
-                              outer_nkrylov=8, outer_maxiter=2000, coarse_op=1 if min(cdims) >= 4 else 0)
+                              outer_nkrylov=8, outer_maxiter=2000, coarse_op=1 if min(cdims) >= 4 else 0,
+                              coarsest_solver=2 if ncl <= 8192 and not args.no_direct else 1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx = mg.setup(p, torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev))
@@ -449,8 +468,9 @@ def uneven_bench(args, wl, torch, latgen, mg):
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         tune = ctx.autotune(nr) if cp != mg.MG_C64 else []
-        log(f"[bench] uneven {dims}: setup {setup_s:.2f} s, coarse tiles {tune}")
-        probs.append({"dims": dims, "ctx": ctx, "b": b, "setup_s": setup_s, "tune": tune})
+        log(f"[bench] uneven {dims}: setup {setup_s:.2f} s ({probs_cs(p)} coarsest solve), coarse tiles {tune}")
+        probs.append({"dims": dims, "ctx": ctx, "b": b, "setup_s": setup_s, "tune": tune,
+                      "coarsest_solver": ["GCR", "CA-GCR(16)", "direct"][p.coarsest_solver]})
     coarse_multi = None
     if cp != mg.MG_C64:
         # the four lattices' level-2 operators: one launch each against one persistent launch over
@@ -526,11 +546,16 @@ def uneven_bench(args, wl, torch, latgen, mg):
                                   f"coarse links {args.coarse_prec or wl.get('coarse_prec', 'fp32')}"},
            "sequential_s": seq_s, "systems_per_s_concurrent": nsys / conc_s, "systems_per_s_sequential": nsys / seq_s,
            "per_lattice": [{"dims": list(p["dims"]), "setup_s": p["setup_s"], "coarse_tiles": p["tune"],
+                            "coarsest_solver": p["coarsest_solver"],
                             "alone": a, "concurrent": c} for p, a, c in zip(probs, seq, conc)],
            "coarse_level2_multi": coarse_multi}
     if not args.no_cpu:
         out["cpu_baseline"] = uneven_oracle_leg(wl, probs, keep)
     print(json.dumps(out), flush=True)
+
+
+def probs_cs(p):
+    return ["GCR", "CA-GCR(16)", "direct"][p.coarsest_solver]
 
 
 def uneven_oracle_leg(wl, probs, keep):
@@ -583,6 +608,8 @@ def main():
     ap.add_argument("--coarse-prec", default=None, choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--eps", type=float, default=None,
                     help="roughness of the synthetic links (U = exp(i eps H)); default: the workload's")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="uneven workload: CA-GCR(16) on every coarsest level (no exact small-level solve)")
     ap.add_argument("--mass-batch", type=int, default=None,
                     help="masses per lockstep solve (default: the workload's)")
     ap.add_argument("--nmass", type=int, default=None, help="solve only the first NMASS masses (profiling runs)")

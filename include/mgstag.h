@@ -111,7 +111,10 @@ typedef struct {
   int32_t coarsest_solver;   /* 0: GCR (coarsest_maxiter directions per restart cycle, stop at coarsest_tol);
                                 1: CA-GCR(s), s = coarsest_maxiter, in a Chebyshev basis on [0, lambda_max]
                                 (lambda_max by power iteration at set-up), coarsest_restarts cycles or
-                                coarsest_tol (Table 1: Chebyshev-basis CA-GCR(16)) */
+                                coarsest_tol (Table 1: Chebyshev-basis CA-GCR(16)); 2: exact, x = A^{-1} b
+                                with the dense inverse of the coarsest operator formed at set-up by
+                                Gauss-Jordan elimination with partial pivoting in FP64 (coarsest levels of
+                                at most 8192 dof; not with coarsest_deflate; MG_E_RANK if singular) */
   int32_t graph_coarsest;    /* 1: with coarsest_solver 1 and coarsest_restarts 1 the coarsest solve (a fixed
                                 launch sequence) is captured once per system count into a HIP graph and
                                 replayed (results identical to the eager launches); 0: always eager */

@@ -165,6 +165,11 @@ void launch_diag_block(const double2* L, double2* X, const Geom& g, int n, hipSt
 void launch_unit_self(double2* L, const Geom& g, int n, hipStream_t st);
 void launch_ns_init(const double2* X, double2* Y, int64_t nsite, int n, hipStream_t st);
 void launch_ns_residual(const double2* T, int64_t nsite, int n, unsigned long long* out, hipStream_t st);
+// dense inverse of the coarsest operator (links [site][9][col][row], ns dof per site) by Gauss-Jordan with
+// partial pivoting: M scratch 2 n^2, f n, piv / pinv / status one word each; inverse column-major
+constexpr int64_t kDirectMax = 8192;   // largest coarsest dof count solved directly
+void dense_coarsest_inverse(const double2* links, const Geom& g, int ns, double2* M, double2* f, int* piv,
+                            double2* pinv, int* status, double2* inv64, float2* inv32, hipStream_t st);
 
 // ---------------------------------------------------------------- BLAS
 template <typename T>

@@ -46,7 +46,10 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   if (p.coarsest_deflate > 0 && p.deflate_maxiter < 1) return fail("deflate_maxiter must be >= 1");
   if (p.deflate_import != 0 && p.deflate_import != 1) return fail("deflate_import must be 0 or 1");
   if (p.coarse_op != 0 && p.coarse_op != 1) return fail("coarse_op must be 0 (Galerkin) or 1 (block-preconditioned)");
-  if (p.coarsest_solver != 0 && p.coarsest_solver != 1) return fail("coarsest_solver must be 0 (GCR) or 1 (CA-GCR)");
+  if (p.coarsest_solver < 0 || p.coarsest_solver > 2)
+    return fail("coarsest_solver must be 0 (GCR), 1 (CA-GCR) or 2 (direct)");
+  if (p.coarsest_solver == 2 && p.coarsest_deflate > 0)
+    return fail("coarsest_deflate needs an iterative coarsest solver (coarsest_solver 0 or 1), not the direct one");
   if (p.graph_coarsest != 0 && p.graph_coarsest != 1) return fail("graph_coarsest must be 0 or 1");
   if (p.compact_masses != 0 && p.compact_masses != 1) return fail("compact_masses must be 0 or 1");
   if (p.coarse_shadow != 0 && p.coarse_shadow != 1) return fail("coarse_shadow must be 0 or 1");
@@ -92,6 +95,8 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   const int kd = p.coarsest_deflate;
   const int64_t ncl = gc[p.nagg - 1].V * 2 * A[p.nagg - 1].nvec;   // coarsest-level dof
   if (kd > ncl) return fail("coarsest_deflate exceeds the coarsest level's dimension");
+  if (p.coarsest_solver == 2 && ncl > kDirectMax)
+    return fail("coarsest_solver 2 (direct) needs a coarsest level of at most 8192 dof");
   if (c) {
     c->P = p;
     c->g0 = g0;
@@ -140,6 +145,11 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     dg = P((size_t)kd * kd * 16);
     drm = P((size_t)kd * kd * 16);
     dri = P((size_t)kd * kd * 16);
+  }
+  void *dinv64 = nullptr, *dinv32 = nullptr;
+  if (p.coarsest_solver == 2) {   // dense inverse of the coarsest operator (column-major)
+    dinv64 = P((size_t)ncl * ncl * 16);
+    dinv32 = P((size_t)ncl * ncl * 8);
   }
   void* status = P(256);
   // ---- scratch
@@ -233,6 +243,9 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     if (c16) e += (size_t)swizzled_link_elems(gc[lc].V, (int)nc) * 2 + 256;
     setup_end = std::max(setup_end, e);
   }
+  if (p.coarsest_solver == 2)   // Gauss-Jordan: [A | 1] (FP64, n x 2n), the factor column, pivot words
+    setup_end = std::max(setup_end, solver_base + (((size_t)2 * ncl * ncl * 16 + 255) & ~(size_t)255) +
+                                        (((size_t)ncl * 16 + 255) & ~(size_t)255) + 512);
   scr.off = std::max(solver_end, setup_end);
   if (c) {
     c->fat64 = (double2*)fat64; c->fat32 = (float2*)fat32; c->fat32p = (float4*)fat32p;
@@ -264,6 +277,8 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
     c->defl_rm = (double2*)drm;
     c->defl_rinv = (double2*)dri;
     c->defl_c = (double2*)dcoef;
+    c->dinv64 = (double2*)dinv64;
+    c->dinv32 = (float2*)dinv32;
     for (int l = 0; l < 2; ++l)
       for (int q = 0; q < 2; ++q) c->shadow16[l][q] = (uint32_t*)sh16[l][q];
     c->scal = (double2*)scal;
@@ -791,6 +806,12 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   }
   launch_conv(lmask(lvl), nullptr, r0, tol * tol, nsys, 1, st);
   check_launch();
+  if (coarsest && P.coarsest_solver == 2) {   // exact: x = A^{-1} b (one product)
+    stats.level[lvl - 1] += 1;
+    direct_apply(lvl, prec, B.x.p, B.b.p, nsys);
+    if (scaled) lincomb(prec, n, nsys, B.x.p, {{B.x.p, slot(lvl, kSlotScale + 1)}}, {}, {});
+    return;
+  }
   const bool deflated = coarsest && defl_k > 0;
   if (deflated) deflate_start(lvl, nsys);   // x = W' Q^H b, r = b - Q Q^H b
   if (coarsest && P.coarsest_solver == 1) {
@@ -822,8 +843,32 @@ void Ctx::level_solve(int lvl, int nsys, SolveStats& stats) {
   if (scaled) lincomb(prec, n, nsys, B.x.p, {{B.x.p, slot(lvl, kSlotScale + 1)}}, {}, {});
 }
 
+// x = A^{-1} b on the coarsest level (coarsest_solver 2): one column-major
+// product, A^{-1} [n x n] times the nsys right-hand-side columns [n x nsys].
+void Ctx::direct_apply(int lvl, int prec, void* x, const void* b, int nsys) {
+  const int64_t n = L[lvl].n;
+  auto fill = [&](auto& g, auto* Ainv) {
+    using T = std::remove_const_t<std::remove_pointer_t<decltype(g.A)>>;
+    g.A = Ainv; g.lda = n; g.sA = 0; g.a_div = 1;
+    g.B = (const T*)b; g.ldb = n; g.sB = 0;
+    g.C = (T*)x; g.ldc = n; g.sC = 0;
+    g.m = (int)n; g.n = nsys; g.k = (int)n; g.batch = 1;
+    g.alpha = 1.0; g.beta = 0.0;
+    launch_bgemm(g, st);
+  };
+  if (prec == P64) {
+    BGemmArgs<double2> g{};
+    fill(g, dinv64);
+  } else {
+    BGemmArgs<float2> g{};
+    fill(g, dinv32);
+  }
+  check_launch();
+}
+
 // CA-GCR(s) cycles on the coarsest level (Table 1: Chebyshev-basis CA-GCR):
-// p_0 = r, p_1 = (A - c) p_0 / d, p_{j+1} = 2 (A - c) p_j / d - p_{j-1}, with
+// p_0 = r, p_1 = (A - c) p_0 / d, p_{j+1} = 2 (A - c) p_j / d - p_{j-1}, each
+// p_j divided by g^j (g: the basis growth per step measured at set-up), with
 // q_j = A p_j from the s operator applications; one Gram reduction of the
 // q_j and r (FP64), an s x s Cholesky solve per system for the minimiser of
 // |r - sum alpha_j q_j|, then x += sum alpha_j p_j, r -= sum alpha_j q_j.
@@ -836,7 +881,7 @@ void Ctx::coarsest_cagcr(int lvl, int nsys, SolveStats& stats, bool have_x) {
   const int s = P.coarsest_maxiter;
   const int prec = B.prec;
   const int64_t n = B.n;
-  const double c = cheb_c, d = cheb_d;
+  const double c = cheb_c, d = cheb_d, gm = cheb_g;
   double2* gram = tslot(lvl, 0);
   double2* coef = tslot(lvl, 160);
   for (int cyc = 0; cyc < P.coarsest_restarts; ++cyc) {
@@ -845,12 +890,14 @@ void Ctx::coarsest_cagcr(int lvl, int nsys, SolveStats& stats, bool have_x) {
     for (int j = 0; j < s; ++j) {
       apply_level(lvl, B.q[j], B.z[j], nsys);
       if (j + 1 == s) break;
+      // p_j / gm^j: p_1 = (A - c) p_0 / (d gm), p_{j+1} = 2 (A - c) p_j / (d gm) - p_{j-1} / gm^2
       if (j == 0)
         lincomb(prec, n, nsys, B.z[1].p, {{B.q[0].p, nullptr}, {B.z[0].p, nullptr}}, {},
-                {make_double2(1.0 / d, 0.0), make_double2(-c / d, 0.0)});
+                {make_double2(1.0 / (d * gm), 0.0), make_double2(-c / (d * gm), 0.0)});
       else
         lincomb(prec, n, nsys, B.z[j + 1].p, {{B.q[j].p, nullptr}, {B.z[j].p, nullptr}, {B.z[j - 1].p, nullptr}}, {},
-                {make_double2(2.0 / d, 0.0), make_double2(-2.0 * c / d, 0.0), make_double2(-1.0, 0.0)});
+                {make_double2(2.0 / (d * gm), 0.0), make_double2(-2.0 * c / (d * gm), 0.0),
+                 make_double2(-1.0 / (gm * gm), 0.0)});
     }
     auto fill = [&](auto& a) {
       using TP = decltype(a.u[0]);

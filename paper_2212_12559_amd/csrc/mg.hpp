@@ -93,6 +93,7 @@ struct Ctx {
   bool unit_self[2]{};      // the stored self block is exactly the identity (the 16-bit stencil skips it)
   uint32_t* shadow16[2][2]{};   // 16-bit copies of the smoother chain's outputs per coarse level (coarse_shadow)
   double cheb_c = 1.0, cheb_d = 1.0;   // CA-GCR coarsest solver: Chebyshev basis of (A - c) / d
+  double cheb_g = 1.0;                 // its per-step growth: basis vector j is divided by cheb_g^j
   int tune[2][3][2]{};      // autotuned (rt, mt) of the 16-bit stencil per level and rhs class (0: built-in)
   std::map<int, hipGraphExec_t> coarsest_graphs;   // captured coarsest solves, by system count
   hipStream_t capture_st = nullptr;
@@ -195,6 +196,10 @@ struct Ctx {
   void deflate_start(int lvl, int nsys);
   void coarsest_cagcr(int lvl, int nsys, SolveStats& stats, bool have_x);
   void estimate_lambda_max();
+  double2* dinv64 = nullptr;            // coarsest_solver 2: A^{-1} of the coarsest operator (column-major)
+  float2* dinv32 = nullptr;
+  void build_direct();                  // set-up: dense coarsest inverse by Gauss-Jordan
+  void direct_apply(int lvl, int prec, void* x, const void* b, int nsys);   // x = A^{-1} b
   void galerkin(int l);
   void finish_links(int l);          // FP32 copy and 16-bit fragments of cl64[l]
   void precondition_links(int l);    // X^{-1} and cl64[l] <- X^{-1} cl64[l] (coarse_op 1)

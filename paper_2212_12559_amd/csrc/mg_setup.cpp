@@ -44,8 +44,33 @@ void Ctx::setup(const void* fat, const void* naik, const void* const* nvs) {
   }
   if (defl_k > 0) build_deflation(nvs && P.deflate_import ? nvs[P.nagg] : nullptr);
   if (P.coarsest_solver == 1) estimate_lambda_max();
+  if (P.coarsest_solver == 2) build_direct();
   setup_phase = false;
   HIPCHK(hipStreamSynchronize(st));
+}
+
+// Exact coarsest solve (coarsest_solver 2): the dense matrix of the coarsest
+// operator, assembled from its FP64 links (block-preconditioned ones when
+// coarse_op is 1, matching the X^{-1} b of the level solve), inverted by
+// Gauss-Jordan with partial pivoting in FP64.
+void Ctx::build_direct() {
+  const int lc = P.nagg - 1;
+  const int ns = ncoarse[lc];
+  const int64_t n = gc[lc].V * ns;
+  const size_t mb = ((size_t)2 * n * n * 16 + 255) & ~(size_t)255;
+  const size_t fb = ((size_t)n * 16 + 255) & ~(size_t)255;
+  double2* M = (double2*)scratch_base;
+  double2* f = (double2*)(scratch_base + mb);
+  int* piv = (int*)(scratch_base + mb + fb);
+  double2* pinv = (double2*)(scratch_base + mb + fb + 256);
+  int* flag = (int*)((char*)status_dev + 160);
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), st));
+  dense_coarsest_inverse(cl64[lc], gc[lc], ns, M, f, piv, pinv, flag, dinv64, dinv32, st);
+  check_launch();
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad) throw Error{MG_E_RANK, "the coarsest operator is singular: no direct coarsest solve"};
 }
 
 // Largest eigenvalue modulus of the coarsest operator by 30 power iterations
@@ -70,6 +95,48 @@ void Ctx::estimate_lambda_max() {
     lincomb(B.prec, n, 1, v.p, {{w.p, nullptr}}, {}, {make_double2(1.0 / nw[0], 0.0)});
   }
   cheb_c = cheb_d = 0.5 * 1.05 * lam;
+  // Per-step growth of the Chebyshev basis on this operator, from the same
+  // recurrence run on a random vector (every eigencomponent present, so an
+  // upper estimate for the residuals of the solves): for a non-Hermitian
+  // operator the spectrum leaves the real interval and T_j grows there.  The
+  // solver divides basis vector j by gamma^j, which spans the same Krylov
+  // space and keeps the vectors of order one (16-bit stencil inputs in range).
+  // The pair (z_j, z_{j-1}) is renormalised every step; gamma is the
+  // geometric mean of the normalisations.
+  cheb_g = 1.0;
+  const int s = P.coarsest_maxiter;
+  if (s > 2) {
+    const Vec* zm = &B.z[0];
+    const Vec* zc = &B.z[1];
+    const Vec* zn = &B.z[2];
+    const double c = cheb_c, d = cheb_d;
+    if (B.prec == P64) launch_random_normal<double2>((double2*)zm->p, n, P.seed + 4343ull, st);
+    else launch_random_normal<float2>((float2*)zm->p, n, P.seed + 4343ull, st);
+    check_launch();
+    norms_host(B.prec, n, 1, zm->p, slot(lc, kSlotNorm), nv);
+    if (!(nv[0] > 0.0)) return;
+    lincomb(B.prec, n, 1, zm->p, {{zm->p, nullptr}}, {}, {make_double2(1.0 / nv[0], 0.0)});
+    apply_level(lc, w, *zm, 1);
+    lincomb(B.prec, n, 1, zc->p, {{w.p, nullptr}, {zm->p, nullptr}}, {},
+            {make_double2(1.0 / d, 0.0), make_double2(-c / d, 0.0)});
+    double lg = 0.0;
+    for (int j = 1; j < s - 1; ++j) {
+      norms_host(B.prec, n, 1, zc->p, slot(lc, kSlotNorm), nv);
+      if (!(nv[0] > 0.0) || !std::isfinite(nv[0])) return;
+      lg += std::log(nv[0]);
+      lincomb(B.prec, n, 1, zc->p, {{zc->p, nullptr}}, {}, {make_double2(1.0 / nv[0], 0.0)});
+      lincomb(B.prec, n, 1, zm->p, {{zm->p, nullptr}}, {}, {make_double2(1.0 / nv[0], 0.0)});
+      apply_level(lc, w, *zc, 1);
+      lincomb(B.prec, n, 1, zn->p, {{w.p, nullptr}, {zc->p, nullptr}, {zm->p, nullptr}}, {},
+              {make_double2(2.0 / d, 0.0), make_double2(-2.0 * c / d, 0.0), make_double2(-1.0, 0.0)});
+      std::swap(zm, zc);
+      std::swap(zc, zn);
+    }
+    norms_host(B.prec, n, 1, zc->p, slot(lc, kSlotNorm), nv);
+    if (!(nv[0] > 0.0) || !std::isfinite(nv[0])) return;
+    lg += std::log(nv[0]);
+    cheb_g = std::max(1.0, std::exp(lg / (s - 1)));
+  }
 }
 
 // Naik links: the full FP64 / FP32 copies, and the 13-real form (Sec. 3.1)

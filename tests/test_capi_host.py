@@ -89,6 +89,8 @@ def test_default_params_table1(m):
     (dict(deflate_import=2), "deflate_import"),
     (dict(coarse_op=2), "coarse_op"),
     (dict(coarsest_solver=3), "coarsest_solver"),
+    (dict(dims=(32, 32, 32, 32), coarsest_solver=2), "8192"),
+    (dict(coarsest_solver=2, coarsest_deflate=16), "iterative"),
     (dict(graph_coarsest=2), "graph_coarsest"),
     (dict(compact_masses=5), "compact_masses"),
     (dict(coarse_shadow=3), "coarse_shadow"),
