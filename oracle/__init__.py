@@ -11,8 +11,8 @@ the method).
 Every function is the plain definition (or the algorithm's steps in the
 paper's order) written in numpy, complex128, with no blocking or fusion.
 
-Parity status per function is stated in each docstring; the near-null
-vectors produced by `solvers.cgne_null_vectors` are *parity unpinned*
-(a long random iteration; only quality metrics are checked).
+Every function is pinned by tests/test_oracle_*.py against closed forms,
+dense solves, brute force or invariants (the CGNE near-null iteration by its
+null-space limit and its Krylov-minimiser property on dense matrices).
 """
 from . import operators, solvers  # noqa: F401

@@ -450,8 +450,9 @@ def test_c0_exact_two_level(torch, mg):
 
 
 def test_gpu_null_vectors(torch, mg):
-    """Null vectors generated on the GPU (CGNE on each level's operator;
-    parity unpinned): the transfer built from them is orthonormal
+    """Null vectors generated on the GPU (CGNE on each level's operator from
+    the GPU's own seeded random starts, so checked by their properties rather
+    than element by element): the transfer built from them is orthonormal
     (R P = 1) and the vectors are much closer to the near-null space than
     random vectors; the MG solve converges with them."""
     cfg = CONFIGS["cubic"]

@@ -134,9 +134,52 @@ def test_three_level_solve_small():
     assert info.iters < iters  # MG needs fewer outer iterations than CG iterations
 
 
+def _rank_deficient(rng, n=30, rank=25):
+    U = np.linalg.qr(latgen.complex_normal(rng, (n, n)))[0]
+    V = np.linalg.qr(latgen.complex_normal(rng, (n, n)))[0]
+    s = np.concatenate([np.linspace(0.5, 2.0, rank), np.zeros(n - rank)])
+    return (U * s) @ V.conj().T, V[:, rank:]
+
+
+def test_cgne_limit_is_null_space_projection():
+    """CGNE from phi0 on a rank-deficient dense A converges to the orthogonal
+    projection of phi0 on null(A) (phi0 + A^dag y stays in phi0 + range(A^dag),
+    and A phi = 0 there only at that projection): a closed form."""
+    rng = np.random.default_rng(31)
+    A, V0 = _rank_deficient(rng)
+    phi0 = latgen.complex_normal(rng, (A.shape[0],))
+    phi, it, rel = sol.cgne_null_vector(lambda v: A @ v, lambda v: A.conj().T @ v, phi0, 1e-14, 500)
+    want = V0 @ (V0.conj().T @ phi0)
+    assert np.linalg.norm(phi - want) <= 1e-10 * np.linalg.norm(phi0)
+    assert rel <= 1e-13
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_cgne_iterate_is_krylov_minimiser(k):
+    """After k steps (no early stop), CG on A A^dag y = -A phi0 minimises the
+    A A^dag-norm error over K_k(A A^dag, -A phi0), i.e. phi_k = phi0 + A^dag y_k
+    is the point of phi0 + A^dag K_k closest to the limit phi* (the null-space
+    projection): brute force by least squares on the explicit power basis."""
+    rng = np.random.default_rng(37)
+    A, V0 = _rank_deficient(rng)
+    Ad = A.conj().T
+    phi0 = latgen.complex_normal(rng, (A.shape[0],))
+    phi, it, _ = sol.cgne_null_vector(lambda v: A @ v, lambda v: Ad @ v, phi0, 0.0, k)
+    assert it == k
+    r0 = -A @ phi0
+    K = [r0]
+    for _ in range(k - 1):
+        K.append(A @ (Ad @ K[-1]))
+    B = Ad @ np.stack(K, axis=1)
+    star = V0 @ (V0.conj().T @ phi0)
+    c = np.linalg.lstsq(B, star - phi0, rcond=None)[0]
+    assert np.linalg.norm(phi - (phi0 + B @ c)) <= 1e-10 * np.linalg.norm(phi0)
+
+
 def test_cgne_null_vectors_reduce_A():
-    """Quality metric only (null vectors are parity unpinned): ||A phi|| / ||phi||
-    falls well below its value on the random start."""
+    """Quality on the KD operator (the closed form and the Krylov minimiser
+    pin the iteration itself): ||A phi|| / ||phi|| falls well below its value
+    on the random start."""
     dims = (4, 4, 4, 4)
     W, N, rng = latgen.hisq_style_links(dims, 0.5, 24)
     m = 0.01
