@@ -125,6 +125,10 @@ typedef struct {
                                 level the stencil also stores its output rounded to the link format, and the
                                 next application reads those 16-bit inputs (results unchanged; half the
                                 staging reads, one more write); 0 (default): off */
+  int32_t cgne_start_import; /* 1: an imported level's null_vectors entry is the CGNE's starting vectors
+                                instead of the near-null vectors themselves (the set-up still runs
+                                setup_maxiter CGNE iterations on them); 0 (default): imported vectors are
+                                used as they are */
   uint64_t seed;             /* seed of the GPU-generated null-vector starts */
 } mg_params;
 

@@ -139,6 +139,7 @@ void mg_default_params(mg_params* p, const int32_t dims[4]) {
   p->graph_coarsest = 1;
   p->compact_masses = 1;
   p->coarse_shadow = 0;   // measured no faster on the 64-rhs level-2 stencil
+  p->cgne_start_import = 0;
   p->seed = 20221224ull;
 }
 

@@ -53,6 +53,7 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
   if (p.graph_coarsest != 0 && p.graph_coarsest != 1) return fail("graph_coarsest must be 0 or 1");
   if (p.compact_masses != 0 && p.compact_masses != 1) return fail("compact_masses must be 0 or 1");
   if (p.coarse_shadow != 0 && p.coarse_shadow != 1) return fail("coarse_shadow must be 0 or 1");
+  if (p.cgne_start_import != 0 && p.cgne_start_import != 1) return fail("cgne_start_import must be 0 or 1");
   const bool naik_kd = p.c3 != 0.0 && p.kd_naik;
   Geom g0{};
   g0.V = 1;

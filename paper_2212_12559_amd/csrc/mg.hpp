@@ -191,7 +191,7 @@ struct Ctx {
   void update_links(const void* fat, const void* naik);
   void build_level(int l, const void* nv_import);
   void pack_naik(const void* naik);
-  void cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2* out);
+  void cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2* out, const double2* start = nullptr);
   void build_deflation(const void* nv_import);
   void deflate_start(int lvl, int nsys);
   void coarsest_cagcr(int lvl, int nsys, SolveStats& stats, bool have_x);

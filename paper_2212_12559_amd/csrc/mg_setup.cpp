@@ -158,10 +158,10 @@ void Ctx::pack_naik(const void* naik) {
 void Ctx::build_level(int l, const void* imp) {
   const Agg& a = A[l];
   const int64_t nflat = a.nagg * 2 * a.nrows;
-  if (imp) {
+  if (imp && !P.cgne_start_import) {
     HIPCHK(hipMemcpyAsync(nv[l], imp, (size_t)a.nvec * nflat * 16, hipMemcpyDeviceToDevice, st));
   } else {
-    cgne_null(l, a.nvec, nflat, P.setup_maxiter[l], P.setup_tol[l], nv[l]);
+    cgne_null(l, a.nvec, nflat, P.setup_maxiter[l], P.setup_tol[l], nv[l], (const double2*)imp);
   }
   launch_gather_null(nv[l], nflat, pp64[l], a, st);
   check_launch();
@@ -177,14 +177,15 @@ void Ctx::build_level(int l, const void* imp) {
   galerkin(l);
 }
 
-// Near-null vectors by CGNE on A phi = 0 from seeded random starts, all nvec
+// Near-null vectors by CGNE on A phi = 0 from seeded random starts (or the
+// caller's starting vectors, FP64), all nvec
 // vectors as one batch (Sec. 2.1, Table 1: CGNE to tol or maxiter):
 //   t = A^dag p, alpha = |r|^2 / |t|^2, phi += alpha t, r -= alpha A t, ...
 // l = 0: A = (B + m0)^{-1} D, A^dag = eps D (B + m0)^{-1} eps.
 // l >= 1: the coarse operator of level l + 1 and its adjoint stencil.
 // nvec vectors of n entries; the result goes to `out` (FP64) and stays in
 // the first scratch block in the level's precision.
-void Ctx::cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2* out) {
+void Ctx::cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2* out, const double2* start) {
   const int nv_ = nvec;
   const int prec = L[l + 1].prec;
   const int lc = l - 1;   // coarse-level index of the operator for l >= 1
@@ -255,8 +256,14 @@ void Ctx::cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2
       check_launch();
     }
   };
-  if (prec == P64) launch_random_normal<double2>((double2*)phi, (int64_t)nv_ * n, P.seed + 7919ull * l, st);
-  else launch_random_normal<float2>((float2*)phi, (int64_t)nv_ * n, P.seed + 7919ull * l, st);
+  if (start) {   // caller's starting vectors (FP64), in the level's precision
+    if (prec == P64) launch_convert<double2, double2>((double2*)phi, start, (int64_t)nv_ * n, st);
+    else launch_convert<double2, float2>((float2*)phi, start, (int64_t)nv_ * n, st);
+  } else if (prec == P64) {
+    launch_random_normal<double2>((double2*)phi, (int64_t)nv_ * n, P.seed + 7919ull * l, st);
+  } else {
+    launch_random_normal<float2>((float2*)phi, (int64_t)nv_ * n, P.seed + 7919ull * l, st);
+  }
   check_launch();
   A_apply(r, phi, false);
   lincomb(prec, n, nv_, r, {{r, nullptr}}, {1}, {});

@@ -54,6 +54,7 @@ class MGParams(ctypes.Structure):
         ("graph_coarsest", ctypes.c_int32),
         ("compact_masses", ctypes.c_int32),
         ("coarse_shadow", ctypes.c_int32),
+        ("cgne_start_import", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 

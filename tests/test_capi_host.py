@@ -94,6 +94,7 @@ def test_default_params_table1(m):
     (dict(graph_coarsest=2), "graph_coarsest"),
     (dict(compact_masses=5), "compact_masses"),
     (dict(coarse_shadow=3), "coarse_shadow"),
+    (dict(cgne_start_import=2), "cgne_start_import"),
     (dict(dims=(8, 8, 8, 8), nvec=(8, 8), coarsest_deflate=32), "dimension"),
 ])
 def test_workspace_validation(m, bad, why):

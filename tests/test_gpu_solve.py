@@ -449,6 +449,38 @@ def test_c0_exact_two_level(torch, mg):
     assert true_rel(cfg, W, N, cfg["mass0"], x.cpu().numpy()[0, 0], b[0]) <= 1e-10
 
 
+def test_gpu_cgne_matches_oracle(torch, mg):
+    """The set-up's CGNE from imported starting vectors (cgne_start_import 1,
+    FP64 levels) against the oracle's cgne_null_vector from the same starts:
+    the level-1 vectors after 12 iterations on the KD operator (Naik kept),
+    then the level-2 vectors after 8 iterations on the Galerkin operator the
+    oracle builds from its own level-1 vectors, element by element.  CG in
+    FP64 over a dozen steps keeps the two within 1e-9 of each other."""
+    from gpu_common import random_null_vectors
+    cfg = CONFIGS["cubic"]
+    W, N, rng = links(cfg)
+    m = cfg["mass0"]
+    starts = random_null_vectors(cfg, rng)
+    log("[setup] cubic GPU CGNE from imported starts vs oracle")
+    ctx = make_ctx(torch, mg, cfg, W, N, starts, fine_prec=mg.MG_C128, coarse_prec=mg.MG_C128, max_nrhs=1,
+                   cgne_start_import=1, setup_maxiter=(12, 8), setup_tol=(0.0, 0.0))
+    nv1 = ctx.export(1, 1).cpu().numpy().reshape(starts[0].shape)
+    nv2 = ctx.export(1, 2).cpu().numpy().reshape(starts[1].shape)
+    ctx.destroy()
+    c3kd = cfg["c3"] if cfg["kd_naik"] else 0.0
+    Kinv = ops.kd_inverse(W, m, cfg["c1"])
+    A = lambda v: ops.kd_operator(v, W, N, Kinv, m, cfg["c1"], c3kd)
+    Ad = lambda v: ops.kd_operator_dagger(v, W, N, Kinv, m, cfg["c1"], c3kd)
+    want1 = np.stack([sol.cgne_null_vector(A, Ad, starts[0][k], 0.0, 12)[0] for k in range(len(starts[0]))])
+    e1 = rel_err(nv1, want1)
+    H1 = oracle_hierarchy(dict(cfg, blocks=cfg["blocks"][:1]), W, N, m, [want1])
+    want2 = np.stack([sol.cgne_null_vector(lambda v: H1.op(2, v), lambda v: H1.op_dag(2, v), starts[1][k], 0.0, 8)[0]
+                      for k in range(len(starts[1]))])
+    e2 = rel_err(nv2, want2)
+    log(f"    level 1 rel err {e1:.2e}, level 2 rel err {e2:.2e}")
+    assert e1 < 1e-9 and e2 < 1e-9, (e1, e2)
+
+
 def test_gpu_null_vectors(torch, mg):
     """Null vectors generated on the GPU (CGNE on each level's operator from
     the GPU's own seeded random starts, so checked by their properties rather
