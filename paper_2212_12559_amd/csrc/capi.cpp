@@ -81,18 +81,7 @@ mg_status mg::apply_dslash_with(Ctx& c, int32_t op, double mass, int32_t dtype, 
           launch_kd_apply(a, c.st);
         }
       } else {
-        c.apply_D(prec, tmp, in, nrhs, c.P.kd_naik != 0, nullptr, mass);
-        if (prec == P64) {
-          KdArgs<double> a{};
-          a.out = (double2*)out; a.in = (const double2*)tmp; a.kinv = c.kinv64 + off; a.g = c.g0;
-          a.in_stride = a.out_stride = c.g0.V * 3; a.nrhs = nrhs; a.slot_stride = c.kinv_slot;
-          launch_kd_apply(a, c.st);
-        } else {
-          KdArgs<float> a{};
-          a.out = (float2*)out; a.in = (const float2*)tmp; a.kinv = c.kinv32 + off; a.g = c.g0;
-          a.in_stride = a.out_stride = c.g0.V * 3; a.nrhs = nrhs; a.slot_stride = c.kinv_slot;
-          launch_kd_apply(a, c.st);
-        }
+        c.apply_kd_operator(prec, out, in, tmp, nrhs, nullptr, mass, 0);
       }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) throw Error{MG_E_HIP, hipGetErrorString(e)};

@@ -8,6 +8,8 @@
 // 512 B (FP32) or 1 KiB (FP64) segment; the backward links W'(x-mu) are the
 // same arrays read at the neighbour, served from L2 / Infinity Cache.  A tile
 // of NR right-hand sides shares every link load.
+#include <stdexcept>
+
 #include "kernels.hpp"
 
 namespace mg {
@@ -175,7 +177,10 @@ __global__ void __launch_bounds__(256) dslash_kernel(const DslashArgs<R> a) {
 // and only the +-z, +-t neighbours and the links are read per site (the
 // per-site reads are what bound the plain kernel: address processing, not
 // bytes).
-template <int NR, bool PAIRS>
+// OFF: only the hops that leave the site's 2^4 hypercube (forward where x_mu
+// is odd, backward where it is even) and no mass term; in z and t the choice
+// is uniform over a workgroup's plane, so half of the per-site gathers go.
+template <int NR, bool PAIRS, bool OFF>
 __global__ void __launch_bounds__(256) dslash_plane_kernel(const DslashArgs<float> a) {
   using T = float2;
   extern __shared__ float4 lds4[];
@@ -249,7 +254,8 @@ __global__ void __launch_bounds__(256) dslash_plane_kernel(const DslashArgs<floa
         for (int k = 0; k < 9; ++k) U[k] = L[k * V + q];
       }
     };
-    {   // forward hop: W'(x) x(x + mu)
+    const bool odd = (c[mu] & 1) != 0;
+    if (!OFF || odd) {   // forward hop: W'(x) x(x + mu)
       const int64_t sf = mu >= 2 ? site_shift(c, mu, 1, a.g) : 0;
       T U[9];
       load_link(U, s);
@@ -273,7 +279,7 @@ __global__ void __launch_bounds__(256) dslash_plane_kernel(const DslashArgs<floa
         }
       }
     }
-    {   // backward hop: -W'(x - mu)^dag x(x - mu)
+    if (!OFF || !odd) {   // backward hop: -W'(x - mu)^dag x(x - mu)
       const int64_t sb = site_shift(c, mu, -1, a.g);
       T U[9];
       load_link(U, sb);
@@ -311,8 +317,10 @@ __global__ void __launch_bounds__(256) dslash_plane_kernel(const DslashArgs<floa
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       T res = acc[r][i];
-      res.x = fmaf(m, xin[i].x, res.x);
-      res.y = fmaf(m, xin[i].y, res.y);
+      if (!OFF) {
+        res.x = fmaf(m, xin[i].x, res.x);
+        res.y = fmaf(m, xin[i].y, res.y);
+      }
       res.x *= sg;
       res.y *= sg;
       a.out[o + i] = res;
@@ -321,17 +329,38 @@ __global__ void __launch_bounds__(256) dslash_plane_kernel(const DslashArgs<floa
 }
 
 template <int NR>
-static bool launch_plane(const DslashArgs<float>& a, hipStream_t st) {
+static bool plane_fits(const DslashArgs<float>& a) {
   const int L0 = a.g.L[0];
   if (L0 > 256 || 256 % L0 || a.g.L[1] % (256 / L0)) return false;
+  return (size_t)NR * (256 / L0 + 2) * 3 * L0 * sizeof(float2) <= 65536;
+}
+
+template <int NR>
+static bool launch_plane(const DslashArgs<float>& a, hipStream_t st) {
+  if (!plane_fits<NR>(a)) return false;
+  const int L0 = a.g.L[0];
   const int RB = 256 / L0;
   const size_t lds = (size_t)NR * (RB + 2) * 3 * L0 * sizeof(float2);
-  if (lds > 65536) return false;
   const int64_t nplane = a.g.V / 256;
   dim3 grid((unsigned)(nplane * ((a.nrhs + NR - 1) / NR)));
-  if (a.fat_pairs) dslash_plane_kernel<NR, true><<<grid, 256, lds, st>>>(a);
-  else dslash_plane_kernel<NR, false><<<grid, 256, lds, st>>>(a);
+  if (a.off_cube) {
+    if (a.fat_pairs) dslash_plane_kernel<NR, true, true><<<grid, 256, lds, st>>>(a);
+    else dslash_plane_kernel<NR, false, true><<<grid, 256, lds, st>>>(a);
+  } else {
+    if (a.fat_pairs) dslash_plane_kernel<NR, true, false><<<grid, 256, lds, st>>>(a);
+    else dslash_plane_kernel<NR, false, false><<<grid, 256, lds, st>>>(a);
+  }
   return true;
+}
+
+bool dslash_plane_ok(const DslashArgs<float>& a) {
+  if (a.nrhs <= 0 || a.g.V <= 0 || (uintptr_t)a.in % 16 != 0 || a.in_stride % 2 != 0) return false;
+  return a.nrhs == 1 ? plane_fits<1>(a) : plane_fits<4>(a);
+}
+
+bool launch_dslash_plane(const DslashArgs<float>& a, hipStream_t st) {
+  if (!dslash_plane_ok(a)) return false;
+  return a.nrhs == 1 ? launch_plane<1>(a, st) : launch_plane<4>(a, st);
 }
 
 template <typename R, int NR>
@@ -354,6 +383,7 @@ static void launch_nr(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hi
 template <typename R>
 void launch_dslash(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st) {
   if (a.nrhs <= 0 || a.g.V <= 0) return;
+  if (a.off_cube) throw std::runtime_error("dslash: the off-cube form is the plane kernel's (launch_dslash_plane)");
   if constexpr (sizeof(R) == 4) {
     // one-hop FP32 full-lattice stencil: in-plane neighbours through LDS
     if (!naik && !cb && !piece && (uintptr_t)a.in % 16 == 0 && a.in_stride % 2 == 0) {

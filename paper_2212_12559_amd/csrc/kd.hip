@@ -13,6 +13,8 @@
 // matrix stored column-major so each column is one coalesced segment; the
 // hypercube's 48 input components are exchanged between lanes with
 // cross-lane shuffles.
+#include <stdexcept>
+
 #include "kernels.hpp"
 
 namespace mg {
@@ -320,14 +322,32 @@ __global__ void __launch_bounds__(256) kd_apply_mfma_lds_kernel(const KdArgs<flo
       c[e] = xs[rr][xo >> 1][sl * 3 + col];
       if (a.eps_out && (__popc(sl) & 1)) { c[e].x = -c[e].x; c[e].y = -c[e].y; }
     }
-    *reinterpret_cast<float4*>(a.out + (int64_t)(r0 + rr) * a.out_stride + rs * 3 + 2 * q) =
-        make_float4(c[0].x, c[0].y, c[1].x, c[1].y);
+    float4 o4 = make_float4(c[0].x, c[0].y, c[1].x, c[1].y);
+    if (a.add) {   // out = (B+m)^{-1} in + add, add laid out as out
+      const float4 ad = *reinterpret_cast<const float4*>(a.add + (int64_t)(r0 + rr) * a.out_stride + rs * 3 + 2 * q);
+      o4.x += ad.x; o4.y += ad.y; o4.z += ad.z; o4.w += ad.w;
+    }
+    *reinterpret_cast<float4*>(a.out + (int64_t)(r0 + rr) * a.out_stride + rs * 3 + 2 * q) = o4;
   }
+}
+
+bool kd_lds_ok(const KdArgs<float>& a) {
+  const int64_t nhc = a.g.V / 16;
+  return a.nrhs >= 16 && (a.rhs_per_slot <= 0 || a.rhs_per_slot % 16 == 0) && (a.g.L[0] / 2) % 4 == 0 &&
+         nhc % 4 == 0 && (uintptr_t)a.in % 16 == 0 && (uintptr_t)a.out % 16 == 0 &&
+         (a.add == nullptr || (uintptr_t)a.add % 16 == 0) && a.in_stride % 2 == 0 && a.out_stride % 2 == 0;
 }
 
 template <typename R>
 void launch_kd_apply(const KdArgs<R>& a, hipStream_t st) {
   if (a.nrhs <= 0) return;
+  if (a.add != nullptr) {   // only the LDS-staged FP32 kernel adds
+    if constexpr (sizeof(R) == 4) {
+      if (!kd_lds_ok(a)) throw std::runtime_error("kd_apply: add needs the LDS-staged FP32 kernel's shapes");
+    } else {
+      throw std::runtime_error("kd_apply: add is FP32 only");
+    }
+  }
   const int64_t nhc = a.g.V / 16;
   const unsigned gx = (unsigned)((nhc + 3) / 4);
   const bool tile16 = sizeof(R) == 4 && a.nrhs >= 16 && (a.rhs_per_slot <= 0 || a.rhs_per_slot % 16 == 0);

@@ -27,9 +27,15 @@ struct DslashArgs {
   int piece;                // Galerkin piece: 0 self, 1 + 2 mu (+mu face), 2 + 2 mu (-mu face)
   int blk[4];               // aggregation block of the piece decomposition
   int eps_out;              // multiply the result by epsilon(x)
+  int off_cube;             // 1: only the hops that leave the site's 2^4 hypercube, no mass term (the rest of
+                            //    D is B + m, which the KD inverse undoes: (B+m)^{-1} D = 1 + (B+m)^{-1} D_off)
 };
 template <typename R>
 void launch_dslash(const DslashArgs<R>& a, bool naik, bool cb, bool piece, hipStream_t st);
+// the one-hop FP32 stencil with the in-plane neighbours in LDS (the only one that implements off_cube):
+// whether it takes this launch, and the launch itself (false: not applicable, nothing launched)
+bool dslash_plane_ok(const DslashArgs<float>& a);
+bool launch_dslash_plane(const DslashArgs<float>& a, hipStream_t st);
 void launch_pack_links(const double2* src, double2* d64, float2* d32, float4* d32p, const Geom& g, double coef,
                        hipStream_t st);
 void launch_export_fine_index(int32_t* out, const Geom& g, const Agg& A, hipStream_t st);
@@ -58,11 +64,14 @@ struct KdArgs {
   int rhs_per_slot;         // rhs r uses slot r / rhs_per_slot (0: slot 0 for all)
   int64_t slot_stride;
   int eps_in, eps_out;      // (B+m)^{-dag} = eps (B+m)^{-1} eps
+  const cplx<R>* add;       // optional: out = (B+m)^{-1} in + add (add laid out as out)
 };
 void launch_kd_inverse(const double2* fat64, const Geom& g, double mass, double2* out64, float2* out32,
                        hipStream_t st);
 template <typename R>
 void launch_kd_apply(const KdArgs<R>& a, hipStream_t st);
+// the FP32 KD kernel with LDS-staged 16-rhs tiles (the only one that implements `add`)
+bool kd_lds_ok(const KdArgs<float>& a);
 
 // ---------------------------------------------------------------- transfer
 template <typename R>

@@ -371,6 +371,39 @@ void Ctx::apply_KD(int prec, void* out, const void* in, int nsys, bool eps_in, b
   check_launch();
 }
 
+// The KD-level operator A = (B+m)^{-1} D.  D = B + m + D_off with D_off the
+// hops that leave a site's 2^4 hypercube (every Naik hop does), so
+// A = 1 + (B+m)^{-1} D_off: where the one-hop plane stencil and the LDS-staged
+// KD kernel take the launch (FP32, truncated KD, 16-rhs tiles), the stencil
+// computes D_off (half the per-site hops) and the KD kernel adds x; otherwise
+// D then (B+m)^{-1}.  tmp: one level-1 vector block for the intermediate.
+void Ctx::apply_kd_operator(int prec, void* out, const void* in, void* tmp, int nsys, const void* mass_rhs,
+                            double mass, int rps) {
+  const bool naik = P.kd_naik != 0 && P.c3 != 0.0;
+  if (prec == P32 && !naik) {
+    DslashArgs<float> d = dslash_args<float>(*this, tmp, in, nsys);
+    d.off_cube = 1;
+    KdArgs<float> k{};
+    k.out = (float2*)out; k.in = (const float2*)tmp; k.add = (const float2*)in;
+    k.kinv = kinv32 + (int64_t)kd_base * kinv_slot;
+    k.g = g0; k.in_stride = k.out_stride = g0.V * 3; k.nrhs = nsys;
+    k.rhs_per_slot = rps; k.slot_stride = kinv_slot;
+    if (dslash_plane_ok(d) && kd_lds_ok(k)) {
+      prof_mark(MG_PROF_DSLASH, 1);
+      launch_dslash_plane(d, st);
+      prof_mark(MG_PROF_DSLASH, 1);
+      check_launch();
+      prof_mark(MG_PROF_KD, 0);
+      launch_kd_apply(k, st);
+      prof_mark(MG_PROF_KD, 0);
+      check_launch();
+      return;
+    }
+  }
+  apply_D(prec, tmp, in, nsys, naik, mass_rhs, mass);
+  apply_KD(prec, out, tmp, nsys, false, false, rps);
+}
+
 void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, bool dag, const uint32_t* in16,
                        uint32_t* out16) {
   prof_mark(MG_PROF_COARSE, lvl);
@@ -450,8 +483,7 @@ void Ctx::apply_level(int lvl, const Vec& out, const Vec& in, int nsys) {
   if (lvl == 0) {
     apply_D(in.prec, out.p, in.p, nsys, true, m, 0.0);
   } else if (lvl == 1) {
-    apply_D(in.prec, L[1].tmp.p, in.p, nsys, P.kd_naik != 0, m, 0.0);
-    apply_KD(in.prec, out.p, L[1].tmp.p, nsys, false, false, rhs_per_slot);
+    apply_kd_operator(in.prec, out.p, in.p, L[1].tmp.p, nsys, m, 0.0, rhs_per_slot);
   } else {
     apply_coarse(lvl, in.prec, out.p, in.p, nsys, false);
   }

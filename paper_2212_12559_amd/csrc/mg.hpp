@@ -147,6 +147,8 @@ struct Ctx {
   void apply_D(int prec, void* out, const void* in, int nsys, bool naik, const void* mass_rhs, double mass,
                bool eps_out = false);
   void apply_KD(int prec, void* out, const void* in, int nsys, bool eps_in, bool eps_out, int rhs_per_slot);
+  void apply_kd_operator(int prec, void* out, const void* in, void* tmp, int nsys, const void* mass_rhs,
+                         double mass, int rps);   // (B+m)^{-1} D, as 1 + (B+m)^{-1} D_off where it can
   void apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, bool dag,
                     const uint32_t* in16 = nullptr, uint32_t* out16 = nullptr);
   void restrict_(int lvl, int prec, void* out, const void* in, int nsys);

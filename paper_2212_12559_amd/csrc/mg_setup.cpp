@@ -218,8 +218,7 @@ void Ctx::cgne_null(int l, int nvec, int64_t n, int maxiter, double tol, double2
     if (l == 0) {
       const bool nk = P.kd_naik != 0;
       if (!dag) {
-        apply_D(prec, tmp, in, nv_, nk, nullptr, P.mass0);
-        apply_KD(prec, out, tmp, nv_, false, false, 0);
+        apply_kd_operator(prec, out, in, tmp, nv_, nullptr, P.mass0, 0);
       } else {
         apply_KD(prec, tmp, in, nv_, true, false, 0);
         apply_D(prec, out, tmp, nv_, nk, nullptr, P.mass0, true);
