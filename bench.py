@@ -41,6 +41,11 @@ WORKLOADS = {
                     nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 300),
                     masses=(0.005, 0.0084691, 0.014345, 0.024298, 0.041156, 0.069711, 0.11808, 0.2),
                     coarse_prec="fp16", mass_batch=4),
+    # MG against CG toward lighter masses (the Sec. 3.2 mass dependence): the 32^4 fields of c2batch, 16 rhs
+    # per mass, one hierarchy built at the lightest mass, fp16 coarse links
+    "massscan": dict(dims=(32, 32, 32, 32), mass=0.0005, nrhs=16, eps=0.5, seed=20221226, kd_naik=0,
+                     nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 300),
+                     masses=(0.005, 0.002, 0.001, 0.0005), coarse_prec="fp16", kind="massscan"),
     # fermion force (the HMC gradient of phi^dag (D^dag D)^-1 phi) at 24^4 HISQ-style, mass 0.01, one phi
     "force24": dict(dims=(24, 24, 24, 24), mass=0.01, nrhs=1, eps=0.5, seed=20221228, kd_naik=0,
                     nvec=(64, 96), blocks=[(4, 4, 4, 4), (2, 2, 2, 2)], setup_iters=(2000, 300), kind="force",
@@ -309,7 +314,7 @@ def cpu_baseline(wl, batch_infos, s, oracle_check=None):
     counts of the measured MG solves, it gives the oracle's time for the same
     work (Krylov BLAS omitted: a lower bound).
 
-    oracle_check: optional (dims, links (W, N), [(mass, b, x)]) of GPU
+    oracle_check: optional (dims, links (W, N), [(mass, rhs, b, x)]) of GPU
     solutions; their true residuals ||b - D(m) x|| / ||b|| are recomputed with
     the oracle's FP64 operator, with the error bound ||x - x*|| <= ||r|| / m
     that holds because D = m + K with K anti-Hermitian (so ||D^-1|| <= 1 / m)."""
@@ -347,13 +352,14 @@ def cpu_baseline(wl, batch_infos, s, oracle_check=None):
         from oracle import operators as ops
         cdims, (W, N), systems = oracle_check
         rows = []
-        for mass, b, x in systems:
+        for mass, rhs, b, x in systems:
             r = b - ops.dslash(x, W, N, mass, 9.0 / 8.0, -1.0 / 24.0)
             rn, bn, xn = np.linalg.norm(r), np.linalg.norm(b), np.linalg.norm(x)
-            rows.append({"mass": mass, "true_rel_residual": rn / bn, "err_bound_rel_x": rn / (mass * xn)})
-            log(f"[bench] oracle check mass {mass}: residual {rn / bn:.3e}, |x - x*| / |x| <= {rn / (mass * xn):.2e}")
+            rows.append({"mass": mass, "rhs": rhs, "true_rel_residual": rn / bn, "err_bound_rel_x": rn / (mass * xn)})
+            log(f"[bench] oracle check mass {mass} rhs {rhs}: residual {rn / bn:.3e}, "
+                f"|x - x*| / |x| <= {rn / (mass * xn):.2e}")
         out["oracle_check"] = {"what": "true residual of GPU solutions recomputed by the oracle's FP64 D at full "
-                                       "size (rhs 0 of every mass), with the bound |x - x*| <= |r| / m",
+                                       "size (rhs 0 and 1 of every mass), with the bound |x - x*| <= |r| / m",
                                "systems": rows,
                                "worst_true_rel_residual": max(r["true_rel_residual"] for r in rows),
                                "worst_err_bound_rel_x": max(r["err_bound_rel_x"] for r in rows)}
@@ -434,6 +440,62 @@ def force_bench(args, wl, torch, latgen, mg):
             "naik_max_err_rel_to_largest": en / float(ref["max_abs_naik"]),
             "action_rel_err": abs(S0 - float(ref["S"])) / abs(float(ref["S"]))}
         log(f"[bench] against the oracle's stored force: {out['oracle_fixture_check']}")
+    print(json.dumps(out), flush=True)
+
+
+def massscan_bench(args, wl, torch, latgen, mg):
+    """MG-GCR and FP64 Schur CG on the same 16 right-hand sides at masses
+    down to 0.0005 (one hierarchy, built at the lightest mass): MG's outer
+    iteration count stays nearly flat while CG's grows, the behaviour Sec. 3.2
+    reports; the line gives the per-mass times and where MG overtakes CG."""
+    dims = wl["dims"]
+    dev = "cuda:0"
+    W, N, rng = latgen.hisq_style_links(dims, wl["eps"], wl["seed"])
+    bt = torch.from_numpy(latgen.fine_vectors(dims, wl["nrhs"], rng)).to(dev)
+    cp = {"fp32": mg.MG_C64, "bf16": mg.MG_CBF16, "fp16": mg.MG_CF16}[args.coarse_prec or wl["coarse_prec"]]
+    setup_iters = tuple(int(v) for v in args.setup_iters.split(",")) if args.setup_iters else wl["setup_iters"]
+    masses = list(wl["masses"])[:args.nmass]
+    p = mg.default_params(dims, mass0=min(masses), nvec=wl["nvec"], block=wl["blocks"], setup_maxiter=setup_iters,
+                          max_nrhs=wl["nrhs"], max_nmass=1, kd_naik=wl["kd_naik"], coarse_prec=cp, outer_nkrylov=8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = mg.setup(p, torch.from_numpy(W).to(dev), torch.from_numpy(N).to(dev))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    ctx.autotune(wl["nrhs"])
+    log(f"[bench] massscan: setup {setup_s:.2f} s at mass {min(masses)}")
+    rows = []
+    for m in masses:
+        xk = torch.zeros((1,) + ctx.fine_shape, dtype=torch.complex64, device=dev)
+        ctx.apply_dslash(2, m, xk)   # the mass's KD inverse, outside the timing
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info, st = ctx.solve([m], bt, tol=1e-10)
+        torch.cuda.synchronize()
+        mg_s = time.perf_counter() - t0
+        del x
+        t0 = time.perf_counter()
+        xc, info_cg, _ = ctx.cg_solve([m], bt, tol=1e-10)
+        torch.cuda.synchronize()
+        cg_s = time.perf_counter() - t0
+        del xc
+        row = {"mass": m, "mg_s": mg_s, "mg_outer_iters": max(i["outer_iters"] for i in info),
+               "mg_level_iters": info[0]["level_iters"],
+               "mg_worst_residual": max(i["true_rel_residual"] for i in info), "cg_s": cg_s,
+               "cg_iters": max(i["outer_iters"] for i in info_cg),
+               "cg_worst_residual": max(i["true_rel_residual"] for i in info_cg), "mg_over_cg": cg_s / mg_s}
+        rows.append(row)
+        log(f"[bench] massscan m {m}: MG {mg_s:.2f} s ({row['mg_outer_iters']} outer), CG {cg_s:.2f} s "
+            f"({row['cg_iters']} iterations): CG / MG {cg_s / mg_s:.2f}")
+    faster = [r["mass"] for r in rows if r["cg_s"] > r["mg_s"]]
+    out = {"metric": "MG-GCR vs FP64 Schur CG time-to-1e-10 against the mass, 32^4 HISQ-style, 16 rhs per mass",
+           "value": rows[-1]["cg_s"] / rows[-1]["mg_s"], "unit": "CG time / MG time at the lightest mass",
+           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": sum(r["mg_s"] for r in rows) * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 outer GCR, f32 K-cycle, 16-bit coarse links (f32 accumulate); f64 CG", "data": "synthetic",
+           "config": {"workload": f"{'x'.join(map(str, dims))} HISQ-style eps {wl['eps']}, masses {masses}, "
+                                  f"{wl['nrhs']} rhs per mass, hierarchy at mass {min(masses)}"},
+           "setup_s": setup_s, "per_mass": rows, "mg_faster_at": faster}
     print(json.dumps(out), flush=True)
 
 
@@ -649,6 +711,9 @@ def main():
     if wl.get("kind") == "uneven":
         uneven_bench(args, wl, torch, latgen, mg)
         return
+    if wl.get("kind") == "massscan":
+        massscan_bench(args, wl, torch, latgen, mg)
+        return
     out = {"metric": "MG-GCR time-to-1e-10 vs plain CG at 32^4 HISQ; Dslash/coarse GB/s, MFMA %",
            "value": None, "unit": "s", "n_gpus": 1, "steps": 0, "warmup": 0, "ms_per_step": None,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
@@ -731,7 +796,7 @@ def c2batch_bench(args, wl, torch, latgen, mg, out):
     del xk
 
     batch_s = []
-    keep = {}   # rhs 0 of every mass from the last step (for the oracle's residual check)
+    keep = {}   # rhs 0 and 1 of every mass from the last step (for the oracle's residual check)
 
     def mg_step(tag, tol=1e-10, chunks=None):
         # lockstep batches of mb masses x nrhs systems; a line per batch and mass
@@ -749,7 +814,7 @@ def c2batch_bench(args, wl, torch, latgen, mg, out):
                 log(f"[bench] {tag} mass {mj}: {max(i['outer_iters'] for i in ij)} outer, batch level iters "
                     f"{ij[0]['level_iters']}, batch {ij[0]['seconds']:.2f} s, "
                     f"max residual {max(i['true_rel_residual'] for i in ij):.2e}")
-                keep[mj] = x[j, 0].clone()
+                keep[mj] = x[j, :2].clone()   # rhs 0 and 1
             del x
         return info_all
 
@@ -828,7 +893,8 @@ def c2batch_bench(args, wl, torch, latgen, mg, out):
     if not args.no_cpu:
         # one info per lockstep batch (one mass, nrhs systems): counts x nrhs single applications
         batch_infos = [infos[-1][j * nr] for j in range(len(masses))]
-        sample = [(mj, b[0], keep[mj].cpu().numpy()) for mj in masses] if args.oracle_check else []
+        sample = ([(mj, r, b[r], keep[mj][r].cpu().numpy()) for mj in masses for r in range(min(2, nr))]
+                  if args.oracle_check else [])
         out["cpu_baseline"] = cpu_baseline(wl, batch_infos, p.smoother_s,
                                            oracle_check=(dims, (W, N), sample) if sample else None)
     log(f"[bench] {elapsed():.0f} s into the run")
