@@ -184,6 +184,28 @@ def test_default_hierarchy_16bit_production_shapes(torch, mg, fmt):
     ctx.destroy()
 
 
+def test_lockstep_truncated_kd_two_masses(torch, mg):
+    """Two masses x 16 rhs in one lockstep solve with the Naik term truncated
+    in the KD level on the production level shapes: the KD-level operator runs
+    as 1 + (B+m)^{-1} D_off with a KD inverse slot per mass (16-rhs tiles), and
+    every system reaches 1e-10 on the oracle's true residual."""
+    cfg = CONFIGS["prod"]
+    W, N, rng = links(cfg)
+    masses = [0.005, 0.02]
+    b = latgen.fine_vectors(cfg["dims"], 16, rng)
+    log("[solve] prod shapes 16 rhs x 2 masses, truncated KD, fp16")
+    ctx = make_ctx(torch, mg, cfg, W, N, None, max_nrhs=32, max_nmass=2, coarse_prec=mg.MG_CF16, coarse_op=1,
+                   coarsest_solver=1, setup_maxiter=(300, 100))
+    x, info, st = ctx.solve(masses, torch.from_numpy(b).to("cuda:0"), tol=1e-10)
+    x = x.cpu().numpy()
+    log(f"    outer iterations {[i['outer_iters'] for i in info]}, levels {info[0]['level_iters']}")
+    for j, m in enumerate(masses):
+        for r in range(16):
+            assert info[j * 16 + r]["status"] == "MG_OK"
+            assert true_rel(cfg, W, N, m, x[j, r], b[r]) <= 1e-10, (m, r)
+    ctx.destroy()
+
+
 def test_fp64_direct_coarsest_matches_oracle(torch, mg):
     """coarsest_solver 2: the coarsest operator's dense inverse (Gauss-Jordan
     with partial pivoting at set-up) applied as one product per coarsest
