@@ -15,6 +15,7 @@
 // (2^-round(log2 max|L|)) undone on the FP32 result.
 #include <algorithm>
 #include <stdexcept>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -173,10 +174,14 @@ __device__ __forceinline__ void coarse_mfma_site(const CoarseMfmaArgs& a, const 
                 sz = (site / ((int64_t)a.g.L[0] * a.g.L[1])) % a.g.L[2];
   const bool xodd = perm && (sx & 1), yswap = perm && ((sy >> 1) & 1), zswap = perm && ((sz >> 1) & 1);
   const int npass = (kc_n - kc_begin + kMfmaCK - 1) / kMfmaCK;
-  // quads of the staging pass: a thread takes quads tid + q nthreads; their
-  // global loads are issued kStageQ at a time before the first is waited for
+  // quads of the staging pass: quad e = tid + q nthreads holds rhs row
+  // e / (KCH / 4) at k offset 4 (e mod KCH / 4); nthreads is a multiple of 64,
+  // so every quad of a thread has the same k offset (and direction) and its
+  // rows step by nthreads / (KCH / 4).  A thread issues the loads of kStageQ
+  // quads before the first is waited for.
   const int nq = NR * (KCH / 4);
   const int qpt = (nq + nthreads - 1) / nthreads;
+  const int kq = 4 * (tid % (KCH / 4)), jq = tid / (KCH / 4), jstep = nthreads / (KCH / 4);
   // A fragments (Re, Im) of a k-chunk
   auto load_a = [&](uint4 (&dst)[MT][2], int kc) {
 #pragma unroll
@@ -200,19 +205,26 @@ __device__ __forceinline__ void coarse_mfma_site(const CoarseMfmaArgs& a, const 
     // direction (n is a multiple of 16) and are two 16-byte loads (one for
     // 16-bit inputs; inputs are 16-byte aligned) and one 8-byte LDS store per
     // plane
-    for (int q0 = 0; q0 < qpt; q0 += kStageQ) {
-      uint4 raw0[kStageQ], raw1[kStageQ];
+    const int k = kc0 * 32 + kq;
+    const int d = min(k / n, 8);
+    const int64_t cb = nbs[d] * n + (k - d * n);   // offset of this thread's k in an input row
+    // The loads are unconditional (a quad outside the input reads element 0
+    // and is zeroed afterwards) and the input format is a compile-time branch:
+    // loads under per-lane branches let the compiler move the conversion into
+    // the branch and wait there, which left one quad in flight per thread.
+    auto stage = [&](auto in16_tag) {
+      constexpr bool I16 = decltype(in16_tag)::value;
+#pragma unroll 1
+      for (int q0 = 0; q0 < qpt; q0 += kStageQ) {
+        uint4 raw0[kStageQ], raw1[kStageQ];
+        bool ok[kStageQ];
 #pragma unroll
-      for (int q = 0; q < kStageQ; ++q) {
-        const int e = tid + (q0 + q) * nthreads;
-        raw0[q] = make_uint4(0u, 0u, 0u, 0u);
-        raw1[q] = make_uint4(0u, 0u, 0u, 0u);
-        const int jj = e / (KCH / 4);
-        const int k = kc0 * 32 + 4 * (e - jj * (KCH / 4));
-        if (q0 + q < qpt && e < nq && r0 + jj < a.nrhs && k < K) {
-          const int d = k / n, col = k - d * n;
-          const int64_t off = (int64_t)(r0 + jj) * a.in_stride + nbs[d] * n + col;
-          if (a.in16) {
+        for (int q = 0; q < kStageQ; ++q) {
+          const int jj = jq + (q0 + q) * jstep;
+          ok[q] = q0 + q < qpt && jj < NR && r0 + jj < a.nrhs && k < K;
+          const int rr = ok[q] ? r0 + jj : 0;
+          const int64_t off = (int64_t)rr * a.in_stride + (ok[q] ? cb : 0);
+          if constexpr (I16) {
             raw0[q] = *reinterpret_cast<const uint4*>(a.in16 + off);
           } else {
             const uint4* src = reinterpret_cast<const uint4*>(a.in + off);
@@ -220,36 +232,37 @@ __device__ __forceinline__ void coarse_mfma_site(const CoarseMfmaArgs& a, const 
             raw1[q] = src[1];
           }
         }
-      }
 #pragma unroll
-      for (int q = 0; q < kStageQ; ++q) {
-        const int e = tid + (q0 + q) * nthreads;
-        if (q0 + q < qpt && e < nq) {
-          const int jj = e / (KCH / 4);
-          const int kl = 4 * (e - jj * (KCH / 4));
-          uint2 pre, pim;
-          const uint4 c = raw0[q];
-          if (a.in16) {   // four packed 16-bit complex numbers, split into the two planes
-            pre.x = (c.x & 0xFFFFu) | (c.y << 16);
-            pre.y = (c.z & 0xFFFFu) | (c.w << 16);
-            pim.x = (c.x >> 16) | (c.y & 0xFFFF0000u);
-            pim.y = (c.z >> 16) | (c.w & 0xFFFF0000u);
-          } else {
-            const float4 v0 = make_float4(__uint_as_float(c.x), __uint_as_float(c.y), __uint_as_float(c.z),
-                                          __uint_as_float(c.w));
-            const uint4 c1 = raw1[q];
-            const float4 v1 = make_float4(__uint_as_float(c1.x), __uint_as_float(c1.y), __uint_as_float(c1.z),
-                                          __uint_as_float(c1.w));
-            pre.x = (uint32_t)to16<FMT>(v0.x) | ((uint32_t)to16<FMT>(v0.z) << 16);
-            pre.y = (uint32_t)to16<FMT>(v1.x) | ((uint32_t)to16<FMT>(v1.z) << 16);
-            pim.x = (uint32_t)to16<FMT>(v0.y) | ((uint32_t)to16<FMT>(v0.w) << 16);
-            pim.y = (uint32_t)to16<FMT>(v1.y) | ((uint32_t)to16<FMT>(v1.w) << 16);
+        for (int q = 0; q < kStageQ; ++q) {
+          const int jj = jq + (q0 + q) * jstep;
+          if (q0 + q < qpt && jj < NR) {
+            uint2 pre, pim;
+            const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+            const uint4 c = ok[q] ? raw0[q] : z;
+            if constexpr (I16) {   // four packed 16-bit complex numbers, split into the two planes
+              pre.x = (c.x & 0xFFFFu) | (c.y << 16);
+              pre.y = (c.z & 0xFFFFu) | (c.w << 16);
+              pim.x = (c.x >> 16) | (c.y & 0xFFFF0000u);
+              pim.y = (c.z >> 16) | (c.w & 0xFFFF0000u);
+            } else {
+              const float4 v0 = make_float4(__uint_as_float(c.x), __uint_as_float(c.y), __uint_as_float(c.z),
+                                            __uint_as_float(c.w));
+              const uint4 c1 = ok[q] ? raw1[q] : z;
+              const float4 v1 = make_float4(__uint_as_float(c1.x), __uint_as_float(c1.y), __uint_as_float(c1.z),
+                                            __uint_as_float(c1.w));
+              pre.x = (uint32_t)to16<FMT>(v0.x) | ((uint32_t)to16<FMT>(v0.z) << 16);
+              pre.y = (uint32_t)to16<FMT>(v1.x) | ((uint32_t)to16<FMT>(v1.z) << 16);
+              pim.x = (uint32_t)to16<FMT>(v0.y) | ((uint32_t)to16<FMT>(v0.w) << 16);
+              pim.y = (uint32_t)to16<FMT>(v1.y) | ((uint32_t)to16<FMT>(v1.w) << 16);
+            }
+            *reinterpret_cast<uint2*>(Bre + jj * KPC + kq) = pre;
+            *reinterpret_cast<uint2*>(Bim + jj * KPC + kq) = pim;
           }
-          *reinterpret_cast<uint2*>(Bre + jj * KPC + kl) = pre;
-          *reinterpret_cast<uint2*>(Bim + jj * KPC + kl) = pim;
         }
       }
-    }
+    };
+    if (a.in16) stage(std::true_type{});
+    else stage(std::false_type{});
     __syncthreads();
 #pragma unroll
     for (int kcl = 0; kcl < kMfmaCK; ++kcl) {

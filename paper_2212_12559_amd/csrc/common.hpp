@@ -121,17 +121,25 @@ struct Agg {
 };
 
 // flat index (into a single-rhs vector of the fine level) of row `row` of
-// aggregate a, chirality sigma
-__host__ __device__ __forceinline__ int64_t agg_row_index(const Agg& A, int64_t a, int sigma, int row) {
-  int ac[4];
+// aggregate a, chirality sigma, as the aggregate's origin plus the row's
+// offset from it: site_index is linear in the coordinates and an aggregate
+// never wraps around the lattice, so
+//   agg_row_index(A, a, sigma, row) = agg_base(A, a) + agg_row_rel(A, sigma, row)
+// and a kernel that walks the rows of one aggregate takes agg_base once.
+__host__ __device__ __forceinline__ int64_t agg_base(const Agg& A, int64_t a) {
+  int c[4];
   int64_t t = a;
-  ac[0] = (int)(t % A.cd[0]); t /= A.cd[0];
-  ac[1] = (int)(t % A.cd[1]); t /= A.cd[1];
-  ac[2] = (int)(t % A.cd[2]);
-  ac[3] = (int)(t / A.cd[2]);
+  c[0] = (int)(t % A.cd[0]) * A.b[0]; t /= A.cd[0];
+  c[1] = (int)(t % A.cd[1]) * A.b[1]; t /= A.cd[1];
+  c[2] = (int)(t % A.cd[2]) * A.b[2];
+  c[3] = (int)(t / A.cd[2]) * A.b[3];
+  const int64_t s = site_index(c, A.fine);
+  return A.kind == 1 ? s * 3 : s * 2 * (int64_t)A.nvec_in;
+}
+__host__ __device__ __forceinline__ int64_t agg_row_rel(const Agg& A, int sigma, int row) {
   int u[4];
-  if (A.kind == 1) {
-    const int j = row / 3, col = row - 3 * (row / 3);
+  if (A.kind == 1) {   // rows (site of chirality sigma, colour); x runs over the sites of that parity
+    const int j = row / 3, col = row - 3 * j;
     const int hb0 = A.b[0] / 2;
     int rest = j / hb0;
     const int i = j - hb0 * rest;
@@ -139,20 +147,18 @@ __host__ __device__ __forceinline__ int64_t agg_row_index(const Agg& A, int64_t 
     u[2] = rest % A.b[2];
     u[3] = rest / A.b[2];
     u[0] = 2 * i + ((u[1] + u[2] + u[3] + sigma) & 1);
-    int c[4];
-    for (int mu = 0; mu < 4; ++mu) c[mu] = ac[mu] * A.b[mu] + u[mu];
-    return site_index(c, A.fine) * 3 + col;
-  } else {
-    const int j = row / A.nvec_in, k = row - A.nvec_in * (row / A.nvec_in);
-    int rest = j;
-    u[0] = rest % A.b[0]; rest /= A.b[0];
-    u[1] = rest % A.b[1]; rest /= A.b[1];
-    u[2] = rest % A.b[2];
-    u[3] = rest / A.b[2];
-    int c[4];
-    for (int mu = 0; mu < 4; ++mu) c[mu] = ac[mu] * A.b[mu] + u[mu];
-    return (site_index(c, A.fine) * 2 + sigma) * (int64_t)A.nvec_in + k;
+    return site_index(u, A.fine) * 3 + col;
   }
+  const int j = row / A.nvec_in, k = row - A.nvec_in * j;   // rows (site, vector) of chirality sigma
+  int rest = j;
+  u[0] = rest % A.b[0]; rest /= A.b[0];
+  u[1] = rest % A.b[1]; rest /= A.b[1];
+  u[2] = rest % A.b[2];
+  u[3] = rest / A.b[2];
+  return (site_index(u, A.fine) * 2 + sigma) * (int64_t)A.nvec_in + k;
+}
+__host__ __device__ __forceinline__ int64_t agg_row_index(const Agg& A, int64_t a, int sigma, int row) {
+  return agg_base(A, a) + agg_row_rel(A, sigma, row);
 }
 
 // ------------------------------------------------------------------ enums

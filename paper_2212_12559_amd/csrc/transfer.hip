@@ -247,24 +247,34 @@ __global__ void __launch_bounds__(512) restrict_mfma_kernel(const RestrictArgs<f
     yr[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
     yi[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  constexpr int kQ = 8;   // gathered values a thread has in flight before it waits
+  // staging: element e = tid + u nthreads of a pass is fine row
+  // row0 + e % kXferChunk of rhs r0 + e / kXferChunk; nthreads is a multiple
+  // of kXferChunk, so a thread's row is the same for every u and its flat
+  // index is formed once per pass (the aggregate's origin once per block).
+  // The gathers are unconditional (an element outside the input reads
+  // element 0 and is zeroed afterwards), so a thread has kQ in flight.
+  const int64_t abase = agg_base(a.A, agg);
+  const int q = tid % kXferChunk, rq = tid / kXferChunk, rstep = nthreads / kXferChunk;
+  const int upt = (16 * RT + rstep - 1) / rstep;
+  constexpr int kQ = RT == 1 ? 2 : 8;   // gathered values a thread has in flight before it waits
   for (int row0 = 0; row0 < nrows; row0 += kXferChunk) {
     __syncthreads();
-    for (int e0 = tid; e0 < kXferChunk * 16 * RT; e0 += kQ * nthreads) {
+    const bool rok = row0 + q < nrows;
+    const int64_t fi = rok ? abase + agg_row_rel(a.A, sigma, row0 + q) : 0;
+#pragma unroll 1
+    for (int u0 = 0; u0 < upt; u0 += kQ) {
       float2 v[kQ];
+      bool ok[kQ];
 #pragma unroll
       for (int u = 0; u < kQ; ++u) {
-        const int e = e0 + u * nthreads;
-        const int rr = e / kXferChunk, q = e - rr * kXferChunk;   // consecutive threads: consecutive rows
-        v[u] = make_float2(0.f, 0.f);
-        if (e < kXferChunk * 16 * RT && row0 + q < nrows && r0 + rr < a.nrhs)
-          v[u] = a.in[(int64_t)(r0 + rr) * a.in_stride + agg_row_index(a.A, agg, sigma, row0 + q)];
+        const int rr = rq + (u0 + u) * rstep;
+        ok[u] = u0 + u < upt && rr < 16 * RT && rok && r0 + rr < a.nrhs;
+        v[u] = a.in[ok[u] ? (int64_t)(r0 + rr) * a.in_stride + fi : 0];
       }
 #pragma unroll
       for (int u = 0; u < kQ; ++u) {
-        const int e = e0 + u * nthreads;
-        const int rr = e / kXferChunk, q = e - rr * kXferChunk;
-        if (e < kXferChunk * 16 * RT) xs[q][rr] = v[u];
+        const int rr = rq + (u0 + u) * rstep;
+        if (u0 + u < upt && rr < 16 * RT) xs[q][rr] = ok[u] ? v[u] : make_float2(0.f, 0.f);
       }
     }
     __syncthreads();
@@ -334,6 +344,7 @@ __global__ void __launch_bounds__(512) prolong_mfma_kernel(const ProlongArgs<flo
   __syncthreads();
   const int kk = lane >> 4, il = lane & 15;
   const int mt_n = (nrows + 15) / 16;
+  const int64_t abase = agg_base(a.A, agg);
   for (int mt = wave; mt < mt_n; mt += 8) {
     const int row = 16 * mt + il;
     f32x4 yr[RT], yi[RT];
@@ -354,7 +365,7 @@ __global__ void __launch_bounds__(512) prolong_mfma_kernel(const ProlongArgs<flo
       }
     }
     if (row >= nrows) continue;
-    const int64_t fi = agg_row_index(a.A, agg, sigma, row);
+    const int64_t fi = abase + agg_row_rel(a.A, sigma, row);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
@@ -376,6 +387,7 @@ void launch_restrict(const RestrictArgs<R>& a, hipStream_t st) {
   if constexpr (sizeof(R) == 4) {
     if (a.nrhs >= 4) {
       const unsigned gx = (unsigned)(a.A.nagg * 2), nt = 64 * ((a.A.nvec + 15) / 16);
+      static_assert(64 % kXferChunk == 0, "restrict_mfma: a thread's staged row must not change with u");
       if (a.nrhs <= 16) restrict_mfma_kernel<1><<<dim3(gx), nt, 0, st>>>(a);
       else restrict_mfma_kernel<4><<<dim3(gx * (unsigned)((a.nrhs + 63) / 64)), nt, 0, st>>>(a);
       return;
