@@ -337,6 +337,10 @@ mg_status mg_autotune(mg_ctx ctx, int32_t nrhs, mg_tune_info* info, void* stream
  *           MG_PROF_PROLONG: transfer level 1 or 2; MG_PROF_DSLASH: 0 for the
  *           stencil with the Naik term, 1 for the one-hop stencil of the KD
  *           level; MG_PROF_KD: 0.
+ *   nrhs  : 0 times every launch; n > 0 only the launches over exactly n
+ *           systems (a lockstep batch shrinks as its systems converge, and
+ *           a measurement meant for the full batch must not mix in the
+ *           smaller launches).  Negative: MG_E_ARG.
  * mg_profile_stop waits for the recorded events and returns the number of
  * launches and their summed duration in milliseconds, then stops recording.
  * Events are created on first use and kept until mg_destroy (host-side
@@ -350,7 +354,7 @@ typedef enum {
   MG_PROF_PROLONG = 4
 } mg_prof_op;
 
-mg_status mg_profile_start(mg_ctx ctx, int32_t op, int32_t level);
+mg_status mg_profile_start(mg_ctx ctx, int32_t op, int32_t level, int32_t nrhs);
 mg_status mg_profile_stop(mg_ctx ctx, int32_t* launches, double* total_ms);
 
 /* Measured ceilings of the device (measurement aids, not part of the

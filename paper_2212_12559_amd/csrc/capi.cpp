@@ -405,12 +405,14 @@ mg_status mg_autotune(mg_ctx ctx, int32_t nrhs, mg_tune_info* info, void* stream
   return guarded([&] { c.autotune(nrhs, info); });
 }
 
-mg_status mg_profile_start(mg_ctx ctx, int32_t op, int32_t level) {
+mg_status mg_profile_start(mg_ctx ctx, int32_t op, int32_t level, int32_t nrhs) {
   if (!ctx) return fail(MG_E_ARG, "null context");
   if (op < MG_PROF_COARSE || op > MG_PROF_PROLONG) return fail(MG_E_ARG, "op must be an mg_prof_op");
+  if (nrhs < 0) return fail(MG_E_ARG, "nrhs must be 0 (every launch) or positive");
   Ctx& c = ctx->c;
   c.prof_op = op;
   c.prof_level = level;
+  c.prof_nrhs = nrhs;
   c.prof_used = 0;
   return MG_OK;
 }

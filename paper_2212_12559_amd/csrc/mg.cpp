@@ -297,8 +297,8 @@ bool Ctx::plan(const mg_params& p, Ctx* c, Arena& pers, Arena& scr, std::string*
 }
 
 // ================================================================ profiling
-void Ctx::prof_mark(int op, int level) {
-  if (op != prof_op || level != prof_level) return;
+void Ctx::prof_mark(int op, int level, int nsys) {
+  if (op != prof_op || level != prof_level || (prof_nrhs > 0 && nsys != prof_nrhs)) return;
   if (prof_used == prof_events.size()) {
     hipEvent_t e;
     HIPCHK(hipEventCreate(&e));
@@ -333,7 +333,7 @@ static DslashArgs<R> dslash_args(const Ctx& c, void* out, const void* in, int ns
 
 void Ctx::apply_D(int prec, void* out, const void* in, int nsys, bool naik, const void* mass_rhs, double mass,
                   bool eps_out) {
-  prof_mark(MG_PROF_DSLASH, naik && P.c3 != 0.0 ? 0 : 1);
+  prof_mark(MG_PROF_DSLASH, naik && P.c3 != 0.0 ? 0 : 1, nsys);
   naik = naik && P.c3 != 0.0;
   if (prec == P64) {
     auto a = dslash_args<double>(*this, out, in, nsys);
@@ -348,12 +348,12 @@ void Ctx::apply_D(int prec, void* out, const void* in, int nsys, bool naik, cons
     a.eps_out = eps_out;
     launch_dslash(a, naik, false, false, st);
   }
-  prof_mark(MG_PROF_DSLASH, naik && P.c3 != 0.0 ? 0 : 1);
+  prof_mark(MG_PROF_DSLASH, naik && P.c3 != 0.0 ? 0 : 1, nsys);
   check_launch();
 }
 
 void Ctx::apply_KD(int prec, void* out, const void* in, int nsys, bool eps_in, bool eps_out, int rps) {
-  prof_mark(MG_PROF_KD, 0);
+  prof_mark(MG_PROF_KD, 0, nsys);
   if (prec == P64) {
     KdArgs<double> a{};
     a.out = (double2*)out; a.in = (const double2*)in; a.kinv = kinv64 + (int64_t)kd_base * kinv_slot;
@@ -367,7 +367,7 @@ void Ctx::apply_KD(int prec, void* out, const void* in, int nsys, bool eps_in, b
     a.rhs_per_slot = rps; a.slot_stride = kinv_slot; a.eps_in = eps_in; a.eps_out = eps_out;
     launch_kd_apply(a, st);
   }
-  prof_mark(MG_PROF_KD, 0);
+  prof_mark(MG_PROF_KD, 0, nsys);
   check_launch();
 }
 
@@ -389,13 +389,13 @@ void Ctx::apply_kd_operator(int prec, void* out, const void* in, void* tmp, int 
     k.g = g0; k.in_stride = k.out_stride = g0.V * 3; k.nrhs = nsys;
     k.rhs_per_slot = rps; k.slot_stride = kinv_slot;
     if (dslash_plane_ok(d) && kd_lds_ok(k)) {
-      prof_mark(MG_PROF_DSLASH, 1);
+      prof_mark(MG_PROF_DSLASH, 1, nsys);
       launch_dslash_plane(d, st);
-      prof_mark(MG_PROF_DSLASH, 1);
+      prof_mark(MG_PROF_DSLASH, 1, nsys);
       check_launch();
-      prof_mark(MG_PROF_KD, 0);
+      prof_mark(MG_PROF_KD, 0, nsys);
       launch_kd_apply(k, st);
-      prof_mark(MG_PROF_KD, 0);
+      prof_mark(MG_PROF_KD, 0, nsys);
       check_launch();
       return;
     }
@@ -406,7 +406,7 @@ void Ctx::apply_kd_operator(int prec, void* out, const void* in, void* tmp, int 
 
 void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, bool dag, const uint32_t* in16,
                        uint32_t* out16) {
-  prof_mark(MG_PROF_COARSE, lvl);
+  prof_mark(MG_PROF_COARSE, lvl, nsys);
   const int l = lvl - 2;
   const int n = ncoarse[l];
   if (prec == P64) {
@@ -431,12 +431,12 @@ void Ctx::apply_coarse(int lvl, int prec, void* out, const void* in, int nsys, b
     a.g = gc[l]; a.n = n; a.in_stride = a.out_stride = gc[l].V * n; a.nrhs = nsys;
     launch_coarse(a, false, dag, st);
   }
-  prof_mark(MG_PROF_COARSE, lvl);
+  prof_mark(MG_PROF_COARSE, lvl, nsys);
   check_launch();
 }
 
 void Ctx::restrict_(int lvl, int prec, void* out, const void* in, int nsys) {
-  prof_mark(MG_PROF_RESTRICT, lvl);
+  prof_mark(MG_PROF_RESTRICT, lvl, nsys);
   const int l = lvl - 1;   // lvl 1: fine -> level 2, lvl 2: level 2 -> level 3
   const Agg& a = A[l];
   const int64_t nin = a.nagg * 2 * a.nrows, nout = a.nagg * 2 * a.nvec;
@@ -451,12 +451,12 @@ void Ctx::restrict_(int lvl, int prec, void* out, const void* in, int nsys) {
     r.in_stride = nin; r.out_stride = nout; r.out_site_stride = 2 * a.nvec; r.nrhs = nsys;
     launch_restrict(r, st);
   }
-  prof_mark(MG_PROF_RESTRICT, lvl);
+  prof_mark(MG_PROF_RESTRICT, lvl, nsys);
   check_launch();
 }
 
 void Ctx::prolong_(int lvl, int prec, void* out, const void* in, int nsys, bool acc) {
-  prof_mark(MG_PROF_PROLONG, lvl);
+  prof_mark(MG_PROF_PROLONG, lvl, nsys);
   const int l = lvl - 1;
   const Agg& a = A[l];
   const int64_t nfine = a.nagg * 2 * a.nrows, ncrs = a.nagg * 2 * a.nvec;
@@ -471,7 +471,7 @@ void Ctx::prolong_(int lvl, int prec, void* out, const void* in, int nsys, bool 
     r.in_stride = ncrs; r.out_stride = nfine; r.nrhs = nsys; r.accumulate = acc; r.unit_col = -1;
     launch_prolong(r, st);
   }
-  prof_mark(MG_PROF_PROLONG, lvl);
+  prof_mark(MG_PROF_PROLONG, lvl, nsys);
   check_launch();
 }
 

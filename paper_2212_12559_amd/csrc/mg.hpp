@@ -133,10 +133,10 @@ struct Ctx {
 
   // kernel timing: while prof_op >= 0, every launch of that operator (at
   // prof_level where it has one) is bracketed by a pair of HIP events
-  int prof_op = -1, prof_level = 0;
+  int prof_op = -1, prof_level = 0, prof_nrhs = 0;   // prof_nrhs > 0: only launches over that many systems
   std::vector<hipEvent_t> prof_events;
   size_t prof_used = 0;
-  void prof_mark(int op, int level);   // records the next event when (op, level) is profiled
+  void prof_mark(int op, int level, int nsys);   // records the next event when (op, level, nsys) is profiled
   ~Ctx();
 
   // ---- layout

@@ -111,7 +111,7 @@ def _load():
         "mg_update_links": (i32, [vp, vp, vp, vp]),
         "mg_autotune": (i32, [vp, i32, P(MGTuneInfo), vp]),
         "mg_apply_coarse_multi": (i32, [P(vp), i32, i32, P(vp), P(vp), P(i32), vp]),
-        "mg_profile_start": (i32, [vp, i32, i32]),
+        "mg_profile_start": (i32, [vp, i32, i32, i32]),
         "mg_profile_stop": (i32, [vp, P(i32), P(f64)]),
         "mg_peak_copy": (i32, [vp, vp, sz, i32, vp, P(f64)]),
         "mg_peak_mfma": (i32, [i32, i32, vp, vp, P(f64)]),
@@ -417,9 +417,10 @@ class Context:
                  "mtiles_per_wave": t.mtiles_per_wave, "candidates": t.candidates, "us_best": t.us_best,
                  "us_default": t.us_default} for t in info if t.level > 0]
 
-    def profile_start(self, op, level=0):
-        """Time every launch of one operator (MG_PROF_*) with HIP events."""
-        _check(LIB.mg_profile_start(self.ctx, op, level), "mg_profile_start")
+    def profile_start(self, op, level=0, nrhs=0):
+        """Time every launch of one operator (MG_PROF_*) with HIP events; with
+        nrhs > 0 only its launches over exactly nrhs systems."""
+        _check(LIB.mg_profile_start(self.ctx, op, level, nrhs), "mg_profile_start")
 
     def profile_stop(self):
         """(launches, total milliseconds) since profile_start."""

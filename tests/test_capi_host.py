@@ -132,7 +132,7 @@ def test_profile_entry_points_validate(m):
     before touching any device state."""
     n = ctypes.c_int32()
     ms = ctypes.c_double()
-    assert m.LIB.mg_profile_start(None, m.MG_PROF_COARSE, 2) == m.MG_E_ARG
+    assert m.LIB.mg_profile_start(None, m.MG_PROF_COARSE, 2, 0) == m.MG_E_ARG
     assert m.LIB.mg_profile_stop(None, ctypes.byref(n), ctypes.byref(ms)) == m.MG_E_ARG
 
 

@@ -242,6 +242,15 @@ def test_profile_counts_launches(case, mg):
     assert n == 3 and ms > 0.0
     n, ms = case.ctx.profile_stop()
     assert n == 0 and ms == 0.0
+    # with an rhs count only the launches over exactly that many systems
+    case.ctx.profile_start(mg.MG_PROF_COARSE, lvl, nrhs=5)
+    case.ctx.apply_coarse(lvl, x)
+    case.ctx.apply_coarse(lvl, x[:3].contiguous())
+    case.ctx.apply_coarse(lvl, x)
+    n, ms = case.ctx.profile_stop()
+    assert n == 2 and ms > 0.0
+    with pytest.raises(RuntimeError):
+        case.ctx.profile_start(mg.MG_PROF_COARSE, lvl, nrhs=-1)
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
