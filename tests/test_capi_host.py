@@ -30,6 +30,54 @@ def test_header_symbols_exported(m):
         assert hasattr(lib, n), f"{n} declared in mgstag.h but not exported"
 
 
+def declared_prototypes():
+    """name -> (return type, [parameter types]) of every function the header
+    declares (comments removed, parameter names dropped)."""
+    src = open(os.path.join(ROOT, "include", "mgstag.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for ret, name, params in re.findall(r"([A-Za-z_][\w\s\*]*?)\b(mg_[a-z_]+)\s*\(([^)]*)\)\s*;", src):
+        ps = [q.strip() for q in params.split(",")]
+        ps = [] if ps == ["void"] or ps == [""] else ps
+        types = []
+        for q in ps:
+            arr = re.search(r"\[[^]]*\]$", q) is not None
+            q = re.sub(r"\s*\[[^]]*\]$", "", q)
+            q = re.sub(r"\b\w+$", "", q).strip()   # drop the parameter name
+            types.append(q + "*" if arr else q)      # an array parameter is a pointer
+        out[name] = (ret.split()[-1].strip() if "*" not in ret else ret.strip(), types)
+    return out
+
+
+def _kind(ctype):
+    """'ptr', 'i32', 'f64', 'size' or 'void' for a C type or a ctypes type."""
+    if isinstance(ctype, str):
+        if "*" in ctype or ctype in ("mg_ctx",):
+            return "ptr"
+        base = ctype.replace("const", "").strip()
+        return {"int32_t": "i32", "mg_status": "i32", "double": "f64", "size_t": "size", "void": "void"}[base]
+    if ctype is None:
+        return "void"
+    if ctype in (ctypes.c_void_p, ctypes.c_char_p) or hasattr(ctype, "_type_") and issubclass(
+            ctype, ctypes._Pointer):
+        return "ptr"
+    return {ctypes.c_int32: "i32", ctypes.c_double: "f64", ctypes.c_size_t: "size"}[ctype]
+
+
+def test_binding_signatures_match_header(m):
+    """Every function of include/mgstag.h has a ctypes prototype in the
+    binding with the same return kind and the same number and kind of
+    arguments (pointer, int32, double, size_t): a stale prototype would
+    pass wrong arguments through the C ABI without any error on the host."""
+    protos = declared_prototypes()
+    assert len(protos) == len(declared_functions())
+    for name, (ret, params) in protos.items():
+        f = getattr(m.LIB, name)
+        assert f.argtypes is not None, f"{name}: no ctypes prototype in the binding"
+        assert [_kind(t) for t in f.argtypes] == [_kind(t) for t in params], name
+        assert _kind(f.restype) == _kind(ret), name
+
+
 def test_params_struct_matches_header(m, tmp_path):
     """sizeof and field offsets of mg_params / mg_solve_info as the C compiler
     lays them out from the header equal the ctypes mirrors."""
